@@ -1,0 +1,316 @@
+"""Plain FP64 CPU reference for rotational OMP in a steerable circular-harmonic basis.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library imports, links or calls this
+module; only the tests, the smoke check and the CPU-baseline timing of the
+benchmark do.  It is written to be checked against the paper by eye: no
+factoring, no blocking, a dense augmented dictionary and a fresh QR
+least-squares solve at every pursuit step.
+
+Paper: McCann, Andrearczyk, Unser, Depeursinge, "Fast Rotational Sparse Coding"
+(arXiv 1806.04374).  Section and equation numbers below refer to it:
+  eq. (2)  rotational sparse coding objective (Sec. II-B)
+  eq. (3)  rotation covariance of the code (Sec. II-B)
+  eq. (4)  rearrangement with a unitary steerable basis (Sec. II-D)
+  eq. (5)  annular circular-harmonic basis functions (Sec. II-D)
+  eq. (6)  rotation multiplies harmonic t by exp(-i t theta0) (Sec. II-D)
+  eq. (7)  sampling on the grid, normalisation, column stacking (Sec. II-D)
+  eq. (8)  steering matrix S_r (Sec. II-D)
+  Sec. II-C and Fig. 2 (pseudocode): augmented dictionary [R_0 D ... R_{R-1} D]
+           and OMP over it.
+  Sec. II-E  proposed algorithm: basis, hat coordinates, R-K-SVD with S_r in
+           place of R_r, back to pixels with Phi.
+
+Readings where the paper is silent (each one is listed in the design notes):
+  * Grid axes: pixel (row i, col j) sits at x = j - c, y = c - i (y up),
+    c = (N-1)/2; angles are atan2(y, x), counter-clockwise.
+  * Disk: pixels with radius < N/2 (97 pixels at N = 11, as printed in III-A).
+  * Radial profiles are Gaussian windows exp(-(rho - rho_s)^2 / (2 sigma^2))
+    with rho_s = s (N/2)/S, s = 1..S and sigma = (N/2)/S, in place of the
+    annulus indicator of eq. (5).  Every harmonic k = 0..T is kept on every
+    profile.  The centre pixel is set to 0 for k != 0 (its angle is undefined).
+  * After the per-column normalisation of eq. (7), the S columns of each
+    harmonic are Loewdin-orthonormalised (Phi_k <- Phi_k G_k^{-1/2}); this
+    keeps the columns of a harmonic orthogonal, as the disjoint annuli of
+    eq. (5) are, and does not change the span or steerability.
+  * Packed real coordinates, harmonic-major: [k=0: s=0..S-1], then for each
+    k = 1..T [Re: s=0..S-1][Im: s=0..S-1].  The real synthesis vectors are
+    Re phi_{s,0}, sqrt(2) Re phi_{s,k} and -sqrt(2) Im phi_{s,k}; a packed pair
+    (a, b) stands for the complex coefficient (a + i b)/sqrt(2) on phi_{s,k}
+    and its conjugate on phi_{s,-k}.
+  * Steering by r multiplies (a + i b) of harmonic k by exp(-i k 2 pi r / R),
+    the sign of eq. (6)/(8).
+  * Pursuit: select the column of largest |correlation|; exact ties go to the
+    smallest atom index, then the smallest angle index; stop early when
+    ||r||^2 <= tau^2 ||x||^2 (tau = 1e-5) or when the selected column is
+    already in the support.  The same atom at another angle may be selected
+    (Sec. II-B).  Empty slots are (-1, -1, 0).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+TAU = 1e-5
+
+
+# --------------------------------------------------------------------------- grid
+def disk_grid(N: int):
+    """Grid of eq. (7) restricted to the circular patch of Sec. III-A.
+
+    Returns (mask [N,N] bool, rho, theta) with rho/theta of the disk pixels in
+    row-major order.  x = col - c, y = c - row, theta = atan2(y, x).
+    """
+    if N < 1 or N % 2 == 0:
+        raise ValueError("N must be odd and positive")
+    c = (N - 1) / 2
+    rows, cols = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    x = cols - c
+    y = c - rows
+    rho = np.sqrt(x * x + y * y)
+    mask = rho < N / 2
+    return mask, rho[mask], np.arctan2(y[mask], x[mask])
+
+
+def default_profiles(N: int, S: int):
+    """Gaussian profile centres rho_s = s (N/2)/S (s = 1..S) and width sigma = (N/2)/S."""
+    sigma = (N / 2) / S
+    return sigma * np.arange(1, S + 1, dtype=np.float64), sigma
+
+
+@dataclasses.dataclass
+class Basis:
+    N: int
+    S: int
+    T: int
+    mask: np.ndarray          # [N, N] disk
+    phi_c: np.ndarray         # [T+1, S, n_pix] complex columns phi_{s,k}, k >= 0
+    phi: np.ndarray           # [n_pix, B] packed real synthesis matrix
+    pinv: np.ndarray          # [B, n_pix] (Phi^T Phi)^{-1} Phi^T
+
+    @property
+    def B(self) -> int:
+        return self.S * (2 * self.T + 1)
+
+    @property
+    def n_pix(self) -> int:
+        return int(self.mask.sum())
+
+
+def build_basis(N: int, S: int, T: int, centres=None, sigma=None) -> Basis:
+    """Discrete steerable basis, eq. (5)-(7), with the Gaussian-profile reading above."""
+    mask, rho, theta = disk_grid(N)
+    if centres is None or sigma is None:
+        centres, sigma = default_profiles(N, S)
+    centres = np.asarray(centres, dtype=np.float64)
+    n = rho.size
+    phi_c = np.zeros((T + 1, S, n), dtype=np.complex128)
+    for k in range(T + 1):
+        for s in range(S):
+            col = np.exp(-((rho - centres[s]) ** 2) / (2.0 * sigma * sigma)) * np.exp(1j * k * theta)
+            if k != 0:
+                col[rho == 0] = 0.0
+            phi_c[k, s] = col / np.linalg.norm(col)
+        # Loewdin orthonormalisation of the S columns of harmonic k
+        cols = phi_c[k].T                                 # [n, S]
+        gram = cols.conj().T @ cols                       # [S, S] Hermitian
+        w, v = np.linalg.eigh(gram)
+        inv_sqrt = (v / np.sqrt(w)) @ v.conj().T
+        phi_c[k] = (cols @ inv_sqrt).T
+    # packed real synthesis vectors, harmonic-major
+    blocks = [phi_c[0].real.T]
+    for k in range(1, T + 1):
+        blocks.append(np.sqrt(2.0) * phi_c[k].real.T)
+        blocks.append(-np.sqrt(2.0) * phi_c[k].imag.T)
+    phi = np.concatenate(blocks, axis=1)                  # [n, B]
+    # biorthogonal partner (Phi^T Phi)^{-1} Phi^T, Sec. II-D
+    pinv = np.linalg.solve(phi.T @ phi, phi.T)
+    return Basis(N, S, T, mask, phi_c, phi, pinv)
+
+
+# --------------------------------------------------------------------------- coordinates
+def project(basis: Basis, patches: np.ndarray) -> np.ndarray:
+    """Hat coordinates x_hat = (Phi^* Phi)^{-1} Phi^* x (Sec. II-E, step 2).
+
+    patches: [P, N, N]; pixels outside the disk are ignored.  Returns [P, B].
+    Computed as a least-squares solve of Phi x_hat = x over the disk pixels.
+    """
+    X = np.asarray(patches, dtype=np.float64).reshape(len(patches), -1)
+    Xd = X[:, basis.mask.ravel()]
+    if Xd.shape[0] == 0:
+        return np.zeros((0, basis.B))
+    sol, *_ = np.linalg.lstsq(basis.phi, Xd.T, rcond=None)
+    return sol.T
+
+
+def to_pixels(basis: Basis, xhat: np.ndarray) -> np.ndarray:
+    """Phi x_hat placed on the N x N grid, zero outside the disk (Sec. II-E, step 4)."""
+    xhat = np.atleast_2d(xhat)
+    out = np.zeros((xhat.shape[0], basis.N * basis.N))
+    out[:, basis.mask.ravel()] = xhat @ basis.phi.T
+    return out.reshape(-1, basis.N, basis.N)
+
+
+def steer(xhat: np.ndarray, theta, S: int, T: int) -> np.ndarray:
+    """Apply the steering matrix of eq. (8) for rotation angle theta (radians).
+
+    Harmonic k of the complex coefficient is multiplied by exp(-i k theta);
+    harmonic 0 is unchanged.  xhat [..., B]; theta broadcasts against xhat[..., 0].
+    """
+    xhat = np.asarray(xhat, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    out = xhat.copy()
+    for k in range(1, T + 1):
+        re = slice(S + 2 * S * (k - 1), S + 2 * S * (k - 1) + S)
+        im = slice(S + 2 * S * (k - 1) + S, S + 2 * S * k)
+        z = xhat[..., re] + 1j * xhat[..., im]
+        z = z * np.exp(-1j * k * theta)[..., None]
+        out[..., re] = z.real
+        out[..., im] = z.imag
+    return out
+
+
+def augmented_dictionary(D_hat: np.ndarray, R: int, S: int, T: int) -> np.ndarray:
+    """Dense augmented dictionary [S_0 D, S_1 D, ..., S_{R-1} D] (Fig. 2 with R_r -> S_r).
+
+    Returned as rows: row j = r*M + m is S_r d_m, shape [M*R, B].
+    """
+    M = D_hat.shape[0]
+    rows = np.empty((R * M, D_hat.shape[1]))
+    for r in range(R):
+        rows[r * M:(r + 1) * M] = steer(D_hat, 2 * np.pi * r / R, S, T)
+    return rows
+
+
+# --------------------------------------------------------------------------- pursuit
+@dataclasses.dataclass
+class Code:
+    atom: np.ndarray      # [P, K] int, -1 for empty slots
+    angle: np.ndarray     # [P, K] int, -1 for empty slots
+    coef: np.ndarray      # [P, K] float64, 0 for empty slots
+    resid2: np.ndarray    # [P] squared hat-domain residual norm
+    corr: np.ndarray      # [P, K] |correlation| of each selection (0 for empty)
+    gap: np.ndarray       # [P, K] relative gap between the two largest |c| at each step
+
+
+def _pick(absc: np.ndarray, M: int) -> int:
+    """Largest |c|; exact ties go to the smallest atom index, then the smallest angle."""
+    best = absc.max()
+    cand = np.flatnonzero(absc == best)
+    m = cand % M
+    r = cand // M
+    order = np.lexsort((r, m))
+    return int(cand[order[0]])
+
+
+def omp(D_aug: np.ndarray, xhat: np.ndarray, K: int, M: int, tau: float = TAU,
+        trace=None) -> Code:
+    """Orthogonal matching pursuit over the augmented dictionary (Sec. II-C).
+
+    D_aug [M*R, B] rows are unit-norm columns of the augmented dictionary; xhat [P, B].
+    Each step: correlate the residual with every column, take the largest
+    magnitude, add it to the support, refit all coefficients on the support by
+    least squares (Householder QR) and recompute the residual.
+    ``trace(p, k, support, coef, residual)`` is called after each step when given.
+    """
+    xhat = np.asarray(xhat, dtype=np.float64)
+    P = xhat.shape[0]
+    atom = -np.ones((P, K), np.int64)
+    angle = -np.ones((P, K), np.int64)
+    coef = np.zeros((P, K))
+    corr = np.zeros((P, K))
+    gap = np.zeros((P, K))
+    resid2 = np.zeros(P)
+    res = xhat.copy()
+    support = [[] for _ in range(P)]
+    active = np.ones(P, dtype=bool)
+    for k in range(K):
+        for p in np.flatnonzero(active):
+            if res[p] @ res[p] <= tau * tau * (xhat[p] @ xhat[p]):
+                active[p] = False
+        idx = np.flatnonzero(active)
+        if idx.size == 0:
+            break
+        C = res[idx] @ D_aug.T                          # correlations of all columns
+        for t, p in enumerate(idx):
+            absc = np.abs(C[t])
+            j = _pick(absc, M)
+            if j in support[p]:
+                active[p] = False
+                continue
+            support[p].append(j)
+            A = D_aug[support[p]].T                     # [B, k+1]
+            Q, Rm = np.linalg.qr(A)
+            a = np.linalg.solve(Rm, Q.T @ xhat[p])
+            res[p] = xhat[p] - A @ a
+            corr[p, k] = absc[j]
+            if absc.size > 1 and absc[j] > 0:
+                second = np.partition(absc, -2)[-2]
+                gap[p, k] = (absc[j] - second) / absc[j]
+            if trace is not None:
+                trace(p, k, list(support[p]), a.copy(), res[p].copy())
+    for p in range(P):
+        s = support[p]
+        if s:
+            A = D_aug[s].T
+            Q, Rm = np.linalg.qr(A)
+            a = np.linalg.solve(Rm, Q.T @ xhat[p])
+            for i, j in enumerate(s):
+                atom[p, i] = j % M
+                angle[p, i] = j // M
+                coef[p, i] = a[i]
+        resid2[p] = res[p] @ res[p]
+    return Code(atom, angle, coef, resid2, corr, gap)
+
+
+def encode(basis: Basis, D_hat: np.ndarray, R: int, patches: np.ndarray, K: int,
+           tau: float = TAU) -> tuple[np.ndarray, Code]:
+    """Sec. II-E steps 2-3 for a fixed dictionary: hat coordinates, then OMP with S_r."""
+    xhat = project(basis, patches)
+    D_aug = augmented_dictionary(D_hat, R, basis.S, basis.T)
+    return xhat, omp(D_aug, xhat, K, D_hat.shape[0], tau)
+
+
+def code_to_hat(D_hat: np.ndarray, R: int, S: int, T: int, code: Code) -> np.ndarray:
+    """sum_i a_i S_{r_i} d_{m_i} for each patch (empty slots contribute nothing)."""
+    P, K = code.atom.shape
+    out = np.zeros((P, D_hat.shape[1]))
+    for p in range(P):
+        for i in range(K):
+            if code.atom[p, i] >= 0:
+                out[p] += code.coef[p, i] * steer(D_hat[code.atom[p, i]],
+                                                  2 * np.pi * code.angle[p, i] / R, S, T)
+    return out
+
+
+def reconstruct(basis: Basis, D_hat: np.ndarray, R: int, code: Code) -> np.ndarray:
+    """Pixel-domain reconstruction Phi sum_i a_i S_{r_i} d_{m_i} (Sec. II-E step 4), [P, N, N]."""
+    return to_pixels(basis, code_to_hat(D_hat, R, basis.S, basis.T, code))
+
+
+def mse(basis: Basis, patches: np.ndarray, recon: np.ndarray) -> float:
+    """Mean over patches and disk pixels of the squared coding error (Sec. III-A metric)."""
+    m = basis.mask
+    d = (np.asarray(patches, np.float64) - recon)[:, m]
+    return float(np.mean(d * d)) if d.size else 0.0
+
+
+def span_error(basis: Basis, patches: np.ndarray) -> float:
+    """Mean squared distance of the patches to span(Phi) on the disk (the lower bound of Sec. III-A)."""
+    xhat = project(basis, patches)
+    return mse(basis, patches, to_pixels(basis, xhat))
+
+
+# --------------------------------------------------------------------------- synthesis
+def synthesize(basis: Basis, D_hat: np.ndarray, atom, angle, weight, noise=None) -> np.ndarray:
+    """Patches sum_i w_i Phi S_{theta_i} d_{m_i} (+ noise on all N x N pixels), [P, N, N]."""
+    atom = np.asarray(atom)
+    P, J = atom.shape
+    hat = np.zeros((P, D_hat.shape[1]))
+    for i in range(J):
+        hat += np.asarray(weight)[:, i, None] * steer(D_hat[atom[:, i]], np.asarray(angle)[:, i],
+                                                     basis.S, basis.T)
+    x = to_pixels(basis, hat)
+    if noise is not None:
+        x = x + noise
+    return x
