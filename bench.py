@@ -1,0 +1,204 @@
+"""Throughput of rotational OMP encoding on one MI355X.
+
+A step is one pass of the whole coding path over the batch: rsc_project (hat
+coordinates) then rsc_omp_encode (K pursuit steps), inputs resident in HBM.
+Default workload: 1,000,000 synthetic 11x11 patches, each 1-4 atoms of a random
+unit-norm 64-atom dictionary at continuous angles with Laplace(0,1) weights plus
+N(0, 0.05^2) noise; K=4 atoms per patch over R=64 angles.
+
+Prints one JSON line.  The CPU baseline leg times the FP64 reference on a
+bounded sample of the same workload and checks the device codes of that sample
+against it (selection match and MSE).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1806_04374_amd import workloads as wl  # noqa: E402
+
+METRIC = "patches encoded/sec (rotational OMP, K atoms, R angles) at matched MSE; p50/p99"
+FP32_MFMA_PEAK = 157.3e12
+
+
+def encode_flops_per_patch(M: int, R: int, S: int, T: int, K: int) -> float:
+    """Algorithmic flops of the pursuit for one patch doing all K steps.
+
+    Correlation (per step): per-harmonic inner products 2*M*S*(1+4T) plus the angle
+    DFT 2*M*R*(2T+1).  Least squares and residual (step k): 2*(2*k*B + k^2).
+    """
+    B = S * (2 * T + 1)
+    corr = 2.0 * (M * S * (1 + 4 * T) + M * R * (2 * T + 1))
+    ls = sum(2.0 * (2 * k * B + k * k) for k in range(1, K + 1))
+    return K * corr + ls
+
+
+def make_inputs(h, w, P, dev):
+    """Synthesize the workload's patches on the device from the seeded draws."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    g = w["geom"]
+    X = torch.empty((P, g.N, g.N), dtype=torch.float32, device=dev)
+    step = 1 << 18
+    for lo in range(0, P, step):
+        n = min(step, P - lo)
+        if w["name"] == "small-fp32":
+            _, d = wl.small_draw(P=n, start=lo)
+        else:
+            _, d = wl.scale_draw(P=n, start=lo)
+        rsc.rsc_synthesize(h, torch.from_numpy(d.atom.astype(np.int32)).to(dev),
+                           torch.from_numpy(d.angle.astype(np.float32)).to(dev),
+                           torch.from_numpy(d.weight.astype(np.float32)).to(dev),
+                           torch.from_numpy(d.noise.astype(np.float32)).to(dev), out=X[lo:lo + n])
+    torch.cuda.synchronize()
+    return X
+
+
+def cpu_baseline(h, w, D, target_s: float, dev):
+    """Time the FP64 reference (as it stands) on a bounded sample of the workload."""
+    import torch
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    from paper_1806_04374_amd import rsc
+    g = w["geom"]
+    basis = orc.build_basis(g.N, g.S, g.T)
+
+    def sample(n):
+        if w["name"] == "small-fp32":
+            _, d = wl.small_draw(P=n)
+        else:
+            _, d = wl.scale_draw(P=n)
+        return orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+
+    n0 = 256
+    X0 = sample(n0)
+    t0 = time.perf_counter()
+    orc.encode(basis, D, w["R"], X0.astype(np.float64), w["K"])
+    dt0 = time.perf_counter() - t0
+    n = int(min(200_000, max(n0, n0 * target_s / max(dt0, 1e-3))))
+    X = sample(n)
+    t0 = time.perf_counter()
+    _, code = orc.encode(basis, D, w["R"], X.astype(np.float64), w["K"])
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    # device codes of the same sample: selection match and matched MSE
+    xd = torch.from_numpy(X).to(dev)
+    xh = rsc.rsc_project(h, xd)
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, w["K"])
+    rec = rsc.rsc_reconstruct(h, atom, angle, coef)
+    torch.cuda.synchronize()
+    a, r = atom.cpu().numpy(), angle.cpu().numpy()
+    match = np.mean([
+        {(x, y) for x, y in zip(a[p], r[p]) if x >= 0} ==
+        {(int(x), int(y)) for x, y in zip(code.atom[p], code.angle[p]) if x >= 0}
+        for p in range(n)])
+    mse_dev = orc.mse(basis, X, rec.cpu().numpy().astype(np.float64))
+    mse_ref = orc.mse(basis, X, orc.reconstruct(basis, D, w["R"], code))
+    return {
+        "value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+        "sample": f"first {n} patches of the same workload (FP64 reference, {dt:.1f} s)",
+        "check": {"selection_match": float(match), "mse_device": mse_dev, "mse_oracle": mse_ref,
+                  "mse_rel_diff": abs(mse_dev - mse_ref) / mse_ref},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["scale", "small"], default="scale")
+    ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the coding path has no cross-GPU step, see the design notes for how it shards.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_04374_amd import rsc
+    dev = torch.device("cuda:0")
+    w = wl.SCALE if args.workload == "scale" else wl.SMALL
+    g = w["geom"]
+    P = args.patches or w["P"]
+    D = wl.draw_dictionary(w["M"], g.B)
+    h = rsc.rsc_create(g.N, g.S, g.T)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+    X = make_inputs(h, w, P, dev)
+    K = w["K"]
+    xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+    outs = (torch.empty((P, K), dtype=torch.int32, device=dev),
+            torch.empty((P, K), dtype=torch.int32, device=dev),
+            torch.empty((P, K), dtype=torch.float32, device=dev),
+            torch.empty((P,), dtype=torch.float32, device=dev))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rsc.rsc_project(h, X, xh, stream=stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s0, s1, s2 in ev:
+        s0.record(stream)
+        rsc.rsc_project(h, X, xh, stream=stream)
+        s1.record(stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+        s2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(c) for a, _, c in ev])
+    proj_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+    enc_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    ms = wall * 1e3 / args.steps
+    flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
+    achieved = flops / (enc_ms.mean() * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": P / (ms * 1e-3),
+        "unit": "patches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "patches_per_s_p50": P / (np.percentile(step_ms, 50) * 1e-3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {P} {g.N}x{g.N} patches, M={w['M']}, K={K}, R={w['R']}, "
+                               f"S={g.S}, T={g.T}, B={g.B}",
+                   "P": P, "N": g.N, "S": g.S, "T": g.T, "M": w["M"], "K": K, "R": w["R"]},
+        "kernels_ms": {"project_mean": float(proj_ms.mean()), "encode_mean": float(enc_ms.mean())},
+        "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_MFMA_PEAK, "traffic": None,
+                     "algorithmic_flops_per_launch": flops},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(h, w, D, args.cpu_seconds, dev)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * rsc.h -- rotational sparse coding on gfx950 (MI355X): C ABI.
+ *
+ * Implements the encoding path of "Fast Rotational Sparse Coding" (McCann,
+ * Andrearczyk, Unser, Depeursinge; arXiv 1806.04374): patches are mapped to
+ * coordinates in a discrete steerable basis (Sec. II-D, II-E step 2) and coded
+ * by orthogonal matching pursuit over every rotation of every atom, with the
+ * rotation R_r replaced by the diagonal steering matrix S_r (eq. (8); Sec. II-C,
+ * Fig. 2; Sec. II-E step 3).  Codes map back to pixels with Phi (Sec. II-E step 4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns rsc_status: 0 on success, a negative code on error.
+ *    Nothing aborts or prints.  rsc_last_error() gives a thread-local message for
+ *    the last failure on the calling thread.
+ *  - Device pointers are HIP device (or managed) addresses owned by the caller.
+ *    The library owns only the handle and its resident copies of the basis,
+ *    dictionary and tables.  Host arrays are copied before the call returns.
+ *  - "stream" is a hipStream_t passed as void*; NULL is the default stream.  The
+ *    compute calls only enqueue work and return; argument errors are reported
+ *    synchronously, launch errors as RSC_E_DEVICE.  rsc_sync() waits.
+ *  - Compute calls never allocate device memory.
+ *  - A handle may be used from one thread at a time; distinct handles are
+ *    independent.
+ *  - Geometry: odd patch side N; pixel (row i, col j) sits at x = j - c,
+ *    y = c - i with c = (N-1)/2 (y up); angles are counter-clockwise.  The patch
+ *    is the disk of radius N/2 (97 pixels at N = 11, as in Sec. III-A); pixels
+ *    outside it are ignored on input and written as 0 on output.
+ *  - Hat coordinates are packed real, B = S(2T+1) per patch, harmonic-major:
+ *    [k=0: s=0..S-1], then for k = 1..T: [Re: s=0..S-1][Im: s=0..S-1].  A pair
+ *    (a, b) of harmonic k stands for the complex coefficient (a + i b)/sqrt(2)
+ *    of the circular harmonic of order k and its conjugate for order -k.
+ *  - Angle index r in [0, R) means a rotation by 2*pi*r/R counter-clockwise:
+ *    harmonic k of a coefficient is multiplied by exp(-i k 2 pi r / R) (eq. (6),
+ *    eq. (8)).  Atom index m is in [0, M).
+ */
+#ifndef RSC_H
+#define RSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSC_OK = 0,
+  RSC_E_INVALID = -1,      /* bad argument: null pointer, size out of range, wrong state */
+  RSC_E_NOMEM = -2,        /* the library could not allocate its own resident copies */
+  RSC_E_DEVICE = -3,       /* a HIP call or kernel launch failed */
+  RSC_E_UNSUPPORTED = -4   /* valid request that this build does not implement */
+} rsc_status;
+
+typedef enum {
+  RSC_FP32 = 0,            /* projection and correlation in FP32 on MFMA */
+  RSC_BF16 = 1,            /* projection and correlation operands in BF16, FP32 accumulation */
+  RSC_FP16 = 2             /* projection and correlation operands in FP16, FP32 accumulation */
+} rsc_precision;
+
+typedef struct rsc_handle rsc_handle;
+
+/*
+ * Build the discrete steerable basis on the host in FP64 and upload it
+ * (Sec. II-D, eq. (5)-(7); Sec. II-E step 1).
+ *
+ * Columns are phi_{s,k}(rho, theta) = g_s(rho) exp(i k theta) for s = 0..S-1 and
+ * k = 0..T, sampled on the disk grid, with g_s(rho) = exp(-(rho - centres[s])^2 /
+ * (2 sigma^2)) in place of the annulus indicator of eq. (5).  The centre pixel is
+ * 0 for k != 0.  Each column is normalised (eq. (7)) and the S columns of every
+ * harmonic are then made orthonormal by symmetric (Loewdin) orthonormalisation.
+ * The biorthogonal partner (Phi^T Phi)^{-1} Phi^T (Sec. II-D) is formed by a
+ * Cholesky factorisation.
+ *
+ *   N        odd patch side, 3 <= N <= 31
+ *   S, T     radial profiles and largest harmonic; (S, T) must be one of the
+ *            compiled geometries (5, 5) or (7, 7), and B = S(2T+1) <= n_pix
+ *   centres  host array [S] of profile centres in pixels, or NULL for
+ *            centres[s] = (s+1) (N/2)/S
+ *   sigma    profile width in pixels, or <= 0 for (N/2)/S (used only when
+ *            centres is NULL or sigma > 0)
+ *   prec     arithmetic of projection and correlation (rsc_precision)
+ *   out      receives the new handle
+ * Errors: RSC_E_INVALID (bad sizes, null out, singular basis), RSC_E_UNSUPPORTED
+ * (geometry or precision not compiled), RSC_E_NOMEM, RSC_E_DEVICE.
+ */
+rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma,
+                      rsc_precision prec, rsc_handle** out);
+
+/*
+ * The same FP64 basis construction as rsc_create, on the host only (no device
+ * needed): for inspection and host-side tests.
+ *   phi   host [N*N, B] or NULL;  pinv  host [B, N*N] or NULL (layouts as in
+ *   rsc_get_basis); n_pix, B, cond_gram may be NULL.  Callers size phi/pinv with
+ *   B = S(2T+1).  Any S >= 1, T >= 0 is accepted here.
+ */
+rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sigma,
+                          double* phi, double* pinv, int* n_pix, int* B, double* cond_gram);
+
+/* Release the handle and its device copies.  NULL is accepted. */
+rsc_status rsc_destroy(rsc_handle* h);
+
+/*
+ * Sizes of the basis: disk pixel count, packed hat dimension B = S(2T+1), and the
+ * 2-norm condition number of Phi^T Phi (FP64).  Any output pointer may be NULL.
+ */
+rsc_status rsc_basis_info(const rsc_handle* h, int* n_pix, int* B, double* cond_gram);
+
+/*
+ * Host copies of the FP64 basis for inspection: phi [N*N, B] (row = pixel in
+ * row-major grid order, zero rows outside the disk) and pinv [B, N*N] (zero
+ * columns outside the disk).  Either pointer may be NULL.
+ */
+rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
+
+/*
+ * Load the dictionary D_hat (Sec. II-C; hat coordinates, Sec. II-E step 3) and the
+ * angle grid size R.
+ *   d_hat  HOST array [M, B] float32, packed hat coordinates, each row of unit
+ *          Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID)
+ *   M      1 <= M <= 256
+ *   R      1 <= R <= 128
+ * Synchronous (the copy to the device completes before return).
+ */
+rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
+
+/*
+ * Projection onto the basis (Sec. II-E step 2): xhat_p = (Phi^T Phi)^{-1} Phi^T x_p.
+ *   patches  device [P, N, N] float32 row-major; off-disk pixels ignored
+ *   P        number of patches, >= 0 (0 is a no-op)
+ *   xhat     device [P, B] float32 row-major, written
+ */
+rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat,
+                       void* stream);
+
+/*
+ * Rotational OMP over the augmented dictionary [S_0 D, ..., S_{R-1} D]
+ * (Fig. 2 with R_r replaced by S_r; Sec. II-C and II-E step 3), K atoms per patch.
+ * Each step selects the (atom, angle) of largest |<S_r d_m, residual>| (exact ties:
+ * smallest m, then smallest r), refits all selected coefficients by least squares
+ * and updates the residual.  A patch stops early when ||residual||^2 <=
+ * 1e-10 ||xhat||^2 or when the best column is already selected.
+ *   xhat         device [P, B] float32 (output of rsc_project)
+ *   P            >= 0
+ *   K            1 <= K <= 8 and K <= B
+ *   atom, angle  device [P, K] int32, slots in selection order; empty slots -1
+ *   coef         device [P, K] float32; empty slots 0
+ *   resid2       device [P] float32 squared hat-domain residual norm, or NULL
+ * Requires rsc_set_dictionary first (else RSC_E_INVALID).
+ */
+rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K,
+                          int32_t* atom, int32_t* angle, float* coef, float* resid2,
+                          void* stream);
+
+/*
+ * Pixels of coded patches (Sec. II-E step 4): x_p = Phi sum_i coef[p,i] S_{angle[p,i]}
+ * d_{atom[p,i]}; slots with atom < 0 are skipped.
+ *   atom, angle, coef  device [P, K] (as written by rsc_omp_encode)
+ *   out                device [P, N, N] float32, 0 outside the disk
+ * Slots with atom >= M or angle outside [0, R) are treated as empty.
+ */
+rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32_t* angle,
+                           const float* coef, int64_t P, int K, float* out, void* stream);
+
+/*
+ * Synthetic patches at continuous angles: out_p = Phi sum_j weight[p,j]
+ * S(theta[p,j]) d_{atom[p,j]} + noise_p, where S(theta) multiplies harmonic k by
+ * exp(-i k theta) (eq. (6)).  Used to build inputs on the device.
+ *   atom    device [P, J] int32 (entries outside [0, M) are skipped)
+ *   theta   device [P, J] float32 radians
+ *   weight  device [P, J] float32
+ *   noise   device [P, N, N] float32 added to every pixel, or NULL
+ *   out     device [P, N, N] float32
+ *   1 <= J <= 16
+ */
+rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float* theta,
+                          const float* weight, int64_t P, int J, const float* noise,
+                          float* out, void* stream);
+
+/* Wait for all work on the stream; reports RSC_E_DEVICE for a failed kernel. */
+rsc_status rsc_sync(void* stream);
+
+/* Message for the last failure on this thread ("" if none).  Valid until the next call. */
+const char* rsc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSC_H */

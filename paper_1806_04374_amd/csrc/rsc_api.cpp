@@ -1,0 +1,294 @@
+// C ABI of librsc: handles, argument validation, host-side table arrangement and
+// device uploads.  All compute is enqueued through the launchers of rsc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rsc.h"
+#include "rsc_internal.h"
+
+struct rsc_handle {
+  rsc::HostBasis basis;
+  rsc::DeviceTables dev;
+  rsc_precision prec = RSC_FP32;
+  bool has_dict = false;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rsc_status fail(rsc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+rsc_status ok() {
+  g_err.clear();
+  return RSC_OK;
+}
+
+rsc_status device_fail(int e, const char* what) {
+  return fail(RSC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(hipError_t(e)));
+}
+
+void free_dev(float*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+rsc_status upload(float*& dst, const std::vector<float>& src, const char* what) {
+  free_dev(dst);
+  if (src.empty()) return RSC_OK;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&dst), src.size() * sizeof(float));
+  if (e != hipSuccess) {
+    dst = nullptr;
+    return fail(RSC_E_NOMEM, std::string("hipMalloc for ") + what + " failed");
+  }
+  e = hipMemcpy(dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(int(e), what);
+  return RSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsc_last_error(void) { return g_err.c_str(); }
+
+rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, rsc_precision prec,
+                      rsc_handle** out) {
+  if (!out) return fail(RSC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
+  if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
+  if (!rsc::encode_supported(S, T))
+    return fail(RSC_E_UNSUPPORTED, "(S, T) must be (5, 5) or (7, 7) in this build");
+  if (prec != RSC_FP32) return fail(RSC_E_UNSUPPORTED, "only RSC_FP32 is implemented");
+  if (centres) {
+    for (int s = 0; s < S; ++s)
+      if (!std::isfinite(centres[s])) return fail(RSC_E_INVALID, "non-finite profile centre");
+  }
+  rsc_handle* h = new (std::nothrow) rsc_handle();
+  if (!h) return fail(RSC_E_NOMEM, "handle allocation failed");
+  std::string err;
+  if (!rsc::build_basis(N, S, T, centres, sigma, h->basis, err)) {
+    delete h;
+    return fail(RSC_E_INVALID, "basis construction failed: " + err);
+  }
+  const rsc::HostBasis& b = h->basis;
+  h->prec = prec;
+  rsc::DeviceTables& d = h->dev;
+  d.N = N;
+  d.S = S;
+  d.T = T;
+  d.B = b.B;
+  const int NN = N * N, KP = (NN + 1) / 2;
+  const int RTB = (b.B + 31) / 32 <= 2 ? 2 : 4;  // row tiles of the compiled projection kernels
+  // projection A operand: row = hat coordinate, contraction = grid pixel
+  std::vector<float> pinvA(size_t(RTB) * KP * 64, 0.f);
+  for (int t = 0; t < RTB; ++t)
+    for (int j = 0; j < KP; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const int row = 32 * t + (l % 32), px = 2 * j + l / 32;
+        if (row < b.B && px < NN) pinvA[(size_t(t) * KP + j) * 64 + l] = float(b.pinv[size_t(row) * NN + px]);
+      }
+  std::vector<float> phiPad(size_t(NN) * b.B);
+  for (size_t i = 0; i < phiPad.size(); ++i) phiPad[i] = float(b.phi[i]);
+  rsc_status s = upload(d.pinvA, pinvA, "projection table");
+  if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
+  if (s != RSC_OK) {
+    rsc_destroy(h);
+    return s;
+  }
+  *out = h;
+  return ok();
+}
+
+rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sigma, double* phi,
+                          double* pinv, int* n_pix, int* B, double* cond_gram) {
+  if (N < 1 || N > 63 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 1..63");
+  if (S < 1 || T < 0 || S > 64 || T > 64) return fail(RSC_E_INVALID, "S must be 1..64 and T 0..64");
+  rsc::HostBasis b;
+  std::string err;
+  if (!rsc::build_basis(N, S, T, centres, sigma, b, err))
+    return fail(RSC_E_INVALID, "basis construction failed: " + err);
+  if (phi) std::memcpy(phi, b.phi.data(), b.phi.size() * sizeof(double));
+  if (pinv) std::memcpy(pinv, b.pinv.data(), b.pinv.size() * sizeof(double));
+  if (n_pix) *n_pix = b.n_pix;
+  if (B) *B = b.B;
+  if (cond_gram) *cond_gram = b.cond;
+  return ok();
+}
+
+rsc_status rsc_destroy(rsc_handle* h) {
+  if (!h) return ok();
+  rsc::DeviceTables& d = h->dev;
+  free_dev(d.pinvA);
+  free_dev(d.phiPad);
+  free_dev(d.dictA);
+  free_dev(d.dictHat);
+  free_dev(d.dftA);
+  free_dev(d.cs);
+  delete h;
+  return ok();
+}
+
+rsc_status rsc_basis_info(const rsc_handle* h, int* n_pix, int* B, double* cond_gram) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (n_pix) *n_pix = h->basis.n_pix;
+  if (B) *B = h->basis.B;
+  if (cond_gram) *cond_gram = h->basis.cond;
+  return ok();
+}
+
+rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (phi) std::memcpy(phi, h->basis.phi.data(), h->basis.phi.size() * sizeof(double));
+  if (pinv) std::memcpy(pinv, h->basis.pinv.data(), h->basis.pinv.size() * sizeof(double));
+  return ok();
+}
+
+rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!d_hat) return fail(RSC_E_INVALID, "d_hat is NULL");
+  if (M < 1 || M > 256) return fail(RSC_E_INVALID, "M must be in 1..256");
+  if (R < 1 || R > 128) return fail(RSC_E_INVALID, "R must be in 1..128");
+  rsc::DeviceTables& d = h->dev;
+  const int S = d.S, T = d.T, B = d.B;
+  for (int m = 0; m < M; ++m) {
+    double n2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+      const double v = d_hat[size_t(m) * B + b];
+      if (!std::isfinite(v)) return fail(RSC_E_INVALID, "non-finite dictionary entry");
+      n2 += v * v;
+    }
+    if (std::fabs(1.0 - std::sqrt(n2)) > 1e-4)
+      return fail(RSC_E_INVALID, "dictionary row " + std::to_string(m) + " is not unit norm");
+  }
+  const int NG = (M + 15) / 16;
+  const int RT = R <= 32 ? 1 : (R <= 64 ? 2 : 4);
+  const int K0 = rsc::k0_steps(S), NKS = rsc::stage1_steps(S, T), NQ = T + 1;
+  auto D = [&](int m, int c) -> float { return m < M ? d_hat[size_t(m) * B + c] : 0.f; };
+  // stage-1 A operand: rows 0..15 give Re C_k of atoms 16g..16g+15, rows 16..31 Im C_k;
+  // the two contraction lanes of a step are (Re, Im) of one profile (k >= 1) or two
+  // consecutive profiles (k = 0, where rows 16..31 are zero).
+  std::vector<float> dictA(size_t(NG) * NKS * 64, 0.f);
+  for (int g = 0; g < NG; ++g)
+    for (int ks = 0; ks < NKS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int row = l % 32, hh = l / 32, a = row % 16, m = 16 * g + a;
+        float v = 0.f;
+        if (ks < K0) {
+          const int s = 2 * ks + hh;
+          if (row < 16 && s < S) v = D(m, s);
+        } else {
+          const int q = ks - K0, k = 1 + q / S, s = q % S, base = S + 2 * S * (k - 1);
+          const float re = D(m, base + s), im = D(m, base + S + s);
+          if (row < 16) v = hh == 0 ? re : im;
+          else v = hh == 0 ? -im : re;
+        }
+        dictA[(size_t(g) * NKS + ks) * 64 + l] = v;
+      }
+  std::vector<float> hat(size_t(NG) * 16 * B, 0.f);
+  for (int m = 0; m < M; ++m)
+    for (int b = 0; b < B; ++b) hat[size_t(m) * B + b] = d_hat[size_t(m) * B + b];
+  // stage-2 A operand: row = angle, contraction lanes (cos, -sin) per harmonic, (1, 0) for k = 0
+  std::vector<float> dftA(size_t(RT) * NQ * 64, 0.f);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int t = 0; t < RT; ++t)
+    for (int q = 0; q < NQ; ++q)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 32 * t + (l % 32), hh = l / 32;
+        if (r >= R) continue;
+        float v;
+        if (q == 0) v = hh == 0 ? 1.f : 0.f;
+        else {
+          const double th = two_pi * double(q) * double(r) / double(R);
+          v = hh == 0 ? float(std::cos(th)) : float(-std::sin(th));
+        }
+        dftA[(size_t(t) * NQ + q) * 64 + l] = v;
+      }
+  std::vector<float> cs(size_t(2) * NQ * R);
+  for (int k = 0; k < NQ; ++k)
+    for (int r = 0; r < R; ++r) {
+      const double th = two_pi * double(k) * double(r) / double(R);
+      cs[size_t(k) * R + r] = float(std::cos(th));
+      cs[size_t(NQ + k) * R + r] = float(std::sin(th));
+    }
+  d.M = M;
+  d.R = R;
+  d.NG = NG;
+  d.RT = RT;
+  if (rsc::encode_lds_bytes(d) > 160 * 1024) {
+    h->has_dict = false;
+    return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
+  }
+  rsc_status s = upload(d.dictA, dictA, "dictionary operand");
+  if (s == RSC_OK) s = upload(d.dictHat, hat, "dictionary");
+  if (s == RSC_OK) s = upload(d.dftA, dftA, "angle DFT operand");
+  if (s == RSC_OK) s = upload(d.cs, cs, "steering table");
+  h->has_dict = s == RSC_OK;
+  return s == RSC_OK ? ok() : s;
+}
+
+rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!patches || !xhat) return fail(RSC_E_INVALID, "null device pointer");
+  if (P > (int64_t(1) << 31) * 64) return fail(RSC_E_INVALID, "P too large");
+  int e = rsc::launch_project(h->dev, patches, P, xhat, stream);
+  return e ? device_fail(e, "projection launch") : ok();
+}
+
+rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
+                          int32_t* angle, float* coef, float* resid2, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "null device pointer");
+  int e = rsc::launch_encode(h->dev, xhat, P, K, atom, angle, coef, resid2, stream);
+  return e ? device_fail(e, "encode launch") : ok();
+}
+
+rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32_t* angle,
+                           const float* coef, int64_t P, int K, float* out, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (K < 1 || K > 16) return fail(RSC_E_INVALID, "K must be in 1..16");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!atom || !angle || !coef || !out) return fail(RSC_E_INVALID, "null device pointer");
+  if (P > (int64_t(1) << 31) * 8) return fail(RSC_E_INVALID, "P too large");
+  int e = rsc::launch_synthesize(h->dev, atom, angle, nullptr, coef, P, K, nullptr, out, stream);
+  return e ? device_fail(e, "reconstruct launch") : ok();
+}
+
+rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float* theta,
+                          const float* weight, int64_t P, int J, const float* noise, float* out,
+                          void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (J < 1 || J > 16) return fail(RSC_E_INVALID, "J must be in 1..16");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!atom || !theta || !weight || !out) return fail(RSC_E_INVALID, "null device pointer");
+  if (P > (int64_t(1) << 31) * 8) return fail(RSC_E_INVALID, "P too large");
+  int e = rsc::launch_synthesize(h->dev, atom, nullptr, theta, weight, P, J, noise, out, stream);
+  return e ? device_fail(e, "synthesize launch") : ok();
+}
+
+rsc_status rsc_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(int(e), "stream synchronize");
+  return ok();
+}
+
+}  // extern "C"

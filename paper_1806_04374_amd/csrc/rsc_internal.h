@@ -1,0 +1,52 @@
+// Internal interfaces of librsc (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rsc {
+
+// FP64 steerable basis on the host.  phi is [N*N][B] and pinv is [B][N*N] with
+// zero rows / columns for pixels outside the disk.
+struct HostBasis {
+  int N = 0, S = 0, T = 0, B = 0, n_pix = 0;
+  double cond = 0.0;
+  std::vector<int> pix;        // disk pixels, row-major grid index
+  std::vector<double> phi;     // [N*N][B]
+  std::vector<double> pinv;    // [B][N*N]
+};
+
+bool build_basis(int N, int S, int T, const double* centres, double sigma, HostBasis& out,
+                 std::string& err);
+
+// Geometry-dependent constants of the encoder.  Stage-1 contraction steps: the
+// k = 0 block pairs profiles (s, s+1) per step, every k >= 1 block uses one step
+// per profile with (Re, Im) as the two contraction lanes.
+constexpr int k0_steps(int S) { return (S + 1) / 2; }
+constexpr int stage1_steps(int S, int T) { return k0_steps(S) + T * S; }
+
+// Device tables owned by a handle (FP32 operand arrangements built on the host).
+struct DeviceTables {
+  int N = 0, S = 0, T = 0, B = 0;
+  int M = 0, R = 0, NG = 0, RT = 0;
+  float* pinvA = nullptr;    // projection A operand [ceil(B/32)][ceil(N*N/2)][64]
+  float* phiPad = nullptr;   // synthesis matrix [N*N][B]
+  float* dictA = nullptr;    // stage-1 A operand [NG][stage1_steps][64]
+  float* dictHat = nullptr;  // dictionary rows [NG*16][B] (zero rows past M)
+  float* dftA = nullptr;     // stage-2 A operand [RT][T+1][64]
+  float* cs = nullptr;       // [2][T+1][R]: cos, then sin, of 2 pi k r / R
+};
+
+// Kernel launchers (rsc_kernels.hip).  Return a hipError_t as int.
+int launch_project(const DeviceTables& t, const float* patches, int64_t P, float* xhat,
+                   void* stream);
+int launch_encode(const DeviceTables& t, const float* xhat, int64_t P, int K, int32_t* atom,
+                  int32_t* angle, float* coef, float* resid2, void* stream);
+int launch_synthesize(const DeviceTables& t, const int32_t* atom, const int32_t* angle_idx,
+                      const float* theta, const float* weight, int64_t P, int J,
+                      const float* noise, float* out, void* stream);
+bool encode_supported(int S, int T);
+size_t encode_lds_bytes(const DeviceTables& t);
+
+}  // namespace rsc

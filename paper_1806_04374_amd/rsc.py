@@ -1,0 +1,227 @@
+"""ctypes binding of librsc (include/rsc.h), same call names as the C ABI.
+
+Only argument marshalling happens here: shape/dtype/device checks, output
+allocation with torch, and passing raw pointers and the current HIP stream.
+Every step of the coding path runs in the library's kernels.  If the library is
+not built, loading fails with an error (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librsc.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "rsc.h")
+
+RSC_OK, RSC_E_INVALID, RSC_E_NOMEM, RSC_E_DEVICE, RSC_E_UNSUPPORTED = 0, -1, -2, -3, -4
+PRECISION = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+_lib = None
+
+
+class RscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rsc status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load librsc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1806_04374_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "rsc_create": [I, I, I, P, D, I, ctypes.POINTER(ctypes.c_void_p)],
+        "rsc_basis_host": [I, I, I, P, D, P, P, P, P, P],
+        "rsc_destroy": [P],
+        "rsc_basis_info": [P, P, P, P],
+        "rsc_get_basis": [P, P, P],
+        "rsc_set_dictionary": [P, P, I, I],
+        "rsc_project": [P, P, I64, P, P],
+        "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
+        "rsc_reconstruct": [P, P, P, P, I64, I, P, P],
+        "rsc_synthesize": [P, P, P, P, I64, I, P, P, P],
+        "rsc_sync": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.rsc_last_error.argtypes = []
+    L.rsc_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions declared in include/rsc.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"\b(rsc_\w+)\s*\(", text)
+
+
+def _check(status: int):
+    if status != RSC_OK:
+        raise RscError(status, lib().rsc_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Handle:
+    """Owner of an rsc_handle*; geometry and dictionary sizes are cached."""
+
+    def __init__(self, ptr, N, S, T):
+        self.ptr = ptr
+        self.N, self.S, self.T = N, S, T
+        n_pix, B, cond = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().rsc_basis_info(ptr, ctypes.byref(n_pix), ctypes.byref(B), ctypes.byref(cond)))
+        self.n_pix, self.B, self.cond = n_pix.value, B.value, cond.value
+        self.M = self.R = None
+
+    def close(self):
+        if self.ptr:
+            lib().rsc_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rsc_create(N: int, S: int, T: int, centres=None, sigma: float = 0.0, prec: str = "fp32") -> Handle:
+    h = ctypes.c_void_p()
+    c = None
+    if centres is not None:
+        c = np.ascontiguousarray(centres, dtype=np.float64)
+    _check(lib().rsc_create(N, S, T, None if c is None else c.ctypes.data_as(ctypes.c_void_p),
+                            float(sigma), PRECISION[prec], ctypes.byref(h)))
+    return Handle(h, N, S, T)
+
+
+def rsc_basis_host(N: int, S: int, T: int, centres=None, sigma: float = 0.0):
+    """FP64 (phi [N*N, B], pinv [B, N*N], cond) built by the library on the host."""
+    B = S * (2 * T + 1)
+    phi = np.zeros((N * N, B))
+    pinv = np.zeros((B, N * N))
+    cond = ctypes.c_double()
+    c = None if centres is None else np.ascontiguousarray(centres, dtype=np.float64)
+    _check(lib().rsc_basis_host(N, S, T, None if c is None else c.ctypes.data_as(ctypes.c_void_p),
+                                float(sigma), phi.ctypes.data_as(ctypes.c_void_p),
+                                pinv.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(cond)))
+    return phi, pinv, cond.value
+
+
+def rsc_get_basis(h: Handle):
+    phi = np.zeros((h.N * h.N, h.B))
+    pinv = np.zeros((h.B, h.N * h.N))
+    _check(lib().rsc_get_basis(h.ptr, phi.ctypes.data_as(ctypes.c_void_p),
+                               pinv.ctypes.data_as(ctypes.c_void_p)))
+    return phi, pinv
+
+
+def rsc_set_dictionary(h: Handle, d_hat, R: int):
+    d = np.ascontiguousarray(d_hat, dtype=np.float32)
+    if d.ndim != 2 or d.shape[1] != h.B:
+        raise ValueError(f"d_hat must be [M, {h.B}]")
+    _check(lib().rsc_set_dictionary(h.ptr, d.ctypes.data_as(ctypes.c_void_p), d.shape[0], R))
+    h.M, h.R = d.shape[0], R
+
+
+def rsc_project(h: Handle, patches, xhat=None, stream=None):
+    import torch
+    P = patches.shape[0]
+    _dev(patches, torch.float32, "patches", (P, h.N, h.N))
+    if xhat is None:
+        xhat = torch.empty((P, h.B), dtype=torch.float32, device=patches.device)
+    _dev(xhat, torch.float32, "xhat", (P, h.B))
+    _check(lib().rsc_project(h.ptr, _ptr(patches), P, _ptr(xhat), _stream(stream)))
+    return xhat
+
+
+def rsc_omp_encode(h: Handle, xhat, K: int, out=None, stream=None):
+    """Returns (atom [P,K] int32, angle [P,K] int32, coef [P,K] f32, resid2 [P] f32)."""
+    import torch
+    P = xhat.shape[0]
+    _dev(xhat, torch.float32, "xhat", (P, h.B))
+    if out is None:
+        dv = xhat.device
+        out = (torch.empty((P, K), dtype=torch.int32, device=dv),
+               torch.empty((P, K), dtype=torch.int32, device=dv),
+               torch.empty((P, K), dtype=torch.float32, device=dv),
+               torch.empty((P,), dtype=torch.float32, device=dv))
+    atom, angle, coef, resid2 = out
+    _dev(atom, torch.int32, "atom", (P, K))
+    _dev(angle, torch.int32, "angle", (P, K))
+    _dev(coef, torch.float32, "coef", (P, K))
+    if resid2 is not None:
+        _dev(resid2, torch.float32, "resid2", (P,))
+    _check(lib().rsc_omp_encode(h.ptr, _ptr(xhat), P, K, _ptr(atom), _ptr(angle), _ptr(coef),
+                                _ptr(resid2), _stream(stream)))
+    return atom, angle, coef, resid2
+
+
+def rsc_reconstruct(h: Handle, atom, angle, coef, out=None, stream=None):
+    import torch
+    P, K = atom.shape
+    _dev(atom, torch.int32, "atom", (P, K))
+    _dev(angle, torch.int32, "angle", (P, K))
+    _dev(coef, torch.float32, "coef", (P, K))
+    if out is None:
+        out = torch.empty((P, h.N, h.N), dtype=torch.float32, device=atom.device)
+    _dev(out, torch.float32, "out", (P, h.N, h.N))
+    _check(lib().rsc_reconstruct(h.ptr, _ptr(atom), _ptr(angle), _ptr(coef), P, K, _ptr(out),
+                                 _stream(stream)))
+    return out
+
+
+def rsc_synthesize(h: Handle, atom, theta, weight, noise=None, out=None, stream=None):
+    import torch
+    P, J = atom.shape
+    _dev(atom, torch.int32, "atom", (P, J))
+    _dev(theta, torch.float32, "theta", (P, J))
+    _dev(weight, torch.float32, "weight", (P, J))
+    if noise is not None:
+        _dev(noise, torch.float32, "noise", (P, h.N, h.N))
+    if out is None:
+        out = torch.empty((P, h.N, h.N), dtype=torch.float32, device=atom.device)
+    _dev(out, torch.float32, "out", (P, h.N, h.N))
+    _check(lib().rsc_synthesize(h.ptr, _ptr(atom), _ptr(theta), _ptr(weight), P, J, _ptr(noise),
+                                _ptr(out), _stream(stream)))
+    return out
+
+
+def rsc_sync(stream=None):
+    _check(lib().rsc_sync(_stream(stream)))

@@ -1,0 +1,269 @@
+"""Device path against the FP64 reference, through the C ABI.
+
+Acceptance: the selected (atom, angle) sets agree on >= 99.9% of patches,
+coefficients of matched patches agree within 1e-4 relative (FP32), and the
+reconstruction MSE agrees within 1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import rsc_oracle as orc
+from paper_1806_04374_amd import workloads as wl
+from tests.parity import compare_codes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MATCH = 0.999
+COEF_REL = 1e-4
+MSE_REL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04374_amd import rsc
+    rsc.lib()
+    return torch.device("cuda:0")
+
+
+def _handle(geom, D, R):
+    from paper_1806_04374_amd import rsc
+    h = rsc.rsc_create(geom.N, geom.S, geom.T)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    return h
+
+
+def _encode(h, X32, K, dev):
+    from paper_1806_04374_amd import rsc
+    x = torch.from_numpy(X32).to(dev)
+    xh = rsc.rsc_project(h, x)
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, xh, K)
+    torch.cuda.synchronize()
+    return xh, atom, angle, coef, r2
+
+
+def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True):
+    """Full path parity: project + encode (+ reconstruct) against the reference."""
+    from paper_1806_04374_amd import rsc
+    basis = basis or orc.build_basis(geom.N, geom.S, geom.T)
+    h = _handle(geom, D, R)
+    xh, atom, angle, coef, r2 = _encode(h, X32, K, dev)
+    xh_ref, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
+    # projection parity (FP32 GEMM against FP64 least squares)
+    err = np.abs(xh.cpu().numpy() - xh_ref).max(axis=1) / np.maximum(np.linalg.norm(xh_ref, axis=1), 1e-30)
+    assert err.max() < 2e-5, (label, err.max())
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    print(label, rep, flush=True)
+    assert rep.match_rate >= MATCH, (label, str(rep))
+    assert rep.coef_bad <= int((1 - MATCH) * rep.n), (label, str(rep))
+    if mse:
+        rec = rsc.rsc_reconstruct(h, atom, angle, coef)
+        torch.cuda.synchronize()
+        mse_gpu = orc.mse(basis, X32, rec.cpu().numpy().astype(np.float64))
+        mse_ref = orc.mse(basis, X32, orc.reconstruct(basis, D, R, code))
+        print(label, "mse", mse_gpu, mse_ref, flush=True)
+        assert abs(mse_gpu - mse_ref) <= MSE_REL * mse_ref + 1e-12, label
+    # reported hat residual agrees with the reference residual
+    r2 = r2.cpu().numpy()
+    close = np.abs(r2 - code.resid2) <= 1e-3 * code.resid2 + 1e-5 * np.einsum("ij,ij->i", xh_ref, xh_ref) + 1e-12
+    assert close.mean() >= MATCH, (label, close.mean())
+    h.close()
+    return rep
+
+
+def test_small_plain_workload_full(dev):
+    """2,000 11x11 patches, M=16, K=2, R=32: two grid-rotated atoms plus N(0, 0.01^2) noise."""
+    w = wl.SMALL
+    geom = w["geom"]
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.small_draw()
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    _check("small", X, D, w["R"], w["K"], geom, dev, basis)
+
+
+def test_scale_workload_ragged_slice(dev):
+    """Scale geometry (M=64, K=4, R=64) on 20,011 patches: many tiles plus a ragged tail."""
+    w = wl.SCALE
+    geom = w["geom"]
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.scale_draw(P=20011)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    _check("scale-20011", X, D, w["R"], w["K"], geom, dev, basis)
+
+
+def test_scale_workload_full_size_sampled(dev):
+    """All 1,000,000 scale patches encoded in one launch; 1,500 sampled patches checked."""
+    from paper_1806_04374_amd import rsc
+    w = wl.SCALE
+    geom = w["geom"]
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.scale_draw()
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    h = _handle(geom, D, w["R"])
+    xh, atom, angle, coef, r2 = _encode(h, X, w["K"], dev)
+    idx = np.sort(np.random.default_rng(0).choice(len(X), 1500, replace=False))
+    idx = np.concatenate([idx, [len(X) - 1]])
+    _, code = orc.encode(basis, D, w["R"], X[idx].astype(np.float64), w["K"])
+    rep = compare_codes(atom.cpu().numpy()[idx], angle.cpu().numpy()[idx], coef.cpu().numpy()[idx], code)
+    print("scale-full-sampled", rep, flush=True)
+    assert rep.match_rate >= 0.995          # 1,501 samples: allows 7 near-tie mismatches
+    assert rep.coef_bad <= 2
+    h.close()
+
+
+def test_large_geometry(dev):
+    """15x15 geometry (S=T=7, B=105), M=128, K=6, R=64 on 3,000 patches."""
+    geom = wl.GEOM15
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D = wl.draw_dictionary(128, geom.B, seed=0)
+    draw = wl.draw_mixtures(3000, geom.N, 128, 6, 0.05, seed=0)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    _check("geom15", X, D, 64, 6, geom, dev, basis)
+
+
+@pytest.mark.parametrize("M,R,K", [(20, 8, 3), (16, 60, 2), (5, 1, 4), (33, 100, 8), (64, 128, 1)])
+def test_uneven_shapes(dev, M, R, K):
+    """Atom counts off the 16-atom tile, angle grids off the 32-angle tile (60 as in the paper)."""
+    geom = wl.GEOM11
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D = wl.draw_dictionary(M, geom.B, seed=3)
+    draw = wl.draw_mixtures(1000, geom.N, M, 3, 0.02, seed=3)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    _check(f"M{M}-R{R}-K{K}", X, D, R, K, geom, dev, basis, mse=K <= 4)
+
+
+def test_edge_cases(dev):
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    M, R = 16, 32
+    D = wl.draw_dictionary(M, geom.B, seed=0)
+    h = _handle(geom, D, R)
+    # empty input is a no-op
+    e = torch.empty((0, 11, 11), dtype=torch.float32, device=dev)
+    xh = rsc.rsc_project(h, e)
+    out = rsc.rsc_omp_encode(h, xh, 2)
+    torch.cuda.synchronize()
+    assert out[0].shape == (0, 2)
+    # zero patches: every slot empty, zero residual
+    z = torch.zeros((5, 11, 11), dtype=torch.float32, device=dev)
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, rsc.rsc_project(h, z), 3)
+    torch.cuda.synchronize()
+    assert (atom.cpu() == -1).all() and (angle.cpu() == -1).all() and (coef.cpu() == 0).all()
+    assert (r2.cpu() == 0).all()
+    # one exact grid-rotated atom: recovered, then the early stop leaves the other slots empty
+    rng = np.random.default_rng(1)
+    a = rng.integers(0, M, (64, 1))
+    r = rng.integers(0, R, (64, 1))
+    wgt = rng.uniform(0.5, 2.0, (64, 1)) * rng.choice([-1, 1], (64, 1))
+    X = orc.synthesize(basis, D, a, 2 * np.pi * r / R, wgt).astype(np.float32)
+    atom, angle, coef, r2 = _encode(h, X, 3, dev)[1:]
+    atom, angle, coef = atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy()
+    assert np.array_equal(atom[:, 0], a[:, 0]) and np.array_equal(angle[:, 0], r[:, 0])
+    assert np.all(atom[:, 1:] == -1)
+    assert np.abs(coef[:, 0] - wgt[:, 0]).max() < 1e-4 * np.abs(wgt).max()
+    # rotation-invariant content: every angle ties, the smallest angle index wins
+    v = np.zeros((3, geom.B), np.float32)
+    v[:, :5] = rng.standard_normal((3, 5))
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, torch.from_numpy(v).to(dev), 1)
+    torch.cuda.synchronize()
+    ref = orc.omp(orc.augmented_dictionary(D, R, 5, 5), v.astype(np.float64), 1, M)
+    assert np.all(ref.angle[:, 0] == 0)
+    assert np.all(angle.cpu().numpy()[:, 0] == 0)
+    assert np.array_equal(atom.cpu().numpy()[:, 0], ref.atom[:, 0])
+    h.close()
+
+
+def test_batch_position_invariance(dev):
+    """A patch gives bit-identical codes wherever it sits in the batch."""
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.scale_draw(P=4099)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    h = _handle(geom, D, 64)
+    full = _encode(h, X, 4, dev)
+    for lo, n in [(0, 1), (7, 33), (1000, 517), (4090, 9)]:
+        part = _encode(h, X[lo:lo + n].copy(), 4, dev)
+        for a, b in zip(full[1:], part[1:]):
+            assert torch.equal(a[lo:lo + n].cpu(), b.cpu())
+    h.close()
+
+
+def test_rotation_equivariance_on_device(dev):
+    """Rotating a patch inside the basis span by r0 grid steps shifts every angle by r0."""
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    M, R, K = 16, 32, 2
+    D = wl.draw_dictionary(M, geom.B, seed=5)
+    draw = wl.draw_mixtures(500, geom.N, M, 2, 0.0, seed=5)
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    v = np.zeros((500, geom.B))
+    for i in range(2):
+        v += draw.weight[:, i, None] * orc.steer(D[draw.atom[:, i]], 2 * np.pi * np.round(draw.angle[:, i] / (2 * np.pi) * R) / R, 5, 5)
+    h = _handle(geom, D, R)
+    base = rsc.rsc_omp_encode(h, torch.from_numpy(v.astype(np.float32)).to(dev), K)
+    torch.cuda.synchronize()
+    ok = tot = 0
+    for r0 in (1, 8, 13):
+        vr = orc.steer(v, 2 * np.pi * r0 / R, 5, 5).astype(np.float32)
+        rot = rsc.rsc_omp_encode(h, torch.from_numpy(vr).to(dev), K)
+        torch.cuda.synchronize()
+        a0, g0 = base[0].cpu().numpy(), base[1].cpu().numpy()
+        a1, g1 = rot[0].cpu().numpy(), rot[1].cpu().numpy()
+        for p in range(len(v)):
+            tot += 1
+            s0 = {(int(a), (int(g) + r0) % R) for a, g in zip(a0[p], g0[p]) if a >= 0}
+            s1 = {(int(a), int(g)) for a, g in zip(a1[p], g1[p]) if a >= 0}
+            ok += s0 == s1
+    assert ok >= 0.995 * tot, (ok, tot)
+    h.close()
+
+
+def test_synthesize_and_reconstruct_match_reference(dev):
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.scale_draw(P=777)
+    h = _handle(geom, D, 64)
+    X_ref = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise)
+    X = rsc.rsc_synthesize(h, torch.from_numpy(draw.atom.astype(np.int32)).to(dev),
+                           torch.from_numpy(draw.angle.astype(np.float32)).to(dev),
+                           torch.from_numpy(draw.weight.astype(np.float32)).to(dev),
+                           torch.from_numpy(draw.noise.astype(np.float32)).to(dev))
+    torch.cuda.synchronize()
+    assert np.abs(X.cpu().numpy() - X_ref).max() < 1e-5 * np.abs(X_ref).max()
+    # reconstruction of given codes on a grid
+    rng = np.random.default_rng(2)
+    code = orc.Code(rng.integers(-1, 64, (777, 4)), rng.integers(0, 64, (777, 4)),
+                    rng.standard_normal((777, 4)), np.zeros(777), np.zeros((777, 4)), np.zeros((777, 4)))
+    code.angle[code.atom < 0] = -1
+    code.coef[code.atom < 0] = 0
+    ref = orc.reconstruct(basis, D, 64, code)
+    out = rsc.rsc_reconstruct(h, torch.from_numpy(code.atom.astype(np.int32)).to(dev),
+                              torch.from_numpy(code.angle.astype(np.int32)).to(dev),
+                              torch.from_numpy(code.coef.astype(np.float32)).to(dev))
+    torch.cuda.synchronize()
+    assert np.abs(out.cpu().numpy() - ref).max() < 1e-5 * np.abs(ref).max()
+    h.close()
+
+
+def test_device_argument_errors(dev):
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    h = rsc.rsc_create(11, 5, 5)
+    x = torch.zeros((4, 55), dtype=torch.float32, device=dev)
+    with pytest.raises(rsc.RscError, match="no dictionary"):
+        rsc.rsc_omp_encode(h, x, 2)
+    bad = np.ones((4, 55), np.float32)
+    with pytest.raises(rsc.RscError, match="unit norm"):
+        rsc.rsc_set_dictionary(h, bad, 8)
+    D = wl.draw_dictionary(4, 55)
+    rsc.rsc_set_dictionary(h, D, 8)
+    with pytest.raises(rsc.RscError, match="K must"):
+        rsc.rsc_omp_encode(h, x, 9)
+    with pytest.raises(rsc.RscError, match="R must"):
+        rsc.rsc_set_dictionary(h, D, 129)
+    h.close()
