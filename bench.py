@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile", choices=["auto", "16", "32"], default="auto")
+    ap.add_argument("--mode", choices=["encode", "copy"], default="encode",
+                    help="copy: only a plain 1 GiB device copy, to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -129,12 +132,23 @@ def main():
     import torch
     from paper_1806_04374_amd import rsc
     dev = torch.device("cuda:0")
+    if args.mode == "copy":
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                          "launches": 3}), flush=True)
+        return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]
     P = args.patches or w["P"]
     D = wl.draw_dictionary(w["M"], g.B)
     h = rsc.rsc_create(g.N, g.S, g.T)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+    rsc.rsc_set_tile(h, args.tile)
     X = make_inputs(h, w, P, dev)
     K = w["K"]
     xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
@@ -187,7 +201,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: {P} {g.N}x{g.N} patches, M={w['M']}, K={K}, R={w['R']}, "
                                f"S={g.S}, T={g.T}, B={g.B}",
-                   "P": P, "N": g.N, "S": g.S, "T": g.T, "M": w["M"], "K": K, "R": w["R"]},
+                   "P": P, "N": g.N, "S": g.S, "T": g.T, "M": w["M"], "K": K, "R": w["R"],
+                   "tile": args.tile},
         "kernels_ms": {"project_mean": float(proj_ms.mean()), "encode_mean": float(enc_ms.mean())},
         "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",

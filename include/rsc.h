@@ -58,6 +58,14 @@ typedef enum {
   RSC_FP16 = 2             /* projection and correlation operands in FP16, FP32 accumulation */
 } rsc_precision;
 
+/* Tile shape of the encoder (both give identical codes up to FP32 rounding order). */
+typedef enum {
+  RSC_TILE_AUTO = 0,       /* the library's choice for the geometry and K */
+  RSC_TILE_16 = 1,         /* 16 patches x 8 atoms per MFMA tile (v_mfma_f32_16x16x4f32) */
+  RSC_TILE_32 = 2          /* 32 patches x 16 atoms per MFMA tile (v_mfma_f32_32x32x2f32);
+                              S = T = 5, K <= 4 and R <= 64 only */
+} rsc_tile;
+
 typedef struct rsc_handle rsc_handle;
 
 /*
@@ -123,6 +131,13 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
  * Synchronous (the copy to the device completes before return).
  */
 rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
+
+/*
+ * Select the encoder tile shape for later rsc_omp_encode calls on this handle.
+ * RSC_TILE_32 on a geometry or K it does not support makes rsc_omp_encode fall
+ * back to RSC_TILE_16.  Errors: RSC_E_INVALID for an unknown value.
+ */
+rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile);
 
 /*
  * Projection onto the basis (Sec. II-E step 2): xhat_p = (Phi^T Phi)^{-1} Phi^T x_p.

@@ -15,6 +15,7 @@ struct rsc_handle {
   rsc::HostBasis basis;
   rsc::DeviceTables dev;
   rsc_precision prec = RSC_FP32;
+  rsc_tile tile = RSC_TILE_AUTO;
   bool has_dict = false;
 };
 
@@ -36,20 +37,22 @@ rsc_status device_fail(int e, const char* what) {
   return fail(RSC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(hipError_t(e)));
 }
 
-void free_dev(float*& p) {
+template <class X>
+void free_dev(X*& p) {
   if (p) (void)hipFree(p);
   p = nullptr;
 }
 
-rsc_status upload(float*& dst, const std::vector<float>& src, const char* what) {
+template <class X>
+rsc_status upload(X*& dst, const std::vector<X>& src, const char* what) {
   free_dev(dst);
   if (src.empty()) return RSC_OK;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&dst), src.size() * sizeof(float));
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&dst), src.size() * sizeof(X));
   if (e != hipSuccess) {
     dst = nullptr;
     return fail(RSC_E_NOMEM, std::string("hipMalloc for ") + what + " failed");
   }
-  e = hipMemcpy(dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice);
+  e = hipMemcpy(dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice);
   if (e != hipSuccess) return device_fail(int(e), what);
   return RSC_OK;
 }
@@ -97,9 +100,28 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
         const int row = 32 * t + (l % 32), px = 2 * j + l / 32;
         if (row < b.B && px < NN) pinvA[(size_t(t) * KP + j) * 64 + l] = float(b.pinv[size_t(row) * NN + px]);
       }
+  // projection operand over disk pixels only (contraction index 2j + u = disk pixel)
+  d.n_pix = b.n_pix;
+  const int KPD = (b.n_pix + 1) / 2;
+  std::vector<float> pinvD;
+  std::vector<int> pixD;
+  if (b.B <= 64) {
+    pinvD.assign(size_t(2) * KPD * 64, 0.f);
+    pixD.assign(size_t(2) * KPD, -1);
+    for (int i = 0; i < b.n_pix; ++i) pixD[i] = b.pix[i];
+    for (int t = 0; t < 2; ++t)
+      for (int j = 0; j < KPD; ++j)
+        for (int l = 0; l < 64; ++l) {
+          const int row = 32 * t + (l % 32), i = 2 * j + l / 32;
+          if (row < b.B && i < b.n_pix)
+            pinvD[(size_t(t) * KPD + j) * 64 + l] = float(b.pinv[size_t(row) * NN + b.pix[i]]);
+        }
+  }
   std::vector<float> phiPad(size_t(NN) * b.B);
   for (size_t i = 0; i < phiPad.size(); ++i) phiPad[i] = float(b.phi[i]);
   rsc_status s = upload(d.pinvA, pinvA, "projection table");
+  if (s == RSC_OK) s = upload(d.pinvD, pinvD, "projection table");
+  if (s == RSC_OK) s = upload(d.pixD, pixD, "pixel table");
   if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
   if (s != RSC_OK) {
     rsc_destroy(h);
@@ -129,11 +151,15 @@ rsc_status rsc_destroy(rsc_handle* h) {
   if (!h) return ok();
   rsc::DeviceTables& d = h->dev;
   free_dev(d.pinvA);
+  free_dev(d.pinvD);
+  free_dev(d.pixD);
   free_dev(d.phiPad);
   free_dev(d.dictA);
   free_dev(d.dictHat);
-  free_dev(d.dftA);
+  free_dev(d.dftA32);
+  free_dev(d.dftA16);
   free_dev(d.cs);
+  free_dev(d.gramH);
   delete h;
   return ok();
 }
@@ -171,69 +197,117 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
       return fail(RSC_E_INVALID, "dictionary row " + std::to_string(m) + " is not unit norm");
   }
   const int NG = (M + 15) / 16;
-  const int RT = R <= 32 ? 1 : (R <= 64 ? 2 : 4);
   const int K0 = rsc::k0_steps(S), NKS = rsc::stage1_steps(S, T), NQ = T + 1;
   auto D = [&](int m, int c) -> float { return m < M ? d_hat[size_t(m) * B + c] : 0.f; };
-  // stage-1 A operand: rows 0..15 give Re C_k of atoms 16g..16g+15, rows 16..31 Im C_k;
-  // the two contraction lanes of a step are (Re, Im) of one profile (k >= 1) or two
-  // consecutive profiles (k = 0, where rows 16..31 are zero).
-  std::vector<float> dictA(size_t(NG) * NKS * 64, 0.f);
-  for (int g = 0; g < NG; ++g)
-    for (int ks = 0; ks < NKS; ++ks)
-      for (int l = 0; l < 64; ++l) {
-        const int row = l % 32, hh = l / 32, a = row % 16, m = 16 * g + a;
-        float v = 0.f;
-        if (ks < K0) {
-          const int s = 2 * ks + hh;
-          if (row < 16 && s < S) v = D(m, s);
-        } else {
-          const int q = ks - K0, k = 1 + q / S, s = q % S, base = S + 2 * S * (k - 1);
-          const float re = D(m, base + s), im = D(m, base + S + s);
-          if (row < 16) v = hh == 0 ? re : im;
-          else v = hh == 0 ? -im : re;
+  // 32x32 tiles, stage-1 operand: rows 0..15 give Re C_k of atoms 16g..16g+15, rows
+  // 16..31 Im C_k; the two contraction lanes of a step are (Re, Im) of one profile
+  // (k >= 1) or two consecutive profiles (k = 0, where rows 16..31 are zero).
+  std::vector<float> dictA;
+  if (S == 5 && T == 5) {
+    dictA.assign(size_t(NG) * NKS * 64, 0.f);
+    for (int g = 0; g < NG; ++g)
+      for (int ks = 0; ks < NKS; ++ks)
+        for (int l = 0; l < 64; ++l) {
+          const int row = l % 32, hh = l / 32, a = row % 16, m = 16 * g + a;
+          float v = 0.f;
+          if (ks < K0) {
+            const int s = 2 * ks + hh;
+            if (row < 16 && s < S) v = D(m, s);
+          } else {
+            const int q = ks - K0, k = 1 + q / S, s = q % S, base = S + 2 * S * (k - 1);
+            const float re = D(m, base + s), im = D(m, base + S + s);
+            if (row < 16) v = hh == 0 ? re : im;
+            else v = hh == 0 ? -im : re;
+          }
+          dictA[(size_t(g) * NKS + ks) * 64 + l] = v;
         }
-        dictA[(size_t(g) * NKS + ks) * 64 + l] = v;
-      }
+  }
   std::vector<float> hat(size_t(NG) * 16 * B, 0.f);
   for (int m = 0; m < M; ++m)
     for (int b = 0; b < B; ++b) hat[size_t(m) * B + b] = d_hat[size_t(m) * B + b];
-  // stage-2 A operand: row = angle, contraction lanes (cos, -sin) per harmonic, (1, 0) for k = 0
-  std::vector<float> dftA(size_t(RT) * NQ * 64, 0.f);
   const double two_pi = 6.283185307179586476925286766559;
-  for (int t = 0; t < RT; ++t)
+  auto cosk = [&](int k, int r) { return float(std::cos(two_pi * double(k) * double(r) / double(R))); };
+  auto sink = [&](int k, int r) { return float(std::sin(two_pi * double(k) * double(r) / double(R))); };
+  // 32x32 tiles, stage-2 operand: row = angle, contraction lanes (cos, -sin) of one
+  // harmonic, (1, 0) for k = 0
+  const int RT32 = R <= 32 ? 1 : (R <= 64 ? 2 : 4);
+  std::vector<float> dftA32(size_t(RT32) * NQ * 64, 0.f);
+  for (int t = 0; t < RT32; ++t)
     for (int q = 0; q < NQ; ++q)
       for (int l = 0; l < 64; ++l) {
         const int r = 32 * t + (l % 32), hh = l / 32;
         if (r >= R) continue;
         float v;
         if (q == 0) v = hh == 0 ? 1.f : 0.f;
-        else {
-          const double th = two_pi * double(q) * double(r) / double(R);
-          v = hh == 0 ? float(std::cos(th)) : float(-std::sin(th));
-        }
-        dftA[(size_t(t) * NQ + q) * 64 + l] = v;
+        else v = hh == 0 ? cosk(q, r) : -sink(q, r);
+        dftA32[(size_t(t) * NQ + q) * 64 + l] = v;
+      }
+  // 16x16 tiles, stage-2 operand: row = angle, four contraction lanes
+  // (cos k, -sin k, cos k', -sin k') for the harmonic pair (k, k') = (2q, 2q+1)
+  const int RT16 = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
+  const int NP = (NQ + 1) / 2;
+  std::vector<float> dftA16(size_t(RT16) * NP * 64, 0.f);
+  for (int t = 0; t < RT16; ++t)
+    for (int q = 0; q < NP; ++q)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 16 * t + (l % 16), kk = l / 16, k = 2 * q + kk / 2;
+        if (r >= R || k > T) continue;
+        float v;
+        if (kk % 2 == 0) v = k == 0 ? 1.f : cosk(k, r);
+        else v = k == 0 ? 0.f : -sink(k, r);
+        dftA16[(size_t(t) * NP + q) * 64 + l] = v;
       }
   std::vector<float> cs(size_t(2) * NQ * R);
   for (int k = 0; k < NQ; ++k)
     for (int r = 0; r < R; ++r) {
-      const double th = two_pi * double(k) * double(r) / double(R);
-      cs[size_t(k) * R + r] = float(std::cos(th));
-      cs[size_t(NQ + k) * R + r] = float(std::sin(th));
+      cs[size_t(k) * R + r] = cosk(k, r);
+      cs[size_t(NQ + k) * R + r] = sink(k, r);
+    }
+  // per-pair harmonic inner products in FP64: H_0 = sum_s a_s b_s (k = 0 block),
+  // H_k = sum_s conj(a_k,s) b_k,s as (Re, Im) for k >= 1
+  const int HQ = 2 * T + 1;
+  std::vector<float> gramH(size_t(M) * M * HQ);
+  for (int a = 0; a < M; ++a)
+    for (int bb = 0; bb < M; ++bb) {
+      float* hh = &gramH[(size_t(a) * M + bb) * HQ];
+      double h0 = 0.0;
+      for (int s = 0; s < S; ++s) h0 += double(D(a, s)) * double(D(bb, s));
+      hh[0] = float(h0);
+      for (int k = 1; k <= T; ++k) {
+        const int base = S + 2 * S * (k - 1);
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < S; ++s) {
+          const double ar = D(a, base + s), ai = D(a, base + S + s);
+          const double br = D(bb, base + s), bi = D(bb, base + S + s);
+          re += ar * br + ai * bi;
+          im += ar * bi - ai * br;
+        }
+        hh[2 * k - 1] = float(re);
+        hh[2 * k] = float(im);
+      }
     }
   d.M = M;
   d.R = R;
   d.NG = NG;
-  d.RT = RT;
-  if (rsc::encode_lds_bytes(d) > 160 * 1024) {
-    h->has_dict = false;
+  h->has_dict = false;
+  if (rsc::encode_lds_bytes(d, RSC_TILE_16) > 160 * 1024)
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
-  }
   rsc_status s = upload(d.dictA, dictA, "dictionary operand");
   if (s == RSC_OK) s = upload(d.dictHat, hat, "dictionary");
-  if (s == RSC_OK) s = upload(d.dftA, dftA, "angle DFT operand");
+  if (s == RSC_OK) s = upload(d.dftA32, dftA32, "angle DFT operand");
+  if (s == RSC_OK) s = upload(d.dftA16, dftA16, "angle DFT operand");
   if (s == RSC_OK) s = upload(d.cs, cs, "steering table");
+  if (s == RSC_OK) s = upload(d.gramH, gramH, "pair table");
   h->has_dict = s == RSC_OK;
   return s == RSC_OK ? ok() : s;
+}
+
+rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (tile != RSC_TILE_AUTO && tile != RSC_TILE_16 && tile != RSC_TILE_32)
+    return fail(RSC_E_INVALID, "unknown tile shape");
+  h->tile = tile;
+  return ok();
 }
 
 rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat, void* stream) {
@@ -254,7 +328,8 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
   if (!xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "null device pointer");
-  int e = rsc::launch_encode(h->dev, xhat, P, K, atom, angle, coef, resid2, stream);
+  const int tile = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
+  int e = rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, resid2, stream);
   return e ? device_fail(e, "encode launch") : ok();
 }
 

@@ -1,0 +1,272 @@
+// Device helpers shared by the gfx950 kernels: MFMA wrappers, cross-lane swaps,
+// the distribution of one patch's packed hat coordinates over the lanes that hold
+// it, and the per-patch least-squares update of orthogonal matching pursuit.
+//
+// MFMA operand layouts used here (single block):
+//   v_mfma_f32_32x32x2f32: lane l supplies A[l%32][l/32] and B[l/32][l%32];
+//     accumulator register v of lane l holds D[8(v/4) + 4(l/32) + v%4][l%32].
+//   v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+//     accumulator register v of lane l holds D[4(l/16) + v][l%16].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rsc {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Early stop of the pursuit when ||r||^2 <= kTau2 ||x||^2 (tau = 1e-5).
+constexpr float kTau2 = 1e-10f;
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void zero(float (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = 0.f;
+}
+
+// Exchange lanes 32..63 of x with lanes 0..31 of y: afterwards x = [x_lo | y_lo],
+// y = [x_hi | y_hi].
+__device__ __forceinline__ void swap32(float& x, float& y) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+
+// Exchange the odd 16-lane rows of x with the even rows of y: afterwards
+// x = [x0 y0 x2 y2], y = [x1 y1 x3 y3] (rows of 16 lanes).
+__device__ __forceinline__ void swap16(float& x, float& y) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+
+// Maximum of x over the two half-waves (the result is the same in every lane pair).
+__device__ __forceinline__ float max_halves(float x) {
+  float a = x, b = x;
+  swap32(a, b);
+  return fmaxf(a, b);
+}
+
+// Maximum of x over the four quarter-waves.
+__device__ __forceinline__ float max_quarters(float x) {
+  float a = x, b = x;
+  swap16(a, b);
+  return max_halves(fmaxf(a, b));
+}
+
+// ----------------------------------------------------------------------------
+// Coordinate layouts.  A patch's B = S(2T+1) packed hat coordinates are spread
+// over W lanes (W = 2: the two half-waves of a 32x32 tile; W = 4: the four
+// quarter-waves of a 16x16 tile).  Register j of sub-lane u holds one coordinate:
+//   harmonic 0 block (j < J0): profile s = W j + u;
+//   harmonic k >= 1 block: the pair index jj = j - J0 - (k-1) J1 selects profile
+//     s = SW jj + soff(u) and part(u) (0 = Re, 1 = Im).
+// These are also the contraction orders of the stage-1 MFMAs.
+template <int S_, int T_, int W_>
+struct Layout {
+  static constexpr int S = S_, T = T_, W = W_;
+  static constexpr int B = S * (2 * T + 1);
+  static constexpr int NQ = T + 1;
+  static constexpr int J0 = (S + W - 1) / W;
+  static constexpr int J1 = (2 * S + W - 1) / W;
+  static constexpr int NKS = J0 + T * J1;
+  static constexpr int SW = W / 2;                       // profiles advanced per k>=1 step
+  __device__ static constexpr int harm(int j) { return j < J0 ? 0 : 1 + (j - J0) / J1; }
+  __device__ static constexpr int pair(int j) { return j < J0 ? j : (j - J0) % J1; }
+  __device__ static constexpr int base(int k) { return k == 0 ? 0 : S + 2 * S * (k - 1); }
+  __device__ static constexpr int soff(int u) { return W == 2 ? 0 : (u >> 1); }
+  __device__ static constexpr int part(int u) { return W == 2 ? u : (u & 1); }
+  // profile index of register j in sub-lane u
+  __device__ static constexpr int prof(int j, int u) {
+    return harm(j) == 0 ? W * j + u : SW * pair(j) + soff(u);
+  }
+  // packed coordinate of register j in sub-lane u, or -1 for padding
+  __device__ static constexpr int coord(int j, int u) {
+    return prof(j, u) >= S ? -1 : (harm(j) == 0 ? prof(j, u) : base(harm(j)) + part(u) * S + prof(j, u));
+  }
+};
+
+// Sum over the W lanes of a patch; bit-identical in all of them.
+template <int W>
+__device__ __forceinline__ float patch_sum(float x) {
+  if (W == 4) x = x + __shfl_xor(x, 16);
+  return x + __shfl_xor(x, 32);
+}
+
+// acc += alpha * S_r d_m on the coordinates sub-lane u holds (steering computed on
+// the fly, nothing else kept in registers).
+template <class L>
+__device__ __forceinline__ void steer_axpy(float (&acc)[L::NKS], float alpha, const float* __restrict__ hat,
+                                           const float* __restrict__ cs, int R, int m, int r, int u) {
+  const float* d = hat + m * L::B;
+  float c[L::NQ], s[L::NQ];
+#pragma unroll
+  for (int k = 1; k <= L::T; ++k) {
+    c[k] = cs[k * R + r];
+    s[k] = cs[(L::NQ + k) * R + r];
+  }
+#pragma unroll
+  for (int j = 0; j < L::NKS; ++j) {
+    const int k = L::harm(j);
+    const int p = L::prof(j, u);
+    const bool valid = p < L::S;
+    const int pc = valid ? p : 0;
+    float v;
+    if (k == 0) {
+      v = d[pc];
+    } else {
+      const int pt = L::part(u);
+      const float ca = pt ? -s[k] : c[k];
+      const float cb = pt ? c[k] : s[k];
+      v = d[L::base(k) + pc] * ca + d[L::base(k) + L::S + pc] * cb;
+    }
+    acc[j] = fmaf(valid ? alpha : 0.f, v, acc[j]);
+  }
+}
+
+// <S_{ra} d_a, S_{rb} d_b> from the per-pair harmonic table
+//   H[(a M + b)(2T+1) + 0]    = sum_s d_{a,s,0} d_{b,s,0}
+//   H[(a M + b)(2T+1) + 2k-1] = Re sum_s conj(w_{a,s,k}) w_{b,s,k}
+//   H[(a M + b)(2T+1) + 2k]   = Im sum_s conj(w_{a,s,k}) w_{b,s,k}
+// as H_0 + sum_k [cos(k phi) Re H_k - sin(k phi) Im H_k], phi = 2 pi (ra - rb) / R.
+template <int T>
+__device__ __forceinline__ float pair_gram(const float* __restrict__ H, const float* __restrict__ cs, int M,
+                                           int R, int a, int ra, int b, int rb) {
+  const float* h = H + (size_t(a) * M + b) * (2 * T + 1);
+  int dr = ra - rb;
+  dr += dr < 0 ? R : 0;
+  float g = h[0];
+#pragma unroll
+  for (int k = 1; k <= T; ++k) g += cs[k * R + dr] * h[2 * k - 1] - cs[(T + 1 + k) * R + dr] * h[2 * k];
+  return g;
+}
+
+// Per-patch state of the pursuit (identical in the W lanes of a patch).
+template <int KMAX>
+struct PursuitState {
+  int selm[KMAX], selr[KMAX];
+  float L[KMAX][KMAX];   // Cholesky factor of the Gram matrix of the selected columns
+  float bv[KMAX];        // <selected column i, x>
+  float cf[KMAX];        // current least-squares coefficients
+  int nsel;
+  bool active;
+};
+
+template <int KMAX>
+__device__ __forceinline__ void init_state(PursuitState<KMAX>& st, bool valid) {
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    st.selm[i] = -1;
+    st.selr[i] = -1;
+    st.bv[i] = 0.f;
+    st.cf[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) st.L[i][j] = 0.f;
+  }
+  st.nsel = 0;
+  st.active = valid;
+}
+
+// Least-squares step after the it-th selection (ms, rs) whose signed correlation
+// with the current residual is cval (Cholesky-based OMP):
+//   g_i = <column i, new column> (table), <new, x> = cval + sum_i g_i a_i,
+//   L is extended by w = L^{-1} g and sqrt(<new,new> - |w|^2),
+//   the coefficients solve L L^T a = [<column i, x>]_i,
+//   the residual moves by -sum_i (a_i - a_i^old) column_i.
+// it is a run-time value (the same in the whole wave); all state arrays are
+// indexed statically with predicates so that they stay in registers.
+template <class L, int KMAX>
+__device__ __forceinline__ void pursuit_update(PursuitState<KMAX>& st, int it, int ms, int rs, float cval,
+                                               const float* __restrict__ hat, const float* __restrict__ cs,
+                                               const float* __restrict__ H, int M, int R, int u,
+                                               float (&res)[L::NKS]) {
+  bool dup = false;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) dup = dup || (i < it && st.selm[i] == ms && st.selr[i] == rs);
+  bool upd = st.active && !dup;
+
+  const float dd = pair_gram<L::T>(H, cs, M, R, ms, rs, ms, rs);
+  float gcol[KMAX];
+  float bx = cval;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    gcol[i] = 0.f;
+    if (i < it) {
+      const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
+      gcol[i] = pair_gram<L::T>(H, cs, M, R, mi, ri, ms, rs);
+      bx += gcol[i] * st.cf[i];
+    }
+  }
+  float w[KMAX];
+  float l2 = dd;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    float s = gcol[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) s -= st.L[i][j] * w[j];
+    w[i] = i < it ? s / st.L[i][i] : 0.f;
+    l2 -= w[i] * w[i];
+  }
+  // a column (numerically) inside the span of the selected ones ends the pursuit
+  upd = upd && (l2 > 1e-6f * dd);
+#pragma unroll
+  for (int r = 0; r < KMAX; ++r) {
+    const bool row = upd && r == it;
+#pragma unroll
+    for (int i = 0; i < r; ++i) st.L[r][i] = row ? w[i] : st.L[r][i];
+    st.L[r][r] = row ? sqrtf(l2) : st.L[r][r];
+    st.bv[r] = row ? bx : st.bv[r];
+    st.selm[r] = row ? ms : st.selm[r];
+    st.selr[r] = row ? rs : st.selr[r];
+  }
+  float y[KMAX], an[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    float s = st.bv[i];
+#pragma unroll
+    for (int j = 0; j < i; ++j) s -= st.L[i][j] * y[j];
+    y[i] = i <= it ? s / st.L[i][i] : 0.f;
+  }
+#pragma unroll
+  for (int i = KMAX - 1; i >= 0; --i) {
+    float s = y[i];
+#pragma unroll
+    for (int j = i + 1; j < KMAX; ++j) s -= st.L[j][i] * an[j];
+    an[i] = i <= it ? s / st.L[i][i] : 0.f;
+  }
+  if (__any(upd)) {
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i <= it) {
+        const float delta = upd ? an[i] - st.cf[i] : 0.f;
+        const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
+        steer_axpy<L>(res, -delta, hat, cs, R, mi, ri, u);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) st.cf[i] = (upd && i <= it) ? an[i] : st.cf[i];
+  st.nsel = upd ? it + 1 : st.nsel;
+  st.active = upd;
+}
+
+template <class L>
+__device__ __forceinline__ float norm2(const float (&v)[L::NKS]) {
+  float a = 0.f;
+#pragma unroll
+  for (int j = 0; j < L::NKS; ++j) a += v[j] * v[j];
+  return patch_sum<L::W>(a);
+}
+
+}  // namespace rsc

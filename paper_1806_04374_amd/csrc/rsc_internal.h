@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include "rsc.h"
+
 namespace rsc {
 
 // FP64 steerable basis on the host.  phi is [N*N][B] and pinv is [B][N*N] with
@@ -28,25 +30,30 @@ constexpr int stage1_steps(int S, int T) { return k0_steps(S) + T * S; }
 
 // Device tables owned by a handle (FP32 operand arrangements built on the host).
 struct DeviceTables {
-  int N = 0, S = 0, T = 0, B = 0;
-  int M = 0, R = 0, NG = 0, RT = 0;
-  float* pinvA = nullptr;    // projection A operand [ceil(B/32)][ceil(N*N/2)][64]
+  int N = 0, S = 0, T = 0, B = 0, n_pix = 0;
+  int M = 0, R = 0, NG = 0;
+  float* pinvA = nullptr;    // projection operand over the grid [RTB][ceil(N*N/2)][64]
+  float* pinvD = nullptr;    // projection operand over disk pixels [2][ceil(n_pix/2)][64] (B <= 64)
+  int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
-  float* dictA = nullptr;    // stage-1 A operand [NG][stage1_steps][64]
-  float* dictHat = nullptr;  // dictionary rows [NG*16][B] (zero rows past M)
-  float* dftA = nullptr;     // stage-2 A operand [RT][T+1][64]
+  float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
+  float* dictHat = nullptr;  // dictionary rows [16*ceil(M/16)][B] (zero rows past M)
+  float* dftA32 = nullptr;   // 32x32-tile stage-2 operand [ceil(R/32)->1,2,4][T+1][64]
+  float* dftA16 = nullptr;   // 16x16-tile stage-2 operand [ceil(R/16)->1,2,4,8][(T+2)/2][64]
   float* cs = nullptr;       // [2][T+1][R]: cos, then sin, of 2 pi k r / R
+  float* gramH = nullptr;    // [M][M][2T+1]: per-atom-pair harmonic inner products (see pair_gram)
 };
 
-// Kernel launchers (rsc_kernels.hip).  Return a hipError_t as int.
-int launch_project(const DeviceTables& t, const float* patches, int64_t P, float* xhat,
-                   void* stream);
-int launch_encode(const DeviceTables& t, const float* xhat, int64_t P, int K, int32_t* atom,
+// Kernel launchers.  Return a hipError_t as int.
+int launch_project(const DeviceTables& t, const float* patches, int64_t P, float* xhat, void* stream);
+int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P, int K, int32_t* atom,
                   int32_t* angle, float* coef, float* resid2, void* stream);
 int launch_synthesize(const DeviceTables& t, const int32_t* atom, const int32_t* angle_idx,
                       const float* theta, const float* weight, int64_t P, int J,
                       const float* noise, float* out, void* stream);
 bool encode_supported(int S, int T);
-size_t encode_lds_bytes(const DeviceTables& t);
+size_t encode_lds_bytes(const DeviceTables& t, int tile);
+bool tile32_usable(const DeviceTables& t, int K);
+size_t project_tiled_lds_bytes(int N, int n_pix);
 
 }  // namespace rsc

@@ -1,0 +1,183 @@
+// Projection onto the steerable basis (Sec. II-E step 2):
+//   xhat_p = (Phi^T Phi)^{-1} Phi^T x_p,
+// an FP32 MFMA GEMM with rows = hat coordinates, columns = patches and the
+// contraction over disk pixels.
+//
+//  * project_tiled_kernel (N*N <= 128): one block of 8 waves per CU loops over
+//    tiles of 8 x 32 patches.  Each wave copies its 32 contiguous patches to LDS
+//    with 16-byte loads, the (Phi^T Phi)^{-1} Phi^T operand stays in LDS for the
+//    whole launch, and the results leave through LDS as contiguous 16-byte stores.
+//  * project_kernel (any size): blocks of 64 patches, operand read from global.
+#include <hip/hip_runtime.h>
+
+#include "rsc_device.h"
+#include "rsc_internal.h"
+
+namespace rsc {
+namespace {
+
+constexpr int kProjWaves = 8;
+
+// pinvD: [2][KPD][64] operand over disk pixels (contraction index 2j + u is disk
+// pixel 2j+u in row-major order); pix: [2*KPD] grid index of each disk pixel or -1.
+template <int NN, int KPD>
+__global__ __launch_bounds__(512) void project_tiled_kernel(const float* __restrict__ patches, int64_t P,
+                                                            int B, const float* __restrict__ pinvD,
+                                                            const int* __restrict__ pix, bool vec_in,
+                                                            bool vec_out, float* __restrict__ xhat) {
+  extern __shared__ float lds[];
+  float* sA = lds;                                    // [2][KPD][64]
+  constexpr int kPixPad = (2 * KPD + 3) & ~3;        // keeps the tiles 16-byte aligned
+  int* sPix = reinterpret_cast<int*>(sA + 2 * KPD * 64);  // [2*KPD]
+  float* tiles = sA + 2 * KPD * 64 + kPixPad;         // [waves][32*NN]
+  for (int i = threadIdx.x; i < 2 * KPD * 64; i += blockDim.x) sA[i] = pinvD[i];
+  for (int i = threadIdx.x; i < 2 * KPD; i += blockDim.x) sPix[i] = pix[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, u = lane >> 5;
+  float* tile = tiles + wave * 32 * NN;
+  const int64_t ntile = (P + 31) / 32;
+  for (int64_t bt = blockIdx.x; bt * kProjWaves < ntile; bt += gridDim.x) {
+    const int64_t wt = bt * kProjWaves + wave;
+    const int64_t p0 = wt * 32;
+    const int np = wt < ntile ? int(P - p0 < 32 ? P - p0 : 32) : 0;
+    const float* src = patches + p0 * NN;
+    if (np == 32 && vec_in) {
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(tile);
+#pragma unroll 4
+      for (int i = lane; i < 8 * NN; i += 64) d4[i] = s4[i];
+    } else {
+      for (int i = lane; i < 32 * NN; i += 64) tile[i] = i < np * NN ? src[i] : 0.f;
+    }
+    __syncthreads();
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.f;
+    const float* mine = tile + col * NN;
+#pragma unroll 7
+    for (int j = 0; j < KPD; ++j) {
+      const int q = sPix[2 * j + u];
+      const float b = q >= 0 ? mine[q] : 0.f;
+      acc0 = mfma32(sA[j * 64 + lane], b, acc0);
+      acc1 = mfma32(sA[(KPD + j) * 64 + lane], b, acc1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int c0 = 8 * (v / 4) + 4 * u + (v % 4);
+      tile[col * B + c0] = acc0[v];
+      if (32 + c0 < B) tile[col * B + 32 + c0] = acc1[v];
+    }
+    __syncthreads();
+    float* dst = xhat + p0 * B;
+    if (np == 32 && vec_out) {
+      const float4* s4 = reinterpret_cast<const float4*>(tile);
+      float4* d4 = reinterpret_cast<float4*>(dst);
+      for (int i = lane; i < 8 * B; i += 64) d4[i] = s4[i];
+    } else {
+      for (int i = lane; i < np * B; i += 64) dst[i] = tile[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Generic fallback: one block = 2 waves = 64 patches, operand from global memory.
+template <int RTB>
+__global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ patches, int64_t P, int NN,
+                                                      int B, const float* __restrict__ pinvA,
+                                                      float* __restrict__ xhat) {
+  extern __shared__ float tile[];  // [64][NN] patches, reused as [64][B] output
+  constexpr int PT = 64;
+  const int KP = (NN + 1) / 2;
+  const int64_t p0 = int64_t(blockIdx.x) * PT;
+  const int np = int(P - p0 < PT ? P - p0 : PT);
+  const float* src = patches + p0 * NN;
+  const int total = np * NN;
+  for (int i = threadIdx.x; i < PT * NN; i += blockDim.x) tile[i] = i < total ? src[i] : 0.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, u = lane >> 5;
+  const float* mine = tile + (wave * 32 + col) * NN;
+  f32x16 acc[RTB];
+#pragma unroll
+  for (int t = 0; t < RTB; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+  const float* A = pinvA + lane;
+#pragma unroll 4
+  for (int j = 0; j < KP; ++j) {
+    const int px = 2 * j + u;
+    const float b = px < NN ? mine[px] : 0.f;
+#pragma unroll
+    for (int t = 0; t < RTB; ++t) acc[t] = mfma32(A[(t * KP + j) * 64], b, acc[t]);
+  }
+  __syncthreads();
+  float* out = tile;
+#pragma unroll
+  for (int t = 0; t < RTB; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int c = 32 * t + 8 * (v / 4) + 4 * u + (v % 4);
+      if (c < B) out[(wave * 32 + col) * B + c] = acc[t][v];
+    }
+  __syncthreads();
+  float* dst = xhat + p0 * B;
+  for (int i = threadIdx.x; i < np * B; i += blockDim.x) dst[i] = out[i];
+}
+
+int cus() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached = n;
+  }
+  return cached;
+}
+
+}  // namespace
+
+size_t project_tiled_lds_bytes(int N, int n_pix) {
+  const int kpd = (n_pix + 1) / 2;
+  return sizeof(float) * (2 * size_t(kpd) * 64 + size_t((2 * kpd + 3) & ~3) + size_t(kProjWaves) * 32 * N * N);
+}
+
+int launch_project(const DeviceTables& t, const float* patches, int64_t P, float* xhat, void* stream) {
+  if (P <= 0) return 0;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int NN = t.N * t.N;
+  if (t.N == 11 && t.B <= 64 && t.pinvD) {
+    constexpr int kNN = 121, kKPD = 49;
+    if ((t.n_pix + 1) / 2 != kKPD) return int(hipErrorInvalidValue);
+    const size_t lds = project_tiled_lds_bytes(t.N, t.n_pix);
+    auto kern = project_tiled_kernel<kNN, kKPD>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return int(e);
+    const int64_t ntile = (P + 31) / 32;
+    int64_t blocks = (ntile + kProjWaves - 1) / kProjWaves;
+    if (blocks > cus()) blocks = cus();
+    const bool vin = (reinterpret_cast<uintptr_t>(patches) & 15) == 0;
+    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (t.B * 32) % 4 == 0;
+    hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * kProjWaves), lds, st, patches, P, t.B,
+                       t.pinvD, t.pixD, vin, vout, xhat);
+    return int(hipGetLastError());
+  }
+  const int64_t blocks = (P + 63) / 64;
+  const size_t lds = sizeof(float) * 64 * size_t(NN > t.B ? NN : t.B);
+  const int rtb = (t.B + 31) / 32;
+  if (rtb <= 2)
+    hipLaunchKernelGGL(project_kernel<2>, dim3(unsigned(blocks)), dim3(128), lds, st, patches, P, NN, t.B,
+                       t.pinvA, xhat);
+  else if (rtb <= 4)
+    hipLaunchKernelGGL(project_kernel<4>, dim3(unsigned(blocks)), dim3(128), lds, st, patches, P, NN, t.B,
+                       t.pinvA, xhat);
+  else
+    return int(hipErrorInvalidValue);
+  return int(hipGetLastError());
+}
+
+}  // namespace rsc

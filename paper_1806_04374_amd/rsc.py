@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "rsc.h")
 
 RSC_OK, RSC_E_INVALID, RSC_E_NOMEM, RSC_E_DEVICE, RSC_E_UNSUPPORTED = 0, -1, -2, -3, -4
 PRECISION = {"fp32": 0, "bf16": 1, "fp16": 2}
+TILE = {"auto": 0, "16": 1, "32": 2}
 
 _lib = None
 
@@ -46,6 +47,7 @@ def lib():
         "rsc_basis_info": [P, P, P, P],
         "rsc_get_basis": [P, P, P],
         "rsc_set_dictionary": [P, P, I, I],
+        "rsc_set_tile": [P, I],
         "rsc_project": [P, P, I64, P, P],
         "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
         "rsc_reconstruct": [P, P, P, P, I64, I, P, P],
@@ -158,6 +160,11 @@ def rsc_set_dictionary(h: Handle, d_hat, R: int):
         raise ValueError(f"d_hat must be [M, {h.B}]")
     _check(lib().rsc_set_dictionary(h.ptr, d.ctypes.data_as(ctypes.c_void_p), d.shape[0], R))
     h.M, h.R = d.shape[0], R
+
+
+def rsc_set_tile(h: Handle, tile: str = "auto"):
+    """Encoder tile shape: "auto", "16" (16x16x4 MFMA tiles) or "32" (32x32x2)."""
+    _check(lib().rsc_set_tile(h.ptr, TILE[str(tile)]))
 
 
 def rsc_project(h: Handle, patches, xhat=None, stream=None):

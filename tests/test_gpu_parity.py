@@ -28,10 +28,11 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _handle(geom, D, R):
+def _handle(geom, D, R, tile="auto"):
     from paper_1806_04374_amd import rsc
     h = rsc.rsc_create(geom.N, geom.S, geom.T)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    rsc.rsc_set_tile(h, tile)
     return h
 
 
@@ -44,11 +45,11 @@ def _encode(h, X32, K, dev):
     return xh, atom, angle, coef, r2
 
 
-def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True):
+def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True, tile="auto"):
     """Full path parity: project + encode (+ reconstruct) against the reference."""
     from paper_1806_04374_amd import rsc
     basis = basis or orc.build_basis(geom.N, geom.S, geom.T)
-    h = _handle(geom, D, R)
+    h = _handle(geom, D, R, tile)
     xh, atom, angle, coef, r2 = _encode(h, X32, K, dev)
     xh_ref, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
     # projection parity (FP32 GEMM against FP64 least squares)
@@ -73,24 +74,26 @@ def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True):
     return rep
 
 
-def test_small_plain_workload_full(dev):
+@pytest.mark.parametrize("tile", ["16", "32"])
+def test_small_plain_workload_full(dev, tile):
     """2,000 11x11 patches, M=16, K=2, R=32: two grid-rotated atoms plus N(0, 0.01^2) noise."""
     w = wl.SMALL
     geom = w["geom"]
     basis = orc.build_basis(geom.N, geom.S, geom.T)
     D, draw = wl.small_draw()
     X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
-    _check("small", X, D, w["R"], w["K"], geom, dev, basis)
+    _check(f"small-t{tile}", X, D, w["R"], w["K"], geom, dev, basis, tile=tile)
 
 
-def test_scale_workload_ragged_slice(dev):
+@pytest.mark.parametrize("tile", ["16", "32"])
+def test_scale_workload_ragged_slice(dev, tile):
     """Scale geometry (M=64, K=4, R=64) on 20,011 patches: many tiles plus a ragged tail."""
     w = wl.SCALE
     geom = w["geom"]
     basis = orc.build_basis(geom.N, geom.S, geom.T)
     D, draw = wl.scale_draw(P=20011)
     X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
-    _check("scale-20011", X, D, w["R"], w["K"], geom, dev, basis)
+    _check(f"scale-20011-t{tile}", X, D, w["R"], w["K"], geom, dev, basis, tile=tile)
 
 
 def test_scale_workload_full_size_sampled(dev):
@@ -123,15 +126,17 @@ def test_large_geometry(dev):
     _check("geom15", X, D, 64, 6, geom, dev, basis)
 
 
-@pytest.mark.parametrize("M,R,K", [(20, 8, 3), (16, 60, 2), (5, 1, 4), (33, 100, 8), (64, 128, 1)])
-def test_uneven_shapes(dev, M, R, K):
-    """Atom counts off the 16-atom tile, angle grids off the 32-angle tile (60 as in the paper)."""
+@pytest.mark.parametrize("M,R,K,tile", [(20, 8, 3, "32"), (20, 8, 3, "16"), (16, 60, 2, "32"), (16, 60, 2, "16"),
+                                        (5, 1, 4, "16"), (33, 100, 8, "16"), (64, 128, 1, "16"),
+                                        (9, 17, 6, "16"), (200, 64, 5, "16")])
+def test_uneven_shapes(dev, M, R, K, tile):
+    """Atom counts off the atom tiles, angle grids off the angle tiles (60 as in the paper)."""
     geom = wl.GEOM11
     basis = orc.build_basis(geom.N, geom.S, geom.T)
     D = wl.draw_dictionary(M, geom.B, seed=3)
     draw = wl.draw_mixtures(1000, geom.N, M, 3, 0.02, seed=3)
     X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
-    _check(f"M{M}-R{R}-K{K}", X, D, R, K, geom, dev, basis, mse=K <= 4)
+    _check(f"M{M}-R{R}-K{K}-t{tile}", X, D, R, K, geom, dev, basis, mse=K <= 4, tile=tile)
 
 
 def test_edge_cases(dev):
@@ -176,14 +181,15 @@ def test_edge_cases(dev):
     h.close()
 
 
-def test_batch_position_invariance(dev):
+@pytest.mark.parametrize("tile", ["16", "32"])
+def test_batch_position_invariance(dev, tile):
     """A patch gives bit-identical codes wherever it sits in the batch."""
     from paper_1806_04374_amd import rsc
     geom = wl.GEOM11
     basis = orc.build_basis(geom.N, geom.S, geom.T)
     D, draw = wl.scale_draw(P=4099)
     X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
-    h = _handle(geom, D, 64)
+    h = _handle(geom, D, 64, tile)
     full = _encode(h, X, 4, dev)
     for lo, n in [(0, 1), (7, 33), (1000, 517), (4090, 9)]:
         part = _encode(h, X[lo:lo + n].copy(), 4, dev)
