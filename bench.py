@@ -110,12 +110,139 @@ def cpu_baseline(h, w, D, target_s: float, dev):
     }
 
 
+def run_ragged(args, dev):
+    """256 texture images of uneven sizes; all stride-1 15x15 windows, K=6, R=64, M=128.
+
+    Inputs are synthesized on the device from the seeded stamp draws.  One step =
+    one replay of a HIP graph holding the image projection and the encoder.
+    """
+    import torch
+    from paper_1806_04374_amd import autotune, rsc
+    w = wl.RAGGED
+    g = w["geom"]
+    K = w["K"]
+    D = wl.draw_dictionary(w["M"], g.B)
+    h = rsc.rsc_create(g.N, g.S, g.T)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+    draws = wl.ragged_draws(args.images or None)
+    batch = rsc.ImageBatch([(d.H, d.W) for d in draws], g.N, dev)
+    pix = torch.from_numpy(np.concatenate([d.noise.ravel() for d in draws]).astype(np.float32)).to(dev)
+    cat = lambda f, dt: torch.from_numpy(np.concatenate([f(d) for d in draws]).astype(dt)).to(dev)
+    rsc.rsc_synthesize_images(
+        h, batch, cat(lambda d: d.atom, np.int32), cat(lambda d: d.angle, np.float32),
+        cat(lambda d: d.amplitude, np.float32),
+        cat(lambda d: d.centre.reshape(-1, 2), np.int32).reshape(-1, 2).contiguous(),
+        torch.from_numpy(np.concatenate([np.full(len(d.atom), i) for i, d in enumerate(draws)])
+                         .astype(np.int32)).to(dev),
+        pix)
+    n_stamps = int(sum(len(d.atom) for d in draws))
+    del draws
+    P = batch.P_total
+    xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+    outs = (torch.empty((P, K), dtype=torch.int32, device=dev), torch.empty((P, K), dtype=torch.int32, device=dev),
+            torch.empty((P, K), dtype=torch.float32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev))
+    rsc.rsc_project_images(h, pix, batch, xhat=xh)
+    torch.cuda.synchronize()
+    tuned = autotune.tune(h, xh[: min(P, 1 << 18)], K, reps=3)
+
+    def step(stream=None):
+        rsc.rsc_project_images(h, pix, batch, xhat=xh, stream=stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    cs = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cs):
+        step(stream=cs)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    # kernel durations from eager launches with events on the launch stream
+    kp, ke = [], []
+    for _ in range(3):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        rsc.rsc_project_images(h, pix, batch, xhat=xh, stream=stream)
+        e1.record(stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        kp.append(e0.elapsed_time(e1))
+        ke.append(e1.elapsed_time(e2))
+    ms = wall * 1e3 / args.steps
+    flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
+    achieved = flops / (np.mean(ke) * 1e-3)
+    out = {
+        "metric": METRIC, "value": P / (ms * 1e-3), "unit": "patches/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {batch.n} images, sides log-uniform {w['side']}, "
+                               f"{P} 15x15 windows, M={w['M']}, K={K}, R={w['R']}, one HIP graph per step",
+                   "P": P, "images": batch.n, "stamps": n_stamps, "N": g.N, "S": g.S, "T": g.T,
+                   "M": w["M"], "K": K, "R": w["R"], "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")}},
+        "autotune": tuned,
+        "kernels_ms": {"project_images_mean": float(np.mean(kp)), "encode_mean": float(np.mean(ke))},
+        "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
+                     "traffic": None, "algorithmic_flops_per_launch": flops},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_ragged(h, w, D, args.cpu_seconds, dev)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_ragged(h, w, D, target_s, dev):
+    """FP64 reference on windows of the first image (reference-synthesized pixels)."""
+    import torch
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    from paper_1806_04374_amd import rsc
+    g = w["geom"]
+    basis = orc.build_basis(g.N, g.S, g.T)
+    d = wl.ragged_draws(1)[0]
+    img = orc.synthesize_image(basis, D, d.H, d.W, d.centre, d.atom, d.angle, d.amplitude, d.noise).astype(np.float32)
+    wins = orc.image_patches(img.astype(np.float64), g.N)
+    t0 = time.perf_counter()
+    orc.encode(basis, D, w["R"], wins[:64], w["K"])
+    dt0 = time.perf_counter() - t0
+    n = int(min(len(wins), max(64, 64 * target_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    _, code = orc.encode(basis, D, w["R"], wins[:n], w["K"])
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    batch = rsc.ImageBatch([(d.H, d.W)], g.N, dev)
+    xh = rsc.rsc_project_images(h, torch.from_numpy(img.ravel()).to(dev), batch)
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh[:n].contiguous(), w["K"])
+    torch.cuda.synchronize()
+    a, r = atom.cpu().numpy(), angle.cpu().numpy()
+    match = np.mean([{(x, y) for x, y in zip(a[p], r[p]) if x >= 0} ==
+                     {(int(x), int(y)) for x, y in zip(code.atom[p], code.angle[p]) if x >= 0} for p in range(n)])
+    return {"value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} windows of image 0 ({d.H}x{d.W}), FP64 reference, {dt:.1f} s",
+            "check": {"selection_match": float(match)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small"], default="scale")
+    ap.add_argument("--workload", choices=["scale", "small", "ragged"], default="scale")
+    ap.add_argument("--images", type=int, default=0, help="ragged: use the first n images (testing only)")
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -141,6 +268,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                           "launches": 3}), flush=True)
+        return
+    if args.workload == "ragged":
+        run_ragged(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

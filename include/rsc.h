@@ -140,6 +140,32 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
 rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile);
 
 /*
+ * Encoder launch shape: tile shape and persistent blocks per compute unit
+ * (0 = as many as fit; larger requests are capped at what fits).  Codes do not
+ * depend on blocks_per_cu; the tile shape changes only FP32 rounding order.
+ * Errors: RSC_E_INVALID for an unknown tile or blocks_per_cu outside 0..16.
+ */
+rsc_status rsc_set_launch(rsc_handle* h, rsc_tile tile, int blocks_per_cu);
+
+/* Current encoder tile shape and blocks per CU (either pointer may be NULL). */
+rsc_status rsc_get_launch(const rsc_handle* h, int* tile, int* blocks_per_cu);
+
+/*
+ * Autotuner: times rsc_omp_encode on a representative sample for every usable tile
+ * shape and blocks_per_cu = 1..4 (median of reps runs, HIP events on the stream),
+ * then keeps the fastest in the handle.  Blocking; not for a hot loop.
+ *   xhat              device [P, B] sample, P >= 1
+ *   atom, angle, coef device [P, K] scratch outputs (overwritten)
+ *   reps              1..100
+ *   report            host [8][3] or NULL: (tile, blocks_per_cu, median ms) per candidate
+ *   n_report          host, number of rows written (may be NULL)
+ * Errors: RSC_E_INVALID (arguments, no dictionary), RSC_E_DEVICE.
+ */
+rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
+                               int32_t* angle, float* coef, int reps, double* report, int* n_report,
+                               void* stream);
+
+/*
  * Projection onto the basis (Sec. II-E step 2): xhat_p = (Phi^T Phi)^{-1} Phi^T x_p.
  *   patches  device [P, N, N] float32 row-major; off-disk pixels ignored
  *   P        number of patches, >= 0 (0 is a no-op)
@@ -191,6 +217,48 @@ rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32
 rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float* theta,
                           const float* weight, int64_t P, int J, const float* noise,
                           float* out, void* stream);
+
+/*
+ * Bytes of device workspace rsc_project_images needs for n_images images
+ * (two int64 prefix-sum arrays of n_images + 1 entries).
+ */
+rsc_status rsc_images_workspace_size(int n_images, size_t* bytes);
+
+/*
+ * Projection of every stride-1 N x N window of a batch of images of uneven sizes
+ * (Sec. II-E step 2 applied to all patches of each image, as in the sliding-window
+ * coding of Sec. III-A).  Window p of image i has its top-left pixel at (y, x),
+ * 0 <= y <= H_i - N, 0 <= x <= W_i - N; windows are numbered image by image, then
+ * row-major by (y, x), and only the disk pixels of each window are used.
+ *   pixels      device float32, image i row-major at pixels + img_offset[i]
+ *   img_offset  device int64 [n_images];  H, W  device int32 [n_images]
+ *   n_images    0 <= n_images <= 2^20 (0 is a no-op)
+ *   P_total     host: sum over images of max(0, H-N+1) * max(0, W-N+1); windows past
+ *               P_total are not written, so it must equal that sum
+ *   workspace   device, >= rsc_images_workspace_size bytes, 8-byte aligned; holds the
+ *               per-image prefix sums computed on the device (no host round trip)
+ *   xhat        device [P_total, B] float32
+ * Everything is enqueued on the stream without allocation or host synchronisation,
+ * so a batch (with rsc_omp_encode after it) can be captured in a HIP graph.
+ * N must be 11 or 15 (RSC_E_UNSUPPORTED otherwise).
+ */
+rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const int64_t* img_offset,
+                              const int32_t* H, const int32_t* W, int n_images, int64_t P_total,
+                              void* workspace, size_t ws_bytes, float* xhat, void* stream);
+
+/*
+ * Adds synthetic stamps to images: for stamp s, amplitude[s] * Phi S(theta[s]) d_{atom[s]}
+ * (an N x N patch, zero off the disk) is added with its centre pixel at
+ * centre[s] = (row, col) of image image[s], clipped at the image borders.  pixels must be
+ * initialised by the caller (for instance with noise).  Overlapping stamps are summed
+ * with atomic adds, so the rounding order of overlaps is not fixed.
+ *   atom int32 [n], theta float32 [n] radians, amplitude float32 [n], centre int32 [n, 2],
+ *   image int32 [n]; img_offset, H, W as in rsc_project_images; all device arrays.
+ */
+rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const float* theta,
+                                 const float* amplitude, const int32_t* centre, const int32_t* image,
+                                 int64_t n_stamps, const int64_t* img_offset, const int32_t* H,
+                                 const int32_t* W, int n_images, float* pixels, void* stream);
 
 /* Wait for all work on the stream; reports RSC_E_DEVICE for a failed kernel. */
 rsc_status rsc_sync(void* stream);

@@ -314,3 +314,36 @@ def synthesize(basis: Basis, D_hat: np.ndarray, atom, angle, weight, noise=None)
     if noise is not None:
         x = x + noise
     return x
+
+
+# --------------------------------------------------------------------------- images
+def synthesize_image(basis: Basis, D_hat: np.ndarray, H: int, W: int, centre, atom, angle, amplitude,
+                     noise=None) -> np.ndarray:
+    """Texture image: sum of stamps amplitude * Phi S_theta d_m (an N x N patch, zero off the
+    disk) whose centre pixel lands on integer position centre = (row, col), clipped at the
+    borders, plus noise [H, W]."""
+    N = basis.N
+    c = (N - 1) // 2
+    img = np.zeros((H, W))
+    atom = np.asarray(atom)
+    if atom.size:
+        stamps = to_pixels(basis, np.asarray(amplitude)[:, None] *
+                           steer(D_hat[atom], np.asarray(angle), basis.S, basis.T))
+        for i in range(atom.size):
+            r0, c0 = int(centre[i][0]) - c, int(centre[i][1]) - c
+            ra, rb = max(r0, 0), min(r0 + N, H)
+            ca, cb = max(c0, 0), min(c0 + N, W)
+            if ra < rb and ca < cb:
+                img[ra:rb, ca:cb] += stamps[i, ra - r0:rb - r0, ca - c0:cb - c0]
+    if noise is not None:
+        img = img + noise
+    return img
+
+
+def image_patches(img: np.ndarray, N: int) -> np.ndarray:
+    """All stride-1 N x N windows of an image, origins in row-major order: [(H-N+1)(W-N+1), N, N]."""
+    H, W = img.shape
+    if H < N or W < N:
+        return np.zeros((0, N, N))
+    v = np.lib.stride_tricks.sliding_window_view(img, (N, N))
+    return v.reshape(-1, N, N)

@@ -27,6 +27,7 @@ SOURCES = [
     ("rsc_project.hip", "hip"),
     ("rsc_encode.hip", "hip"),
     ("rsc_synth.hip", "hip"),
+    ("rsc_images.hip", "hip"),
 ]
 
 
@@ -54,7 +55,7 @@ def _compile(src: str, kind: str, extra: list[str], verbose: bool) -> str:
 def build(verbose: bool = False, resource_usage: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     extra = ["-Rpass-analysis=kernel-resource-usage"] if resource_usage else []
-    with ThreadPoolExecutor(max_workers=5) as ex:
+    with ThreadPoolExecutor(max_workers=6) as ex:
         objs = list(ex.map(lambda s: _compile(s[0], s[1], extra if s[0].endswith(".hip") else [], verbose),
                            SOURCES))
     tmp = LIB + ".tmp"

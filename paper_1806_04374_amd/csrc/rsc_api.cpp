@@ -2,6 +2,7 @@
 // device uploads.  All compute is enqueued through the launchers of rsc_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -117,12 +118,26 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
             pinvD[(size_t(t) * KPD + j) * 64 + l] = float(b.pinv[size_t(row) * NN + b.pix[i]]);
         }
   }
+  // image projection operand (row tiles of 32 hat coordinates, disk-pixel contraction)
+  const int RTBI = (b.B + 31) / 32 <= 2 ? 2 : 4;
+  std::vector<float> pinvI(size_t(RTBI) * KPD * 64, 0.f);
+  std::vector<int> dpixI(size_t(2) * KPD, -1);
+  for (int i = 0; i < b.n_pix; ++i) dpixI[i] = ((b.pix[i] / N) << 8) | (b.pix[i] % N);
+  for (int t = 0; t < RTBI; ++t)
+    for (int j = 0; j < KPD; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const int row = 32 * t + (l % 32), i = 2 * j + l / 32;
+        if (row < b.B && i < b.n_pix)
+          pinvI[(size_t(t) * KPD + j) * 64 + l] = float(b.pinv[size_t(row) * NN + b.pix[i]]);
+      }
   std::vector<float> phiPad(size_t(NN) * b.B);
   for (size_t i = 0; i < phiPad.size(); ++i) phiPad[i] = float(b.phi[i]);
   rsc_status s = upload(d.pinvA, pinvA, "projection table");
   if (s == RSC_OK) s = upload(d.pinvD, pinvD, "projection table");
   if (s == RSC_OK) s = upload(d.pixD, pixD, "pixel table");
   if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
+  if (s == RSC_OK) s = upload(d.pinvI, pinvI, "image projection table");
+  if (s == RSC_OK) s = upload(d.dpixI, dpixI, "image pixel table");
   if (s != RSC_OK) {
     rsc_destroy(h);
     return s;
@@ -153,6 +168,8 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.pinvA);
   free_dev(d.pinvD);
   free_dev(d.pixD);
+  free_dev(d.pinvI);
+  free_dev(d.dpixI);
   free_dev(d.phiPad);
   free_dev(d.dictA);
   free_dev(d.dictHat);
@@ -310,6 +327,88 @@ rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile) {
   return ok();
 }
 
+rsc_status rsc_set_launch(rsc_handle* h, rsc_tile tile, int blocks_per_cu) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (tile != RSC_TILE_AUTO && tile != RSC_TILE_16 && tile != RSC_TILE_32)
+    return fail(RSC_E_INVALID, "unknown tile shape");
+  if (blocks_per_cu < 0 || blocks_per_cu > 16) return fail(RSC_E_INVALID, "blocks_per_cu must be in 0..16");
+  h->tile = tile;
+  h->dev.enc_bpc = blocks_per_cu;
+  return ok();
+}
+
+rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
+                               int32_t* angle, float* coef, int reps, double* report, int* n_report,
+                               void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  if (P < 1 || !xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "need a non-empty sample");
+  if (reps < 1 || reps > 100) return fail(RSC_E_INVALID, "reps must be in 1..100");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int tiles[2] = {RSC_TILE_16, RSC_TILE_32};
+  const int ntiles = rsc::tile32_usable(h->dev, K) ? 2 : 1;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(RSC_E_DEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(RSC_E_DEVICE, "hipEventCreate failed");
+  }
+  const int saved_bpc = h->dev.enc_bpc;
+  double best_ms = 1e300;
+  int best_tile = RSC_TILE_16, best_bpc = 0, nrep = 0;
+  rsc_status status = RSC_OK;
+  for (int ti = 0; ti < ntiles && status == RSC_OK; ++ti) {
+    for (int bpc = 1; bpc <= 4 && status == RSC_OK; ++bpc) {
+      h->dev.enc_bpc = bpc;
+      int e = rsc::launch_encode(h->dev, tiles[ti], xhat, P, K, atom, angle, coef, nullptr, stream);
+      if (e) { status = device_fail(e, "autotune launch"); break; }
+      std::vector<float> ms(reps);
+      for (int r = 0; r < reps && status == RSC_OK; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) { status = fail(RSC_E_DEVICE, "event record"); break; }
+        e = rsc::launch_encode(h->dev, tiles[ti], xhat, P, K, atom, angle, coef, nullptr, stream);
+        if (e) { status = device_fail(e, "autotune launch"); break; }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms[r], e0, e1) != hipSuccess) {
+          status = fail(RSC_E_DEVICE, "event timing");
+          break;
+        }
+      }
+      if (status != RSC_OK) break;
+      std::sort(ms.begin(), ms.end());
+      const double med = ms[reps / 2];
+      if (report && nrep < 8) {
+        report[3 * nrep] = tiles[ti];
+        report[3 * nrep + 1] = bpc;
+        report[3 * nrep + 2] = med;
+      }
+      ++nrep;
+      if (med < best_ms) {
+        best_ms = med;
+        best_tile = tiles[ti];
+        best_bpc = bpc;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != RSC_OK) {
+    h->dev.enc_bpc = saved_bpc;
+    return status;
+  }
+  h->tile = rsc_tile(best_tile);
+  h->dev.enc_bpc = best_bpc;
+  if (n_report) *n_report = nrep < 8 ? nrep : 8;
+  return ok();
+}
+
+rsc_status rsc_get_launch(const rsc_handle* h, int* tile, int* blocks_per_cu) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (tile) *tile = h->tile;
+  if (blocks_per_cu) *blocks_per_cu = h->dev.enc_bpc;
+  return ok();
+}
+
 rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
@@ -358,6 +457,46 @@ rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float*
   if (P > (int64_t(1) << 31) * 8) return fail(RSC_E_INVALID, "P too large");
   int e = rsc::launch_synthesize(h->dev, atom, nullptr, theta, weight, P, J, noise, out, stream);
   return e ? device_fail(e, "synthesize launch") : ok();
+}
+
+rsc_status rsc_images_workspace_size(int n_images, size_t* bytes) {
+  if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
+  if (n_images < 0) return fail(RSC_E_INVALID, "n_images must be >= 0");
+  *bytes = rsc::images_workspace_bytes(n_images);
+  return ok();
+}
+
+rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const int64_t* img_offset,
+                              const int32_t* H, const int32_t* W, int n_images, int64_t P_total,
+                              void* workspace, size_t ws_bytes, float* xhat, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (n_images < 0 || n_images > (1 << 20)) return fail(RSC_E_INVALID, "n_images must be in 0..2^20");
+  if (P_total < 0) return fail(RSC_E_INVALID, "P_total must be >= 0");
+  if (n_images == 0 || P_total == 0) return ok();
+  if (!pixels || !img_offset || !H || !W || !workspace || !xhat)
+    return fail(RSC_E_INVALID, "null device pointer");
+  if (ws_bytes < rsc::images_workspace_bytes(n_images)) return fail(RSC_E_INVALID, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(RSC_E_INVALID, "workspace not 8-byte aligned");
+  if (!((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)))
+    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for N = 11 and N = 15");
+  int e = rsc::launch_project_images(h->dev, pixels, img_offset, H, W, n_images, P_total, workspace, xhat,
+                                     stream);
+  return e ? device_fail(e, "image projection launch") : ok();
+}
+
+rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const float* theta,
+                                 const float* amplitude, const int32_t* centre, const int32_t* image,
+                                 int64_t n_stamps, const int64_t* img_offset, const int32_t* H,
+                                 const int32_t* W, int n_images, float* pixels, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (n_stamps < 0 || n_stamps > (int64_t(1) << 31) - 1) return fail(RSC_E_INVALID, "n_stamps out of range");
+  if (n_stamps == 0) return ok();
+  if (!atom || !theta || !amplitude || !centre || !image || !img_offset || !H || !W || !pixels)
+    return fail(RSC_E_INVALID, "null device pointer");
+  int e = rsc::launch_stamps(h->dev, atom, theta, amplitude, centre, image, n_stamps, img_offset, H, W,
+                             n_images, pixels, stream);
+  return e ? device_fail(e, "stamp launch") : ok();
 }
 
 rsc_status rsc_sync(void* stream) {

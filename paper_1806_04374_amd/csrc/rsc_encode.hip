@@ -387,7 +387,7 @@ int num_cus() {
 // Persistent grid: at most as many blocks as fit on the device at once; each wave
 // then walks the patch tiles with a stride of the whole grid.
 template <class Kern, class... Args>
-int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, hipStream_t st, Args... args) {
+int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, int bpc, hipStream_t st, Args... args) {
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -397,6 +397,7 @@ int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, hipStream_t st,
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
+  if (bpc > 0 && bpc < per_cu) per_cu = bpc;
   const int64_t cap = int64_t(num_cus()) * per_cu;
   if (blocks > cap) blocks = cap;
   hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(256), lds, st, args...);
@@ -406,13 +407,13 @@ int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, hipStream_t st,
 template <int S, int T, int RT, int KMAX>
 int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
   return launch_persistent(encode32_kernel<S, T, RT, KMAX>, encode_lds_bytes(t, RSC_TILE_32),
-                           (prm.P + 31) / 32, st, prm, t.NG);
+                           (prm.P + 31) / 32, t.enc_bpc, st, prm, t.NG);
 }
 
 template <int S, int T, int RT, int KMAX>
 int launch16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
   return launch_persistent(encode16_kernel<S, T, RT, KMAX>, encode_lds_bytes(t, RSC_TILE_16),
-                           (prm.P + 15) / 16, st, prm);
+                           (prm.P + 15) / 16, t.enc_bpc, st, prm);
 }
 
 template <int S, int T, int RT>

@@ -32,9 +32,12 @@ constexpr int stage1_steps(int S, int T) { return k0_steps(S) + T * S; }
 struct DeviceTables {
   int N = 0, S = 0, T = 0, B = 0, n_pix = 0;
   int M = 0, R = 0, NG = 0;
+  int enc_bpc = 0;           // encoder blocks per CU (0: as many as fit)
   float* pinvA = nullptr;    // projection operand over the grid [RTB][ceil(N*N/2)][64]
   float* pinvD = nullptr;    // projection operand over disk pixels [2][ceil(n_pix/2)][64] (B <= 64)
   int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
+  float* pinvI = nullptr;    // image projection operand over disk pixels [2 or 4][ceil(n_pix/2)][64]
+  int* dpixI = nullptr;      // (dy << 8 | dx) of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
   float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
   float* dictHat = nullptr;  // dictionary rows [16*ceil(M/16)][B] (zero rows past M)
@@ -55,5 +58,12 @@ bool encode_supported(int S, int T);
 size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
+size_t images_workspace_bytes(int n_images);
+int launch_project_images(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
+                          const int32_t* H, const int32_t* W, int n, int64_t P_total, void* ws, float* xhat,
+                          void* stream);
+int launch_stamps(const DeviceTables& t, const int32_t* atom, const float* theta, const float* amplitude,
+                  const int32_t* centre, const int32_t* image, int64_t n_stamps, const int64_t* img_offset,
+                  const int32_t* H, const int32_t* W, int n_images, float* pixels, void* stream);
 
 }  // namespace rsc

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(512) void project_tiled_kernel(const float* __restr
   float* tile = tiles + wave * 32 * NN;
   const int64_t ntile = (P + 31) / 32;
   for (int64_t bt = blockIdx.x; bt * kProjWaves < ntile; bt += gridDim.x) {
+    asm volatile("" ::: "memory");   // keep the LDS operand reads inside the loop
     const int64_t wt = bt * kProjWaves + wave;
     const int64_t p0 = wt * 32;
     const int np = wt < ntile ? int(P - p0 < 32 ? P - p0 : 32) : 0;

@@ -48,11 +48,17 @@ def lib():
         "rsc_get_basis": [P, P, P],
         "rsc_set_dictionary": [P, P, I, I],
         "rsc_set_tile": [P, I],
+        "rsc_set_launch": [P, I, I],
+        "rsc_get_launch": [P, P, P],
+        "rsc_autotune_encode": [P, P, I64, I, P, P, P, I, P, P, P],
         "rsc_project": [P, P, I64, P, P],
         "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
         "rsc_reconstruct": [P, P, P, P, I64, I, P, P],
         "rsc_synthesize": [P, P, P, P, I64, I, P, P, P],
         "rsc_sync": [P],
+        "rsc_images_workspace_size": [I, P],
+        "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
+        "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -167,6 +173,33 @@ def rsc_set_tile(h: Handle, tile: str = "auto"):
     _check(lib().rsc_set_tile(h.ptr, TILE[str(tile)]))
 
 
+def rsc_set_launch(h: Handle, tile: str = "auto", blocks_per_cu: int = 0):
+    _check(lib().rsc_set_launch(h.ptr, TILE[str(tile)], int(blocks_per_cu)))
+
+
+def rsc_get_launch(h: Handle):
+    t, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().rsc_get_launch(h.ptr, ctypes.byref(t), ctypes.byref(b)))
+    return {v: k for k, v in TILE.items()}[t.value], b.value
+
+
+def rsc_autotune_encode(h: Handle, xhat, K: int, reps: int = 5, stream=None):
+    """Times the encoder launch shapes on the sample xhat and keeps the fastest.
+    Returns [(tile, blocks_per_cu, median_ms), ...]."""
+    import torch
+    P = xhat.shape[0]
+    _dev(xhat, torch.float32, "xhat", (P, h.B))
+    atom = torch.empty((P, K), dtype=torch.int32, device=xhat.device)
+    angle = torch.empty_like(atom)
+    coef = torch.empty((P, K), dtype=torch.float32, device=xhat.device)
+    rep = np.zeros((8, 3))
+    n = ctypes.c_int()
+    _check(lib().rsc_autotune_encode(h.ptr, _ptr(xhat), P, K, _ptr(atom), _ptr(angle), _ptr(coef), reps,
+                                     rep.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n), _stream(stream)))
+    names = {v: k for k, v in TILE.items()}
+    return [(names[int(r[0])], int(r[1]), float(r[2])) for r in rep[:n.value]]
+
+
 def rsc_project(h: Handle, patches, xhat=None, stream=None):
     import torch
     P = patches.shape[0]
@@ -228,6 +261,71 @@ def rsc_synthesize(h: Handle, atom, theta, weight, noise=None, out=None, stream=
     _check(lib().rsc_synthesize(h.ptr, _ptr(atom), _ptr(theta), _ptr(weight), P, J, _ptr(noise),
                                 _ptr(out), _stream(stream)))
     return out
+
+
+class ImageBatch:
+    """Device description of a batch of images packed back to back (row-major).
+
+    Holds the device arrays img_offset (int64), H, W (int32) and the workspace that
+    rsc_project_images needs, plus the host copies of the sizes.
+    """
+
+    def __init__(self, sizes, N: int, device):
+        import torch
+        sizes = np.asarray(sizes, dtype=np.int64).reshape(-1, 2)
+        self.n = len(sizes)
+        self.H = sizes[:, 0].copy()
+        self.W = sizes[:, 1].copy()
+        off = np.zeros(self.n, np.int64)
+        if self.n:
+            off[1:] = np.cumsum(self.H * self.W)[:-1]
+        self.offset = off
+        self.total_pixels = int((self.H * self.W).sum())
+        self.patches_per_image = np.maximum(self.H - N + 1, 0) * np.maximum(self.W - N + 1, 0)
+        self.P_total = int(self.patches_per_image.sum())
+        self.d_offset = torch.from_numpy(off).to(device)
+        self.d_H = torch.from_numpy(self.H.astype(np.int32)).to(device)
+        self.d_W = torch.from_numpy(self.W.astype(np.int32)).to(device)
+        nb = ctypes.c_size_t()
+        _check(lib().rsc_images_workspace_size(self.n, ctypes.byref(nb)))
+        self.workspace = torch.empty(max(nb.value // 8, 1), dtype=torch.int64, device=device)
+        self.ws_bytes = nb.value
+
+
+def rsc_images_workspace_size(n_images: int) -> int:
+    nb = ctypes.c_size_t()
+    _check(lib().rsc_images_workspace_size(n_images, ctypes.byref(nb)))
+    return nb.value
+
+
+def rsc_project_images(h: Handle, pixels, batch: "ImageBatch", xhat=None, stream=None):
+    """Hat coordinates of every stride-1 window of every image: [P_total, B]."""
+    import torch
+    _dev(pixels, torch.float32, "pixels", (batch.total_pixels,))
+    if xhat is None:
+        xhat = torch.empty((batch.P_total, h.B), dtype=torch.float32, device=pixels.device)
+    _dev(xhat, torch.float32, "xhat", (batch.P_total, h.B))
+    _check(lib().rsc_project_images(h.ptr, _ptr(pixels), _ptr(batch.d_offset), _ptr(batch.d_H),
+                                    _ptr(batch.d_W), batch.n, batch.P_total, _ptr(batch.workspace),
+                                    batch.ws_bytes, _ptr(xhat), _stream(stream)))
+    return xhat
+
+
+def rsc_synthesize_images(h: Handle, batch: "ImageBatch", atom, theta, amplitude, centre, image,
+                          pixels, stream=None):
+    """Adds stamps to pixels (device float32 [total_pixels], initialised by the caller)."""
+    import torch
+    n = atom.shape[0]
+    _dev(atom, torch.int32, "atom", (n,))
+    _dev(theta, torch.float32, "theta", (n,))
+    _dev(amplitude, torch.float32, "amplitude", (n,))
+    _dev(centre, torch.int32, "centre", (n, 2))
+    _dev(image, torch.int32, "image", (n,))
+    _dev(pixels, torch.float32, "pixels", (batch.total_pixels,))
+    _check(lib().rsc_synthesize_images(h.ptr, _ptr(atom), _ptr(theta), _ptr(amplitude), _ptr(centre),
+                                       _ptr(image), n, _ptr(batch.d_offset), _ptr(batch.d_H),
+                                       _ptr(batch.d_W), batch.n, _ptr(pixels), _stream(stream)))
+    return pixels
 
 
 def rsc_sync(stream=None):

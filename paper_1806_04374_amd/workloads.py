@@ -215,3 +215,16 @@ def scale_draw(P: int | None = None, start: int = 0, seed: int = 0) -> tuple[np.
     D = draw_dictionary(w["M"], g.B, seed)
     return D, draw_mixtures(w["P"] if P is None else P, g.N, w["M"], w["J"],
                             w["sigma"], seed, start)
+
+
+def ragged_draws(n_images: int | None = None, first: int = 0, seed: int = 0,
+                 square: bool = False, side=None, M: int | None = None):
+    """Stamp draws of the ragged image batch: sizes log-uniform on the side range (H and W
+    drawn independently unless ``square``), then each image's stamp process."""
+    w = RAGGED
+    lo, hi = side or w["side"]
+    n_all = w["n_images"] if n_images is None else first + n_images
+    sizes = draw_image_sizes(n_all, lo, hi, square, seed)
+    M = w["M"] if M is None else M
+    return [draw_image(i, int(sizes[i, 0]), int(sizes[i, 1]), M, w["density"], w["sigma"], seed)
+            for i in range(first, n_all)]

@@ -442,3 +442,34 @@ def test_planted_signed_argmax_is_caught():
         if int(np.argmax(Da @ X[p])) != int(np.argmin(errs)):
             mismatches += 1
     assert mismatches > 0
+
+
+# ----------------------------------------------------------------------------- images
+def test_image_windows_and_stamps(b15):
+    N, c = 15, 7
+    D = wl.draw_dictionary(8, b15.B, seed=2)
+    img = orc.synthesize_image(b15, D, 40, 50, [(20, 25)], [3], [0.4], [1.5])
+    stamp = orc.to_pixels(b15, 1.5 * orc.steer(D[3], 0.4, 7, 7))[0]
+    pts = orc.image_patches(img, N)
+    assert pts.shape == ((40 - N + 1) * (50 - N + 1), N, N)
+    # the window whose centre is the stamp centre is the stamp itself
+    k = (20 - c) * (50 - N + 1) + (25 - c)
+    assert np.abs(pts[k] - stamp).max() < 1e-14
+    # window at (y, x) is img[y:y+N, x:x+N], row-major origins
+    y, x = 7, 31
+    assert np.array_equal(pts[y * (50 - N + 1) + x], img[y:y + N, x:x + N])
+    # clipping at the border keeps only the inside part
+    img2 = orc.synthesize_image(b15, D, 20, 20, [(0, 19)], [3], [0.4], [1.5])
+    assert np.abs(img2[0:8, 12:20] - stamp[7:15, 0:8]).max() < 1e-14
+    assert abs(img2.sum() - stamp[7:15, 0:8].sum()) < 1e-12
+    # images smaller than a window have no patches
+    assert orc.image_patches(np.zeros((14, 30)), N).shape == (0, N, N)
+
+
+def test_ragged_workload_sizes():
+    sizes = wl.draw_image_sizes(256, 64, 1024, False)
+    assert sizes.min() >= 64 and sizes.max() <= 1024
+    # log-uniform: median side near sqrt(64 * 1024) = 256
+    assert 200 < np.median(sizes) < 330
+    sq = wl.draw_image_sizes(50, 32, 2048, True)
+    assert np.array_equal(sq[:, 0], sq[:, 1])
