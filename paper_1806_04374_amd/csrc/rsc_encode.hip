@@ -136,31 +136,41 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
             acc[q][v] = x;
             acc[q][v + 8] = y;
           }
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-          const int m = g * 16 + a;
-          if (m >= M) break;
+        // Pass 1 over the 16 atoms x RT angle tiles of the group, software-pipelined:
+        // the MFMA chain of the next (atom, tile) unit is issued before the |.| max
+        // reduction of the current one.  Atoms past M have all-zero operands, so their
+        // scores are exactly 0 and never beat the first atom under the strict '>'.
+        constexpr int NU = 16 * RT;
+        f32x16 ob[2];
+        auto chain = [&](int a, int t) {
           const int v = 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2);
-          f32x16 o[RT];
+          f32x16 o;
 #pragma unroll
-          for (int t = 0; t < RT; ++t)
+          for (int i = 0; i < 16; ++i) o[i] = 0.f;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) o[t][i] = 0.f;
+          for (int q = 0; q < NQ; ++q) o = mfma32(F[t][q], acc[q][v], o);
+          return o;
+        };
+        ob[0] = chain(0, 0);
+        float amax = 0.f;
 #pragma unroll
-          for (int q = 0; q < NQ; ++q)
+        for (int un = 0; un < NU; ++un) {
+          const int a = un / RT, t = un % RT;
+          if (un + 1 < NU) ob[(un + 1) & 1] = chain((un + 1) / RT, (un + 1) % RT);
+          const f32x16& o = ob[un & 1];
+          float tm = fabsf(o[0]);
 #pragma unroll
-            for (int t = 0; t < RT; ++t) o[t] = mfma32(F[t][q], acc[q][v], o[t]);
-          float amax = fabsf(o[0][0]);
+          for (int i = 1; i < 16; ++i) tm = fmaxf(tm, fabsf(o[i]));
+          amax = t == 0 ? tm : fmaxf(amax, tm);
+          if (t == RT - 1) {
+            const int v = 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2);
+            const float am = max_halves(amax);
+            const bool gt = am > best;
+            best = gt ? am : best;
+            bm = gt ? g * 16 + a : bm;
 #pragma unroll
-          for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) amax = fmaxf(amax, fabsf(o[t][i]));
-          amax = max_halves(amax);
-          const bool gt = amax > best;
-          best = gt ? amax : best;
-          bm = gt ? m : bm;
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][v] : bop[q];
+            for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][v] : bop[q];
+          }
         }
       }
       // ---------------- (b) pass 2: angles of the best atom, same arithmetic
@@ -299,33 +309,34 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
             if (2 * q + 1 < NQ) acc[2 * q + 1][v] = y;
             else acc_pad[v] = y;
           }
+        // pipelined pass 1 over 8 atoms x RT angle tiles (see the 32x32 kernel)
+        constexpr int NU = 8 * RT;
+        auto opnd = [&](int q, int a) -> float {
+          return a < 4 ? acc[2 * q][a] : (2 * q + 1 < NQ ? acc[2 * q + 1][a - 4] : acc_pad[a - 4]);
+        };
+        auto chain = [&](int a, int t) {
+          f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int m = g * 8 + a;
-          if (m >= M) break;
-          f32x4 o[RT];
+          for (int q = 0; q < NP; ++q) o = mfma16(F[t][q], opnd(q, a), o);
+          return o;
+        };
+        f32x4 ob[2];
+        ob[0] = chain(0, 0);
+        float amax = 0.f;
 #pragma unroll
-          for (int t = 0; t < RT; ++t) o[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int un = 0; un < NU; ++un) {
+          const int a = un / RT, t = un % RT;
+          if (un + 1 < NU) ob[(un + 1) & 1] = chain((un + 1) / RT, (un + 1) % RT);
+          const f32x4& o = ob[un & 1];
+          const float tm = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fmaxf(fabsf(o[2]), fabsf(o[3])));
+          amax = t == 0 ? tm : fmaxf(amax, tm);
+          if (t == RT - 1) {
+            const float am = max_quarters(amax);
+            const bool gt = am > best;
+            best = gt ? am : best;
+            bm = gt ? g * 8 + a : bm;
 #pragma unroll
-          for (int q = 0; q < NP; ++q)
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-              const float opv = a < 4 ? acc[2 * q][a] : (2 * q + 1 < NQ ? acc[2 * q + 1][a - 4] : acc_pad[a - 4]);
-              o[t] = mfma16(F[t][q], opv, o[t]);
-            }
-          float amax = fabsf(o[0][0]);
-#pragma unroll
-          for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(o[t][i]));
-          amax = max_quarters(amax);
-          const bool gt = amax > best;
-          best = gt ? amax : best;
-          bm = gt ? m : bm;
-#pragma unroll
-          for (int q = 0; q < NP; ++q) {
-            const float opv = a < 4 ? acc[2 * q][a] : (2 * q + 1 < NQ ? acc[2 * q + 1][a - 4] : acc_pad[a - 4]);
-            bop[q] = gt ? opv : bop[q];
+            for (int q = 0; q < NP; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
           }
         }
       }
