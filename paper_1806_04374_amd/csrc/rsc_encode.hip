@@ -309,35 +309,35 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
             if (2 * q + 1 < NQ) acc[2 * q + 1][v] = y;
             else acc_pad[v] = y;
           }
-        // pipelined pass 1 over 8 atoms x RT angle tiles (see the 32x32 kernel)
-        constexpr int NU = 8 * RT;
+        // pass 1 over the 8 atoms, software-pipelined by atom: the RT independent
+        // MFMA chains of the next atom are issued before the |.| max of the current one
         auto opnd = [&](int q, int a) -> float {
           return a < 4 ? acc[2 * q][a] : (2 * q + 1 < NQ ? acc[2 * q + 1][a - 4] : acc_pad[a - 4]);
         };
-        auto chain = [&](int a, int t) {
-          f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 ob[2][RT];
+        auto chains = [&](int a, f32x4 (&o)[RT]) {
 #pragma unroll
-          for (int q = 0; q < NP; ++q) o = mfma16(F[t][q], opnd(q, a), o);
-          return o;
+          for (int t = 0; t < RT; ++t) o[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) o[t] = mfma16(F[t][q], opnd(q, a), o[t]);
         };
-        f32x4 ob[2];
-        ob[0] = chain(0, 0);
-        float amax = 0.f;
+        chains(0, ob[0]);
 #pragma unroll
-        for (int un = 0; un < NU; ++un) {
-          const int a = un / RT, t = un % RT;
-          if (un + 1 < NU) ob[(un + 1) & 1] = chain((un + 1) / RT, (un + 1) % RT);
-          const f32x4& o = ob[un & 1];
-          const float tm = fmaxf(fmaxf(fabsf(o[0]), fabsf(o[1])), fmaxf(fabsf(o[2]), fabsf(o[3])));
-          amax = t == 0 ? tm : fmaxf(amax, tm);
-          if (t == RT - 1) {
-            const float am = max_quarters(amax);
-            const bool gt = am > best;
-            best = gt ? am : best;
-            bm = gt ? g * 8 + a : bm;
+        for (int a = 0; a < 8; ++a) {
+          if (a + 1 < 8) chains(a + 1, ob[(a + 1) & 1]);
+          float amax = fabsf(ob[a & 1][0][0]);
 #pragma unroll
-            for (int q = 0; q < NP; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
-          }
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(ob[a & 1][t][i]));
+          const float am = max_quarters(amax);
+          const bool gt = am > best;
+          best = gt ? am : best;
+          bm = gt ? g * 8 + a : bm;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
         }
       }
       int rs;
