@@ -28,6 +28,11 @@ from paper_1806_04374_amd import workloads as wl  # noqa: E402
 METRIC = "patches encoded/sec (rotational OMP, K atoms, R angles) at matched MSE; p50/p99"
 FP32_MFMA_PEAK = 157.3e12
 
+# HBM bytes per encoder launch from rocprofv3 FETCH_SIZE and WRITE_SIZE counters, each
+# scaled by the factor a plain 1 GiB copy gives (reads x2.0, writes x1.0); measured on the
+# same kernel and workload (profiles/encode_scale-fp32_counters.md).  None when not measured.
+TRAFFIC = {}
+
 
 def encode_flops_per_patch(M: int, R: int, S: int, T: int, K: int) -> float:
     """Algorithmic flops of the pursuit for one patch doing all K steps.
@@ -184,6 +189,8 @@ def run_ragged(args, dev):
     ms = wall * 1e3 / args.steps
     flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
     achieved = flops / (np.mean(ke) * 1e-3)
+    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
+    executed = mfma_pp * P / (np.mean(ke) * 1e-3)
     out = {
         "metric": METRIC, "value": P / (ms * 1e-3), "unit": "patches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -197,7 +204,9 @@ def run_ragged(args, dev):
         "kernels_ms": {"project_images_mean": float(np.mean(kp)), "encode_mean": float(np.mean(ke))},
         "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
-                     "traffic": None, "algorithmic_flops_per_launch": flops},
+                     "traffic": TRAFFIC.get(w["name"]), "algorithmic_flops_per_launch": flops,
+                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / FP32_MFMA_PEAK,
+                     "tile": tile_used},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -313,6 +322,8 @@ def main():
     ms = wall * 1e3 / args.steps
     flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
     achieved = flops / (enc_ms.mean() * 1e-3)
+    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
+    executed = mfma_pp * P / (enc_ms.mean() * 1e-3)
     out = {
         "metric": METRIC,
         "value": P / (ms * 1e-3),
@@ -336,8 +347,10 @@ def main():
         "kernels_ms": {"project_mean": float(proj_ms.mean()), "encode_mean": float(enc_ms.mean())},
         "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_MFMA_PEAK, "traffic": None,
-                     "algorithmic_flops_per_launch": flops},
+                     "frac": achieved / FP32_MFMA_PEAK, "traffic": TRAFFIC.get(w["name"]),
+                     "algorithmic_flops_per_launch": flops,
+                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / FP32_MFMA_PEAK,
+                     "tile": tile_used},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

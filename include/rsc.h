@@ -147,6 +147,14 @@ rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile);
  */
 rsc_status rsc_set_launch(rsc_handle* h, rsc_tile tile, int blocks_per_cu);
 
+/*
+ * The encoder kernel rsc_omp_encode would run for K on this handle: its tile shape
+ * (RSC_TILE_16 or RSC_TILE_32, after resolving RSC_TILE_AUTO and fallbacks) and the
+ * matrix-core floating-point operations it executes per patch when all K steps run
+ * (padding included).  Either output pointer may be NULL.
+ */
+rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_flops_per_patch);
+
 /* Current encoder tile shape and blocks per CU (either pointer may be NULL). */
 rsc_status rsc_get_launch(const rsc_handle* h, int* tile, int* blocks_per_cu);
 

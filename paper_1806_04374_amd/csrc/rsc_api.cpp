@@ -175,6 +175,7 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.dictHat);
   free_dev(d.dftA32);
   free_dev(d.dftA16);
+  free_dev(d.dftA16s);
   free_dev(d.cs);
   free_dev(d.gramH);
   delete h;
@@ -245,35 +246,49 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   const double two_pi = 6.283185307179586476925286766559;
   auto cosk = [&](int k, int r) { return float(std::cos(two_pi * double(k) * double(r) / double(R))); };
   auto sink = [&](int k, int r) { return float(std::sin(two_pi * double(k) * double(r) / double(R))); };
-  // 32x32 tiles, stage-2 operand: row = angle, contraction lanes (cos, -sin) of one
-  // harmonic, (1, 0) for k = 0
-  const int RT32 = R <= 32 ? 1 : (R <= 64 ? 2 : 4);
-  std::vector<float> dftA32(size_t(RT32) * NQ * 64, 0.f);
-  for (int t = 0; t < RT32; ++t)
+  // 32x32 tiles, stage-2 operand (even R <= 64): row = angle r < R/2, contraction
+  // lanes (cos, -sin) of one harmonic, (1, 0) for k = 0
+  std::vector<float> dftA32;
+  if (R % 2 == 0 && R <= 64) {
+    dftA32.assign(size_t(NQ) * 64, 0.f);
     for (int q = 0; q < NQ; ++q)
       for (int l = 0; l < 64; ++l) {
-        const int r = 32 * t + (l % 32), hh = l / 32;
-        if (r >= R) continue;
-        float v;
-        if (q == 0) v = hh == 0 ? 1.f : 0.f;
-        else v = hh == 0 ? cosk(q, r) : -sink(q, r);
-        dftA32[(size_t(t) * NQ + q) * 64 + l] = v;
+        const int r = l % 32, hh = l / 32;
+        if (r >= R / 2) continue;
+        dftA32[size_t(q) * 64 + l] = q == 0 ? (hh == 0 ? 1.f : 0.f) : (hh == 0 ? cosk(q, r) : -sink(q, r));
       }
-  // 16x16 tiles, stage-2 operand: row = angle, four contraction lanes
-  // (cos k, -sin k, cos k', -sin k') for the harmonic pair (k, k') = (2q, 2q+1)
+  }
+  // 16x16 tiles: four contraction lanes (cos k1, -sin k1, cos k2, -sin k2) per step.
+  auto lane16 = [&](int k1, int k2, int r, int kk) -> float {
+    const int k = kk < 2 ? k1 : k2;
+    if (k > T) return 0.f;
+    if (kk % 2 == 0) return k == 0 ? 1.f : cosk(k, r);
+    return k == 0 ? 0.f : -sink(k, r);
+  };
+  // direct (odd R): steps (2q, 2q+1), tiles of 16 angles covering r < R
   const int RT16 = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
   const int NP = (NQ + 1) / 2;
   std::vector<float> dftA16(size_t(RT16) * NP * 64, 0.f);
   for (int t = 0; t < RT16; ++t)
     for (int q = 0; q < NP; ++q)
       for (int l = 0; l < 64; ++l) {
-        const int r = 16 * t + (l % 16), kk = l / 16, k = 2 * q + kk / 2;
-        if (r >= R || k > T) continue;
-        float v;
-        if (kk % 2 == 0) v = k == 0 ? 1.f : cosk(k, r);
-        else v = k == 0 ? 0.f : -sink(k, r);
-        dftA16[(size_t(t) * NP + q) * 64 + l] = v;
+        const int r = 16 * t + (l % 16);
+        if (r < R) dftA16[(size_t(t) * NP + q) * 64 + l] = lane16(2 * q, 2 * q + 1, r, l / 16);
       }
+  // split (even R): E steps (4j, 4j+2) then O steps (4j+1, 4j+3), tiles covering r < R/2
+  std::vector<float> dftA16s;
+  if (R % 2 == 0) {
+    const int NE = T / 2 + 1, NO = (T + 1) / 2, SE = (NE + 1) / 2, SO = (NO + 1) / 2, NS = SE + SO;
+    const int half = R / 2, HT = half <= 16 ? 1 : (half <= 32 ? 2 : 4);
+    dftA16s.assign(size_t(HT) * NS * 64, 0.f);
+    for (int t = 0; t < HT; ++t)
+      for (int q = 0; q < NS; ++q)
+        for (int l = 0; l < 64; ++l) {
+          const int r = 16 * t + (l % 16);
+          const int k1 = q < SE ? 4 * q : 4 * (q - SE) + 1;
+          if (r < half) dftA16s[(size_t(t) * NS + q) * 64 + l] = lane16(k1, k1 + 2, r, l / 16);
+        }
+  }
   std::vector<float> cs(size_t(2) * NQ * R);
   for (int k = 0; k < NQ; ++k)
     for (int r = 0; r < R; ++r) {
@@ -313,6 +328,7 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   if (s == RSC_OK) s = upload(d.dictHat, hat, "dictionary");
   if (s == RSC_OK) s = upload(d.dftA32, dftA32, "angle DFT operand");
   if (s == RSC_OK) s = upload(d.dftA16, dftA16, "angle DFT operand");
+  if (s == RSC_OK) s = upload(d.dftA16s, dftA16s, "angle DFT operand");
   if (s == RSC_OK) s = upload(d.cs, cs, "steering table");
   if (s == RSC_OK) s = upload(d.gramH, gramH, "pair table");
   h->has_dict = s == RSC_OK;
@@ -399,6 +415,16 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   h->tile = rsc_tile(best_tile);
   h->dev.enc_bpc = best_bpc;
   if (n_report) *n_report = nrep < 8 ? nrep : 8;
+  return ok();
+}
+
+rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_flops_per_patch) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  const int t = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
+  if (tile) *tile = t;
+  if (mfma_flops_per_patch) *mfma_flops_per_patch = rsc::encode_mfma_flops_per_patch(h->dev, t, K);
   return ok();
 }
 

@@ -6,24 +6,27 @@
 //       diagonal per harmonic (eq. (8)), so
 //         <S_r d_m, x> = C_0 + sum_{k>=1} [cos(2 pi k r/R) Re C_k - sin(2 pi k r/R) Im C_k],
 //         C_k = sum_s conj(d_{m,s,k}) x_{s,k}.
-//       Stage 1 forms Re C_k and Im C_k on MFMA (rows: atoms x {Re, Im}), a
+//       Stage 1 forms Re C_k and Im C_k on MFMA (rows: atoms x {Re, Im}); a
 //       cross-lane swap turns its accumulators into the operand of stage 2, the
-//       R-point angle DFT on MFMA (rows: angles).  The argmax of |score| runs in
-//       two passes: per atom only the maximum over angles is compared (max3
-//       reductions), and the winning atom's stage-2 operand is kept; its angles are
-//       then recomputed with the same instructions (bit-identical scores) and
-//       searched for the argmax.  Exact ties go to the smallest atom, then the
-//       smallest angle.
+//       angle DFT on MFMA (rows: angles).  For even R the DFT is split by harmonic
+//       parity (one radix-2 step): with E(r) the sum over even k and O(r) over odd k,
+//       score(r) = E(r) + O(r) and score(r + R/2) = E(r) - O(r), so only R/2 angle
+//       rows are computed, and the largest |score| of an atom over all R angles is
+//       max_r (|E(r)| + |O(r)|), bit-identical to the maximum of the rounded scores.
+//       The argmax runs in two passes: per atom only that maximum is compared and the
+//       winning atom's stage-2 operand kept; its angles are then recomputed with the
+//       same instructions (bit-identical scores) and searched.  Exact ties go to the
+//       smallest atom, then the smallest angle.
 //   (c) extends the Cholesky factor of the selected columns, solves the least
-//       squares and recomputes the residual, all in registers.
+//       squares and updates the residual, all in registers.
 //
 // Two tile shapes:
 //   encode32: v_mfma_f32_32x32x2f32, 32 patches per wave, 16 atoms per stage-1
 //             tile; dictionary operand pre-arranged in LDS.  (S, T) = (5, 5), K <= 4,
-//             R <= 64.
+//             even R <= 64.
 //   encode16: v_mfma_f32_16x16x4f32, 16 patches per wave, 8 atoms per stage-1
 //             tile; dictionary operand read from the packed dictionary in LDS.
-//             Any compiled (S, T), K <= 8.
+//             Any compiled (S, T), K <= 8, any R (odd R without the split).
 #include <hip/hip_runtime.h>
 
 #include "rsc_device.h"
@@ -64,12 +67,13 @@ __device__ __forceinline__ void write_codes(const EncodeParams& prm, int64_t p, 
 }
 
 // ============================================================== 32x32 tiles
-template <int S, int T, int RT, int KMAX>
+// F[q]: stage-2 operand of harmonic q for angle rows r < R/2 (rows past R/2 zero).
+template <int S, int T, int KMAX>
 __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int NG) {
   using L = Layout<S, T, 2>;
-  constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B, J0 = L::J0;
+  constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B;
   extern __shared__ float lds[];
-  const int R = prm.R, M = prm.M, K = prm.K;
+  const int R = prm.R, M = prm.M, K = prm.K, HALF = prm.R / 2;
   float* sA = lds;                       // [NG][NKS][64]
   float* sHat = sA + NG * NKS * 64;      // [NG*16][B]
   float* sCs = sHat + NG * 16 * B;       // [2][NQ][R]
@@ -83,11 +87,9 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, u = lane >> 5;
-  float F[RT][NQ];
+  float F[NQ];
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) F[t][q] = prm.dftA[(t * NQ + q) * 64 + lane];
+  for (int q = 0; q < NQ; ++q) F[q] = prm.dftA[q * 64 + lane];
 
   const int64_t nwt = (prm.P + 31) / 32;
   for (int64_t wt = int64_t(blockIdx.x) * 4 + wave; wt < nwt; wt += int64_t(gridDim.x) * 4) {
@@ -136,40 +138,36 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
             acc[q][v] = x;
             acc[q][v + 8] = y;
           }
-        // Pass 1 over the 16 atoms x RT angle tiles of the group, software-pipelined:
-        // the MFMA chain of the next (atom, tile) unit is issued before the |.| max
-        // reduction of the current one.  Atoms past M have all-zero operands, so their
-        // scores are exactly 0 and never beat the first atom under the strict '>'.
-        constexpr int NU = 16 * RT;
-        f32x16 ob[2];
-        auto chain = [&](int a, int t) {
-          const int v = 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2);
+        // Per atom: E (even harmonics) and O (odd harmonics) chains; the E chain of
+        // the next atom is issued before the reduction of the current one.  Atoms
+        // past M have all-zero operands: their scores are exactly 0 and never beat
+        // the first atom under the strict '>'.
+        auto vreg = [](int a) { return 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2); };
+        auto chain = [&](int a, int parity) {
           f32x16 o;
 #pragma unroll
           for (int i = 0; i < 16; ++i) o[i] = 0.f;
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) o = mfma32(F[t][q], acc[q][v], o);
+          for (int q = parity; q < NQ; q += 2) o = mfma32(F[q], acc[q][vreg(a)], o);
           return o;
         };
-        ob[0] = chain(0, 0);
-        float amax = 0.f;
+        f32x16 e_cur = chain(0, 0), o_cur = chain(0, 1);
 #pragma unroll
-        for (int un = 0; un < NU; ++un) {
-          const int a = un / RT, t = un % RT;
-          if (un + 1 < NU) ob[(un + 1) & 1] = chain((un + 1) / RT, (un + 1) % RT);
-          const f32x16& o = ob[un & 1];
-          float tm = fabsf(o[0]);
+        for (int a = 0; a < 16; ++a) {
+          f32x16 e_next;
+          if (a + 1 < 16) e_next = chain(a + 1, 0);
+          float am = fabsf(e_cur[0]) + fabsf(o_cur[0]);
 #pragma unroll
-          for (int i = 1; i < 16; ++i) tm = fmaxf(tm, fabsf(o[i]));
-          amax = t == 0 ? tm : fmaxf(amax, tm);
-          if (t == RT - 1) {
-            const int v = 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2);
-            const float am = max_halves(amax);
-            const bool gt = am > best;
-            best = gt ? am : best;
-            bm = gt ? g * 16 + a : bm;
+          for (int i = 1; i < 16; ++i) am = fmaxf(am, fabsf(e_cur[i]) + fabsf(o_cur[i]));
+          am = max_halves(am);
+          const bool gt = am > best;
+          best = gt ? am : best;
+          bm = gt ? g * 16 + a : bm;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][v] : bop[q];
+          for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][vreg(a)] : bop[q];
+          if (a + 1 < 16) {
+            o_cur = chain(a + 1, 1);
+            e_cur = e_next;
           }
         }
       }
@@ -177,28 +175,27 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
       int rs;
       float cval;
       {
-        f32x16 o[RT];
+        f32x16 e, o;
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
+        for (int i = 0; i < 16; ++i) e[i] = o[i] = 0.f;
 #pragma unroll
-          for (int i = 0; i < 16; ++i) o[t][i] = 0.f;
+        for (int q = 0; q < NQ; q += 2) e = mfma32(F[q], bop[q], e);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-          for (int t = 0; t < RT; ++t) o[t] = mfma32(F[t][q], bop[q], o[t]);
+        for (int q = 1; q < NQ; q += 2) o = mfma32(F[q], bop[q], o);
         float rb = -1.f, rv = 0.f;
         int rc = 0;
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
+        for (int h = 0; h < 2; ++h)          // angles r < R/2 first, then r + R/2
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            const float val = fabsf(o[t][i]);
+            const int row = 8 * (i / 4) + 4 * u + (i % 4);
+            const float sc = h == 0 ? e[i] + o[i] : e[i] - o[i];
+            const float val = row < HALF ? fabsf(sc) : -1.f;
             const bool gt = val > rb;
             rb = gt ? val : rb;
-            rv = gt ? o[t][i] : rv;
-            rc = gt ? 32 * t + 8 * (i / 4) + (i % 4) : rc;
+            rv = gt ? sc : rv;
+            rc = gt ? row + h * HALF : rc;
           }
-        rc += 4 * u;
         const float ob = __shfl_xor(rb, 32), ov = __shfl_xor(rv, 32);
         const int oc = __shfl_xor(rc, 32);
         const bool take = (ob > rb) || (ob == rb && oc < rc);
@@ -215,13 +212,21 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
 }
 
 // ============================================================== 16x16 tiles
-template <int S, int T, int RT, int KMAX>
+// SPLIT (even R): each stage-2 step contracts a pair of harmonics of one parity,
+// (4j, 4j+2) for E and (4j+1, 4j+3) for O; HT tiles of 16 angle rows cover r < R/2.
+// dftA: [HT][SE + SO][64] (E steps first).
+// Direct (odd R): steps contract harmonic pairs (2q, 2q+1); HT tiles cover r < R.
+// dftA: [HT][NP][64].
+template <int S, int T, int HT, int KMAX, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
   using L = Layout<S, T, 4>;
-  constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B, J0 = L::J0, J1 = L::J1;
-  constexpr int NP = (NQ + 1) / 2;       // harmonic pairs per stage-2 step
+  constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B;
+  constexpr int NE = T / 2 + 1, NO = (T + 1) / 2;           // even / odd harmonics
+  constexpr int SE = SPLIT ? (NE + 1) / 2 : (NQ + 1) / 2;   // steps feeding the E (or only) chain
+  constexpr int SO = SPLIT ? (NO + 1) / 2 : 0;              // steps feeding the O chain
+  constexpr int NS = SE + SO;
   extern __shared__ float lds[];
-  const int R = prm.R, M = prm.M, K = prm.K;
+  const int R = prm.R, M = prm.M, K = prm.K, HALF = SPLIT ? prm.R / 2 : prm.R;
   const int NG = (M + 7) / 8;
   float* sHat = lds;                     // [NG*8][B]
   float* sCs = sHat + NG * 8 * B;        // [2][NQ][R]
@@ -244,11 +249,15 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
   const float sgn = (is_im && part == 0) ? -1.f : 1.f;
   const float* arow_hat = sHat + a_of_row * B;
 
-  float F[RT][NP];
+  float F[HT][NS];
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+  for (int t = 0; t < HT; ++t)
 #pragma unroll
-    for (int q = 0; q < NP; ++q) F[t][q] = prm.dftA[(t * NP + q) * 64 + lane];
+    for (int q = 0; q < NS; ++q) F[t][q] = prm.dftA[(t * NS + q) * 64 + lane];
+
+  // harmonics contracted by step q: (k1, k2)
+  auto k1_of = [](int q) { return SPLIT ? (q < SE ? 4 * q : 4 * (q - SE) + 1) : 2 * q; };
+  auto k2_of = [](int q) { return SPLIT ? (q < SE ? 4 * q + 2 : 4 * (q - SE) + 3) : 2 * q + 1; };
 
   const int64_t nwt = (prm.P + 15) / 16;
   for (int64_t wt = int64_t(blockIdx.x) * 4 + wave; wt < nwt; wt += int64_t(gridDim.x) * 4) {
@@ -270,7 +279,7 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
 
       float best = -1.f;
       int bm = 0;
-      float bop[NP];
+      float bop[NS];
       zero(bop);
       for (int g = 0; g < NG; ++g) {
         const float* hg = arow_hat + g * 8 * B;
@@ -294,81 +303,95 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
           }
           acc[k] = mfma16(av, res[j], acc[k]);
         }
-        // quarters 0,1 hold (Re, Im) of atom v, quarters 2,3 of atom v+4; the swap of
-        // harmonics (2q, 2q+1) gives the operand [Re_k Im_k Re_k' Im_k'] of atoms v, v+4
-        // (in place: operand of atom a < 4 is acc[2q][a], of atom a >= 4 acc[2q+1][a-4])
-        f32x4 acc_pad = f32x4{0.f, 0.f, 0.f, 0.f};
+        // quarters 0,1 hold (Re, Im) of atom v, quarters 2,3 of atom v+4.  Swapping
+        // harmonics (k1, k2) of a step gives the operand [Re_k1 Im_k1 Re_k2 Im_k2]
+        // of atoms v and v+4, kept in place: atom a < 4 in acc[k1][a], atom a >= 4 in
+        // acc[k2][a-4] (or pad[q][a-4] when k2 > T).
+        float pad[NS][4];
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
+        for (int q = 0; q < NS; ++q)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            float x = acc[2 * q][v];
-            float y = (2 * q + 1 < NQ) ? acc[2 * q + 1][v] : 0.f;
+            const int k1 = k1_of(q), k2 = k2_of(q);
+            float x = acc[k1][v];
+            float y = k2 <= T ? acc[k2][v] : 0.f;
             swap32(x, y);
-            acc[2 * q][v] = x;
-            if (2 * q + 1 < NQ) acc[2 * q + 1][v] = y;
-            else acc_pad[v] = y;
+            acc[k1][v] = x;
+            if (k2 <= T) acc[k2][v] = y;
+            pad[q][v] = y;
           }
-        // pass 1 over the 8 atoms, software-pipelined by atom: the RT independent
-        // MFMA chains of the next atom are issued before the |.| max of the current one
         auto opnd = [&](int q, int a) -> float {
-          return a < 4 ? acc[2 * q][a] : (2 * q + 1 < NQ ? acc[2 * q + 1][a - 4] : acc_pad[a - 4]);
+          const int k1 = k1_of(q), k2 = k2_of(q);
+          return a < 4 ? acc[k1][a] : (k2 <= T ? acc[k2][a - 4] : pad[q][a - 4]);
         };
-        f32x4 ob[2][RT];
-        auto chains = [&](int a, f32x4 (&o)[RT]) {
+        // per atom: HT tiles x (E, O) chains; the chains of the next atom are issued
+        // before the reduction of the current one
+        f32x4 ob[2][2][HT];
+        auto chains = [&](int a, f32x4 (&o)[2][HT]) {
 #pragma unroll
-          for (int t = 0; t < RT; ++t) o[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+          for (int t = 0; t < HT; ++t) o[0][t] = o[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int q = 0; q < NP; ++q)
+          for (int q = 0; q < NS; ++q)
 #pragma unroll
-            for (int t = 0; t < RT; ++t) o[t] = mfma16(F[t][q], opnd(q, a), o[t]);
+            for (int t = 0; t < HT; ++t) {
+              const int c = q < SE ? 0 : 1;
+              o[c][t] = mfma16(F[t][q], opnd(q, a), o[c][t]);
+            }
         };
         chains(0, ob[0]);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           if (a + 1 < 8) chains(a + 1, ob[(a + 1) & 1]);
-          float amax = fabsf(ob[a & 1][0][0]);
+          const f32x4 (&o)[2][HT] = ob[a & 1];
+          float am = 0.f;
 #pragma unroll
-          for (int t = 0; t < RT; ++t)
+          for (int t = 0; t < HT; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) amax = fmaxf(amax, fabsf(ob[a & 1][t][i]));
-          const float am = max_quarters(amax);
+            for (int i = 0; i < 4; ++i)
+              am = fmaxf(am, SPLIT ? fabsf(o[0][t][i]) + fabsf(o[1][t][i]) : fabsf(o[0][t][i]));
+          am = max_quarters(am);
           const bool gt = am > best;
           best = gt ? am : best;
           bm = gt ? g * 8 + a : bm;
 #pragma unroll
-          for (int q = 0; q < NP; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
+          for (int q = 0; q < NS; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
         }
       }
       int rs;
       float cval;
       {
-        f32x4 o[RT];
+        f32x4 o[2][HT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) o[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < HT; ++t) o[0][t] = o[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
+        for (int q = 0; q < NS; ++q)
 #pragma unroll
-          for (int t = 0; t < RT; ++t) o[t] = mfma16(F[t][q], bop[q], o[t]);
+          for (int t = 0; t < HT; ++t) {
+            const int c = q < SE ? 0 : 1;
+            o[c][t] = mfma16(F[t][q], bop[q], o[c][t]);
+          }
         float rb = -1.f, rv = 0.f;
         int rc = 0;
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
+        for (int h = 0; h < (SPLIT ? 2 : 1); ++h)   // angles r < R/2 first, then r + R/2
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float val = fabsf(o[t][i]);
-            const bool gt = val > rb;
-            rb = gt ? val : rb;
-            rv = gt ? o[t][i] : rv;
-            rc = gt ? 16 * t + i : rc;
-          }
-        rc += 4 * u;
+          for (int t = 0; t < HT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = 16 * t + 4 * u + i;
+              const float sc = SPLIT ? (h == 0 ? o[0][t][i] + o[1][t][i] : o[0][t][i] - o[1][t][i]) : o[0][t][i];
+              const float val = row < HALF ? fabsf(sc) : -1.f;
+              const bool gt = val > rb;
+              rb = gt ? val : rb;
+              rv = gt ? sc : rv;
+              rc = gt ? row + h * HALF : rc;
+            }
 #pragma unroll
         for (int sh = 16; sh <= 32; sh *= 2) {
-          const float ob = __shfl_xor(rb, sh), ov = __shfl_xor(rv, sh);
+          const float ob2 = __shfl_xor(rb, sh), ov = __shfl_xor(rv, sh);
           const int oc = __shfl_xor(rc, sh);
-          const bool take = (ob > rb) || (ob == rb && oc < rc);
-          rb = take ? ob : rb;
+          const bool take = (ob2 > rb) || (ob2 == rb && oc < rc);
+          rb = take ? ob2 : rb;
           rv = take ? ov : rv;
           rc = take ? oc : rc;
         }
@@ -415,38 +438,44 @@ int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, int bpc, hipStr
   return int(hipGetLastError());
 }
 
-template <int S, int T, int RT, int KMAX>
+template <int S, int T, int KMAX>
 int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  return launch_persistent(encode32_kernel<S, T, RT, KMAX>, encode_lds_bytes(t, RSC_TILE_32),
-                           (prm.P + 31) / 32, t.enc_bpc, st, prm, t.NG);
+  return launch_persistent(encode32_kernel<S, T, KMAX>, encode_lds_bytes(t, RSC_TILE_32), (prm.P + 31) / 32,
+                           t.enc_bpc, st, prm, t.NG);
 }
 
-template <int S, int T, int RT, int KMAX>
+template <int S, int T, int HT, int KMAX, bool SPLIT>
 int launch16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  return launch_persistent(encode16_kernel<S, T, RT, KMAX>, encode_lds_bytes(t, RSC_TILE_16),
+  return launch_persistent(encode16_kernel<S, T, HT, KMAX, SPLIT>, encode_lds_bytes(t, RSC_TILE_16),
                            (prm.P + 15) / 16, t.enc_bpc, st, prm);
 }
 
-template <int S, int T, int RT>
+template <int S, int T, int HT, bool SPLIT>
 int k16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  if (prm.K <= 2) return launch16<S, T, RT, 2>(t, prm, st);
-  if (prm.K <= 4) return launch16<S, T, RT, 4>(t, prm, st);
-  return launch16<S, T, RT, 8>(t, prm, st);
+  if (prm.K <= 2) return launch16<S, T, HT, 2, SPLIT>(t, prm, st);
+  if (prm.K <= 4) return launch16<S, T, HT, 4, SPLIT>(t, prm, st);
+  return launch16<S, T, HT, 8, SPLIT>(t, prm, st);
 }
 
+// angle tiles of 16 rows: R/2 rows with the split (even R), R rows without
 template <int S, int T>
 int r16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  const int rt = (t.R + 15) / 16;
-  if (rt <= 1) return k16<S, T, 1>(t, prm, st);
-  if (rt <= 2) return k16<S, T, 2>(t, prm, st);
-  if (rt <= 4) return k16<S, T, 4>(t, prm, st);
-  return k16<S, T, 8>(t, prm, st);
+  if (t.R % 2 == 0) {
+    const int ht = (t.R / 2 + 15) / 16;
+    if (ht <= 1) return k16<S, T, 1, true>(t, prm, st);
+    if (ht <= 2) return k16<S, T, 2, true>(t, prm, st);
+    return k16<S, T, 4, true>(t, prm, st);
+  }
+  const int ht = (t.R + 15) / 16;
+  if (ht <= 1) return k16<S, T, 1, false>(t, prm, st);
+  if (ht <= 2) return k16<S, T, 2, false>(t, prm, st);
+  if (ht <= 4) return k16<S, T, 4, false>(t, prm, st);
+  return k16<S, T, 8, false>(t, prm, st);
 }
 
 int r32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  const int rt = (t.R + 31) / 32;
-  if (prm.K <= 2) return rt <= 1 ? launch32<5, 5, 1, 2>(t, prm, st) : launch32<5, 5, 2, 2>(t, prm, st);
-  return rt <= 1 ? launch32<5, 5, 1, 4>(t, prm, st) : launch32<5, 5, 2, 4>(t, prm, st);
+  if (prm.K <= 2) return launch32<5, 5, 2>(t, prm, st);
+  return launch32<5, 5, 4>(t, prm, st);
 }
 
 }  // namespace
@@ -464,8 +493,33 @@ size_t encode_lds_bytes(const DeviceTables& t, int tile) {
 }
 
 bool tile32_usable(const DeviceTables& t, int K) {
-  return t.S == 5 && t.T == 5 && K <= 4 && t.R <= 64 && t.dictA &&
+  return t.S == 5 && t.T == 5 && K <= 4 && t.R <= 64 && t.R % 2 == 0 && t.dictA &&
          encode_lds_bytes(t, RSC_TILE_32) <= 80 * 1024;
+}
+
+double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K) {
+  const int S = t.S, T = t.T, NQ = T + 1;
+  if (tile == RSC_TILE_32) {
+    // per wave of 32 patches and step: NG stage-1 tiles of stage1_steps MFMAs, 16 atoms x
+    // (T+1) stage-2 MFMAs per group, plus the winner's recompute; 2*32*32*2 flops each
+    const double per_step = double(t.NG) * (stage1_steps(S, T) + 16.0 * NQ) + NQ;
+    return K * per_step * 4096.0 / 32.0;
+  }
+  const int W = 4, J0 = (S + W - 1) / W, J1 = (2 * S + W - 1) / W, NKS = J0 + T * J1;
+  int ht, ns;
+  if (t.R % 2 == 0) {
+    const int NE = T / 2 + 1, NO = (T + 1) / 2;
+    ht = (t.R / 2 + 15) / 16;
+    ht = ht <= 1 ? 1 : (ht <= 2 ? 2 : 4);
+    ns = (NE + 1) / 2 + (NO + 1) / 2;
+  } else {
+    ht = (t.R + 15) / 16;
+    ht = ht <= 1 ? 1 : (ht <= 2 ? 2 : (ht <= 4 ? 4 : 8));
+    ns = (NQ + 1) / 2;
+  }
+  const int ng8 = (t.M + 7) / 8;
+  const double per_step = double(ng8) * (NKS + 8.0 * ht * ns) + ht * ns;
+  return K * per_step * 2048.0 / 16.0;
 }
 
 int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P, int K, int32_t* atom,
@@ -477,7 +531,8 @@ int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P,
     EncodeParams prm{xhat, P, K, t.M, t.R, t.dictA, t.dictHat, t.dftA32, t.cs, t.gramH, atom, angle, coef, resid2};
     return r32(t, prm, st);
   }
-  EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.dftA16, t.cs, t.gramH, atom, angle, coef, resid2};
+  EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.R % 2 == 0 ? t.dftA16s : t.dftA16, t.cs, t.gramH,
+                   atom, angle, coef, resid2};
   if (t.S == 5 && t.T == 5) return r16<5, 5>(t, prm, st);
   if (t.S == 7 && t.T == 7) return r16<7, 7>(t, prm, st);
   return int(hipErrorInvalidValue);

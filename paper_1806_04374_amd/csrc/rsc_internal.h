@@ -41,8 +41,9 @@ struct DeviceTables {
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
   float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
   float* dictHat = nullptr;  // dictionary rows [16*ceil(M/16)][B] (zero rows past M)
-  float* dftA32 = nullptr;   // 32x32-tile stage-2 operand [ceil(R/32)->1,2,4][T+1][64]
-  float* dftA16 = nullptr;   // 16x16-tile stage-2 operand [ceil(R/16)->1,2,4,8][(T+2)/2][64]
+  float* dftA32 = nullptr;   // 32x32-tile stage-2 operand, angles r < R/2 [T+1][64] (even R <= 64)
+  float* dftA16 = nullptr;   // 16x16-tile stage-2 operand, all angles [ceil(R/16)->1,2,4,8][(T+2)/2][64]
+  float* dftA16s = nullptr;  // 16x16-tile stage-2 operand, parity split [ceil(R/32)->1,2,4][E+O steps][64]
   float* cs = nullptr;       // [2][T+1][R]: cos, then sin, of 2 pi k r / R
   float* gramH = nullptr;    // [M][M][2T+1]: per-atom-pair harmonic inner products (see pair_gram)
 };
@@ -57,6 +58,7 @@ int launch_synthesize(const DeviceTables& t, const int32_t* atom, const int32_t*
 bool encode_supported(int S, int T);
 size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
+double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
 size_t images_workspace_bytes(int n_images);
 int launch_project_images(const DeviceTables& t, const float* pixels, const int64_t* img_offset,

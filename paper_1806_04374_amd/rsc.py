@@ -50,6 +50,7 @@ def lib():
         "rsc_set_tile": [P, I],
         "rsc_set_launch": [P, I, I],
         "rsc_get_launch": [P, P, P],
+        "rsc_encode_info": [P, I, P, P],
         "rsc_autotune_encode": [P, P, I64, I, P, P, P, I, P, P, P],
         "rsc_project": [P, P, I64, P, P],
         "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
@@ -175,6 +176,13 @@ def rsc_set_tile(h: Handle, tile: str = "auto"):
 
 def rsc_set_launch(h: Handle, tile: str = "auto", blocks_per_cu: int = 0):
     _check(lib().rsc_set_launch(h.ptr, TILE[str(tile)], int(blocks_per_cu)))
+
+
+def rsc_encode_info(h: Handle, K: int):
+    """(tile actually used for K, executed MFMA flops per patch)."""
+    t, f = ctypes.c_int(), ctypes.c_double()
+    _check(lib().rsc_encode_info(h.ptr, K, ctypes.byref(t), ctypes.byref(f)))
+    return {v: k for k, v in TILE.items()}[t.value], f.value
 
 
 def rsc_get_launch(h: Handle):
