@@ -214,6 +214,88 @@ def run_ragged(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_serving(args, dev):
+    """Open-loop Poisson trace of encode requests (square images, sides log-uniform
+    32..2048, 15x15 windows, M=128, K=6, R=64): continuous batching against
+    one-request-at-a-time encoding of the same trace."""
+    import torch
+    from paper_1806_04374_amd import autotune, rsc, serve
+    w = wl.SERVING
+    g = w["geom"]
+    K = w["K"]
+    D = wl.draw_dictionary(w["M"], g.B)
+    h = rsc.rsc_create(g.N, g.S, g.T)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+    arrivals, sides = wl.serving_trace(args.duration, args.rate)
+    n = len(arrivals)
+    sizes = sides.astype(np.int64) ** 2
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    host = torch.empty(int(offs[-1]), dtype=torch.float32, pin_memory=True)
+    gen = torch.Generator(device=dev)
+    t_gen = time.perf_counter()
+    for i in range(n):           # request images: seeded device noise plus stamps
+        sd = int(sides[i])
+        gen.manual_seed(1_000_003 * 7 + i)
+        pix = torch.randn(sd * sd, generator=gen, device=dev) * w["sigma"]
+        centre, atom, angle, amp = wl.request_stamps(i, sd, sd, w["M"], w["density"])
+        if len(atom):
+            b1 = rsc.ImageBatch([(sd, sd)], g.N, dev)
+            rsc.rsc_synthesize_images(
+                h, b1, torch.from_numpy(atom.astype(np.int32)).to(dev),
+                torch.from_numpy(angle.astype(np.float32)).to(dev), torch.from_numpy(amp.astype(np.float32)).to(dev),
+                torch.from_numpy(centre.astype(np.int32)).to(dev), torch.zeros(len(atom), dtype=torch.int32, device=dev),
+                pix)
+        host[int(offs[i]):int(offs[i + 1])].copy_(pix)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    total_windows = int(((sides - g.N + 1).clip(0) ** 2).sum())
+    # tune the encoder launch shape on one large image before the trace
+    big = int(np.argmax(sides))
+    b1 = rsc.ImageBatch([(int(sides[big]), int(sides[big]))], g.N, dev)
+    xs = rsc.rsc_project_images(h, host[int(offs[big]):int(offs[big + 1])].to(dev), b1)
+    tuned = autotune.tune(h, xs[: min(len(xs), 1 << 18)], K, reps=3)
+    del xs
+
+    def make(i):
+        sd = int(sides[i])
+        return serve.Request(i, float(arrivals[i]), host[int(offs[i]):int(offs[i + 1])].view(sd, sd), sd, sd)
+
+    keep = lambda r: r.rid % 50 == 0
+    budget = int(args.budget_gib * (1 << 30))
+    be = serve.DeviceBackend(h, K, budget, args.step_windows, keep_codes=keep)
+    sch = serve.Scheduler(be, budget // 4, args.step_windows)
+    served = [make(i) for i in range(n)]
+    t0 = time.perf_counter()
+    serve.replay(sch, served, realtime=True)
+    span = time.perf_counter() - t0
+    rep = serve.latency_report(served, warmup=5.0 if args.duration > 10 else 0.0)
+    alone = [make(i) for i in range(n)]
+    t1 = time.perf_counter()
+    serve.encode_one_at_a_time(h, K, alone, realtime=True, keep_codes=keep)
+    span1 = time.perf_counter() - t1
+    rep1 = serve.latency_report(alone, warmup=5.0 if args.duration > 10 else 0.0)
+    same = [all(np.array_equal(a, b) for a, b in zip(x.codes, y.codes))
+            for x, y in zip(served, alone) if x.codes is not None and x.windows]
+    out = {
+        "metric": METRIC, "value": total_windows / span, "unit": "patches/s", "n_gpus": 1,
+        "steps": sch.steps, "warmup": 0, "ms_per_step": span * 1e3 / max(sch.steps, 1),
+        "p50_ms": rep.get("p50_s", float("nan")) * 1e3, "p99_ms": rep.get("p99_s", float("nan")) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: Poisson {args.rate:g} req/s for {args.duration:g} s, square sides "
+                               f"log-uniform {w['side']}, 15x15 windows, M={w['M']}, K={K}, R={w['R']}",
+                   "requests": n, "windows": total_windows, "budget_gib": args.budget_gib,
+                   "step_windows": args.step_windows, "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")}},
+        "serving": {"continuous_batching": dict(rep, makespan_s=span, patches_per_s=total_windows / span,
+                                                max_active=sch.max_active, rejected=len(sch.rejected)),
+                    "one_at_a_time": dict(rep1, makespan_s=span1, patches_per_s=total_windows / span1),
+                    "speedup_throughput": span1 / span,
+                    "codes_identical_alone_vs_mix": f"{sum(same)}/{len(same)} sampled requests",
+                    "offered_patches_per_s": total_windows / args.duration,
+                    "input_generation_s": t_gen},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_ragged(h, w, D, target_s, dev):
     """FP64 reference on windows of the first image (reference-synthesized pixels)."""
     import torch
@@ -250,7 +332,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged"], default="scale")
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving"], default="scale")
+    ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for request pixels")
+    ap.add_argument("--step-windows", type=int, default=1 << 22, help="serving: windows per device step")
     ap.add_argument("--images", type=int, default=0, help="ragged: use the first n images (testing only)")
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -280,6 +366,9 @@ def main():
         return
     if args.workload == "ragged":
         run_ragged(args, dev)
+        return
+    if args.workload == "serving":
+        run_serving(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

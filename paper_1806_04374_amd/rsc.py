@@ -278,17 +278,25 @@ class ImageBatch:
     rsc_project_images needs, plus the host copies of the sizes.
     """
 
-    def __init__(self, sizes, N: int, device):
+    def __init__(self, sizes, N: int, device, offsets=None):
+        """sizes: [(H, W)]; offsets: element offset of each image in the pixel buffer
+        (default: images packed back to back)."""
         import torch
         sizes = np.asarray(sizes, dtype=np.int64).reshape(-1, 2)
         self.n = len(sizes)
         self.H = sizes[:, 0].copy()
         self.W = sizes[:, 1].copy()
-        off = np.zeros(self.n, np.int64)
-        if self.n:
-            off[1:] = np.cumsum(self.H * self.W)[:-1]
+        if offsets is None:
+            off = np.zeros(self.n, np.int64)
+            if self.n:
+                off[1:] = np.cumsum(self.H * self.W)[:-1]
+        else:
+            off = np.asarray(offsets, dtype=np.int64).reshape(-1)
+            if off.shape[0] != self.n or (self.n and off.min() < 0):
+                raise ValueError("offsets must be one non-negative offset per image")
         self.offset = off
         self.total_pixels = int((self.H * self.W).sum())
+        self.min_pixels = int((off + self.H * self.W).max()) if self.n else 0
         self.patches_per_image = np.maximum(self.H - N + 1, 0) * np.maximum(self.W - N + 1, 0)
         self.P_total = int(self.patches_per_image.sum())
         self.d_offset = torch.from_numpy(off).to(device)
@@ -309,7 +317,9 @@ def rsc_images_workspace_size(n_images: int) -> int:
 def rsc_project_images(h: Handle, pixels, batch: "ImageBatch", xhat=None, stream=None):
     """Hat coordinates of every stride-1 window of every image: [P_total, B]."""
     import torch
-    _dev(pixels, torch.float32, "pixels", (batch.total_pixels,))
+    _dev(pixels, torch.float32, "pixels")
+    if pixels.dim() != 1 or pixels.shape[0] < batch.min_pixels:
+        raise ValueError(f"pixels must be 1-D with at least {batch.min_pixels} elements")
     if xhat is None:
         xhat = torch.empty((batch.P_total, h.B), dtype=torch.float32, device=pixels.device)
     _dev(xhat, torch.float32, "xhat", (batch.P_total, h.B))
@@ -329,7 +339,9 @@ def rsc_synthesize_images(h: Handle, batch: "ImageBatch", atom, theta, amplitude
     _dev(amplitude, torch.float32, "amplitude", (n,))
     _dev(centre, torch.int32, "centre", (n, 2))
     _dev(image, torch.int32, "image", (n,))
-    _dev(pixels, torch.float32, "pixels", (batch.total_pixels,))
+    _dev(pixels, torch.float32, "pixels")
+    if pixels.dim() != 1 or pixels.shape[0] < batch.min_pixels:
+        raise ValueError(f"pixels must be 1-D with at least {batch.min_pixels} elements")
     _check(lib().rsc_synthesize_images(h.ptr, _ptr(atom), _ptr(theta), _ptr(amplitude), _ptr(centre),
                                        _ptr(image), n, _ptr(batch.d_offset), _ptr(batch.d_H),
                                        _ptr(batch.d_W), batch.n, _ptr(pixels), _stream(stream)))

@@ -17,7 +17,8 @@ Reproducibility: every stream is a ``numpy.random.SeedSequence(seed,
 spawn_key=...)`` so that any slice of patches can be drawn without drawing
 the ones before it.  Stream keys: (0,) dictionary, (1, c) structure of chunk
 c, (2, c) weights of chunk c, (3, c) noise of chunk c, (4,) image sizes,
-(5, i) stamps of image i, (6, i) noise of image i, (7,) request arrivals.
+(5, i) stamps of image i, (6, i) noise of image i, (7,) request arrivals,
+(8,) request image sides, (9, i) stamps of request i.
 Patch streams are cut in chunks of ``CHUNK`` patches.
 """
 from __future__ import annotations
@@ -228,3 +229,23 @@ def ragged_draws(n_images: int | None = None, first: int = 0, seed: int = 0,
     M = w["M"] if M is None else M
     return [draw_image(i, int(sizes[i, 0]), int(sizes[i, 1]), M, w["density"], w["sigma"], seed)
             for i in range(first, n_all)]
+
+
+def serving_trace(duration: float | None = None, rate: float | None = None, seed: int = 0):
+    """Open-loop request trace: Poisson arrival times (s) and square image sides,
+    log-uniform on the serving side range."""
+    w = SERVING
+    t = draw_arrivals(w["rate"] if rate is None else rate, w["duration"] if duration is None else duration, seed)
+    lo, hi = w["side"]
+    rs = _rng(seed, 8)
+    side = np.rint(np.exp(rs.uniform(math.log(lo), math.log(hi), t.size))).astype(np.int64).clip(lo, hi)
+    return t, side
+
+
+def request_stamps(i: int, H: int, W: int, M: int, density: float, seed: int = 0):
+    """Stamp process of request i (centres, atoms, angles, amplitudes), as draw_image but
+    without the pixel noise, which the serving benchmark draws on the device."""
+    rs = _rng(seed, 9, i)
+    n = rs.poisson(density * H * W)
+    centre = np.stack([rs.integers(0, H, n), rs.integers(0, W, n)], axis=1)
+    return centre, rs.integers(0, M, n), rs.uniform(0.0, 2 * np.pi, n), rs.standard_normal(n)

@@ -1,0 +1,74 @@
+"""Encode server on the device: every request's codes are bit-identical alone and in
+the served mix (mixed sizes, admission under a small memory budget, many steps)."""
+import numpy as np
+import pytest
+
+from oracle import rsc_oracle as orc
+from paper_1806_04374_amd import workloads as wl
+from tests.parity import compare_codes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM15
+    D = wl.draw_dictionary(128, g.B, seed=0)
+    h = rsc.rsc_create(g.N, g.S, g.T)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), 64)
+    yield g, D, h
+    h.close()
+
+
+def _image(basis, D, i, side):
+    centre, atom, angle, amp = wl.request_stamps(i, side, side, 128, 0.02, seed=5)
+    noise = 0.05 * np.random.default_rng(i).standard_normal((side, side))
+    return orc.synthesize_image(basis, D, side, side, centre, atom, angle, amp, noise).astype(np.float32)
+
+
+def test_served_codes_equal_alone(setup):
+    from paper_1806_04374_amd import rsc, serve
+    g, D, h = setup
+    basis = orc.build_basis(g.N, g.S, g.T)
+    rng = np.random.default_rng(11)
+    sides = list(rng.integers(10, 130, 24)) + [14, 15, 16]
+    reqs = [serve.Request(i, 0.0, _image(basis, D, i, int(s)), int(s), int(s)) for i, s in enumerate(sides)]
+    be = serve.DeviceBackend(h, 6, budget_bytes=4 * 40_000, step_windows=3000)
+    sch = serve.Scheduler(be, budget_elems=40_000, step_windows=3000)
+    serve.replay(sch, reqs, realtime=False)
+    assert len(sch.finished) == len(reqs) and not sch.rejected
+    assert sch.steps > 5 and sch.max_active > 1
+    dev = torch.device("cuda:0")
+    for r in reqs:
+        if r.windows == 0:
+            continue
+        batch = rsc.ImageBatch([(r.H, r.W)], g.N, dev)
+        xh = rsc.rsc_project_images(h, torch.from_numpy(r.pixels.ravel()).to(dev), batch)
+        atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, 6)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.codes[0], atom.cpu().numpy()), r.rid
+        assert np.array_equal(r.codes[1], angle.cpu().numpy()), r.rid
+        assert np.array_equal(r.codes[2], coef.cpu().numpy()), r.rid
+    # two served requests against the FP64 reference
+    for r in reqs[:2]:
+        wins = orc.image_patches(r.pixels.astype(np.float64), g.N)
+        _, code = orc.encode(basis, D, 64, wins, 6)
+        rep = compare_codes(r.codes[0], r.codes[1], r.codes[2], code)
+        assert rep.match_rate >= 0.99 and rep.coef_bad == 0, str(rep)
+
+
+def test_one_at_a_time_baseline_matches(setup):
+    from paper_1806_04374_amd import serve
+    g, D, h = setup
+    basis = orc.build_basis(g.N, g.S, g.T)
+    reqs = [serve.Request(i, 0.0, _image(basis, D, 100 + i, s), s, s) for i, s in enumerate([20, 33, 15, 47])]
+    serve.encode_one_at_a_time(h, 6, reqs, realtime=False)
+    for r in reqs:
+        wins = orc.image_patches(r.pixels.astype(np.float64), g.N)
+        _, code = orc.encode(basis, D, 64, wins, 6)
+        rep = compare_codes(r.codes[0], r.codes[1], r.codes[2], code)
+        assert rep.match_rate >= 0.99, str(rep)
