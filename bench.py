@@ -27,11 +27,24 @@ from paper_1806_04374_amd import workloads as wl  # noqa: E402
 
 METRIC = "patches encoded/sec (rotational OMP, K atoms, R angles) at matched MSE; p50/p99"
 FP32_MFMA_PEAK = 157.3e12
+HALF_MFMA_PEAK = 2.5e15          # dense BF16 / FP16 matrix peak
+DTYPE = {"fp32": "f32", "bf16": "bf16 (FP32 accumulation, FP32 re-score)",
+         "fp16": "f16 (FP32 accumulation, FP32 re-score)"}
 
 # HBM bytes per encoder launch from rocprofv3 FETCH_SIZE and WRITE_SIZE counters, each
-# scaled by the factor a plain 1 GiB copy gives (reads x2.0, writes x1.0); measured on the
-# same kernel and workload (profiles/encode_scale-fp32_counters.md).  None when not measured.
-TRAFFIC = {}
+# scaled by the factor a plain 1 GiB copy gives (reads x2.0, writes x1.0), measured on the
+# same kernel and workload (profiles/encode32_scale-fp32_counters.md and
+# profiles/encode16_ragged-images_kernel_trace.md).  Valid for the encoder as of those
+# counter runs; a workload missing here reports null.
+TRAFFIC = {
+    "scale-fp32": {"read": 227.3e6, "write": 54.1e6},      # algorithmic 220.0e6 / 52.0e6
+    "ragged-images": {"read": 12.80e9, "write": 2.22e9},   # algorithmic 12.21e9 / 2.21e9
+}
+
+
+def traffic(name: str):
+    t = TRAFFIC.get(name)
+    return None if t is None else t["read"] + t["write"]
 
 
 def encode_flops_per_patch(M: int, R: int, S: int, T: int, K: int) -> float:
@@ -204,7 +217,7 @@ def run_ragged(args, dev):
         "kernels_ms": {"project_images_mean": float(np.mean(kp)), "encode_mean": float(np.mean(ke))},
         "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
-                     "traffic": TRAFFIC.get(w["name"]), "algorithmic_flops_per_launch": flops,
+                     "traffic": traffic(w["name"]), "algorithmic_flops_per_launch": flops,
                      "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / FP32_MFMA_PEAK,
                      "tile": tile_used},
         "cpu_baseline": None,
@@ -342,6 +355,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", choices=["auto", "16", "32"], default="auto")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32",
+                    help="encoder correlation precision (16-bit forms re-score candidates in FP32)")
     ap.add_argument("--mode", choices=["encode", "copy"], default="encode",
                     help="copy: only a plain 1 GiB device copy, to calibrate byte counters")
     args = ap.parse_args()
@@ -374,7 +389,7 @@ def main():
     g = w["geom"]
     P = args.patches or w["P"]
     D = wl.draw_dictionary(w["M"], g.B)
-    h = rsc.rsc_create(g.N, g.S, g.T)
+    h = rsc.rsc_create(g.N, g.S, g.T, prec=args.prec)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
     rsc.rsc_set_tile(h, args.tile)
     X = make_inputs(h, w, P, dev)
@@ -413,6 +428,7 @@ def main():
     achieved = flops / (enc_ms.mean() * 1e-3)
     tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
     executed = mfma_pp * P / (enc_ms.mean() * 1e-3)
+    peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     out = {
         "metric": METRIC,
         "value": P / (ms * 1e-3),
@@ -427,21 +443,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: {P} {g.N}x{g.N} patches, M={w['M']}, K={K}, R={w['R']}, "
                                f"S={g.S}, T={g.T}, B={g.B}",
                    "P": P, "N": g.N, "S": g.S, "T": g.T, "M": w["M"], "K": K, "R": w["R"],
-                   "tile": args.tile},
+                   "tile": args.tile, "precision": args.prec},
         "kernels_ms": {"project_mean": float(proj_ms.mean()), "encode_mean": float(enc_ms.mean())},
-        "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
-                     "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_MFMA_PEAK, "traffic": TRAFFIC.get(w["name"]),
+        "roofline": {"kernel": "encode_kernel" if args.prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": traffic(w["name"]) if args.prec == "fp32" else None,
                      "algorithmic_flops_per_launch": flops,
-                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / FP32_MFMA_PEAK,
+                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / peak,
                      "tile": tile_used},
         "cpu_baseline": None,
     }
+    if args.prec != "fp32":
+        out["precision_stats"] = rsc.rsc_precision_stats(h)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(h, w, D, args.cpu_seconds, dev)
     print(json.dumps(out), flush=True)

@@ -54,8 +54,8 @@ typedef enum {
 
 typedef enum {
   RSC_FP32 = 0,            /* projection and correlation in FP32 on MFMA */
-  RSC_BF16 = 1,            /* projection and correlation operands in BF16, FP32 accumulation */
-  RSC_FP16 = 2             /* projection and correlation operands in FP16, FP32 accumulation */
+  RSC_BF16 = 1,            /* correlation operands in BF16, FP32 accumulation, FP32 re-score */
+  RSC_FP16 = 2             /* correlation operands in FP16, FP32 accumulation, FP32 re-score */
 } rsc_precision;
 
 /* Tile shape of the encoder (both give identical codes up to FP32 rounding order). */
@@ -87,7 +87,8 @@ typedef struct rsc_handle rsc_handle;
  *            centres[s] = (s+1) (N/2)/S
  *   sigma    profile width in pixels, or <= 0 for (N/2)/S (used only when
  *            centres is NULL or sigma > 0)
- *   prec     arithmetic of projection and correlation (rsc_precision)
+ *   prec     arithmetic of the encoder's correlation (rsc_precision); see
+ *            rsc_omp_encode for what the 16-bit forms compute
  *   out      receives the new handle
  * Errors: RSC_E_INVALID (bad sizes, null out, singular basis), RSC_E_UNSUPPORTED
  * (geometry or precision not compiled), RSC_E_NOMEM, RSC_E_DEVICE.
@@ -126,9 +127,11 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
  * angle grid size R.
  *   d_hat  HOST array [M, B] float32, packed hat coordinates, each row of unit
  *          Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID)
- *   M      1 <= M <= 256
- *   R      1 <= R <= 128
+ *   M      1 <= M <= 256 (BF16 / FP16 handles: M <= 128)
+ *   R      1 <= R <= 128 (BF16 / FP16 handles: R <= 64)
  * Synchronous (the copy to the device completes before return).
+ * Errors: RSC_E_INVALID (arguments), RSC_E_UNSUPPORTED (sizes beyond the compiled
+ * limits of the handle's precision, or tables beyond the 160 KiB LDS of a CU).
  */
 rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
 
@@ -151,7 +154,9 @@ rsc_status rsc_set_launch(rsc_handle* h, rsc_tile tile, int blocks_per_cu);
  * The encoder kernel rsc_omp_encode would run for K on this handle: its tile shape
  * (RSC_TILE_16 or RSC_TILE_32, after resolving RSC_TILE_AUTO and fallbacks) and the
  * matrix-core floating-point operations it executes per patch when all K steps run
- * (padding included).  Either output pointer may be NULL.
+ * (padding included).  Either output pointer may be NULL.  For BF16 / FP16 handles
+ * the count covers the 16-bit instructions only (the FP32 re-score of candidates
+ * depends on the data; see rsc_precision_stats) and the tile is RSC_TILE_32.
  */
 rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_flops_per_patch);
 
@@ -196,6 +201,14 @@ rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, flo
  *   coef         device [P, K] float32; empty slots 0
  *   resid2       device [P] float32 squared hat-domain residual norm, or NULL
  * Requires rsc_set_dictionary first (else RSC_E_INVALID).
+ *
+ * BF16 / FP16 handles: the correlations of every (atom, angle) are formed with
+ * 16-bit operands and FP32 accumulation; every atom whose 16-bit maximum over the
+ * angles lies within 4u ||residual|| of the largest one (u = 2^-8 for BF16, 2^-11
+ * for FP16) is re-scored over all angles in FP32, and the selection is taken from
+ * the FP32 scores.  The least squares run in FP32 while an upper bound on the
+ * condition number of the selected columns' Gram matrix, k ||L^{-1}||_F^2, stays
+ * <= 1e6; above it the patch's least squares are re-solved in FP64 from then on.
  */
 rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K,
                           int32_t* atom, int32_t* angle, float* coef, float* resid2,
@@ -267,6 +280,20 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
                                  const float* amplitude, const int32_t* centre, const int32_t* image,
                                  int64_t n_stamps, const int64_t* img_offset, const int32_t* H,
                                  const int32_t* W, int n_images, float* pixels, void* stream);
+
+/*
+ * Counters of the BF16 / FP16 encoder, accumulated over its launches on this handle
+ * (the FP32 re-scoring of candidates and the FP64 least-squares fallback described
+ * at rsc_omp_encode):
+ *   out[0]  pursuit steps (patch x step) that re-scored candidates
+ *   out[1]  candidates re-scored in FP32, summed over those steps
+ *   out[2]  largest number of candidates in one step
+ *   out[3]  steps whose least squares went to the FP64 solve
+ *   out     host [4] int64, or NULL; reset != 0 clears the counters after reading.
+ * Blocking: waits for the whole device first.  Launches that overlap the call may
+ * or may not be counted.  RSC_E_UNSUPPORTED for FP32 handles.
+ */
+rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset);
 
 /* Wait for all work on the stream; reports RSC_E_DEVICE for a failed kernel. */
 rsc_status rsc_sync(void* stream);

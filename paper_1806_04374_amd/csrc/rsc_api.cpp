@@ -58,6 +58,22 @@ rsc_status upload(X*& dst, const std::vector<X>& src, const char* what) {
   return RSC_OK;
 }
 
+// Round to the nearest BF16 / FP16 value (ties to even); returns the bit pattern.
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof(u));
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+uint16_t to_f16(float f) {
+  const _Float16 h = static_cast<_Float16>(f);
+  uint16_t r;
+  std::memcpy(&r, &h, sizeof(r));
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -72,7 +88,7 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
   if (!rsc::encode_supported(S, T))
     return fail(RSC_E_UNSUPPORTED, "(S, T) must be (5, 5) or (7, 7) in this build");
-  if (prec != RSC_FP32) return fail(RSC_E_UNSUPPORTED, "only RSC_FP32 is implemented");
+  if (prec != RSC_FP32 && prec != RSC_BF16 && prec != RSC_FP16) return fail(RSC_E_INVALID, "unknown precision");
   if (centres) {
     for (int s = 0; s < S; ++s)
       if (!std::isfinite(centres[s])) return fail(RSC_E_INVALID, "non-finite profile centre");
@@ -138,6 +154,7 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
   if (s == RSC_OK) s = upload(d.pinvI, pinvI, "image projection table");
   if (s == RSC_OK) s = upload(d.dpixI, dpixI, "image pixel table");
+  if (s == RSC_OK && prec != RSC_FP32) s = upload(d.lpStats, std::vector<unsigned long long>(4, 0ull), "counters");
   if (s != RSC_OK) {
     rsc_destroy(h);
     return s;
@@ -178,6 +195,12 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.dftA16s);
   free_dev(d.cs);
   free_dev(d.gramH);
+  free_dev(d.lpA);
+  free_dev(d.lpF16);
+  free_dev(d.lpF32);
+  free_dev(d.gramH64);
+  free_dev(d.cs64);
+  free_dev(d.lpStats);
   delete h;
   return ok();
 }
@@ -298,13 +321,16 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   // per-pair harmonic inner products in FP64: H_0 = sum_s a_s b_s (k = 0 block),
   // H_k = sum_s conj(a_k,s) b_k,s as (Re, Im) for k >= 1
   const int HQ = 2 * T + 1;
+  const bool lp = h->prec != RSC_FP32;
   std::vector<float> gramH(size_t(M) * M * HQ);
+  std::vector<double> gramH64(lp ? gramH.size() : 0);
   for (int a = 0; a < M; ++a)
     for (int bb = 0; bb < M; ++bb) {
       float* hh = &gramH[(size_t(a) * M + bb) * HQ];
       double h0 = 0.0;
       for (int s = 0; s < S; ++s) h0 += double(D(a, s)) * double(D(bb, s));
       hh[0] = float(h0);
+      if (lp) gramH64[(size_t(a) * M + bb) * HQ] = h0;
       for (int k = 1; k <= T; ++k) {
         const int base = S + 2 * S * (k - 1);
         double re = 0.0, im = 0.0;
@@ -316,13 +342,83 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
         }
         hh[2 * k - 1] = float(re);
         hh[2 * k] = float(im);
+        if (lp) {
+          gramH64[(size_t(a) * M + bb) * HQ + 2 * k - 1] = re;
+          gramH64[(size_t(a) * M + bb) * HQ + 2 * k] = im;
+        }
       }
     }
+  // 16-bit encoder tables
+  std::vector<uint16_t> lpA, lpF16;
+  std::vector<float> lpF32;
+  std::vector<double> cs64;
+  bool split = false;
+  if (lp) {
+    if (!rsc::encode_lp_supported(S, T, M, R))
+      return fail(RSC_E_UNSUPPORTED, "16-bit encoder: needs M <= 128 and R <= 64 in this build");
+    auto cvt = [&](float v) { return h->prec == RSC_BF16 ? to_bf16(v) : to_f16(v); };
+    // stage 1: lane l gives row l % 32 = (atom 4(row/8) + row%4, Re/Im = (row/4)%2) and
+    // contraction slots 8(l/32)..+7: the residual's harmonic-k block, Re parts (k = 0:
+    // even profiles) in the low half-wave, Im parts (k = 0: odd profiles) in the high
+    lpA.assign(size_t(NG) * NQ * 64 * 8, 0);
+    for (int g = 0; g < NG; ++g)
+      for (int k = 0; k < NQ; ++k)
+        for (int l = 0; l < 64; ++l) {
+          const int row = l % 32, hh = l / 32, a = 4 * (row / 8) + row % 4, part = (row / 4) % 2;
+          const int m = 16 * g + a;
+          for (int i = 0; i < 8; ++i) {
+            float v = 0.f;
+            if (k == 0) {
+              const int s = 2 * i + hh;
+              if (part == 0 && s < S) v = D(m, s);
+            } else if (i < S) {
+              const int base = S + 2 * S * (k - 1);
+              const float re = D(m, base + i), im = D(m, base + S + i);
+              v = part == 0 ? (hh == 0 ? re : im) : (hh == 0 ? -im : re);
+            }
+            lpA[((size_t(g) * NQ + k) * 64 + l) * 8 + i] = cvt(v);
+          }
+        }
+    const int RT = (R + 31) / 32;
+    // stage 2: row = angle 32t + l%32, slots k of the low half-wave cos(k theta),
+    // of the high half-wave -sin(k theta)
+    lpF16.assign(size_t(RT) * 64 * 8, 0);
+    for (int t = 0; t < RT; ++t)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 32 * t + l % 32, hh = l / 32;
+        if (r >= R) continue;
+        for (int k = 0; k < NQ; ++k) {
+          const float v = hh == 0 ? (k == 0 ? 1.f : cosk(k, r)) : (k == 0 ? 0.f : -sink(k, r));
+          lpF16[(size_t(t) * 64 + l) * 8 + k] = cvt(v);
+        }
+      }
+    // FP32 re-score operand: radix-2 split (rows r < R/2) for even R in 33..64, else
+    // RT tiles of the direct DFT; contraction lanes (cos, -sin), (1, 0) for k = 0
+    split = R % 2 == 0 && R > 32;
+    const int FT = split ? 1 : RT, rows = split ? R / 2 : R;
+    lpF32.assign(size_t(FT) * NQ * 64, 0.f);
+    for (int t = 0; t < FT; ++t)
+      for (int l = 0; l < 64; ++l) {
+        const int r = 32 * t + l % 32, hh = l / 32;
+        if (r >= rows) continue;
+        for (int k = 0; k < NQ; ++k)
+          lpF32[(size_t(t) * NQ + k) * 64 + l] = hh == 0 ? (k == 0 ? 1.f : cosk(k, r)) : (k == 0 ? 0.f : -sink(k, r));
+      }
+    cs64.resize(cs.size());
+    for (int k = 0; k < NQ; ++k)
+      for (int r = 0; r < R; ++r) {
+        cs64[size_t(k) * R + r] = std::cos(two_pi * double(k) * double(r) / double(R));
+        cs64[size_t(NQ + k) * R + r] = std::sin(two_pi * double(k) * double(r) / double(R));
+      }
+  }
   d.M = M;
   d.R = R;
   d.NG = NG;
+  d.lpSplit = split;
   h->has_dict = false;
-  if (rsc::encode_lds_bytes(d, RSC_TILE_16) > 160 * 1024)
+  if (lp && rsc::encode_lp_lds_bytes(d) > 160 * 1024)
+    return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
+  if (!lp && rsc::encode_lds_bytes(d, RSC_TILE_16) > 160 * 1024)
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
   rsc_status s = upload(d.dictA, dictA, "dictionary operand");
   if (s == RSC_OK) s = upload(d.dictHat, hat, "dictionary");
@@ -331,6 +427,11 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   if (s == RSC_OK) s = upload(d.dftA16s, dftA16s, "angle DFT operand");
   if (s == RSC_OK) s = upload(d.cs, cs, "steering table");
   if (s == RSC_OK) s = upload(d.gramH, gramH, "pair table");
+  if (s == RSC_OK) s = upload(d.lpA, lpA, "16-bit dictionary operand");
+  if (s == RSC_OK) s = upload(d.lpF16, lpF16, "16-bit angle DFT operand");
+  if (s == RSC_OK) s = upload(d.lpF32, lpF32, "angle DFT operand");
+  if (s == RSC_OK) s = upload(d.gramH64, gramH64, "FP64 pair table");
+  if (s == RSC_OK) s = upload(d.cs64, cs64, "FP64 steering table");
   h->has_dict = s == RSC_OK;
   return s == RSC_OK ? ok() : s;
 }
@@ -362,8 +463,13 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   if (P < 1 || !xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "need a non-empty sample");
   if (reps < 1 || reps > 100) return fail(RSC_E_INVALID, "reps must be in 1..100");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  int tiles[2] = {RSC_TILE_16, RSC_TILE_32};
-  const int ntiles = rsc::tile32_usable(h->dev, K) ? 2 : 1;
+  const bool lp = h->prec != RSC_FP32;
+  int tiles[2] = {lp ? RSC_TILE_32 : RSC_TILE_16, RSC_TILE_32};
+  const int ntiles = (!lp && rsc::tile32_usable(h->dev, K)) ? 2 : 1;
+  auto run = [&](int tile) {
+    return lp ? rsc::launch_encode_lp(h->dev, h->prec, xhat, P, K, atom, angle, coef, nullptr, stream)
+              : rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, nullptr, stream);
+  };
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(RSC_E_DEVICE, "hipEventCreate failed");
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -377,12 +483,12 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   for (int ti = 0; ti < ntiles && status == RSC_OK; ++ti) {
     for (int bpc = 1; bpc <= 4 && status == RSC_OK; ++bpc) {
       h->dev.enc_bpc = bpc;
-      int e = rsc::launch_encode(h->dev, tiles[ti], xhat, P, K, atom, angle, coef, nullptr, stream);
+      int e = run(tiles[ti]);
       if (e) { status = device_fail(e, "autotune launch"); break; }
       std::vector<float> ms(reps);
       for (int r = 0; r < reps && status == RSC_OK; ++r) {
         if (hipEventRecord(e0, st) != hipSuccess) { status = fail(RSC_E_DEVICE, "event record"); break; }
-        e = rsc::launch_encode(h->dev, tiles[ti], xhat, P, K, atom, angle, coef, nullptr, stream);
+        e = run(tiles[ti]);
         if (e) { status = device_fail(e, "autotune launch"); break; }
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms[r], e0, e1) != hipSuccess) {
@@ -422,6 +528,11 @@ rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_f
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  if (h->prec != RSC_FP32) {
+    if (tile) *tile = RSC_TILE_32;
+    if (mfma_flops_per_patch) *mfma_flops_per_patch = rsc::encode_lp_mfma_flops_per_patch(h->dev, K);
+    return ok();
+  }
   const int t = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
   if (tile) *tile = t;
   if (mfma_flops_per_patch) *mfma_flops_per_patch = rsc::encode_mfma_flops_per_patch(h->dev, t, K);
@@ -453,6 +564,10 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
   if (!xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "null device pointer");
+  if (h->prec != RSC_FP32) {
+    int e = rsc::launch_encode_lp(h->dev, h->prec, xhat, P, K, atom, angle, coef, resid2, stream);
+    return e ? device_fail(e, "encode launch") : ok();
+  }
   const int tile = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
   int e = rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, resid2, stream);
   return e ? device_fail(e, "encode launch") : ok();
@@ -523,6 +638,24 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
   int e = rsc::launch_stamps(h->dev, atom, theta, amplitude, centre, image, n_stamps, img_offset, H, W,
                              n_images, pixels, stream);
   return e ? device_fail(e, "stamp launch") : ok();
+}
+
+rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (h->prec == RSC_FP32 || !h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "FP32 handles keep no counters");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return device_fail(int(e), "device synchronize");
+  unsigned long long v[4];
+  e = hipMemcpy(v, h->dev.lpStats, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(int(e), "counter read");
+  if (out)
+    for (int i = 0; i < 4; ++i) out[i] = int64_t(v[i]);
+  if (reset) {
+    e = hipMemset(h->dev.lpStats, 0, sizeof(v));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return device_fail(int(e), "counter reset");
+  }
+  return ok();
 }
 
 rsc_status rsc_sync(void* stream) {

@@ -31,6 +31,7 @@
 
 #include "rsc_device.h"
 #include "rsc_internal.h"
+#include "rsc_launch.h"
 
 namespace rsc {
 namespace {
@@ -406,38 +407,6 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
 }
 
 // ============================================================== launchers
-int num_cus() {
-  static int cached = -1;
-  if (cached < 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      n = 256;
-    cached = n;
-  }
-  return cached;
-}
-
-// Persistent grid: at most as many blocks as fit on the device at once; each wave
-// then walks the patch tiles with a stride of the whole grid.
-template <class Kern, class... Args>
-int launch_persistent(Kern kern, size_t lds, int64_t wave_tiles, int bpc, hipStream_t st, Args... args) {
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return int(e);
-  }
-  int64_t blocks = (wave_tiles + 3) / 4;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  if (bpc > 0 && bpc < per_cu) per_cu = bpc;
-  const int64_t cap = int64_t(num_cus()) * per_cu;
-  if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(256), lds, st, args...);
-  return int(hipGetLastError());
-}
-
 template <int S, int T, int KMAX>
 int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
   return launch_persistent(encode32_kernel<S, T, KMAX>, encode_lds_bytes(t, RSC_TILE_32), (prm.P + 31) / 32,

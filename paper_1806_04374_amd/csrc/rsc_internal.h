@@ -46,6 +46,15 @@ struct DeviceTables {
   float* dftA16s = nullptr;  // 16x16-tile stage-2 operand, parity split [ceil(R/32)->1,2,4][E+O steps][64]
   float* cs = nullptr;       // [2][T+1][R]: cos, then sin, of 2 pi k r / R
   float* gramH = nullptr;    // [M][M][2T+1]: per-atom-pair harmonic inner products (see pair_gram)
+  // 16-bit encoder (BF16 / FP16 handles)
+  uint16_t* lpA = nullptr;   // stage-1 operand [NG][T+1][64][8]
+  uint16_t* lpF16 = nullptr; // stage-2 operand [ceil(R/32)][64][8]
+  float* lpF32 = nullptr;    // FP32 re-score angle DFT operand: [T+1][64] rows r < R/2 when
+                             // lpSplit, else [ceil(R/32)][T+1][64]
+  bool lpSplit = false;      // even R in 33..64: radix-2 split in the FP32 re-score
+  double* gramH64 = nullptr; // FP64 pair table [M][M][2T+1]
+  double* cs64 = nullptr;    // FP64 [2][T+1][R] cos, sin
+  unsigned long long* lpStats = nullptr;  // [4] counters (rsc_precision_stats)
 };
 
 // Kernel launchers.  Return a hipError_t as int.
@@ -60,6 +69,11 @@ size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
+bool encode_lp_supported(int S, int T, int M, int R);
+size_t encode_lp_lds_bytes(const DeviceTables& t);
+double encode_lp_mfma_flops_per_patch(const DeviceTables& t, int K);
+int launch_encode_lp(const DeviceTables& t, int prec, const float* xhat, int64_t P, int K, int32_t* atom,
+                     int32_t* angle, float* coef, float* resid2, void* stream);
 size_t images_workspace_bytes(int n_images);
 int launch_project_images(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
                           const int32_t* H, const int32_t* W, int n, int64_t P_total, void* ws, float* xhat,

@@ -60,6 +60,7 @@ def lib():
         "rsc_images_workspace_size": [I, P],
         "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
         "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
+        "rsc_precision_stats": [P, P, I],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -346,6 +347,13 @@ def rsc_synthesize_images(h: Handle, batch: "ImageBatch", atom, theta, amplitude
                                        _ptr(image), n, _ptr(batch.d_offset), _ptr(batch.d_H),
                                        _ptr(batch.d_W), batch.n, _ptr(pixels), _stream(stream)))
     return pixels
+
+
+def rsc_precision_stats(h: Handle, reset: bool = False) -> dict:
+    """Counters of a BF16 / FP16 handle's encoder (blocking)."""
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().rsc_precision_stats(h.ptr, out, 1 if reset else 0))
+    return {"steps_rescored": out[0], "candidates": out[1], "max_candidates": out[2], "fp64_solves": out[3]}
 
 
 def rsc_sync(stream=None):

@@ -68,7 +68,8 @@ def test_argument_errors_without_device(L):
     assert b"odd" in L.rsc_last_error()
     assert L.rsc_create(11, 4, 4, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED
     assert L.rsc_create(11, 5, 5, None, 0.0, 0, None) == rsc.RSC_E_INVALID
-    assert L.rsc_create(11, 5, 5, None, 0.0, 7, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED
+    assert L.rsc_create(11, 5, 5, None, 0.0, 7, ctypes.byref(h)) == rsc.RSC_E_INVALID
+    assert L.rsc_precision_stats(None, None, 0) == rsc.RSC_E_INVALID
     assert L.rsc_set_dictionary(None, None, 4, 8) == rsc.RSC_E_INVALID
     assert L.rsc_project(None, None, 10, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_omp_encode(None, None, 10, 2, None, None, None, None, None) == rsc.RSC_E_INVALID

@@ -1,0 +1,207 @@
+"""BF16 / FP16 encoders against the FP64 reference, through the C ABI.
+
+The 16-bit correlation only proposes candidates: the selection is taken from FP32
+scores, the least squares run in FP32 (FP64 where the Gram matrix of the selected
+columns is ill-conditioned).  So the acceptance is the FP32 path's: selected
+(atom, angle) sets agree on >= 99.9% of patches, matched coefficients within 1e-4
+relative, reconstruction MSE within 1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import rsc_oracle as orc
+from paper_1806_04374_amd import workloads as wl
+from tests.parity import compare_codes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MATCH = 0.999
+COEF_REL = 1e-4
+MSE_REL = 1e-3
+PRECS = ["bf16", "fp16"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_04374_amd import rsc
+    rsc.lib()
+    return torch.device("cuda:0")
+
+
+def _handle(geom, D, R, prec):
+    from paper_1806_04374_amd import rsc
+    h = rsc.rsc_create(geom.N, geom.S, geom.T, prec=prec)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    return h
+
+
+def _run(h, X32, K, dev):
+    from paper_1806_04374_amd import rsc
+    xh = rsc.rsc_project(h, torch.from_numpy(X32).to(dev))
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, xh, K)
+    torch.cuda.synchronize()
+    return atom, angle, coef, r2
+
+
+def _check(label, X32, D, R, K, geom, dev, prec, basis=None):
+    from paper_1806_04374_amd import rsc
+    basis = basis or orc.build_basis(geom.N, geom.S, geom.T)
+    h = _handle(geom, D, R, prec)
+    rsc.rsc_precision_stats(h, reset=True)
+    atom, angle, coef, r2 = _run(h, X32, K, dev)
+    stats = rsc.rsc_precision_stats(h)
+    _, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    print(label, prec, rep, stats, flush=True)
+    assert rep.match_rate >= MATCH, (label, prec, str(rep))
+    assert rep.coef_bad <= int((1 - MATCH) * rep.n), (label, prec, str(rep))
+    rec = rsc.rsc_reconstruct(h, atom, angle, coef)
+    torch.cuda.synchronize()
+    mse_gpu = orc.mse(basis, X32, rec.cpu().numpy().astype(np.float64))
+    mse_ref = orc.mse(basis, X32, orc.reconstruct(basis, D, R, code))
+    print(label, prec, "mse", mse_gpu, mse_ref, flush=True)
+    assert abs(mse_gpu - mse_ref) <= MSE_REL * mse_ref + 1e-12, (label, prec)
+    # every pursuit step that ran re-scored at least one candidate
+    steps = int((code.atom >= 0).sum())
+    assert stats["steps_rescored"] >= steps * MATCH, (stats, steps)
+    assert stats["candidates"] >= stats["steps_rescored"]
+    h.close()
+    return rep, stats
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_small_plain_workload(dev, prec):
+    """2,000 11x11 patches, M=16, K=2, R=32 (the small plain workload), 16-bit correlation."""
+    w = wl.SMALL
+    g = w["geom"]
+    basis = orc.build_basis(g.N, g.S, g.T)
+    D, d = wl.small_draw()
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    _check("small", X, D, w["R"], w["K"], g, dev, prec, basis)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_scale_workload_slice(dev, prec):
+    """Scale geometry (M=64, K=4, R=64) on 20,011 patches: many tiles and a ragged tail."""
+    w = wl.SCALE
+    g = w["geom"]
+    basis = orc.build_basis(g.N, g.S, g.T)
+    D, d = wl.scale_draw(P=20011)
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    _, stats = _check("scale-20011", X, D, w["R"], w["K"], g, dev, prec, basis)
+    # the window keeps few candidates per step on this workload
+    assert stats["candidates"] <= 3 * stats["steps_rescored"], stats
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_geometry15(dev, prec):
+    """15x15 patches, S = T = 7, M = 128, K = 6, R = 64, 3,001 patches."""
+    g = wl.GEOM15
+    basis = orc.build_basis(g.N, g.S, g.T)
+    M, K, R = 128, 6, 64
+    D = wl.draw_dictionary(M, g.B, seed=3)
+    d = wl.draw_mixtures(3001, g.N, M, 4, 0.05, seed=3)
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    _check("geom15", X, D, R, K, g, dev, prec, basis)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,R,K", [(40, 17, 3), (16, 50, 8), (7, 32, 1), (128, 64, 4), (1, 1, 2)])
+def test_uneven_shapes(dev, prec, M, R, K):
+    """A partial atom group, odd and ragged angle counts, K = 1 and 8, M = 1."""
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    D = wl.draw_dictionary(M, g.B, seed=11 + M)
+    d = wl.draw_mixtures(1537, g.N, M, 3, 0.05, seed=11 + R)
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    _check(f"M{M}-R{R}-K{K}", X, D, R, K, g, dev, prec, basis)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_exact_sparse_recovery(dev, prec):
+    """Noise-free patches of 2 grid-rotated atoms: the supports and the coefficients
+    come back exactly (the pursuit stops on the residual threshold)."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    D, d = wl.small_draw(P=999)
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, 0 * d.noise).astype(np.float32)
+    h = _handle(g, D, 32, prec)
+    atom, angle, coef, r2 = _run(h, X, 3, dev)
+    _, code = orc.encode(basis, D, 32, X.astype(np.float64), 3)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    print("exact", prec, rep, flush=True)
+    assert rep.match_rate >= MATCH, str(rep)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fp64_fallback_on_ill_conditioned_gram(dev, prec):
+    """Two atoms 1e-3 apart (R = 1): once both are selected the Gram matrix has
+    cond ~ 4e6, beyond the FP32 bound, so the least squares are re-solved in FP64;
+    the coefficients then match the reference's QR solve."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    rng = np.random.default_rng(5)
+    d1 = rng.standard_normal(g.B)
+    d1 /= np.linalg.norm(d1)
+    n = rng.standard_normal(g.B)
+    n -= (n @ d1) * d1
+    d2 = d1 + 1e-3 * n / np.linalg.norm(n)
+    d2 /= np.linalg.norm(d2)
+    # FP32-representable rows, used as they are on both sides
+    D = np.stack([d1, d2]).astype(np.float32).astype(np.float64)
+    P = 200
+    # magnitudes 0.5..1.5 keep the one-step residual (~1e-3 |w|) far above the stopping
+    # threshold, so both columns are always selected whichever of the two (a near tie)
+    # comes first
+    w = rng.uniform(0.5, 1.5, (P, 2)) * rng.choice([-1.0, 1.0], (P, 2))
+    # coordinates handed over directly (a projection's FP32 rounding would be amplified
+    # ~1e3 times by this Gram matrix on both sides alike)
+    xh = (w @ D).astype(np.float32)
+    h = _handle(g, D, 1, prec)
+    rsc.rsc_precision_stats(h, reset=True)
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, torch.from_numpy(xh).to(dev), 2)
+    torch.cuda.synchronize()
+    stats = rsc.rsc_precision_stats(h)
+    code = orc.omp(orc.augmented_dictionary(D, 1, g.S, g.T), xh.astype(np.float64), 2, 2)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    print("fp64-fallback", prec, rep, stats, flush=True)
+    assert stats["fp64_solves"] >= P * MATCH, stats
+    assert rep.match_rate >= MATCH, str(rep)
+    assert rep.coef_bad <= int((1 - MATCH) * P), str(rep)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_limits_and_edge_cases(dev, prec):
+    """Sizes beyond the 16-bit encoder's limits are refused; empty input is a no-op;
+    one patch and 33 patches (a tile and one lane) give the reference's codes."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    D = wl.draw_dictionary(200, g.B, seed=1)
+    h = rsc.rsc_create(g.N, g.S, g.T, prec=prec)
+    with pytest.raises(rsc.RscError) as e:
+        rsc.rsc_set_dictionary(h, D.astype(np.float32), 32)
+    assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    with pytest.raises(rsc.RscError) as e:
+        rsc.rsc_set_dictionary(h, D[:16].astype(np.float32), 100)
+    assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    h.close()
+    basis = orc.build_basis(g.N, g.S, g.T)
+    Dm, d = wl.small_draw(P=33)
+    X = orc.synthesize(basis, Dm, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    h = _handle(g, Dm, 32, prec)
+    xh = torch.empty((0, g.B), dtype=torch.float32, device=dev)
+    out = rsc.rsc_omp_encode(h, xh, 2)
+    assert out[0].shape == (0, 2)
+    for n in (1, 33):
+        atom, angle, coef, _ = _run(h, X[:n], 2, dev)
+        _, code = orc.encode(basis, Dm, 32, X[:n].astype(np.float64), 2)
+        rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+        assert rep.matched == n, str(rep)
+    h.close()
