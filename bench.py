@@ -309,6 +309,123 @@ def run_serving(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def _timed_runs(h, X, xh, outs, K, n, warmup, stream):
+    """n timed (project + encode) runs on one stream; per-run ms from HIP events."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    for _ in range(warmup):
+        rsc.rsc_project(h, X, xh, stream=stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        rsc.rsc_project(h, X, xh, stream=stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def run_precision(args, dev):
+    """FP32, BF16 and FP16 encoders on the same inputs: the small plain workload
+    (2,000 patches, latency over >= 100 runs) and the 10^6-patch scale workload
+    (throughput), with each form's codes checked against the FP64 reference in the
+    CPU baseline leg."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    precs = ["fp32", "bf16", "fp16"]
+    res = {"small": {}, "scale": {}}
+    codes = {"small": {}, "scale": {}}
+    inputs = {}
+    stream = torch.cuda.current_stream()
+    for name, w, runs in (("small", wl.SMALL, max(args.steps, 100)), ("scale", wl.SCALE, max(args.steps, 20))):
+        g = w["geom"]
+        K = w["K"]
+        D = wl.draw_dictionary(w["M"], g.B)
+        P = w["P"]
+        X = None
+        for prec in precs:
+            h = rsc.rsc_create(g.N, g.S, g.T, prec=prec)
+            rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+            if X is None:
+                X = make_inputs(h, w, P, dev)
+            xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+            outs = (torch.empty((P, K), dtype=torch.int32, device=dev), torch.empty((P, K), dtype=torch.int32, device=dev),
+                    torch.empty((P, K), dtype=torch.float32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev))
+            ms = _timed_runs(h, X, xh, outs, K, runs, args.warmup, stream)
+            p50 = float(np.percentile(ms, 50))
+            res[name][prec] = {"p50_ms": p50, "p99_ms": float(np.percentile(ms, 99)), "runs": int(runs),
+                               "patches_per_s_p50": P / (p50 * 1e-3)}
+            if prec != "fp32":
+                res[name][prec]["stats_per_run"] = {k: v / (runs + args.warmup)
+                                                    for k, v in rsc.rsc_precision_stats(h).items()}
+            n_check = P if name == "small" else min(P, args.check_patches)
+            rec = rsc.rsc_reconstruct(h, outs[0][:n_check], outs[1][:n_check], outs[2][:n_check])
+            torch.cuda.synchronize()
+            codes[name][prec] = tuple(t[:n_check].cpu().numpy() for t in outs[:3]) + (rec.cpu().numpy(),)
+            h.close()
+        inputs[name] = (w, D, X[: (w["P"] if name == "small" else min(w["P"], args.check_patches))].cpu().numpy())
+        for prec in precs:
+            res[name][prec]["speedup_vs_fp32"] = res[name]["fp32"]["p50_ms"] / res[name][prec]["p50_ms"]
+    best = max(("bf16", "fp16"), key=lambda q: res["scale"][q]["patches_per_s_p50"])
+    out = {
+        "metric": METRIC, "value": res["scale"][best]["patches_per_s_p50"], "unit": "patches/s", "n_gpus": 1,
+        "steps": int(res["scale"][best]["runs"]), "warmup": args.warmup, "ms_per_step": res["scale"][best]["p50_ms"],
+        "p50_ms": res["scale"][best]["p50_ms"], "p99_ms": res["scale"][best]["p99_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
+        "config": {"workload": f"precision forms: scale-fp32 inputs (10^6 11x11 patches, M=64, K=4, R=64) in "
+                               f"{best}; small-fp32 inputs (2,000 patches, M=16, K=2, R=32) for latency",
+                   "precision": best},
+        "precision": res,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline_precision(inputs, codes)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_precision(inputs, codes):
+    """FP64 reference on the small inputs (all 2,000) and a prefix of the scale inputs:
+    its time, and each precision form's errors against it."""
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    from tests.parity import compare_codes
+    errors = {}
+    timing = {}
+    for name, (w, D, X) in inputs.items():
+        g = w["geom"]
+        basis = orc.build_basis(g.N, g.S, g.T)
+        t0 = time.perf_counter()
+        _, code = orc.encode(basis, D, w["R"], X.astype(np.float64), w["K"])
+        timing[name] = (len(X), time.perf_counter() - t0)
+        mse_ref = orc.mse(basis, X, orc.reconstruct(basis, D, w["R"], code))
+        errors[name] = {}
+        for prec, (atom, angle, coef, rec) in codes[name].items():
+            rep = compare_codes(atom, angle, coef, code, 1e-4)
+            errs = []
+            for p in range(len(X)):
+                o = {(int(a), int(r)): float(c) for a, r, c in zip(code.atom[p], code.angle[p], code.coef[p]) if a >= 0}
+                gg = {(int(a), int(r)): float(c) for a, r, c in zip(atom[p], angle[p], coef[p]) if a >= 0}
+                if set(o) == set(gg) and o:
+                    sc = max(abs(v) for v in o.values())
+                    errs.append(max(abs(gg[k] - v) / max(abs(v), 1e-3 * sc) for k, v in o.items()))
+            errs = np.array(errs) if errs else np.zeros(1)
+            mse_dev = orc.mse(basis, X, rec.astype(np.float64))
+            errors[name][prec] = {"patches": len(X), "selection_match": rep.match_rate,
+                                  "coef_rel_err_median": float(np.median(errs)),
+                                  "coef_rel_err_p99": float(np.percentile(errs, 99)),
+                                  "coef_rel_err_max": float(errs.max()),
+                                  "mse_device": mse_dev, "mse_oracle": mse_ref,
+                                  "mse_rel_diff": abs(mse_dev - mse_ref) / mse_ref}
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    n, dt = timing["scale"]
+    base = {"value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} patches of the scale inputs (FP64 reference, {dt:.1f} s); "
+                      f"small inputs: {timing['small'][0]} patches in {timing['small'][1]:.2f} s"}
+    return base, errors
+
+
 def cpu_baseline_ragged(h, w, D, target_s, dev):
     """FP64 reference on windows of the first image (reference-synthesized pixels)."""
     import torch
@@ -345,7 +462,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving"], default="scale")
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision"], default="scale")
+    ap.add_argument("--check-patches", type=int, default=50_000,
+                    help="precision: scale-workload patches checked against the reference")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for request pixels")
@@ -384,6 +503,9 @@ def main():
         return
     if args.workload == "serving":
         run_serving(args, dev)
+        return
+    if args.workload == "precision":
+        run_precision(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

@@ -74,6 +74,19 @@ uint16_t to_f16(float f) {
   return r;
 }
 
+float from_bf16(uint16_t b) {
+  const uint32_t u = uint32_t(b) << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof(f));
+  return f;
+}
+
+float from_f16(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, sizeof(h));
+  return float(h);
+}
+
 }  // namespace
 
 extern "C" {
@@ -154,7 +167,39 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
   if (s == RSC_OK) s = upload(d.pinvI, pinvI, "image projection table");
   if (s == RSC_OK) s = upload(d.dpixI, dpixI, "image pixel table");
+  d.prec = prec;
   if (s == RSC_OK && prec != RSC_FP32) s = upload(d.lpStats, std::vector<unsigned long long>(4, 0ull), "counters");
+  if (s == RSC_OK && prec != RSC_FP32 && b.B <= 64) {
+    // compensated 16-bit projection operand: pinv split into 16-bit parts, each the
+    // rounding of what the previous parts leave (3 parts for BF16, 2 for FP16)
+    const int KS = (b.n_pix + 15) / 16, NP = prec == RSC_BF16 ? 3 : 2;
+    const size_t part = size_t(2) * KS * 64 * 8;
+    // FP16: operand scaled by 2^sh so that its largest entry lies in [2^10, 2^11)
+    double amax = 0.0;
+    for (double v : b.pinv) amax = std::max(amax, std::fabs(v));
+    int ex = 0;
+    (void)std::frexp(amax, &ex);
+    const int sh = (prec == RSC_FP16 && amax > 0.0) ? 11 - ex : 0;
+    d.lpPinvUnscale = float(std::ldexp(1.0, -sh));
+    std::vector<uint16_t> pp(NP * part, 0);
+    std::vector<int> pix16(size_t(16) * KS, -1);
+    for (int i = 0; i < b.n_pix; ++i) pix16[i] = b.pix[i];
+    for (int t = 0; t < 2; ++t)
+      for (int j = 0; j < KS; ++j)
+        for (int l = 0; l < 64; ++l)
+          for (int i = 0; i < 8; ++i) {
+            const int row = 32 * t + l % 32, px = 16 * j + 8 * (l / 32) + i;
+            if (row >= b.B || px >= b.n_pix) continue;
+            double rem = std::ldexp(b.pinv[size_t(row) * NN + b.pix[px]], sh);
+            for (int q = 0; q < NP; ++q) {
+              const uint16_t hb = prec == RSC_BF16 ? to_bf16(float(rem)) : to_f16(float(rem));
+              pp[q * part + ((size_t(t) * KS + j) * 64 + l) * 8 + i] = hb;
+              rem -= prec == RSC_BF16 ? double(from_bf16(hb)) : double(from_f16(hb));
+            }
+          }
+    s = upload(d.lpPinv, pp, "16-bit projection table");
+    if (s == RSC_OK) s = upload(d.lpPix16, pix16, "pixel table");
+  }
   if (s != RSC_OK) {
     rsc_destroy(h);
     return s;
@@ -201,6 +246,8 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.gramH64);
   free_dev(d.cs64);
   free_dev(d.lpStats);
+  free_dev(d.lpPinv);
+  free_dev(d.lpPix16);
   delete h;
   return ok();
 }

@@ -35,59 +35,10 @@
 #include "rsc_device.h"
 #include "rsc_internal.h"
 #include "rsc_launch.h"
+#include "rsc_lp.h"
 
 namespace rsc {
 namespace {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-template <int PREC>
-struct Lp;
-
-template <>
-struct Lp<RSC_BF16> {
-  using V8 = bf16x8;
-  using V2 = bf16x2;
-  static constexpr float unit = 0x1p-8f;
-  __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-template <>
-struct Lp<RSC_FP16> {
-  using V8 = f16x8;
-  using V2 = f16x2;
-  static constexpr float unit = 0x1p-11f;
-  __device__ static f32x16 mfma(V8 a, V8 b, f32x16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-  }
-};
-
-// Two floats rounded to the 16-bit format (round to nearest even), packed into
-// one 32-bit register (x in the low half).
-template <class P>
-__device__ __forceinline__ unsigned pack2(float x, float y) {
-  return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{x, y}, typename P::V2));
-}
-
-// Eight floats rounded to the 16-bit format (round to nearest even), packed.
-template <class P>
-__device__ __forceinline__ typename P::V8 pack8(const float (&v)[8]) {
-  typename P::V8 r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const typename P::V2 h = __builtin_convertvector(f32x2{v[2 * i], v[2 * i + 1]}, typename P::V2);
-    r[2 * i] = h[0];
-    r[2 * i + 1] = h[1];
-  }
-  return r;
-}
 
 struct LpParams {
   const float* xhat;

@@ -31,6 +31,7 @@ constexpr int stage1_steps(int S, int T) { return k0_steps(S) + T * S; }
 // Device tables owned by a handle (FP32 operand arrangements built on the host).
 struct DeviceTables {
   int N = 0, S = 0, T = 0, B = 0, n_pix = 0;
+  int prec = RSC_FP32;       // rsc_precision of the handle
   int M = 0, R = 0, NG = 0;
   int enc_bpc = 0;           // encoder blocks per CU (0: as many as fit)
   float* pinvA = nullptr;    // projection operand over the grid [RTB][ceil(N*N/2)][64]
@@ -55,6 +56,12 @@ struct DeviceTables {
   double* gramH64 = nullptr; // FP64 pair table [M][M][2T+1]
   double* cs64 = nullptr;    // FP64 [2][T+1][R] cos, sin
   unsigned long long* lpStats = nullptr;  // [4] counters (rsc_precision_stats)
+  // compensated 16-bit projection (N = 11): 3 (BF16) or 2 (FP16) 16-bit parts of the
+  // operand over disk pixels [parts][2][ceil(n_pix/16)][64][8], and the grid index of
+  // disk pixel i [16 ceil(n_pix/16)]
+  uint16_t* lpPinv = nullptr;
+  int* lpPix16 = nullptr;
+  float lpPinvUnscale = 1.f;  // 2^-s where the operand parts hold 2^s (Phi^T Phi)^{-1} Phi^T
 };
 
 // Kernel launchers.  Return a hipError_t as int.

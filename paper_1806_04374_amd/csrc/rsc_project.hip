@@ -4,19 +4,41 @@
 // contraction over disk pixels.
 //
 //  * project_tiled_kernel (N*N <= 128): one block of 8 waves per CU loops over
-//    tiles of 8 x 32 patches.  Each wave copies its 32 contiguous patches to LDS
-//    with 16-byte loads, the (Phi^T Phi)^{-1} Phi^T operand stays in LDS for the
-//    whole launch, and the results leave through LDS as contiguous 16-byte stores.
+//    tiles of 8 x 32 patches.  Each wave copies its 32 contiguous patches to its
+//    own LDS tile with 16-byte loads, the (Phi^T Phi)^{-1} Phi^T operand stays in
+//    LDS for the whole launch, and the results leave through the same tile as
+//    contiguous 16-byte stores; the waves need no block-wide barrier.
+//  * project_tiled_lp_kernel: the same tiling (6 waves per block) with 16-bit MFMA
+//    operands (v_mfma_f32_32x32x16_{bf16,f16}, contraction over 16 disk pixels per
+//    step) in compensated form: the patch values and the operand are split into
+//    16-bit parts and the products down to FP32 order are accumulated in FP32 --
+//    FP16: x = hi + lo, hi*hi + hi*lo + lo*hi; BF16: x = hi + mid + lo,
+//    hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid.  This keeps the coordinates
+//    at FP32 accuracy; a single 16-bit product would be amplified by the basis'
+//    conditioning.  FP16 has a narrow exponent range, so each patch is first scaled
+//    by a power of two that puts its largest value in [2^10, 2^11) (the operand is
+//    pre-scaled the same way on the host), keeping the remainders normal; the
+//    scales are exact and removed per column after the accumulation.
 //  * project_kernel (any size): blocks of 64 patches, operand read from global.
 #include <hip/hip_runtime.h>
 
 #include "rsc_device.h"
 #include "rsc_internal.h"
+#include "rsc_lp.h"
 
 namespace rsc {
 namespace {
 
 constexpr int kProjWaves = 8;
+
+// Orders a wave's LDS accesses to its own tile (waits for its LDS operations; no
+// block-wide barrier, so the waves of a block run their load / compute / store
+// phases independently).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // pinvD: [2][KPD][64] operand over disk pixels (contraction index 2j + u is disk
 // pixel 2j+u in row-major order); pix: [2*KPD] grid index of each disk pixel or -1.
@@ -51,7 +73,7 @@ __global__ __launch_bounds__(512) void project_tiled_kernel(const float* __restr
     } else {
       for (int i = lane; i < 32 * NN; i += 64) tile[i] = i < np * NN ? src[i] : 0.f;
     }
-    __syncthreads();
+    wave_lds_fence();
     f32x16 acc0, acc1;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc0[i] = acc1[i] = 0.f;
@@ -63,14 +85,14 @@ __global__ __launch_bounds__(512) void project_tiled_kernel(const float* __restr
       acc0 = mfma32(sA[j * 64 + lane], b, acc0);
       acc1 = mfma32(sA[(KPD + j) * 64 + lane], b, acc1);
     }
-    __syncthreads();
+    wave_lds_fence();
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int c0 = 8 * (v / 4) + 4 * u + (v % 4);
       tile[col * B + c0] = acc0[v];
       if (32 + c0 < B) tile[col * B + 32 + c0] = acc1[v];
     }
-    __syncthreads();
+    wave_lds_fence();
     float* dst = xhat + p0 * B;
     if (np == 32 && vec_out) {
       const float4* s4 = reinterpret_cast<const float4*>(tile);
@@ -79,7 +101,129 @@ __global__ __launch_bounds__(512) void project_tiled_kernel(const float* __restr
     } else {
       for (int i = lane; i < np * B; i += 64) dst[i] = tile[i];
     }
-    __syncthreads();
+    wave_lds_fence();
+  }
+}
+
+constexpr int kProjWavesLp = 6;
+
+// pinvP: NP parts of the operand, each [2][KS][64] x 8 16-bit (NP = 3 for BF16: hi,
+// mid, lo; NP = 2 for FP16: hi, lo); lane l gives row 32t + l%32 and disk pixels
+// 16j + 8(l/32) + i.  pix16: [16 KS] grid index of disk pixel i, -1 past n_pix.
+template <int NN, int KS, int PREC>
+__global__ __launch_bounds__(64 * kProjWavesLp) void project_tiled_lp_kernel(
+    const float* __restrict__ patches, int64_t P, int B, const uint4* __restrict__ pinvP,
+    const int* __restrict__ pix16, float a_unscale, bool vec_in, bool vec_out, float* __restrict__ xhat) {
+  using Pr = Lp<PREC>;
+  using V8 = typename Pr::V8;
+  constexpr int NP = PREC == RSC_BF16 ? 3 : 2;
+  extern __shared__ uint4 lds4[];
+  uint4* sA = lds4;                                         // [NP][2][KS][64]
+  int* sPix = reinterpret_cast<int*>(sA + NP * 2 * KS * 64);  // [16 KS]
+  float* tiles = reinterpret_cast<float*>(sPix + 16 * KS);    // [waves][32*NN]
+  for (int i = threadIdx.x; i < NP * 2 * KS * 64; i += blockDim.x) sA[i] = pinvP[i];
+  for (int i = threadIdx.x; i < 16 * KS; i += blockDim.x) sPix[i] = pix16[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, u = lane >> 5;
+  float* tile = tiles + wave * 32 * NN;
+  const int64_t ntile = (P + 31) / 32;
+  auto A = [&](int part, int t, int j) { return __builtin_bit_cast(V8, sA[((part * 2 + t) * KS + j) * 64 + lane]); };
+  for (int64_t bt = blockIdx.x; bt * kProjWavesLp < ntile; bt += gridDim.x) {
+    asm volatile("" ::: "memory");
+    const int64_t wt = bt * kProjWavesLp + wave;
+    const int64_t p0 = wt * 32;
+    const int np = wt < ntile ? int(P - p0 < 32 ? P - p0 : 32) : 0;
+    const float* src = patches + p0 * NN;
+    if (np == 32 && vec_in) {
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4* d4 = reinterpret_cast<float4*>(tile);
+#pragma unroll 4
+      for (int i = lane; i < 8 * NN; i += 64) d4[i] = s4[i];
+    } else {
+      for (int i = lane; i < 32 * NN; i += 64) tile[i] = i < np * NN ? src[i] : 0.f;
+    }
+    wave_lds_fence();
+    f32x16 acc[2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.f;
+    const float* mine = tile + col * NN;
+    float xs[KS][8];
+#pragma unroll
+    for (int j = 0; j < KS; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int q = sPix[16 * j + 8 * u + i];
+        xs[j][i] = q >= 0 ? mine[q >= 0 ? q : 0] : 0.f;
+      }
+    float unscale = a_unscale;
+    if (NP == 2) {
+      // power-of-two scale of this patch (both half-waves of the column agree)
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(xs[j][i]));
+      m = max_halves(m);
+      int ex = 0;
+      (void)frexpf(m, &ex);                 // m in [2^(ex-1), 2^ex)
+      const int e = m > 0.f ? 11 - ex : 0;  // largest value in [2^10, 2^11)
+      const float sc = ldexpf(1.f, e);
+      unscale = ldexpf(a_unscale, -e);
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[j][i] *= sc;
+    }
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      if (NP == 3) {
+        V8 xh, xm, xl;
+        split8x3<Pr>(xs[j], xh, xm, xl);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          acc[t] = Pr::mfma(A(0, t, j), xh, acc[t]);
+          acc[t] = Pr::mfma(A(0, t, j), xm, acc[t]);
+          acc[t] = Pr::mfma(A(1, t, j), xh, acc[t]);
+          acc[t] = Pr::mfma(A(0, t, j), xl, acc[t]);
+          acc[t] = Pr::mfma(A(2, t, j), xh, acc[t]);
+          acc[t] = Pr::mfma(A(1, t, j), xm, acc[t]);
+        }
+      } else {
+        V8 xh, xl;
+        split8<Pr>(xs[j], xh, xl);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          acc[t] = Pr::mfma(A(0, t, j), xh, acc[t]);
+          acc[t] = Pr::mfma(A(0, t, j), xl, acc[t]);
+          acc[t] = Pr::mfma(A(1, t, j), xh, acc[t]);
+        }
+      }
+    }
+    if (unscale != 1.f) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[0][v] *= unscale;
+        acc[1][v] *= unscale;
+      }
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int c0 = 8 * (v / 4) + 4 * u + (v % 4);
+      tile[col * B + c0] = acc[0][v];
+      if (32 + c0 < B) tile[col * B + 32 + c0] = acc[1][v];
+    }
+    wave_lds_fence();
+    float* dst = xhat + p0 * B;
+    if (np == 32 && vec_out) {
+      const float4* s4 = reinterpret_cast<const float4*>(tile);
+      float4* d4 = reinterpret_cast<float4*>(dst);
+      for (int i = lane; i < 8 * B; i += 64) d4[i] = s4[i];
+    } else {
+      for (int i = lane; i < np * B; i += 64) dst[i] = tile[i];
+    }
+    wave_lds_fence();
   }
 }
 
@@ -146,10 +290,34 @@ size_t project_tiled_lds_bytes(int N, int n_pix) {
   return sizeof(float) * (2 * size_t(kpd) * 64 + size_t((2 * kpd + 3) & ~3) + size_t(kProjWaves) * 32 * N * N);
 }
 
+size_t project_lp_lds_bytes(int N, int n_pix, int prec) {
+  const int ks = (n_pix + 15) / 16, np = prec == RSC_BF16 ? 3 : 2;
+  return size_t(np) * 2 * ks * 64 * 16 + sizeof(int) * 16 * size_t(ks) +
+         sizeof(float) * size_t(kProjWavesLp) * 32 * N * N;
+}
+
 int launch_project(const DeviceTables& t, const float* patches, int64_t P, float* xhat, void* stream) {
   if (P <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int NN = t.N * t.N;
+  if (t.prec != RSC_FP32 && t.N == 11 && t.B <= 64 && t.lpPinv) {
+    constexpr int kNN = 121, kKS = 7;
+    if ((t.n_pix + 15) / 16 != kKS) return int(hipErrorInvalidValue);
+    const size_t lds = project_lp_lds_bytes(t.N, t.n_pix, t.prec);
+    auto kern = t.prec == RSC_BF16 ? project_tiled_lp_kernel<kNN, kKS, RSC_BF16>
+                                   : project_tiled_lp_kernel<kNN, kKS, RSC_FP16>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return int(e);
+    const int64_t ntile = (P + 31) / 32;
+    int64_t blocks = (ntile + kProjWavesLp - 1) / kProjWavesLp;
+    if (blocks > cus()) blocks = cus();
+    const bool vin = (reinterpret_cast<uintptr_t>(patches) & 15) == 0;
+    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (t.B * 32) % 4 == 0;
+    hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * kProjWavesLp), lds, st, patches, P, t.B,
+                       reinterpret_cast<const uint4*>(t.lpPinv), t.lpPix16, t.lpPinvUnscale, vin, vout, xhat);
+    return int(hipGetLastError());
+  }
   if (t.N == 11 && t.B <= 64 && t.pinvD) {
     constexpr int kNN = 121, kKPD = 49;
     if ((t.n_pix + 1) / 2 != kKPD) return int(hipErrorInvalidValue);

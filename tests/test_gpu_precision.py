@@ -38,11 +38,17 @@ def _handle(geom, D, R, prec):
     return h
 
 
-def _run(h, X32, K, dev):
+def _run(h, X32, K, dev, basis=None):
     from paper_1806_04374_amd import rsc
     xh = rsc.rsc_project(h, torch.from_numpy(X32).to(dev))
     atom, angle, coef, r2 = rsc.rsc_omp_encode(h, xh, K)
     torch.cuda.synchronize()
+    if basis is not None:
+        # the compensated 16-bit projection stays close to FP32 accuracy
+        ref = orc.project(basis, X32.astype(np.float64))
+        err = np.abs(xh.cpu().numpy() - ref).max(axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+        print("projection max rel err", err.max(), flush=True)
+        assert err.max() < 1e-4, err.max()
     return atom, angle, coef, r2
 
 
@@ -51,7 +57,7 @@ def _check(label, X32, D, R, K, geom, dev, prec, basis=None):
     basis = basis or orc.build_basis(geom.N, geom.S, geom.T)
     h = _handle(geom, D, R, prec)
     rsc.rsc_precision_stats(h, reset=True)
-    atom, angle, coef, r2 = _run(h, X32, K, dev)
+    atom, angle, coef, r2 = _run(h, X32, K, dev, basis)
     stats = rsc.rsc_precision_stats(h)
     _, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
     rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
