@@ -140,7 +140,7 @@ def run_ragged(args, dev):
     g = w["geom"]
     K = w["K"]
     D = wl.draw_dictionary(w["M"], g.B)
-    h = rsc.rsc_create(g.N, g.S, g.T)
+    h = rsc.rsc_create(g.N, g.S, g.T, prec=args.prec)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
     draws = wl.ragged_draws(args.images or None)
     batch = rsc.ImageBatch([(d.H, d.W) for d in draws], g.N, dev)
@@ -204,24 +204,30 @@ def run_ragged(args, dev):
     achieved = flops / (np.mean(ke) * 1e-3)
     tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
     executed = mfma_pp * P / (np.mean(ke) * 1e-3)
+    peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     out = {
         "metric": METRIC, "value": P / (ms * 1e-3), "unit": "patches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "p50_ms": float(np.percentile(step_ms, 50)), "p99_ms": float(np.percentile(step_ms, 99)),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.prec],
+        "data": "synthetic",
         "config": {"workload": f"{w['name']}: {batch.n} images, sides log-uniform {w['side']}, "
                                f"{P} 15x15 windows, M={w['M']}, K={K}, R={w['R']}, one HIP graph per step",
                    "P": P, "images": batch.n, "stamps": n_stamps, "N": g.N, "S": g.S, "T": g.T,
-                   "M": w["M"], "K": K, "R": w["R"], "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")}},
+                   "M": w["M"], "K": K, "R": w["R"], "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")},
+                   "precision": args.prec},
         "autotune": tuned,
         "kernels_ms": {"project_images_mean": float(np.mean(kp)), "encode_mean": float(np.mean(ke))},
-        "roofline": {"kernel": "encode_kernel", "bound": "mfma", "achieved": achieved / 1e12,
-                     "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
-                     "traffic": traffic(w["name"]), "algorithmic_flops_per_launch": flops,
-                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / FP32_MFMA_PEAK,
+        "roofline": {"kernel": "encode_kernel" if args.prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
+                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic(w["name"]) if args.prec == "fp32" else None,
+                     "algorithmic_flops_per_launch": flops,
+                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / peak,
                      "tile": tile_used},
         "cpu_baseline": None,
     }
+    if args.prec != "fp32":
+        out["precision_stats"] = rsc.rsc_precision_stats(h)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_ragged(h, w, D, args.cpu_seconds, dev)
     print(json.dumps(out), flush=True)
@@ -237,7 +243,7 @@ def run_serving(args, dev):
     g = w["geom"]
     K = w["K"]
     D = wl.draw_dictionary(w["M"], g.B)
-    h = rsc.rsc_create(g.N, g.S, g.T)
+    h = rsc.rsc_create(g.N, g.S, g.T, prec=args.prec)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
     arrivals, sides = wl.serving_trace(args.duration, args.rate)
     n = len(arrivals)
@@ -282,22 +288,33 @@ def run_serving(args, dev):
     serve.replay(sch, served, realtime=True)
     span = time.perf_counter() - t0
     rep = serve.latency_report(served, warmup=5.0 if args.duration > 10 else 0.0)
+    # baseline: one request at a time through an FP32 handle, same trace
+    if args.prec == "fp32":
+        h_base = h
+    else:
+        h_base = rsc.rsc_create(g.N, g.S, g.T)
+        rsc.rsc_set_dictionary(h_base, D.astype(np.float32), w["R"])
     alone = [make(i) for i in range(n)]
     t1 = time.perf_counter()
-    serve.encode_one_at_a_time(h, K, alone, realtime=True, keep_codes=keep)
+    serve.encode_one_at_a_time(h_base, K, alone, realtime=True, keep_codes=lambda r: False)
     span1 = time.perf_counter() - t1
     rep1 = serve.latency_report(alone, warmup=5.0 if args.duration > 10 else 0.0)
-    same = [all(np.array_equal(a, b) for a, b in zip(x.codes, y.codes))
-            for x, y in zip(served, alone) if x.codes is not None and x.windows]
+    # batching invariance: sampled requests encoded alone (untimed) with the serving handle
+    sampled = [make(r.rid) for r in served if r.codes is not None and r.windows]
+    serve.encode_one_at_a_time(h, K, sampled, realtime=False)
+    by_id = {r.rid: r for r in served}
+    same = [all(np.array_equal(a, b) for a, b in zip(by_id[r.rid].codes, r.codes)) for r in sampled]
     out = {
         "metric": METRIC, "value": total_windows / span, "unit": "patches/s", "n_gpus": 1,
         "steps": sch.steps, "warmup": 0, "ms_per_step": span * 1e3 / max(sch.steps, 1),
         "p50_ms": rep.get("p50_s", float("nan")) * 1e3, "p99_ms": rep.get("p99_s", float("nan")) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.prec],
+        "data": "synthetic",
         "config": {"workload": f"{w['name']}: Poisson {args.rate:g} req/s for {args.duration:g} s, square sides "
                                f"log-uniform {w['side']}, 15x15 windows, M={w['M']}, K={K}, R={w['R']}",
                    "requests": n, "windows": total_windows, "budget_gib": args.budget_gib,
-                   "step_windows": args.step_windows, "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")}},
+                   "step_windows": args.step_windows, "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")},
+                   "precision": args.prec},
         "serving": {"continuous_batching": dict(rep, makespan_s=span, patches_per_s=total_windows / span,
                                                 max_active=sch.max_active, rejected=len(sch.rejected)),
                     "one_at_a_time": dict(rep1, makespan_s=span1, patches_per_s=total_windows / span1),
@@ -358,8 +375,9 @@ def run_precision(args, dev):
             res[name][prec] = {"p50_ms": p50, "p99_ms": float(np.percentile(ms, 99)), "runs": int(runs),
                                "patches_per_s_p50": P / (p50 * 1e-3)}
             if prec != "fp32":
-                res[name][prec]["stats_per_run"] = {k: v / (runs + args.warmup)
-                                                    for k, v in rsc.rsc_precision_stats(h).items()}
+                st = rsc.rsc_precision_stats(h)
+                res[name][prec]["stats_per_run"] = {k: (v if k == "max_candidates" else v / (runs + args.warmup))
+                                                    for k, v in st.items()}
             n_check = P if name == "small" else min(P, args.check_patches)
             rec = rsc.rsc_reconstruct(h, outs[0][:n_check], outs[1][:n_check], outs[2][:n_check])
             torch.cuda.synchronize()

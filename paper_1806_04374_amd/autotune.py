@@ -1,6 +1,6 @@
 """Launch-shape autotuning with a JSON cache.
 
-The first time a (geometry, dictionary size, angle grid, K, device) combination is
+The first time a (geometry, dictionary size, angle grid, K, precision, device) combination is
 seen, the encoder's usable launch shapes are timed on a sample of the caller's own
 coordinates (rsc_autotune_encode) and the fastest is stored; later calls apply the
 cached choice without timing.  Cache file: $RSC_AUTOTUNE_CACHE, else
@@ -22,7 +22,7 @@ def cache_path() -> str:
 def key(h: rsc.Handle, K: int) -> str:
     import torch
     name = torch.cuda.get_device_name(0).replace(" ", "_") if torch.cuda.is_available() else "cpu"
-    return f"N{h.N}-S{h.S}-T{h.T}-M{h.M}-R{h.R}-K{K}-{name}"
+    return f"N{h.N}-S{h.S}-T{h.T}-M{h.M}-R{h.R}-K{K}-{getattr(h, 'prec', 'fp32')}-{name}"
 
 
 def _load(path):

@@ -111,9 +111,10 @@ def _dev(t, dtype, name, shape=None):
 class Handle:
     """Owner of an rsc_handle*; geometry and dictionary sizes are cached."""
 
-    def __init__(self, ptr, N, S, T):
+    def __init__(self, ptr, N, S, T, prec="fp32"):
         self.ptr = ptr
         self.N, self.S, self.T = N, S, T
+        self.prec = prec
         n_pix, B, cond = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         _check(lib().rsc_basis_info(ptr, ctypes.byref(n_pix), ctypes.byref(B), ctypes.byref(cond)))
         self.n_pix, self.B, self.cond = n_pix.value, B.value, cond.value
@@ -138,7 +139,7 @@ def rsc_create(N: int, S: int, T: int, centres=None, sigma: float = 0.0, prec: s
         c = np.ascontiguousarray(centres, dtype=np.float64)
     _check(lib().rsc_create(N, S, T, None if c is None else c.ctypes.data_as(ctypes.c_void_p),
                             float(sigma), PRECISION[prec], ctypes.byref(h)))
-    return Handle(h, N, S, T)
+    return Handle(h, N, S, T, prec)
 
 
 def rsc_basis_host(N: int, S: int, T: int, centres=None, sigma: float = 0.0):
