@@ -253,6 +253,8 @@ def run_serving(args, dev):
     gen = torch.Generator(device=dev)
     t_gen = time.perf_counter()
     for i in range(n):           # request images: seeded device noise plus stamps
+        if i % 500 == 0:
+            print(f"serving: generating request {i}/{n}", file=sys.stderr, flush=True)
         sd = int(sides[i])
         gen.manual_seed(1_000_003 * 7 + i)
         pix = torch.randn(sd * sd, generator=gen, device=dev) * w["sigma"]
@@ -280,25 +282,37 @@ def run_serving(args, dev):
         return serve.Request(i, float(arrivals[i]), host[int(offs[i]):int(offs[i + 1])].view(sd, sd), sd, sd)
 
     keep = lambda r: r.rid % 50 == 0
-    budget = int(args.budget_gib * (1 << 30))
+    if args.budget_gib > 0:
+        budget = int(args.budget_gib * (1 << 30))
+    else:
+        # free HBM minus 8 GiB, less the step slots the backend allocates next to the pool
+        free, _ = torch.cuda.mem_get_info()
+        slot_bytes = 2 * args.step_windows * (g.B + 3 * K) * 4
+        budget = max(1 << 30, free - (8 << 30) - slot_bytes)
     be = serve.DeviceBackend(h, K, budget, args.step_windows, keep_codes=keep)
     sch = serve.Scheduler(be, budget // 4, args.step_windows)
     served = [make(i) for i in range(n)]
+    print(f"serving: replaying {n} requests over {args.duration:g} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     serve.replay(sch, served, realtime=True)
     span = time.perf_counter() - t0
     rep = serve.latency_report(served, warmup=5.0 if args.duration > 10 else 0.0)
+    print(f"serving: continuous batching done in {span:.1f} s", file=sys.stderr, flush=True)
     # baseline: one request at a time through an FP32 handle, same trace
     if args.prec == "fp32":
         h_base = h
     else:
         h_base = rsc.rsc_create(g.N, g.S, g.T)
         rsc.rsc_set_dictionary(h_base, D.astype(np.float32), w["R"])
-    alone = [make(i) for i in range(n)]
-    t1 = time.perf_counter()
-    serve.encode_one_at_a_time(h_base, K, alone, realtime=True, keep_codes=lambda r: False)
-    span1 = time.perf_counter() - t1
-    rep1 = serve.latency_report(alone, warmup=5.0 if args.duration > 10 else 0.0)
+    if args.no_baseline:
+        span1, rep1 = None, None
+    else:
+        alone = [make(i) for i in range(n)]
+        t1 = time.perf_counter()
+        serve.encode_one_at_a_time(h_base, K, alone, realtime=True, keep_codes=lambda r: False)
+        span1 = time.perf_counter() - t1
+        rep1 = serve.latency_report(alone, warmup=5.0 if args.duration > 10 else 0.0)
+        print(f"serving: one-at-a-time baseline done in {span1:.1f} s", file=sys.stderr, flush=True)
     # batching invariance: sampled requests encoded alone (untimed) with the serving handle
     sampled = [make(r.rid) for r in served if r.codes is not None and r.windows]
     serve.encode_one_at_a_time(h, K, sampled, realtime=False)
@@ -312,13 +326,14 @@ def run_serving(args, dev):
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: Poisson {args.rate:g} req/s for {args.duration:g} s, square sides "
                                f"log-uniform {w['side']}, 15x15 windows, M={w['M']}, K={K}, R={w['R']}",
-                   "requests": n, "windows": total_windows, "budget_gib": args.budget_gib,
+                   "requests": n, "windows": total_windows, "budget_gib": budget / (1 << 30),
                    "step_windows": args.step_windows, "launch": {k: tuned[k] for k in ("tile", "blocks_per_cu")},
                    "precision": args.prec},
         "serving": {"continuous_batching": dict(rep, makespan_s=span, patches_per_s=total_windows / span,
                                                 max_active=sch.max_active, rejected=len(sch.rejected)),
-                    "one_at_a_time": dict(rep1, makespan_s=span1, patches_per_s=total_windows / span1),
-                    "speedup_throughput": span1 / span,
+                    "one_at_a_time": None if rep1 is None else dict(rep1, makespan_s=span1,
+                                                                      patches_per_s=total_windows / span1),
+                    "speedup_throughput": None if span1 is None else span1 / span,
                     "codes_identical_alone_vs_mix": f"{sum(same)}/{len(same)} sampled requests",
                     "offered_patches_per_s": total_windows / args.duration,
                     "input_generation_s": t_gen},
@@ -485,7 +500,9 @@ def main():
                     help="precision: scale-workload patches checked against the reference")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: mean requests per second")
-    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: HBM budget for request pixels")
+    ap.add_argument("--budget-gib", type=float, default=64.0,
+                    help="serving: HBM budget for request pixels (<= 0: free HBM minus 8 GiB)")
+    ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time leg")
     ap.add_argument("--step-windows", type=int, default=1 << 22, help="serving: windows per device step")
     ap.add_argument("--images", type=int, default=0, help="ragged: use the first n images (testing only)")
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")

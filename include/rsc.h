@@ -20,6 +20,8 @@
  *    compute calls only enqueue work and return; argument errors are reported
  *    synchronously, launch errors as RSC_E_DEVICE.  rsc_sync() waits.
  *  - Compute calls never allocate device memory.
+ *  - Calls that use the dictionary (encode, reconstruct, synthesis, autotuning,
+ *    encoder info) return RSC_E_NOT_READY until rsc_set_dictionary succeeds.
  *  - A handle may be used from one thread at a time; distinct handles are
  *    independent.
  *  - Geometry: odd patch side N; pixel (row i, col j) sits at x = j - c,
@@ -49,7 +51,8 @@ typedef enum {
   RSC_E_INVALID = -1,      /* bad argument: null pointer, size out of range, wrong state */
   RSC_E_NOMEM = -2,        /* the library could not allocate its own resident copies */
   RSC_E_DEVICE = -3,       /* a HIP call or kernel launch failed */
-  RSC_E_UNSUPPORTED = -4   /* valid request that this build does not implement */
+  RSC_E_UNSUPPORTED = -4,  /* valid request that this build does not implement */
+  RSC_E_NOT_READY = -5     /* the handle has no dictionary yet (rsc_set_dictionary) */
 } rsc_status;
 
 typedef enum {
@@ -172,7 +175,7 @@ rsc_status rsc_get_launch(const rsc_handle* h, int* tile, int* blocks_per_cu);
  *   reps              1..100
  *   report            host [8][3] or NULL: (tile, blocks_per_cu, median ms) per candidate
  *   n_report          host, number of rows written (may be NULL)
- * Errors: RSC_E_INVALID (arguments, no dictionary), RSC_E_DEVICE.
+ * Errors: RSC_E_INVALID (arguments), RSC_E_NOT_READY (no dictionary), RSC_E_DEVICE.
  */
 rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
                                int32_t* angle, float* coef, int reps, double* report, int* n_report,
@@ -200,7 +203,7 @@ rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, flo
  *   atom, angle  device [P, K] int32, slots in selection order; empty slots -1
  *   coef         device [P, K] float32; empty slots 0
  *   resid2       device [P] float32 squared hat-domain residual norm, or NULL
- * Requires rsc_set_dictionary first (else RSC_E_INVALID).
+ * Requires rsc_set_dictionary first (else RSC_E_NOT_READY).
  *
  * BF16 / FP16 handles: the correlations of every (atom, angle) are formed with
  * 16-bit operands and FP32 accumulation; every atom whose 16-bit maximum over the

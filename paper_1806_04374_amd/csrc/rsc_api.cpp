@@ -505,7 +505,7 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
                                int32_t* angle, float* coef, int reps, double* report, int* n_report,
                                void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
   if (P < 1 || !xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "need a non-empty sample");
   if (reps < 1 || reps > 100) return fail(RSC_E_INVALID, "reps must be in 1..100");
@@ -573,7 +573,7 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
 
 rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_flops_per_patch) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
   if (h->prec != RSC_FP32) {
     if (tile) *tile = RSC_TILE_32;
@@ -606,7 +606,7 @@ rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, flo
 rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
                           int32_t* angle, float* coef, float* resid2, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
@@ -623,7 +623,7 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
 rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32_t* angle,
                            const float* coef, int64_t P, int K, float* out, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 16) return fail(RSC_E_INVALID, "K must be in 1..16");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
@@ -637,7 +637,7 @@ rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float*
                           const float* weight, int64_t P, int J, const float* noise, float* out,
                           void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (J < 1 || J > 16) return fail(RSC_E_INVALID, "J must be in 1..16");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
@@ -677,7 +677,7 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
                                  int64_t n_stamps, const int64_t* img_offset, const int32_t* H,
                                  const int32_t* W, int n_images, float* pixels, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (!h->has_dict) return fail(RSC_E_INVALID, "no dictionary loaded");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (n_stamps < 0 || n_stamps > (int64_t(1) << 31) - 1) return fail(RSC_E_INVALID, "n_stamps out of range");
   if (n_stamps == 0) return ok();
   if (!atom || !theta || !amplitude || !centre || !image || !img_offset || !H || !W || !pixels)

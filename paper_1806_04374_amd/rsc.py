@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librsc.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "rsc.h")
 
-RSC_OK, RSC_E_INVALID, RSC_E_NOMEM, RSC_E_DEVICE, RSC_E_UNSUPPORTED = 0, -1, -2, -3, -4
+RSC_OK, RSC_E_INVALID, RSC_E_NOMEM, RSC_E_DEVICE, RSC_E_UNSUPPORTED, RSC_E_NOT_READY = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp32": 0, "bf16": 1, "fp16": 2}
 TILE = {"auto": 0, "16": 1, "32": 2}
 

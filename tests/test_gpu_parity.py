@@ -261,8 +261,9 @@ def test_device_argument_errors(dev):
     geom = wl.GEOM11
     h = rsc.rsc_create(11, 5, 5)
     x = torch.zeros((4, 55), dtype=torch.float32, device=dev)
-    with pytest.raises(rsc.RscError, match="no dictionary"):
+    with pytest.raises(rsc.RscError, match="no dictionary") as e:
         rsc.rsc_omp_encode(h, x, 2)
+    assert e.value.status == rsc.RSC_E_NOT_READY
     bad = np.ones((4, 55), np.float32)
     with pytest.raises(rsc.RscError, match="unit norm"):
         rsc.rsc_set_dictionary(h, bad, 8)
