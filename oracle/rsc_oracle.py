@@ -44,6 +44,18 @@ Readings where the paper is silent (each one is listed in the design notes):
     ||r||^2 <= tau^2 ||x||^2 (tau = 1e-5) or when the selected column is
     already in the support.  The same atom at another angle may be selected
     (Sec. II-B).  Empty slots are (-1, -1, 0).
+  * Dictionary update (R-K-SVD, Fig. 2 and Sec. II-C), in hat coordinates
+    (Sec. II-E): the augmented dictionary is built once per outer iteration, so
+    every atom is updated from the same codes and the same old dictionary.  When
+    a patch uses atom m more than once, r0 is the angle of the first such slot in
+    selection order.  The first singular vector's sign is chosen to agree with
+    the old atom (<d_new, d_old> > 0; when that is 0, the largest-magnitude
+    coordinate is made positive, the first one on ties).  Atoms that no patch
+    uses are reset, in increasing index, to the directions of the patches with
+    the largest current coding error ||x_p - D a_p||^2, one distinct patch each,
+    in decreasing order of that error (ties: smaller patch index); patches
+    with zero coordinates are skipped.  After the last iteration the pursuit runs
+    once more so that the codes belong to the final dictionary.
 """
 from __future__ import annotations
 
@@ -347,3 +359,86 @@ def image_patches(img: np.ndarray, N: int) -> np.ndarray:
         return np.zeros((0, N, N))
     v = np.lib.stride_tricks.sliding_window_view(img, (N, N))
     return v.reshape(-1, N, N)
+
+
+# --------------------------------------------------------------------------- dictionary update
+def _sign_like(u: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """u or -u: the one with <u, ref> > 0; if <u, ref> = 0, the one whose
+    largest-magnitude coordinate (the first on ties) is positive."""
+    s = float(u @ ref)
+    if s < 0 or (s == 0 and u[int(np.argmax(np.abs(u)))] < 0):
+        return -u
+    return u
+
+
+def rksvd_update(D_hat: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, code: Code):
+    """Atom update of rotational K-SVD (Fig. 2, the loop over m; Sec. II-C).
+
+    For each atom m, every patch p whose code uses m contributes one column
+    S_{-r0} (x_p - D b_p) to Y_m: b_p is the code of p with the entry of atom m at
+    angle r0 removed, so the column is what atom m has to explain, turned upright
+    with respect to m.  The new atom is the first left singular vector of Y_m.
+    Atoms used by no patch are reset (see the module header).
+
+    D_hat [M, B] is the dictionary the codes were computed with; xhat [P, B].
+    Returns (D_new [M, B], usage [M], reset [M]) where reset[m] is the patch an
+    unused atom was reset to (-1 otherwise).
+    """
+    D_hat = np.asarray(D_hat, dtype=np.float64)
+    xhat = np.asarray(xhat, dtype=np.float64)
+    M, B = D_hat.shape
+    P, K = code.atom.shape
+    D_new = D_hat.copy()
+    usage = np.zeros(M, np.int64)
+    for m in range(M):
+        cols = []
+        for p in range(P):
+            slots = [i for i in range(K) if code.atom[p, i] == m]
+            if not slots:
+                continue
+            i0 = slots[0]
+            r0 = int(code.angle[p, i0])
+            others = np.zeros(B)
+            for i in range(K):
+                if i != i0 and code.atom[p, i] >= 0:
+                    theta = 2 * np.pi * code.angle[p, i] / R
+                    others += code.coef[p, i] * steer(D_hat[code.atom[p, i]], theta, S, T)
+            cols.append(steer(xhat[p] - others, -2 * np.pi * r0 / R, S, T))
+        usage[m] = len(cols)
+        if cols:
+            Y = np.stack(cols, axis=1)                       # [B, n_m]
+            U, _, _ = np.linalg.svd(Y, full_matrices=False)
+            D_new[m] = _sign_like(U[:, 0], D_hat[m])
+    reset = -np.ones(M, np.int64)
+    order = sorted(range(P), key=lambda p: (-float(code.resid2[p]), p))
+    nxt = 0
+    for m in range(M):
+        if usage[m] > 0:
+            continue
+        while nxt < P and not np.any(xhat[order[nxt]]):
+            nxt += 1
+        if nxt == P:
+            break
+        p = order[nxt]
+        D_new[m] = xhat[p] / np.linalg.norm(xhat[p])
+        reset[m] = p
+        nxt += 1
+    return D_new, usage, reset
+
+
+def rksvd(D_init: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, K: int, n_iter: int,
+          tau: float = TAU):
+    """Rotational K-SVD in hat coordinates (Fig. 2 with R_r -> S_r, Sec. II-E):
+    n_iter rounds of pursuit and atom update from D_init, then one more pursuit.
+    Returns (D [M, B], codes of the final dictionary, coding error sum_p ||r_p||^2
+    after each round's pursuit)."""
+    D = np.asarray(D_init, dtype=np.float64).copy()
+    M = D.shape[0]
+    history = []
+    for _ in range(n_iter):
+        code = omp(augmented_dictionary(D, R, S, T), xhat, K, M, tau)
+        history.append(float(code.resid2.sum()))
+        D, _, _ = rksvd_update(D, R, S, T, xhat, code)
+    code = omp(augmented_dictionary(D, R, S, T), xhat, K, M, tau)
+    history.append(float(code.resid2.sum()))
+    return D, code, history
