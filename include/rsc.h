@@ -285,6 +285,57 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
                                  const int32_t* W, int n_images, float* pixels, void* stream);
 
 /*
+ * Workspace bytes for rsc_rksvd_update and rsc_rksvd_train on P patches with the
+ * handle's current dictionary sizes (M, B).  Requires a dictionary (RSC_E_NOT_READY).
+ */
+rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, size_t* bytes);
+
+/*
+ * Dictionary update of rotational K-SVD (Fig. 2, the loop over atoms; Sec. II-C), in hat
+ * coordinates (Sec. II-E), from codes computed with the handle's current dictionary D.
+ * Every atom is updated from the same codes and the same D (the augmented dictionary
+ * of Fig. 2 is built once per outer iteration).  For atom m, each patch p whose code
+ * uses m contributes the column S_{-r0}(xhat_p - D b_p): r0 is the angle of the first
+ * slot (selection order) holding m and b_p the code without that entry.  The new atom
+ * is the first left singular vector of those columns, with the sign that agrees with
+ * the old atom (<new, old> > 0; on 0, largest-magnitude coordinate positive).  Atoms used
+ * by no patch take, in index order, the directions xhat_p / ||xhat_p|| of the patches
+ * with the largest coding error resid2 (positive errors only, distinct patches, ties to
+ * the smaller p); with none left they keep their value.
+ *   xhat                device [P, B] float32
+ *   atom, angle, coef   device [P, K] codes as written by rsc_omp_encode (K <= 8)
+ *   resid2              device [P] float32 coding error of each patch
+ *   workspace           device, >= rsc_rksvd_workspace_size bytes, 256-byte aligned
+ *   d_new               device [M, B] float32 output, unit rows
+ *   usage               device [M] int32 output, patches using each atom
+ *   reset               device [M] int32 output (reset patch or -1), or NULL
+ * Enqueued on the stream; the handle's dictionary is not changed (pass d_new to
+ * rsc_set_dictionary).  Errors: RSC_E_INVALID, RSC_E_NOT_READY, RSC_E_UNSUPPORTED
+ * (B > 128), RSC_E_DEVICE.
+ */
+rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, int K, const int32_t* atom,
+                            const int32_t* angle, const float* coef, const float* resid2, void* workspace,
+                            size_t ws_bytes, float* d_new, int32_t* usage, int32_t* reset, void* stream);
+
+/*
+ * Rotational K-SVD learning loop (Fig. 2 with R_r -> S_r; Sec. II-C, II-E): loads d_init,
+ * then n_iter times rsc_omp_encode + rsc_rksvd_update + rsc_set_dictionary, then one
+ * more rsc_omp_encode so that the codes belong to the final dictionary.
+ *   xhat                       device [P, B] float32
+ *   d_init                     host [M, B] float32, unit rows; R the angle grid
+ *   workspace, ws_bytes        as for rsc_rksvd_update (size queried after a dictionary
+ *                              of the same M is loaded)
+ *   atom, angle, coef, resid2  device outputs: codes of the final pursuit
+ *   d_out                      host [M, B] float32: the learned dictionary
+ *   history                    host [n_iter + 1] float64 or NULL: sum of resid2 after
+ *                              each pursuit
+ * Blocking (the dictionary returns to the host each iteration to rebuild the tables).
+ */
+rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, int n_iter, const float* d_init,
+                           int M, int R, void* workspace, size_t ws_bytes, int32_t* atom, int32_t* angle,
+                           float* coef, float* resid2, float* d_out, double* history, void* stream);
+
+/*
  * Counters of the BF16 / FP16 encoder, accumulated over its launches on this handle
  * (the FP32 re-scoring of candidates and the FP64 least-squares fallback described
  * at rsc_omp_encode):

@@ -53,9 +53,10 @@ Readings where the paper is silent (each one is listed in the design notes):
     coordinate is made positive, the first one on ties).  Atoms that no patch
     uses are reset, in increasing index, to the directions of the patches with
     the largest current coding error ||x_p - D a_p||^2, one distinct patch each,
-    in decreasing order of that error (ties: smaller patch index); patches
-    with zero coordinates are skipped.  After the last iteration the pursuit runs
-    once more so that the codes belong to the final dictionary.
+    in decreasing order of that error (ties: smaller patch index); only patches
+    with a positive error qualify, and an unused atom keeps its value when none
+    is left.  After the last iteration the pursuit runs once more so that the
+    codes belong to the final dictionary.
 """
 from __future__ import annotations
 
@@ -415,9 +416,7 @@ def rksvd_update(D_hat: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, co
     for m in range(M):
         if usage[m] > 0:
             continue
-        while nxt < P and not np.any(xhat[order[nxt]]):
-            nxt += 1
-        if nxt == P:
+        if nxt == P or code.resid2[order[nxt]] <= 0:
             break
         p = order[nxt]
         D_new[m] = xhat[p] / np.linalg.norm(xhat[p])

@@ -29,6 +29,7 @@ SOURCES = [
     ("rsc_encode_lp.hip", "hip"),
     ("rsc_synth.hip", "hip"),
     ("rsc_images.hip", "hip"),
+    ("rsc_rksvd.hip", "hip"),
 ]
 
 

@@ -451,13 +451,13 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
         for (int k = 0; k < NQ; ++k)
           lpF32[(size_t(t) * NQ + k) * 64 + l] = hh == 0 ? (k == 0 ? 1.f : cosk(k, r)) : (k == 0 ? 0.f : -sink(k, r));
       }
-    cs64.resize(cs.size());
-    for (int k = 0; k < NQ; ++k)
-      for (int r = 0; r < R; ++r) {
-        cs64[size_t(k) * R + r] = std::cos(two_pi * double(k) * double(r) / double(R));
-        cs64[size_t(NQ + k) * R + r] = std::sin(two_pi * double(k) * double(r) / double(R));
-      }
   }
+  cs64.resize(cs.size());
+  for (int k = 0; k < NQ; ++k)
+    for (int r = 0; r < R; ++r) {
+      cs64[size_t(k) * R + r] = std::cos(two_pi * double(k) * double(r) / double(R));
+      cs64[size_t(NQ + k) * R + r] = std::sin(two_pi * double(k) * double(r) / double(R));
+    }
   d.M = M;
   d.R = R;
   d.NG = NG;
@@ -685,6 +685,113 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
   int e = rsc::launch_stamps(h->dev, atom, theta, amplitude, centre, image, n_stamps, img_offset, H, W,
                              n_images, pixels, stream);
   return e ? device_fail(e, "stamp launch") : ok();
+}
+
+namespace {
+
+// Workspace of the dictionary update: partial covariances, per-chunk counts, the FP64
+// sum slot, then (for training) the new dictionary, usage and reset arrays.
+struct RkLayout {
+  size_t update = 0, dnew = 0, usage = 0, reset = 0, total = 0;
+};
+
+RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  RkLayout L;
+  L.update = al(rsc::rksvd_workspace_bytes(d, P));
+  L.dnew = L.update;
+  L.usage = L.dnew + al(sizeof(float) * size_t(d.M) * d.B);
+  L.reset = L.usage + al(sizeof(int32_t) * size_t(d.M));
+  L.total = L.reset + al(sizeof(int32_t) * size_t(d.M));
+  return L;
+}
+
+double* rk_sum_slot(const rsc::DeviceTables& d, int64_t P, void* ws) {
+  // the last 8 doubles of the update area
+  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + rsc::rksvd_workspace_bytes(d, P) - 8 * sizeof(double));
+}
+
+}  // namespace
+
+rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, size_t* bytes) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
+  if (P < 1) return fail(RSC_E_INVALID, "P must be >= 1");
+  *bytes = rk_layout(h->dev, P).total;
+  return ok();
+}
+
+rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, int K, const int32_t* atom,
+                            const int32_t* angle, const float* coef, const float* resid2, void* workspace,
+                            size_t ws_bytes, float* d_new, int32_t* usage, int32_t* reset, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
+  if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
+  if (P < 1) return fail(RSC_E_INVALID, "P must be >= 1");
+  if (!xhat || !atom || !angle || !coef || !resid2 || !workspace || !d_new || !usage)
+    return fail(RSC_E_INVALID, "null device pointer");
+  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
+  const RkLayout L = rk_layout(h->dev, P);
+  if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
+  int32_t* rs = reset ? reset : reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + L.reset);
+  int e = rsc::launch_rksvd_update(h->dev, xhat, P, K, atom, angle, coef, resid2, workspace, d_new, usage, rs,
+                                   stream);
+  return e ? device_fail(e, "dictionary update launch") : ok();
+}
+
+rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, int n_iter, const float* d_init,
+                           int M, int R, void* workspace, size_t ws_bytes, int32_t* atom, int32_t* angle,
+                           float* coef, float* resid2, float* d_out, double* history, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (n_iter < 0 || n_iter > 10000) return fail(RSC_E_INVALID, "n_iter must be in 0..10000");
+  if (!d_init || !d_out) return fail(RSC_E_INVALID, "null host pointer");
+  if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
+  if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
+    return fail(RSC_E_INVALID, "null device pointer or empty input");
+  rsc_status s = rsc_set_dictionary(h, d_init, M, R);
+  if (s != RSC_OK) return s;
+  const RkLayout L = rk_layout(h->dev, P);
+  if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
+  char* w = reinterpret_cast<char*>(workspace);
+  float* dn = reinterpret_cast<float*>(w + L.dnew);
+  int32_t* us = reinterpret_cast<int32_t*>(w + L.usage);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<float> host(size_t(M) * h->dev.B);
+  std::memcpy(host.data(), d_init, host.size() * sizeof(float));
+  auto coding_error = [&](int at) -> rsc_status {
+    if (!history) return RSC_OK;
+    double* slot = rk_sum_slot(h->dev, P, workspace);
+    int e = rsc::launch_sum(resid2, P, slot, stream);
+    if (e) return device_fail(e, "sum launch");
+    hipError_t he = hipMemcpyAsync(&history[at], slot, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    return he == hipSuccess ? RSC_OK : device_fail(int(he), "history copy");
+  };
+  for (int it = 0; it <= n_iter; ++it) {
+    s = rsc_omp_encode(h, xhat, P, K, atom, angle, coef, resid2, stream);
+    if (s == RSC_OK) s = coding_error(it);
+    if (s != RSC_OK || it == n_iter) break;
+    s = rsc_rksvd_update(h, xhat, P, K, atom, angle, coef, resid2, workspace, ws_bytes, dn, us, nullptr, stream);
+    if (s != RSC_OK) break;
+    hipError_t he = hipMemcpyAsync(host.data(), dn, host.size() * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return device_fail(int(he), "dictionary copy");
+    // rows leave the device at unit norm up to FP32 rounding; renormalise in FP64
+    for (int m = 0; m < M; ++m) {
+      double n2 = 0.0;
+      for (int b = 0; b < h->dev.B; ++b) n2 += double(host[size_t(m) * h->dev.B + b]) * host[size_t(m) * h->dev.B + b];
+      const double inv = n2 > 0.0 ? 1.0 / std::sqrt(n2) : 0.0;
+      for (int b = 0; b < h->dev.B; ++b)
+        host[size_t(m) * h->dev.B + b] = float(host[size_t(m) * h->dev.B + b] * inv);
+    }
+    s = rsc_set_dictionary(h, host.data(), M, R);
+    if (s != RSC_OK) break;
+  }
+  if (s != RSC_OK) return s;
+  std::memcpy(d_out, host.data(), host.size() * sizeof(float));
+  return ok();
 }
 
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {

@@ -54,7 +54,7 @@ struct DeviceTables {
                              // lpSplit, else [ceil(R/32)][T+1][64]
   bool lpSplit = false;      // even R in 33..64: radix-2 split in the FP32 re-score
   double* gramH64 = nullptr; // FP64 pair table [M][M][2T+1]
-  double* cs64 = nullptr;    // FP64 [2][T+1][R] cos, sin
+  double* cs64 = nullptr;    // FP64 [2][T+1][R] cos, sin (every handle)
   unsigned long long* lpStats = nullptr;  // [4] counters (rsc_precision_stats)
   // compensated 16-bit projection (N = 11): 3 (BF16) or 2 (FP16) 16-bit parts of the
   // operand over disk pixels [parts][2][ceil(n_pix/16)][64][8], and the grid index of
@@ -76,6 +76,12 @@ size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
+int rksvd_chunks(int M, int64_t P);
+size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P);
+int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int K, const int32_t* atom,
+                        const int32_t* angle, const float* coef, const float* resid2, void* ws,
+                        float* d_new, int32_t* usage, int32_t* reset, void* stream);
+int launch_sum(const float* x, int64_t n, double* out, void* stream);
 bool encode_lp_supported(int S, int T, int M, int R);
 size_t encode_lp_lds_bytes(const DeviceTables& t);
 double encode_lp_mfma_flops_per_patch(const DeviceTables& t, int K);

@@ -61,6 +61,9 @@ def lib():
         "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
         "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
         "rsc_precision_stats": [P, P, I],
+        "rsc_rksvd_workspace_size": [P, I64, P],
+        "rsc_rksvd_update": [P, P, I64, I, P, P, P, P, P, ctypes.c_size_t, P, P, P, P],
+        "rsc_rksvd_train": [P, P, I64, I, I, P, I, I, P, ctypes.c_size_t, P, P, P, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -348,6 +351,66 @@ def rsc_synthesize_images(h: Handle, batch: "ImageBatch", atom, theta, amplitude
                                        _ptr(image), n, _ptr(batch.d_offset), _ptr(batch.d_H),
                                        _ptr(batch.d_W), batch.n, _ptr(pixels), _stream(stream)))
     return pixels
+
+
+def rsc_rksvd_workspace_size(h: Handle, P: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().rsc_rksvd_workspace_size(h.ptr, int(P), ctypes.byref(n)))
+    return n.value
+
+
+def _workspace(nbytes, dev):
+    import torch
+    # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+
+
+def rsc_rksvd_update(h: Handle, xhat, atom, angle, coef, resid2, workspace=None, stream=None):
+    """Dictionary update from codes under the handle's dictionary; returns device
+    (d_new [M, B] float32, usage [M] int32, reset [M] int32)."""
+    import torch
+    P, K = atom.shape
+    for t, dt in ((xhat, torch.float32), (atom, torch.int32), (angle, torch.int32), (coef, torch.float32),
+                  (resid2, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("device contiguous tensors of the documented dtypes expected")
+    if xhat.shape != (P, h.B) or resid2.shape != (P,):
+        raise ValueError("shape mismatch")
+    nbytes = rsc_rksvd_workspace_size(h, P)
+    ws = workspace if workspace is not None else _workspace(nbytes, xhat.device)
+    d_new = torch.empty((h.M, h.B), dtype=torch.float32, device=xhat.device)
+    usage = torch.empty((h.M,), dtype=torch.int32, device=xhat.device)
+    reset = torch.empty((h.M,), dtype=torch.int32, device=xhat.device)
+    _check(lib().rsc_rksvd_update(h.ptr, _ptr(xhat), int(P), int(K), _ptr(atom), _ptr(angle), _ptr(coef),
+                                  _ptr(resid2), _ptr(ws), ws.numel(), _ptr(d_new), _ptr(usage), _ptr(reset),
+                                  _stream(stream)))
+    return d_new, usage, reset
+
+
+def rsc_rksvd_train(h: Handle, xhat, d_init, R: int, K: int, n_iter: int, stream=None):
+    """R-K-SVD from d_init (host [M, B]); returns (D [M, B] numpy, codes of the final
+    pursuit (atom, angle, coef, resid2) on the device, coding-error history numpy)."""
+    import torch
+    d_init = np.ascontiguousarray(d_init, dtype=np.float32)
+    M, B = d_init.shape
+    P = xhat.shape[0]
+    if xhat.dtype != torch.float32 or not xhat.is_contiguous() or xhat.shape != (P, h.B) or B != h.B:
+        raise ValueError("xhat must be device [P, B] float32 and d_init [M, B]")
+    rsc_set_dictionary(h, d_init, R)
+    ws = _workspace(rsc_rksvd_workspace_size(h, P), xhat.device)
+    dev = xhat.device
+    atom = torch.empty((P, K), dtype=torch.int32, device=dev)
+    angle = torch.empty((P, K), dtype=torch.int32, device=dev)
+    coef = torch.empty((P, K), dtype=torch.float32, device=dev)
+    resid2 = torch.empty((P,), dtype=torch.float32, device=dev)
+    d_out = np.empty_like(d_init)
+    hist = np.zeros(n_iter + 1)
+    _check(lib().rsc_rksvd_train(h.ptr, _ptr(xhat), int(P), int(K), int(n_iter),
+                                 d_init.ctypes.data_as(ctypes.c_void_p), int(M), int(R), _ptr(ws), ws.numel(),
+                                 _ptr(atom), _ptr(angle), _ptr(coef), _ptr(resid2),
+                                 d_out.ctypes.data_as(ctypes.c_void_p), hist.ctypes.data_as(ctypes.c_void_p),
+                                 _stream(stream)))
+    return d_out, (atom, angle, coef, resid2), hist
 
 
 def rsc_precision_stats(h: Handle, reset: bool = False) -> dict:
