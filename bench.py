@@ -459,6 +459,96 @@ def cpu_baseline_precision(inputs, codes):
     return base, errors
 
 
+FP64_VECTOR_PEAK = 78.6e12
+
+
+def run_rksvd(args, dev):
+    """R-K-SVD learning on the scale workload: 10^6 patches, M=64, K=4, R=64, from the
+    generating dictionary perturbed by N(0, 0.1^2) and renormalised.  Times whole
+    iterations (pursuit + dictionary update + table rebuild) and their parts."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    w = wl.SCALE
+    g = w["geom"]
+    K, R = w["K"], w["R"]
+    P = args.patches or w["P"]
+    D = wl.draw_dictionary(w["M"], g.B)
+    D0 = D + 0.1 * np.random.default_rng(31).standard_normal(D.shape)
+    D0 = (D0 / np.linalg.norm(D0, axis=1, keepdims=True)).astype(np.float32)
+    h = rsc.rsc_create(g.N, g.S, g.T, prec=args.prec)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    X = make_inputs(h, w, P, dev)
+    xh = rsc.rsc_project(h, X)
+    torch.cuda.synchronize()
+    n_iter = max(args.steps, 1)
+    # warm-up: one iteration (compiles nothing, but touches every kernel and allocation)
+    rsc.rsc_rksvd_train(h, xh, D0, R, K, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Dn, codes, hist = rsc.rsc_rksvd_train(h, xh, D0, R, K, n_iter)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # one iteration's parts, events on the launch stream
+    stream = torch.cuda.current_stream()
+    rsc.rsc_set_dictionary(h, D0, R)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ws = torch.empty(rsc.rsc_rksvd_workspace_size(h, P, K), dtype=torch.uint8, device=dev)
+    enc_ms, upd_ms = [], []
+    for _ in range(3):
+        ev[0].record(stream)
+        atom, angle, coef, r2 = rsc.rsc_omp_encode(h, xh, K, stream=stream)
+        ev[1].record(stream)
+        d_new, usage, _ = rsc.rsc_rksvd_update(h, xh, atom, angle, coef, r2, workspace=ws, stream=stream)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        enc_ms.append(ev[0].elapsed_time(ev[1]))
+        upd_ms.append(ev[1].elapsed_time(ev[2]))
+    host = d_new.cpu().numpy()
+    host /= np.linalg.norm(host, axis=1, keepdims=True)
+    t1 = time.perf_counter()
+    rsc.rsc_set_dictionary(h, host, R)
+    load_ms = (time.perf_counter() - t1) * 1e3
+    pairs = int((usage.cpu().numpy()).sum())
+    # algorithmic FP64 work of the update: per (patch, atom) pair the outer product y y^T
+    # (2 B^2) and the K - 1 steered atoms and the upright turn (about 6 B (K - 1) + 6 B)
+    upd_flops = pairs * (2.0 * g.B * g.B + 6.0 * g.B * K)
+    per_iter = wall / (n_iter + 1)          # n_iter updates and n_iter + 1 pursuits
+    out = {
+        "metric": "patches per second per R-K-SVD iteration (pursuit + dictionary update)",
+        "value": P / per_iter, "unit": "patches/s", "n_gpus": 1, "steps": n_iter, "warmup": 1,
+        "ms_per_step": per_iter * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[args.prec] + "; update in f64", "data": "synthetic",
+        "config": {"workload": f"rksvd: {P} 11x11 patches, M={w['M']}, K={K}, R={R}, {n_iter} iterations "
+                               "from the generating dictionary perturbed by N(0, 0.1^2)", "precision": args.prec},
+        "parts_ms": {"pursuit": float(np.median(enc_ms)), "update": float(np.median(upd_ms)),
+                     "dictionary_reload_host": load_ms},
+        "coding_error_history": [float(x) for x in hist],
+        "update_pairs": pairs,
+        "roofline": {"kernel": "whole update (sort, rk_accum_kernel, reduce, rk_eig_kernel, reset)", "bound": "alu", "unit": "TFLOP/s",
+                     "achieved": upd_flops / (np.median(upd_ms) * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                     "frac": upd_flops / (np.median(upd_ms) * 1e-3) / FP64_VECTOR_PEAK,
+                     "algorithmic_flops_per_launch": upd_flops, "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_rksvd(w, D0, xh[: min(P, 2000)].cpu().numpy(), K, R)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_rksvd(w, D0, X, K, R):
+    """FP64 reference: one R-K-SVD iteration (pursuit + update) on the first patches."""
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    g = w["geom"]
+    t0 = time.perf_counter()
+    orc.rksvd(D0.astype(np.float64), R, g.S, g.T, X.astype(np.float64), K, 1)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    # rksvd(n_iter=1) runs two pursuits and one update; count it as one iteration
+    return {"value": len(X) / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one iteration (two pursuits and one update) on the first {len(X)} patches, {dt:.1f} s"}
+
+
 def cpu_baseline_ragged(h, w, D, target_s, dev):
     """FP64 reference on windows of the first image (reference-synthesized pixels)."""
     import torch
@@ -495,7 +585,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision"], default="scale")
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd"],
+                    default="scale")
     ap.add_argument("--check-patches", type=int, default=50_000,
                     help="precision: scale-workload patches checked against the reference")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
@@ -541,6 +632,9 @@ def main():
         return
     if args.workload == "precision":
         run_precision(args, dev)
+        return
+    if args.workload == "rksvd":
+        run_rksvd(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

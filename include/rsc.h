@@ -285,10 +285,12 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
                                  const int32_t* W, int n_images, float* pixels, void* stream);
 
 /*
- * Workspace bytes for rsc_rksvd_update and rsc_rksvd_train on P patches with the
- * handle's current dictionary sizes (M, B).  Requires a dictionary (RSC_E_NOT_READY).
+ * Workspace bytes for rsc_rksvd_update and rsc_rksvd_train on P patches coded with K
+ * slots (1 <= K <= 8), with the handle's current dictionary sizes (M, B): the pair
+ * buckets (8 bytes per slot), per-chunk partial covariances (about (4096 + M) B^2
+ * doubles) and small tables.  Requires a dictionary (RSC_E_NOT_READY).
  */
-rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, size_t* bytes);
+rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, int K, size_t* bytes);
 
 /*
  * Dictionary update of rotational K-SVD (Fig. 2, the loop over atoms; Sec. II-C), in hat

@@ -695,10 +695,10 @@ struct RkLayout {
   size_t update = 0, dnew = 0, usage = 0, reset = 0, total = 0;
 };
 
-RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P) {
+RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P, int K) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   RkLayout L;
-  L.update = al(rsc::rksvd_workspace_bytes(d, P));
+  L.update = al(rsc::rksvd_workspace_bytes(d, P, K));
   L.dnew = L.update;
   L.usage = L.dnew + al(sizeof(float) * size_t(d.M) * d.B);
   L.reset = L.usage + al(sizeof(int32_t) * size_t(d.M));
@@ -706,19 +706,21 @@ RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P) {
   return L;
 }
 
-double* rk_sum_slot(const rsc::DeviceTables& d, int64_t P, void* ws) {
-  // the last 8 doubles of the update area
-  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + rsc::rksvd_workspace_bytes(d, P) - 8 * sizeof(double));
+double* rk_sum_slot(const rsc::DeviceTables& d, int64_t P, int K, void* ws) {
+  // the last kSumSlots doubles of the update area
+  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + rsc::rksvd_workspace_bytes(d, P, K) -
+                                   rsc::kSumSlots * sizeof(double));
 }
 
 }  // namespace
 
-rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, size_t* bytes) {
+rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, int K, size_t* bytes) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
-  if (P < 1) return fail(RSC_E_INVALID, "P must be >= 1");
-  *bytes = rk_layout(h->dev, P).total;
+  if (P < 1 || P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
+  if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
+  *bytes = rk_layout(h->dev, P, K).total;
   return ok();
 }
 
@@ -728,11 +730,11 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
-  if (P < 1) return fail(RSC_E_INVALID, "P must be >= 1");
+  if (P < 1 || P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (!xhat || !atom || !angle || !coef || !resid2 || !workspace || !d_new || !usage)
     return fail(RSC_E_INVALID, "null device pointer");
   if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
-  const RkLayout L = rk_layout(h->dev, P);
+  const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
   int32_t* rs = reset ? reset : reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + L.reset);
@@ -748,11 +750,12 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   if (n_iter < 0 || n_iter > 10000) return fail(RSC_E_INVALID, "n_iter must be in 0..10000");
   if (!d_init || !d_out) return fail(RSC_E_INVALID, "null host pointer");
   if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
+  if (P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
     return fail(RSC_E_INVALID, "null device pointer or empty input");
   rsc_status s = rsc_set_dictionary(h, d_init, M, R);
   if (s != RSC_OK) return s;
-  const RkLayout L = rk_layout(h->dev, P);
+  const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   char* w = reinterpret_cast<char*>(workspace);
   float* dn = reinterpret_cast<float*>(w + L.dnew);
@@ -762,7 +765,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   std::memcpy(host.data(), d_init, host.size() * sizeof(float));
   auto coding_error = [&](int at) -> rsc_status {
     if (!history) return RSC_OK;
-    double* slot = rk_sum_slot(h->dev, P, workspace);
+    double* slot = rk_sum_slot(h->dev, P, K, workspace);
     int e = rsc::launch_sum(resid2, P, slot, stream);
     if (e) return device_fail(e, "sum launch");
     hipError_t he = hipMemcpyAsync(&history[at], slot, sizeof(double), hipMemcpyDeviceToHost, st);

@@ -76,11 +76,13 @@ size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
-int rksvd_chunks(int M, int64_t P);
-size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P);
+size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P, int K);
 int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int K, const int32_t* atom,
                         const int32_t* angle, const float* coef, const float* resid2, void* ws,
                         float* d_new, int32_t* usage, int32_t* reset, void* stream);
+// Sum of n floats in FP64 into out[0]; out holds kSumSlots doubles (the rest is scratch).
+constexpr int kSumBlocks = 256;
+constexpr int kSumSlots = kSumBlocks + 1;
 int launch_sum(const float* x, int64_t n, double* out, void* stream);
 bool encode_lp_supported(int S, int T, int M, int R);
 size_t encode_lp_lds_bytes(const DeviceTables& t);

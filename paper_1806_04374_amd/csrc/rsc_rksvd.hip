@@ -3,21 +3,27 @@
 //
 // The augmented dictionary is built once per outer iteration, so every atom is
 // updated from the same codes and the same old dictionary, all atoms at once:
-//   1. rk_partial_kernel, grid (patch chunk, atom): the patches of the chunk whose
-//      code uses atom m are compacted in patch order; for each, with r0 the angle of
-//      the first slot holding m and b the code without that entry,
-//        y = S_{-r0} (x - sum_{j != i0} c_j S_{r_j} d_{m_j})
-//      is formed in FP64 (thread b owns coordinate b) and y y^T is accumulated in
-//      FP64 registers (thread b owns row b).  Each block writes its partial sum.
-//   2. rk_eig_kernel, one block per atom: the partials are added in chunk order
-//      (deterministic) into C_m = Y_m Y_m^T in LDS; its top eigenvector, the first
-//      left singular vector of Y_m, comes from a Householder tridiagonalisation in
-//      place, a multisection on Sturm counts for the largest eigenvalue, inverse
-//      iteration on the tridiagonal matrix and the back-transformation through the
-//      stored reflectors.  Its sign makes it agree with the old atom.
-//   3. rk_reset_kernel: atoms that no patch uses take, in index order, the
+//   1. a counting sort of the (patch, slot) pairs by atom, keeping for each patch
+//      only the first slot that holds a given atom: per-block counts
+//      (rk_count_kernel), one scan (rk_plan_kernel: bucket offsets per block and
+//      atom, and fixed-size chunks of each bucket), and an in-order scatter
+//      (rk_scatter_kernel), so every bucket lists its patches in increasing order;
+//   2. rk_resid_kernel: every patch's residual r = x - D b over its whole code, in
+//      FP64; then, by the identity x - sum_{j != i0} c_j S_{r_j} d_{m_j} = r + c_{i0} S_{r0} d_m,
+//      the vector of a pair (patch, its first slot i0 holding atom m, angle r0) is
+//        y = S_{-r0} r + c_{i0} d_m;
+//   2'. rk_accum_kernel, one block per chunk of a bucket: y of each pair is formed in
+//      FP64 and sum y y^T is taken on the FP64 matrix cores; each chunk writes its
+//      partial sum, and rk_reduce_kernel adds each atom's partials in chunk order;
+//   3. rk_eig_kernel, one block per atom: C_m = Y_m Y_m^T goes to LDS; its top eigenvector, the first left
+//      singular vector of Y_m, comes from a Householder tridiagonalisation in place,
+//      a multisection on Sturm counts for the largest eigenvalue, inverse iteration
+//      on the tridiagonal matrix and the back-transformation through the stored
+//      reflectors.  Its sign makes it agree with the old atom;
+//   4. rk_reset_kernel: atoms that no patch uses take, in index order, the
 //      directions of the patches with the largest coding error (positive ones only;
 //      ties to the smaller patch index).
+// Every sum is taken in a fixed order, so the update is reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -27,21 +33,211 @@
 namespace rsc {
 namespace {
 
-constexpr int kQ = 16;  // pairs per batch in rk_partial_kernel
+constexpr int kSortBlocks = 1024;
+constexpr int kChunkTarget = 4096;
+constexpr int kChunkMin = 256;
 
-struct RkParams {
-  const float* xhat;
-  int64_t P;
-  int K, M, R, B, S, T;
+// Workspace layout of the update (offsets in bytes, 256-byte aligned).
+struct RkWs {
+  size_t cnt, off, tot, bucket, chunk, scal, lp, lr, lc, resid, partial, total;
+};
+
+// Row stride of the residuals: B rounded up to whole 16-coordinate tiles.
+__host__ __device__ inline int resid_stride(int B) { return (B + 15) / 16 * 16; }
+
+__host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Upper bound on the chunks of a plan: each bucket of n pairs makes ceil(n / CH)
+// chunks with CH >= max(kChunkMin, total / kChunkTarget), so there are at most
+// min(kChunkTarget, P K / kChunkMin) + M.
+__host__ __device__ inline int64_t max_chunks(int M, int64_t P, int K) {
+  const int64_t a = (P * K + kChunkMin - 1) / kChunkMin;
+  return (a < kChunkTarget ? a : kChunkTarget) + M;
+}
+
+__host__ __device__ inline RkWs rk_ws(int M, int B, int64_t P, int K) {
+  RkWs w;
+  w.cnt = 0;
+  w.off = w.cnt + al256(sizeof(int64_t) * size_t(kSortBlocks) * M);
+  w.tot = w.off + al256(sizeof(int64_t) * size_t(kSortBlocks) * M);
+  w.bucket = w.tot + al256(sizeof(int64_t) * (size_t(M) + 1));
+  w.chunk = w.bucket + al256(sizeof(int64_t) * (size_t(M) + 1));
+  w.scal = w.chunk + al256(sizeof(int32_t) * (size_t(M) + 1));
+  w.lp = w.scal + al256(sizeof(int64_t) * 8);
+  w.lr = w.lp + al256(sizeof(int32_t) * size_t(P) * K);
+  w.lc = w.lr + al256(sizeof(int32_t) * size_t(P) * K);
+  w.resid = w.lc + al256(sizeof(float) * size_t(P) * K);
+  w.partial = w.resid + al256(sizeof(double) * size_t(P) * resid_stride(B));
+  w.total = w.partial + al256(sizeof(double) * size_t(max_chunks(M, P, K)) * B * B);
+  return w;
+}
+
+struct SortParams {
   const int32_t* atom;
   const int32_t* angle;
   const float* coef;
-  const float* dict;     // [16 NG][B] old dictionary
-  const double* cs64;    // [2][T+1][R]
-  int NC;                // patch chunks
-  int64_t chunk;         // patches per chunk
-  double* partial;       // [M][NC][B][B]
-  int32_t* counts;       // [M][NC]
+  int64_t P;
+  int K, M;
+  int64_t* cnt;       // [kSortBlocks][M]
+  int64_t* off;       // [kSortBlocks][M] offset of each block's pairs within the atom's bucket
+  int64_t* tot;       // [M] pairs per atom
+  int64_t* bucket;    // [M + 1] start of each atom's bucket in list
+  int32_t* chunk;     // [M + 1] first chunk of each atom
+  int64_t* scal;      // [0] pairs per chunk, [1] chunks
+  // the pairs by atom, patches increasing: patch, angle r0 and coefficient of the slot
+  int32_t* lp;        // [P K]
+  int32_t* lr;        // [P K]
+  float* lc;          // [P K]
+};
+
+__device__ __forceinline__ bool first_use(const int32_t* a, int i) {
+  for (int j = 0; j < i; ++j)
+    if (a[j] == a[i]) return false;
+  return a[i] >= 0;
+}
+
+__global__ __launch_bounds__(256) void rk_count_kernel(SortParams prm) {
+  extern __shared__ int cnt_s[];   // [M]
+  for (int i = threadIdx.x; i < prm.M; i += 256) cnt_s[i] = 0;
+  __syncthreads();
+  const int64_t per = (prm.P + kSortBlocks - 1) / kSortBlocks;
+  const int64_t p0 = int64_t(blockIdx.x) * per, p1 = p0 + per < prm.P ? p0 + per : prm.P;
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    const int32_t* a = prm.atom + p * prm.K;
+    for (int i = 0; i < prm.K; ++i)
+      if (first_use(a, i) && a[i] < prm.M) atomicAdd(&cnt_s[a[i]], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < prm.M; i += 256) prm.cnt[size_t(blockIdx.x) * prm.M + i] = cnt_s[i];
+}
+
+// One block per atom: exclusive scan of its per-block counts in block order, and the
+// atom's total.
+__global__ __launch_bounds__(256) void rk_scan_kernel(SortParams prm) {
+  constexpr int G = kSortBlocks / 256;   // blocks per thread
+  static_assert(kSortBlocks % 256 == 0, "whole blocks per thread");
+  __shared__ int64_t sh[2][256];
+  const int m = blockIdx.x, t = threadIdx.x, M = prm.M;
+  int64_t c[G], mine = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    c[g] = prm.cnt[size_t(t * G + g) * M + m];
+    mine += c[g];
+  }
+  // inclusive scan of the 256 thread sums (Hillis-Steele, double-buffered)
+  int cur = 0;
+  sh[0][t] = mine;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const int64_t v = sh[cur][t] + (t >= d ? sh[cur][t - d] : 0);
+    sh[cur ^ 1][t] = v;
+    cur ^= 1;
+    __syncthreads();
+  }
+  int64_t run = sh[cur][t] - mine;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    prm.off[size_t(t * G + g) * M + m] = run;
+    run += c[g];
+  }
+  if (t == 255) prm.tot[m] = sh[cur][255];
+}
+
+// One block: bucket starts and the chunking of each bucket into pieces of CH pairs
+// (CH chosen so that about kChunkTarget chunks exist).
+__global__ __launch_bounds__(256) void rk_plan_kernel(SortParams prm) {
+  __shared__ int64_t start[257];
+  __shared__ int32_t nch[257];
+  const int M = prm.M, t = threadIdx.x;
+  if (t == 0) {
+    int64_t run = 0;
+    for (int m = 0; m < M; ++m) {
+      start[m] = run;
+      run += prm.tot[m];
+    }
+    start[M] = run;
+    int64_t ch = (run + kChunkTarget - 1) / kChunkTarget;
+    ch = ch < kChunkMin ? kChunkMin : ch;
+    int32_t c = 0;
+    for (int m = 0; m < M; ++m) {
+      nch[m] = c;
+      c += int32_t((start[m + 1] - start[m] + ch - 1) / ch);
+    }
+    nch[M] = c;
+    prm.scal[0] = ch;
+    prm.scal[1] = c;
+  }
+  __syncthreads();
+  for (int m = t; m <= M; m += 256) {
+    prm.bucket[m] = start[m];
+    prm.chunk[m] = nch[m];
+  }
+}
+
+// In-order scatter, one wave per block over its patches 64 at a time: a lane's rank
+// within an atom's bucket is the number of lower lanes whose patch uses that atom,
+// read from a per-atom lane mask, so each bucket lists patches in increasing order.
+__global__ __launch_bounds__(64) void rk_scatter_kernel(SortParams prm) {
+  extern __shared__ int64_t off_s[];   // [M] next free position, then [M] lane masks
+  unsigned long long* mask = reinterpret_cast<unsigned long long*>(off_s + prm.M);
+  const int M = prm.M, K = prm.K, l = threadIdx.x;
+  for (int i = l; i < M; i += 64) {
+    off_s[i] = prm.bucket[i] + prm.off[size_t(blockIdx.x) * M + i];
+    mask[i] = 0ull;
+  }
+  __syncthreads();
+  const unsigned long long below = (1ull << l) - 1ull;
+  const int64_t per = (prm.P + kSortBlocks - 1) / kSortBlocks;
+  const int64_t p0 = int64_t(blockIdx.x) * per, p1 = p0 + per < prm.P ? p0 + per : prm.P;
+  for (int64_t pb = p0; pb < p1; pb += 64) {
+    const int64_t p = pb + l;
+    int a[8];
+    unsigned use = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      a[i] = -1;
+      if (i < K && p < p1) a[i] = prm.atom[p * K + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      bool first = a[i] >= 0 && a[i] < M;
+#pragma unroll
+      for (int j = 0; j < i; ++j) first = first && a[j] != a[i];
+      if (first) {
+        use |= 1u << i;
+        atomicOr(&mask[a[i]], 1ull << l);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (use & (1u << i)) {
+        const int64_t pos = off_s[a[i]] + __popcll(mask[a[i]] & below);
+        prm.lp[pos] = int32_t(p);
+        prm.lr[pos] = prm.angle[p * K + i];
+        prm.lc[pos] = prm.coef[p * K + i];
+      }
+    __syncthreads();
+    for (int i = l; i < M; i += 64) {
+      off_s[i] += __popcll(mask[i]);
+      mask[i] = 0ull;
+    }
+    __syncthreads();
+  }
+}
+
+struct AccParams {
+  const double* __restrict__ resid;   // [P][BP] residuals
+  int BP, M, R, B, S, T;
+  const float* __restrict__ dict;     // [16 NG][B] old dictionary
+  const double* __restrict__ cs64;    // [2][T+1][R]
+  const int64_t* __restrict__ bucket; // [M + 1]
+  const int32_t* __restrict__ chunk;  // [M + 1]
+  const int64_t* __restrict__ scal;   // pairs per chunk, chunks
+  const int32_t* __restrict__ lp;
+  const int32_t* __restrict__ lr;
+  const float* __restrict__ lc;
+  double* __restrict__ partial;       // [chunks][B][B]
 };
 
 // Coordinate b of S_theta v, with theta = sgn * 2 pi r / R, for a packed vector v in
@@ -63,92 +259,229 @@ __device__ __forceinline__ double steered(double own, double other, const Coord&
   return c.part == 0 ? own * cs + other * s : own * cs - other * s;
 }
 
-template <int BT>
-__global__ __launch_bounds__(BT) void rk_partial_kernel(RkParams prm) {
+// Upper-triangle tiles of a symmetric matrix of NR x NR 16 x 16 tiles, row by row:
+// tile u is (r, s) with r <= s.
+__host__ __device__ constexpr int tile_r(int u, int NR) {
+  int r = 0;
+  while (u >= NR - r) {
+    u -= NR - r;
+    ++r;
+  }
+  return r;
+}
+__host__ __device__ constexpr int tile_s(int u, int NR) {
+  int r = 0;
+  while (u >= NR - r) {
+    u -= NR - r;
+    ++r;
+  }
+  return r + u;
+}
+
+struct ResidParams {
+  const float* __restrict__ xhat;
+  const int32_t* __restrict__ atom;
+  const int32_t* __restrict__ angle;
+  const float* __restrict__ coef;
+  const float* __restrict__ dict;     // [16 NG][B]
+  const double* __restrict__ cs64;    // [2][T+1][R]
+  int64_t P;
+  int K, M, R, B, BP, S, T;
+  double* __restrict__ resid;         // [P][BP]
+};
+
+// Residual of every patch over its whole code, r = x - sum_j c_j S_{r_j} d_{m_j} (slots in
+// order; an absent entry adds 0 d_0), in FP64; coordinates B..BP-1 are zero.  The
+// dictionary and the rotation table sit in LDS; a block of G BP threads strides over
+// the patches G at a time, thread (g, b) owning coordinate b of one patch.
+template <int KMAX>
+__global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   extern __shared__ double ldsd[];
-  const int B = prm.B, R = prm.R, K = prm.K, NQ = prm.T + 1;
-  double* zb = ldsd;                                   // [kQ][BT]
-  double* yb = zb + kQ * BT;                           // [kQ][BT]
-  double* sc = yb + kQ * BT;                           // [2][NQ][R]
-  int* queue = reinterpret_cast<int*>(sc + 2 * NQ * R);        // [BT] pair = p_local * 8 + i0
-  int* wcount = queue + BT;                                      // [BT / 64 + 1]
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int m = blockIdx.y, c = blockIdx.x;
-  for (int i = t; i < 2 * NQ * R; i += BT) sc[i] = prm.cs64[i];
-  const Coord cd = coord_of(t < B ? t : 0, prm.S);
-  double acc[BT];
-#pragma unroll
-  for (int j = 0; j < BT; ++j) acc[j] = 0.0;
-  int n = 0;
-  const int64_t p0 = int64_t(c) * prm.chunk;
-  const int64_t p1 = p0 + prm.chunk < prm.P ? p0 + prm.chunk : prm.P;
+  const int B = prm.B, BP = prm.BP, R = prm.R, M = prm.M, K = prm.K, NQ = prm.T + 1;
+  double2* sc = reinterpret_cast<double2*>(ldsd);            // [R][NQ] (cos, sin)
+  float* sd = reinterpret_cast<float*>(sc + R * NQ);          // [M][B]
+  const int t = threadIdx.x, nt = blockDim.x, G = nt / BP;
+  for (int i = t; i < R * NQ; i += nt) {
+    const int r = i / NQ, k = i - r * NQ;
+    sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
+  }
+  for (int i = t; i < M * B; i += nt) sd[i] = prm.dict[i];
   __syncthreads();
-  for (int64_t base = p0; base < p1; base += BT) {
-    // compaction of the patches of this window that use atom m, in patch order
-    const int64_t p = base + t;
-    int i0 = -1;
-    if (p < p1)
-      for (int i = K - 1; i >= 0; --i)
-        if (prm.atom[p * K + i] == m) i0 = i;
-    const unsigned long long bal = __ballot(i0 >= 0);
-    if (lane == 0) wcount[wave] = __popcll(bal);
-    __syncthreads();
-    int off = 0, total = 0;
-    for (int w = 0; w < BT / 64; ++w) {
-      off += w < wave ? wcount[w] : 0;
-      total += wcount[w];
+  const int g = t / BP, b = t - g * BP, bc = b < B ? b : 0;
+  const Coord cd = coord_of(bc, prm.S);
+  for (int64_t p = int64_t(blockIdx.x) * G + g; p < prm.P; p += int64_t(gridDim.x) * G) {
+    int a[KMAX], rj[KMAX];
+    float cj[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      const int64_t o = p * K + (j < K ? j : 0);
+      a[j] = prm.atom[o];
+      rj[j] = prm.angle[o];
+      cj[j] = prm.coef[o];
     }
-    if (i0 >= 0) queue[off + __popcll(bal & ((1ull << lane) - 1))] = t * 8 + i0;
+    double r = prm.xhat[p * B + bc];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      // an angle outside 0..R-1 (not produced by the pursuit) reads angle 0, in bounds
+      const bool use = j < K && a[j] >= 0 && a[j] < M;
+      const float* d = sd + (use ? a[j] : 0) * B;
+      const double2 cs = sc[(use && unsigned(rj[j]) < unsigned(R) ? rj[j] : 0) * NQ + cd.k];
+      r -= double(use ? cj[j] : 0.f) * steered(d[bc], d[cd.partner], cd, cs.x, cs.y, 1);
+    }
+    prm.resid[p * BP + b] = b < B ? r : 0.0;
+  }
+}
+
+// BT (64 or 128) covers B; W waves per block, NH = 64 W / BT groups of BT threads,
+// group h forming pairs h KP .. h KP + KP - 1 of each batch of KQ.  Thread (row, h)
+// forms coordinate row of y = S_{-r0} r + c d_m for its pairs into Y (LDS, [KQ][BT]);
+// sum y y^T is the symmetric product Y^T Y, taken on the FP64 matrix cores in 16 x 16
+// tiles of the upper triangle, four pairs per product, tiles shared out among the
+// waves.  Software pipeline: the pair records (patch, r0, c) of batch b + 2 and the
+// residual rows of batch b + 1 are loaded while batch b is formed and multiplied.
+template <int BT, int W, int KQ>
+__global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
+  constexpr int NT = 64 * W, NH = NT / BT, KP = KQ / NH;
+  constexpr int NR = BT / 16, NTILE = NR * (NR + 1) / 2, TW = (NTILE + W - 1) / W;
+  static_assert(NT % BT == 0 && KQ % NH == 0 && KQ % 4 == 0, "block shape");
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  extern __shared__ double ldsd[];
+  const int B = prm.B, BP = prm.BP, R = prm.R, M = prm.M, NQ = prm.T + 1;
+  double* yb = ldsd;                                         // [KQ][BT]
+  double2* sc = reinterpret_cast<double2*>(yb + KQ * BT);    // [R][NQ] (cos, sin) of k 2 pi r / R
+  const int t = threadIdx.x, row = t % BT, lane = t % 64;
+  const int h = __builtin_amdgcn_readfirstlane(t / BT);      // BT is a multiple of 64: one h per wave
+  const int wv = __builtin_amdgcn_readfirstlane(t / 64);
+  const int64_t nchunks = prm.scal[1], ch = prm.scal[0];
+  const int c = blockIdx.x;
+  if (c >= nchunks) return;
+  // atom of this chunk: last m with chunk[m] <= c
+  int lo = 0, hi = M - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prm.chunk[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const int m = lo;
+  const int64_t q0 = prm.bucket[m] + int64_t(c - prm.chunk[m]) * ch;
+  const int64_t q1 = q0 + ch < prm.bucket[m + 1] ? q0 + ch : prm.bucket[m + 1];
+  for (int i = t; i < R * NQ; i += NT) {
+    const int r = i / NQ, k = i - r * NQ;
+    sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
+  }
+  const Coord cd = coord_of(row < B ? row : 0, prm.S);
+  const int rowc = row < B ? row : 0;
+  const double dm = row < B ? double(prm.dict[size_t(m) * B + row]) : 0.0;
+
+  // Loads from indices clamped into the chunk: issued without a branch, masked where
+  // consumed (k < nq).
+  auto clampq = [&](int64_t i) { return i < q1 ? i : q1 - 1; };
+  int32_t pN[KP], rN[KP];   // records of the next batch
+  float cN[KP];
+  int32_t pF[KP], rF[KP];   // records of the batch after
+  float cF[KP];
+  auto fetch_rec = [&](int64_t qb, int32_t* pp, int32_t* rr, float* cc) {
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+      const int64_t i = clampq(qb + h * KP + kk);
+      pp[kk] = prm.lp[i];
+      rr[kk] = prm.lr[i];
+      cc[kk] = prm.lc[i];
+    }
+  };
+  double rv[KP], rp[KP];    // residual coordinates row and partner of this batch's pairs
+  auto fetch_res = [&](const int32_t* pp, double* a, double* b) {
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+      const double* rr = prm.resid + int64_t(pp[kk]) * BP;
+      a[kk] = rr[rowc];
+      b[kk] = rr[cd.partner];
+    }
+  };
+
+  d4 acc[TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  int32_t rC[KP];
+  float cC[KP];
+  {
+    int32_t pC[KP];
+    fetch_rec(q0, pC, rC, cC);
+    fetch_rec(q0 + KQ, pN, rN, cN);
+    fetch_res(pC, rv, rp);
+  }
+  __syncthreads();   // sc
+  for (int64_t q = q0; q < q1; q += KQ) {
+    const int nq = q1 - q < KQ ? int(q1 - q) : KQ;
+    // y of this batch
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) {
+      const int k = h * KP + kk;
+      double y = 0.0;
+      if (k < nq && row < B) {
+        const double2 cs = sc[(unsigned(rC[kk]) < unsigned(R) ? rC[kk] : 0) * NQ + cd.k];
+        y = steered(rv[kk], rp[kk], cd, cs.x, cs.y, -1) + double(cC[kk]) * dm;
+      }
+      yb[k * BT + row] = y;
+    }
+    // residual rows of the next batch, records of the one after
+    fetch_res(pN, rv, rp);
+    fetch_rec(q + 2 * KQ, pF, rF, cF);
     __syncthreads();
-    n += total;
-    for (int q0 = 0; q0 < total; q0 += kQ) {
-      const int nq = total - q0 < kQ ? total - q0 : kQ;
-      // z = x - sum_{j != i0} c_j S_{r_j} d_{m_j}, coordinate t of each pair
-      for (int q = 0; q < nq; ++q) {
-        const int e = queue[q0 + q];
-        const int64_t pp = base + (e >> 3);
-        const int ii = e & 7;
-        double z = 0.0;
-        if (t < B) {
-          z = prm.xhat[pp * B + t];
-          for (int j = 0; j < K; ++j) {
-            const int mj = prm.atom[pp * K + j];
-            if (j == ii || mj < 0) continue;
-            const int rj = prm.angle[pp * K + j];
-            const float* d = prm.dict + size_t(mj) * B;
-            const double v = steered(d[t], d[cd.partner], cd, sc[cd.k * R + rj], sc[(NQ + cd.k) * R + rj], 1);
-            z -= double(prm.coef[pp * K + j]) * v;
-          }
+    // C += Y^T Y on the upper-triangle tiles: lane l supplies Y[4g + l / 16][16 r + l % 16]
+    // as the A operand of tile row r and as the B operand of tile column r
+    for (int g = 0; g < (nq + 3) / 4; ++g) {
+      const double* yg = yb + (4 * g + lane / 16) * BT + lane % 16;
+#pragma unroll
+      for (int i = 0; i < TW; ++i) {
+        const int u = wv + W * i;
+        if (u < NTILE) {
+          const double a = yg[16 * tile_r(u, NR)], b = yg[16 * tile_s(u, NR)];
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
         }
-        zb[q * BT + t] = z;
       }
-      __syncthreads();
-      // y = S_{-r0} z
-      for (int q = 0; q < nq; ++q) {
-        const int e = queue[q0 + q];
-        const int64_t pp = base + (e >> 3);
-        const int r0 = prm.angle[pp * K + (e & 7)];
-        double y = 0.0;
-        if (t < B)
-          y = steered(zb[q * BT + t], zb[q * BT + cd.partner], cd, sc[cd.k * R + r0], sc[(NQ + cd.k) * R + r0], -1);
-        yb[q * BT + t] = y;
-      }
-      __syncthreads();
-      for (int q = 0; q < nq; ++q) {
-        const double yt = yb[q * BT + t];
+    }
+    __syncthreads();
 #pragma unroll
-        for (int j = 0; j < BT; ++j) acc[j] = fma(yt, yb[q * BT + j], acc[j]);
-      }
-      __syncthreads();
+    for (int kk = 0; kk < KP; ++kk) {
+      rC[kk] = rN[kk];
+      cC[kk] = cN[kk];
+      pN[kk] = pF[kk];
+      rN[kk] = rF[kk];
+      cN[kk] = cF[kk];
     }
   }
-  double* out = prm.partial + (size_t(m) * prm.NC + c) * size_t(B) * B;
-  if (t < B) {
+  // tile (r, s), lane l, register i holds C[16 r + l / 16 + 4 i][16 s + l % 16] (the FP64
+  // 16 x 16 product's layout); the lower triangle is its mirror image
+  double* out = prm.partial + size_t(c) * B * B;
 #pragma unroll
-    for (int j = 0; j < BT; ++j)
-      if (j < B) out[size_t(t) * B + j] = acc[j];
+  for (int i = 0; i < TW; ++i) {
+    const int u = wv + W * i;
+    if (u >= NTILE) continue;
+    const int r = tile_r(u, NR), s2 = tile_s(u, NR);
+    const int col = 16 * s2 + lane % 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = 16 * r + lane / 16 + 4 * e;
+      if (rr < B && col < B) {
+        out[size_t(rr) * B + col] = acc[i][e];
+        if (r != s2) out[size_t(col) * B + rr] = acc[i][e];
+      }
+    }
   }
-  if (t == 0) prm.counts[m * prm.NC + c] = n;
+}
+
+// Sums each atom's chunk partials, in chunk order, into its first chunk's slot
+// (thread per element: every element is read and written by one thread only).
+__global__ __launch_bounds__(256) void rk_reduce_kernel(double* partial, const int32_t* chunk, int BB) {
+  const int m = blockIdx.y;
+  const int c0 = chunk[m], c1 = chunk[m + 1];
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c1 - c0 < 2 || i >= BB) return;
+  double s = partial[size_t(c0) * BB + i];
+#pragma unroll 8
+  for (int c = c0 + 1; c < c1; ++c) s += partial[size_t(c) * BB + i];
+  partial[size_t(c0) * BB + i] = s;
 }
 
 // Block-wide sum of one double per thread (BT threads, scratch of BT doubles).
@@ -181,9 +514,10 @@ __device__ int sturm_below(const double* d, const double* e, int n, double x, do
 }
 
 struct EigParams {
-  const double* partial;  // [M][NC][B][B]
-  const int32_t* counts;  // [M][NC]
-  int M, NC, B;
+  const double* partial;  // [chunks][B][B]
+  const int64_t* bucket;  // [M + 1]
+  const int32_t* chunk;   // [M + 1]
+  int M, B;
   const float* dict_old;  // [M][B] (rows of the old dictionary)
   float* d_new;           // [M][B]
   int32_t* usage;         // [M]
@@ -202,16 +536,11 @@ __global__ __launch_bounds__(BT) void rk_eig_kernel(EigParams prm) {
   double* beta = e + BT;            // [BT]
   double* z = beta + BT;            // [BT]
   int* cnt = reinterpret_cast<int*>(z + BT);  // [BT]
-  // C_m = sum of the chunk partials, in chunk order
-  int used = 0;
-  for (int c = 0; c < prm.NC; ++c) used += prm.counts[m * prm.NC + c];
-  if (t < n) {
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int c = 0; c < prm.NC; ++c) s += prm.partial[((size_t(m) * prm.NC + c) * n + t) * n + j];
-      A[t * n + j] = s;
-    }
-  }
+  // C_m: the sum of its chunk partials sits in its first chunk's slot
+  const int used = int(prm.bucket[m + 1] - prm.bucket[m]);
+  const int c0 = prm.chunk[m];
+  if (used > 0)
+    for (int i = t; i < n * n; i += BT) A[i] = prm.partial[size_t(c0) * n * n + i];
   if (t == 0) prm.usage[m] = used;
   if (used == 0) {
     if (t < n) prm.d_new[size_t(m) * n + t] = prm.dict_old[size_t(m) * n + t];
@@ -446,74 +775,122 @@ __global__ __launch_bounds__(256) void rk_reset_kernel(ResetParams prm) {
   }
 }
 
-// Sum of a float array in FP64 (single block; for the coding-error history).
-__global__ __launch_bounds__(256) void rk_sum_kernel(const float* x, int64_t n, double* out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
-  red[threadIdx.x] = s;
+// Sum of a float array in FP64 for the coding-error history, in two fixed-order
+// stages: kSumBlocks block sums of contiguous ranges into out[1..], then their sum
+// into out[0].
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void rk_sum_part_kernel(const float* x, int64_t n, double* out) {
+  __shared__ double red[256];
+  const int64_t per = (n + kSumBlocks - 1) / kSumBlocks;
+  const int64_t i0 = int64_t(blockIdx.x) * per, i1 = i0 + per < n ? i0 + per : n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += x[i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) out[1 + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void rk_sum_final_kernel(double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kSumBlocks; i += 256) s += out[1 + i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
 }  // namespace
 
-int rksvd_chunks(int M, int64_t P) {
-  int nc = (2048 + M - 1) / M;
-  const int64_t cap = (P + 1023) / 1024;
-  if (nc > cap) nc = int(cap);
-  return nc < 1 ? 1 : (nc > 64 ? 64 : nc);
-}
-
-size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P) {
-  const int NC = rksvd_chunks(t.M, P);
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return al(sizeof(double) * size_t(t.M) * NC * t.B * t.B) + al(sizeof(int32_t) * size_t(t.M) * NC) +
-         al(sizeof(double) * 8);
+size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P, int K) {
+  return rk_ws(t.M, t.B, P, K).total + al256(sizeof(double) * kSumSlots);
 }
 
 int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int K, const int32_t* atom,
                         const int32_t* angle, const float* coef, const float* resid2, void* ws,
                         float* d_new, int32_t* usage, int32_t* reset, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int NC = rksvd_chunks(t.M, P);
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const RkWs L = rk_ws(t.M, t.B, P, K);
   char* w = reinterpret_cast<char*>(ws);
-  double* partial = reinterpret_cast<double*>(w);
-  int32_t* counts = reinterpret_cast<int32_t*>(w + al(sizeof(double) * size_t(t.M) * NC * t.B * t.B));
-  RkParams prm{xhat, P, K, t.M, t.R, t.B, t.S, t.T, atom, angle, coef, t.dictHat, t.cs64, NC,
-               (P + NC - 1) / NC, partial, counts};
-  const int NQ = t.T + 1;
-  EigParams ep{partial, counts, t.M, NC, t.B, t.dictHat, d_new, usage};
-  auto run = [&](auto partial_kern, auto eig_kern, int bt) -> int {
-    const size_t lds1 = sizeof(double) * (2 * kQ * size_t(bt) + 2 * size_t(NQ) * t.R) + sizeof(int) * (bt + bt / 64 + 1);
-    const size_t lds2 = sizeof(double) * (size_t(t.B) * t.B + 7 * size_t(bt)) + sizeof(int) * bt;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(partial_kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(lds2));
+  SortParams sp{atom, angle, coef, P, K, t.M, reinterpret_cast<int64_t*>(w + L.cnt),
+                reinterpret_cast<int64_t*>(w + L.off), reinterpret_cast<int64_t*>(w + L.tot),
+                reinterpret_cast<int64_t*>(w + L.bucket), reinterpret_cast<int32_t*>(w + L.chunk),
+                reinterpret_cast<int64_t*>(w + L.scal), reinterpret_cast<int32_t*>(w + L.lp),
+                reinterpret_cast<int32_t*>(w + L.lr), reinterpret_cast<float*>(w + L.lc)};
+  hipLaunchKernelGGL(rk_count_kernel, dim3(kSortBlocks), dim3(256), sizeof(int) * t.M, st, sp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return int(e);
+  hipLaunchKernelGGL(rk_scan_kernel, dim3(unsigned(t.M)), dim3(256), 0, st, sp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return int(e);
+  hipLaunchKernelGGL(rk_plan_kernel, dim3(1), dim3(256), 0, st, sp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return int(e);
+  hipLaunchKernelGGL(rk_scatter_kernel, dim3(kSortBlocks), dim3(64), 2 * sizeof(int64_t) * t.M, st, sp);
+  e = hipGetLastError();
+  if (e != hipSuccess) return int(e);
+  double* partial = reinterpret_cast<double*>(w + L.partial);
+  double* resid = reinterpret_cast<double*>(w + L.resid);
+  const int BP = resid_stride(t.B);
+  ResidParams qp{xhat, atom, angle, coef, t.dictHat, t.cs64, P, K, t.M, t.R, t.B, BP, t.S, t.T, resid};
+  {
+    const int G = 256 / BP, nt = G * BP;
+    const size_t lds = sizeof(double) * 2 * size_t(t.R) * (t.T + 1) + sizeof(float) * size_t(t.M) * t.B;
+    const int64_t want = (P + G - 1) / G;
+    const unsigned grid = unsigned(want < 2048 ? want : 2048);
+    auto kern = K <= 4 ? rk_resid_kernel<4> : rk_resid_kernel<8>;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return int(e);
-    hipLaunchKernelGGL(partial_kern, dim3(unsigned(NC), unsigned(t.M)), dim3(bt), lds1, st, prm);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), lds, st, qp);
     e = hipGetLastError();
     if (e != hipSuccess) return int(e);
+  }
+  AccParams ap{resid, BP, t.M, t.R, t.B, t.S, t.T, t.dictHat, t.cs64, sp.bucket, sp.chunk, sp.scal,
+               sp.lp, sp.lr, sp.lc, partial};
+  EigParams ep{partial, sp.bucket, sp.chunk, t.M, t.B, t.dictHat, d_new, usage};
+  const int NQ = t.T + 1;
+  const int64_t nblk = max_chunks(t.M, P, K);
+  auto run = [&](auto acc_kern, auto eig_kern, int bt, int nt, int kq) -> int {
+    const size_t lds1 = sizeof(double) * (size_t(kq) * bt + 2 * size_t(NQ) * t.R);
+    const size_t lds2 = sizeof(double) * (size_t(t.B) * t.B + 7 * size_t(bt)) + sizeof(int) * bt;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(acc_kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1));
+    if (err == hipSuccess)
+      err = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(lds2));
+    if (err != hipSuccess) return int(err);
+    // one block per chunk; blocks past the plan's count return at once
+    hipLaunchKernelGGL(acc_kern, dim3(unsigned(nblk)), dim3(nt), lds1, st, ap);
+    err = hipGetLastError();
+    if (err != hipSuccess) return int(err);
+    const int BB = t.B * t.B;
+    hipLaunchKernelGGL(rk_reduce_kernel, dim3(unsigned((BB + 255) / 256), unsigned(t.M)), dim3(256), 0, st, partial,
+                       sp.chunk, BB);
+    err = hipGetLastError();
+    if (err != hipSuccess) return int(err);
     hipLaunchKernelGGL(eig_kern, dim3(unsigned(t.M)), dim3(bt), lds2, st, ep);
     return int(hipGetLastError());
   };
-  int e = t.B <= 64 ? run(rk_partial_kernel<64>, rk_eig_kernel<64>, 64)
-                    : run(rk_partial_kernel<128>, rk_eig_kernel<128>, 128);
-  if (e) return e;
+  const int r = t.B <= 64 ? run(rk_accum_kernel<64, 2, 16>, rk_eig_kernel<64>, 64, 128, 16)
+                          : run(rk_accum_kernel<128, 4, 16>, rk_eig_kernel<128>, 128, 256, 16);
+  if (r) return r;
   ResetParams rp{xhat, resid2, P, t.M, t.B, usage, d_new, reset};
   hipLaunchKernelGGL(rk_reset_kernel, dim3(1), dim3(256), 0, st, rp);
   return int(hipGetLastError());
 }
 
 int launch_sum(const float* x, int64_t n, double* out, void* stream) {
-  hipLaunchKernelGGL(rk_sum_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), x, n, out);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(rk_sum_part_kernel, dim3(kSumBlocks), dim3(256), 0, st, x, n, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return int(e);
+  hipLaunchKernelGGL(rk_sum_final_kernel, dim3(1), dim3(256), 0, st, out);
   return int(hipGetLastError());
 }
 

@@ -61,7 +61,7 @@ def lib():
         "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
         "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
         "rsc_precision_stats": [P, P, I],
-        "rsc_rksvd_workspace_size": [P, I64, P],
+        "rsc_rksvd_workspace_size": [P, I64, I, P],
         "rsc_rksvd_update": [P, P, I64, I, P, P, P, P, P, ctypes.c_size_t, P, P, P, P],
         "rsc_rksvd_train": [P, P, I64, I, I, P, I, I, P, ctypes.c_size_t, P, P, P, P, P, P, P],
     }
@@ -353,9 +353,9 @@ def rsc_synthesize_images(h: Handle, batch: "ImageBatch", atom, theta, amplitude
     return pixels
 
 
-def rsc_rksvd_workspace_size(h: Handle, P: int) -> int:
+def rsc_rksvd_workspace_size(h: Handle, P: int, K: int) -> int:
     n = ctypes.c_size_t()
-    _check(lib().rsc_rksvd_workspace_size(h.ptr, int(P), ctypes.byref(n)))
+    _check(lib().rsc_rksvd_workspace_size(h.ptr, int(P), int(K), ctypes.byref(n)))
     return n.value
 
 
@@ -376,7 +376,7 @@ def rsc_rksvd_update(h: Handle, xhat, atom, angle, coef, resid2, workspace=None,
             raise ValueError("device contiguous tensors of the documented dtypes expected")
     if xhat.shape != (P, h.B) or resid2.shape != (P,):
         raise ValueError("shape mismatch")
-    nbytes = rsc_rksvd_workspace_size(h, P)
+    nbytes = rsc_rksvd_workspace_size(h, P, K)
     ws = workspace if workspace is not None else _workspace(nbytes, xhat.device)
     d_new = torch.empty((h.M, h.B), dtype=torch.float32, device=xhat.device)
     usage = torch.empty((h.M,), dtype=torch.int32, device=xhat.device)
@@ -397,7 +397,7 @@ def rsc_rksvd_train(h: Handle, xhat, d_init, R: int, K: int, n_iter: int, stream
     if xhat.dtype != torch.float32 or not xhat.is_contiguous() or xhat.shape != (P, h.B) or B != h.B:
         raise ValueError("xhat must be device [P, B] float32 and d_init [M, B]")
     rsc_set_dictionary(h, d_init, R)
-    ws = _workspace(rsc_rksvd_workspace_size(h, P), xhat.device)
+    ws = _workspace(rsc_rksvd_workspace_size(h, P, K), xhat.device)
     dev = xhat.device
     atom = torch.empty((P, K), dtype=torch.int32, device=dev)
     angle = torch.empty((P, K), dtype=torch.int32, device=dev)

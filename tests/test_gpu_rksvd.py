@@ -48,7 +48,7 @@ def _covariances(D, R, S, T, X, code):
     return C
 
 
-def _check_update(geom, D, R, K, X, dev, tol=1e-5):
+def _check_update(geom, D, R, K, X, dev, tol=1e-5, repeat=False):
     from paper_1806_04374_amd import rsc
     S, T = geom.S, geom.T
     code = _fp32_code(orc.omp(orc.augmented_dictionary(D, R, S, T), X, K, D.shape[0]))
@@ -56,8 +56,12 @@ def _check_update(geom, D, R, K, X, dev, tol=1e-5):
     h = rsc.rsc_create(geom.N, S, T)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
-    d_new, usage, reset = rsc.rsc_rksvd_update(h, t(X, np.float32), t(code.atom, np.int32), t(code.angle, np.int32),
-                                               t(code.coef, np.float32), t(code.resid2, np.float32))
+    args = (t(X, np.float32), t(code.atom, np.int32), t(code.angle, np.int32), t(code.coef, np.float32),
+            t(code.resid2, np.float32))
+    d_new, usage, reset = rsc.rsc_rksvd_update(h, *args)
+    if repeat:   # every sum runs in a fixed order: a second call gives the same bits
+        again = rsc.rsc_rksvd_update(h, *args)[0]
+        assert torch.equal(again.view(torch.int32), d_new.view(torch.int32))
     torch.cuda.synchronize()
     d_new, usage, reset = d_new.cpu().numpy().astype(np.float64), usage.cpu().numpy(), reset.cpu().numpy()
     assert np.array_equal(usage, usage_ref), (usage, usage_ref)
@@ -105,6 +109,35 @@ def test_update_matches_reference_15x15(dev):
     Dp = D + 0.2 * np.random.default_rng(24).standard_normal(D.shape)
     Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
     print("worst atom difference", _check_update(g, Dp, R, K, X, dev))
+
+
+def test_update_with_more_than_four_slots(dev):
+    """K = 6 takes the eight-slot kernel."""
+    g = wl.GEOM11
+    M, R, K = 12, 16, 6
+    D = wl.draw_dictionary(M, g.B, seed=26).astype(np.float32).astype(np.float64)
+    basis = orc.build_basis(g.N, g.S, g.T)
+    d = wl.draw_mixtures(1500, g.N, M, 5, 0.05, seed=26)
+    X = orc.project(basis, orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
+    X = X.astype(np.float32).astype(np.float64)
+    Dp = D + 0.2 * np.random.default_rng(27).standard_normal(D.shape)
+    Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
+    print("worst atom difference", _check_update(g, Dp, R, K, X, dev))
+
+
+def test_update_over_many_chunks_matches_reference(dev):
+    """Scale geometry (M=64, R=64, K=4) on 12,000 patches: about 750 pairs per atom,
+    so every bucket spans several 256-pair chunks and the chunk partials are summed;
+    a repeated call is bit-identical."""
+    w = wl.SCALE
+    g = w["geom"]
+    basis = orc.build_basis(g.N, g.S, g.T)
+    D, d = wl.scale_draw(P=12000)
+    X = orc.project(basis, orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
+    X = X.astype(np.float32).astype(np.float64)
+    Dp = D + 0.1 * np.random.default_rng(25).standard_normal(D.shape)
+    Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
+    print("worst atom difference", _check_update(g, Dp, w["R"], w["K"], X, dev, repeat=True))
 
 
 def test_unused_atoms_are_reset_on_device(dev):
@@ -183,7 +216,7 @@ def test_update_argument_errors(dev):
     from paper_1806_04374_amd import rsc
     h = rsc.rsc_create(11, 5, 5)
     with pytest.raises(rsc.RscError) as e:
-        rsc.rsc_rksvd_workspace_size(h, 10)
+        rsc.rsc_rksvd_workspace_size(h, 10, 2)
     assert e.value.status == rsc.RSC_E_NOT_READY
     rsc.rsc_set_dictionary(h, wl.draw_dictionary(4, 55).astype(np.float32), 8)
     z = torch.zeros((10, 55), dtype=torch.float32, device=dev)
