@@ -42,8 +42,9 @@ struct RkWs {
   size_t cnt, off, tot, bucket, chunk, scal, lp, lr, lc, resid, partial, total;
 };
 
-// Row stride of the residuals: B rounded up to whole 16-coordinate tiles.
-__host__ __device__ inline int resid_stride(int B) { return (B + 15) / 16 * 16; }
+// Row stride of the residuals: one or two whole waves per patch, so that a wave's
+// patch index is uniform (its code entries come through scalar loads).
+__host__ __device__ inline int resid_stride(int B) { return B <= 64 ? 64 : 128; }
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -252,11 +253,13 @@ __device__ __forceinline__ Coord coord_of(int b, int S) {
   return rem < S ? Coord{k, 0, b + S} : Coord{k, 1, b - S};
 }
 
-__device__ __forceinline__ double steered(double own, double other, const Coord& c, double cs, double sn, int sgn) {
-  if (c.k == 0) return own;
-  const double s = sgn * sn;
-  // (a + i b) exp(-i k theta): Re' = a cos + b sin, Im' = b cos - a sin
-  return c.part == 0 ? own * cs + other * s : own * cs - other * s;
+// Coordinate of S_theta v, theta = sgn 2 pi r / R, from the coordinate's own value, its
+// partner's and (cos, sin) of k theta for its harmonic k: harmonic k is multiplied by
+// exp(-i k theta), so Re' = a cos + b sin and Im' = b cos - a sin, i.e. sigma = +sgn for a
+// real part and -sgn for an imaginary part.  For harmonic 0 the table holds
+// (cos, sin) = (1, 0), which returns own exactly.
+__device__ __forceinline__ double rot(double own, double other, double cs, double sn, double sigma) {
+  return fma(own, cs, other * (sigma * sn));
 }
 
 // Upper-triangle tiles of a symmetric matrix of NR x NR 16 x 16 tiles, row by row:
@@ -299,36 +302,53 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   extern __shared__ double ldsd[];
   const int B = prm.B, BP = prm.BP, R = prm.R, M = prm.M, K = prm.K, NQ = prm.T + 1;
   double2* sc = reinterpret_cast<double2*>(ldsd);            // [R][NQ] (cos, sin)
-  float* sd = reinterpret_cast<float*>(sc + R * NQ);          // [M][B]
+  float2* sd = reinterpret_cast<float2*>(sc + R * NQ);        // [M][B] (d_b, d_partner(b))
   const int t = threadIdx.x, nt = blockDim.x, G = nt / BP;
   for (int i = t; i < R * NQ; i += nt) {
     const int r = i / NQ, k = i - r * NQ;
     sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
   }
-  for (int i = t; i < M * B; i += nt) sd[i] = prm.dict[i];
+  for (int i = t; i < M * B; i += nt) {
+    const int a = i / B, bb = i - a * B;
+    sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.S).partner]};
+  }
   __syncthreads();
-  const int g = t / BP, b = t - g * BP, bc = b < B ? b : 0;
+  const int g = __builtin_amdgcn_readfirstlane(t / BP), b = t - g * BP, bc = b < B ? b : 0;
   const Coord cd = coord_of(bc, prm.S);
-  for (int64_t p = int64_t(blockIdx.x) * G + g; p < prm.P; p += int64_t(gridDim.x) * G) {
-    int a[KMAX], rj[KMAX];
-    float cj[KMAX];
+  const double sig = cd.part == 0 ? 1.0 : -1.0;
+  // Two patches per wave and pass.  Lane j of the wave loads code entry j of each (a
+  // vector load, so no wait on the shared LDS/scalar counter), and the entries are
+  // broadcast with readlane; every load is issued before any value is used.
+  constexpr int U = 2;
+  const int64_t stride = int64_t(gridDim.x) * G;
+  const int lane = t % 64, jl = lane < K ? lane : 0;
+  for (int64_t p0 = int64_t(blockIdx.x) * G + g; p0 < prm.P; p0 += U * stride) {
+    int av[U], rv[U];
+    float cv[U];
+    double r[U];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      const int64_t o = p * K + (j < K ? j : 0);
-      a[j] = prm.atom[o];
-      rj[j] = prm.angle[o];
-      cj[j] = prm.coef[o];
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = p0 + u * stride < prm.P ? p0 + u * stride : p0;
+      av[u] = prm.atom[p * K + jl];
+      rv[u] = prm.angle[p * K + jl];
+      cv[u] = prm.coef[p * K + jl];
+      r[u] = prm.xhat[p * B + bc];
     }
-    double r = prm.xhat[p * B + bc];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      // an angle outside 0..R-1 (not produced by the pursuit) reads angle 0, in bounds
-      const bool use = j < K && a[j] >= 0 && a[j] < M;
-      const float* d = sd + (use ? a[j] : 0) * B;
-      const double2 cs = sc[(use && unsigned(rj[j]) < unsigned(R) ? rj[j] : 0) * NQ + cd.k];
-      r -= double(use ? cj[j] : 0.f) * steered(d[bc], d[cd.partner], cd, cs.x, cs.y, 1);
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int j = 0; j < KMAX; ++j) {
+        const int aj = __builtin_amdgcn_readlane(av[u], j), rj = __builtin_amdgcn_readlane(rv[u], j);
+        const float cj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cv[u]), j));
+        // an angle outside 0..R-1 (not produced by the pursuit) reads angle 0, in bounds
+        const bool use = j < K && aj >= 0 && aj < M;
+        const float2 dd = sd[(use ? aj : 0) * B + bc];
+        const double2 cs = sc[(use && unsigned(rj) < unsigned(R) ? rj : 0) * NQ + cd.k];
+        r[u] = fma(-double(use ? cj : 0.f), rot(dd.x, dd.y, cs.x, cs.y, sig), r[u]);
+      }
+      const int64_t p = p0 + u * stride;
+      if (p < prm.P) prm.resid[p * BP + b] = b < B ? r[u] : 0.0;
     }
-    prm.resid[p * BP + b] = b < B ? r : 0.0;
   }
 }
 
@@ -372,40 +392,46 @@ __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
   const Coord cd = coord_of(row < B ? row : 0, prm.S);
   const int rowc = row < B ? row : 0;
   const double dm = row < B ? double(prm.dict[size_t(m) * B + row]) : 0.0;
+  const double sig = cd.part == 0 ? -1.0 : 1.0;   // turning back by -r0
 
   // Loads from indices clamped into the chunk: issued without a branch, masked where
   // consumed (k < nq).
   auto clampq = [&](int64_t i) { return i < q1 ? i : q1 - 1; };
-  int32_t pN[KP], rN[KP];   // records of the next batch
-  float cN[KP];
-  int32_t pF[KP], rF[KP];   // records of the batch after
-  float cF[KP];
-  auto fetch_rec = [&](int64_t qb, int32_t* pp, int32_t* rr, float* cc) {
-#pragma unroll
-    for (int kk = 0; kk < KP; ++kk) {
-      const int64_t i = clampq(qb + h * KP + kk);
-      pp[kk] = prm.lp[i];
-      rr[kk] = prm.lr[i];
-      cc[kk] = prm.lc[i];
-    }
+  // Pair records (patch, r0, c) of a batch: lane kk of each wave loads pair h KP + kk (a
+  // vector load: scalar loads would share the LDS wait counter and be waited for at
+  // the first LDS access), and readlane broadcasts them.
+  const int lk = lane % KP;
+  int32_t pN, rN, pF, rF;   // records of the next batch and of the one after
+  float cN, cF;
+  auto fetch_rec = [&](int64_t qb, int32_t& pp, int32_t& rr, float& cc) {
+    const int64_t i = clampq(qb + h * KP + lk);
+    pp = prm.lp[i];
+    rr = prm.lr[i];
+    cc = prm.lc[i];
   };
   double rv[KP], rp[KP];    // residual coordinates row and partner of this batch's pairs
-  auto fetch_res = [&](const int32_t* pp, double* a, double* b) {
+  auto fetch_res = [&](int32_t pp, double* a, double* b) {
 #pragma unroll
     for (int kk = 0; kk < KP; ++kk) {
-      const double* rr = prm.resid + int64_t(pp[kk]) * BP;
+      const double* rr = prm.resid + int64_t(__builtin_amdgcn_readlane(pp, kk)) * BP;
       a[kk] = rr[rowc];
       b[kk] = rr[cd.partner];
     }
   };
 
   d4 acc[TW];
+  int ta[TW], tb[TW];   // LDS offsets of this wave's tiles' row and column blocks (-1: no tile)
 #pragma unroll
-  for (int i = 0; i < TW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-  int32_t rC[KP];
-  float cC[KP];
+  for (int i = 0; i < TW; ++i) {
+    acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    const int u = wv + W * i;
+    ta[i] = u < NTILE ? 16 * tile_r(u, NR) : -1;
+    tb[i] = u < NTILE ? 16 * tile_s(u, NR) : -1;
+  }
+  int32_t rC;
+  float cC;
   {
-    int32_t pC[KP];
+    int32_t pC;
     fetch_rec(q0, pC, rC, cC);
     fetch_rec(q0 + KQ, pN, rN, cN);
     fetch_res(pC, rv, rp);
@@ -419,8 +445,10 @@ __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
       const int k = h * KP + kk;
       double y = 0.0;
       if (k < nq && row < B) {
-        const double2 cs = sc[(unsigned(rC[kk]) < unsigned(R) ? rC[kk] : 0) * NQ + cd.k];
-        y = steered(rv[kk], rp[kk], cd, cs.x, cs.y, -1) + double(cC[kk]) * dm;
+        const int r0 = __builtin_amdgcn_readlane(rC, kk);
+        const float c0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cC), kk));
+        const double2 cs = sc[(unsigned(r0) < unsigned(R) ? r0 : 0) * NQ + cd.k];
+        y = fma(double(c0), dm, rot(rv[kk], rp[kk], cs.x, cs.y, sig));
       }
       yb[k * BT + row] = y;
     }
@@ -433,23 +461,15 @@ __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
     for (int g = 0; g < (nq + 3) / 4; ++g) {
       const double* yg = yb + (4 * g + lane / 16) * BT + lane % 16;
 #pragma unroll
-      for (int i = 0; i < TW; ++i) {
-        const int u = wv + W * i;
-        if (u < NTILE) {
-          const double a = yg[16 * tile_r(u, NR)], b = yg[16 * tile_s(u, NR)];
-          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
-        }
-      }
+      for (int i = 0; i < TW; ++i)
+        if (NTILE % W == 0 || ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(yg[ta[i]], yg[tb[i]], acc[i], 0, 0, 0);
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KP; ++kk) {
-      rC[kk] = rN[kk];
-      cC[kk] = cN[kk];
-      pN[kk] = pF[kk];
-      rN[kk] = rF[kk];
-      cN[kk] = cF[kk];
-    }
+    rC = rN;
+    cC = cN;
+    pN = pF;
+    rN = rF;
+    cN = cF;
   }
   // tile (r, s), lane l, register i holds C[16 r + l / 16 + 4 i][16 s + l % 16] (the FP64
   // 16 x 16 product's layout); the lower triangle is its mirror image
@@ -841,7 +861,7 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
   ResidParams qp{xhat, atom, angle, coef, t.dictHat, t.cs64, P, K, t.M, t.R, t.B, BP, t.S, t.T, resid};
   {
     const int G = 256 / BP, nt = G * BP;
-    const size_t lds = sizeof(double) * 2 * size_t(t.R) * (t.T + 1) + sizeof(float) * size_t(t.M) * t.B;
+    const size_t lds = sizeof(double) * 2 * size_t(t.R) * (t.T + 1) + sizeof(float) * 2 * size_t(t.M) * t.B;
     const int64_t want = (P + G - 1) / G;
     const unsigned grid = unsigned(want < 2048 ? want : 2048);
     auto kern = K <= 4 ? rk_resid_kernel<4> : rk_resid_kernel<8>;
@@ -851,8 +871,8 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
     e = hipGetLastError();
     if (e != hipSuccess) return int(e);
   }
-  AccParams ap{resid, BP, t.M, t.R, t.B, t.S, t.T, t.dictHat, t.cs64, sp.bucket, sp.chunk, sp.scal,
-               sp.lp, sp.lr, sp.lc, partial};
+  AccParams ap{resid,     BP,        t.M,     t.R,   t.B,   t.S,   t.T,  t.dictHat, t.cs64,
+               sp.bucket, sp.chunk, sp.scal, sp.lp, sp.lr, sp.lc, partial};
   EigParams ep{partial, sp.bucket, sp.chunk, t.M, t.B, t.dictHat, d_new, usage};
   const int NQ = t.T + 1;
   const int64_t nblk = max_chunks(t.M, P, K);
