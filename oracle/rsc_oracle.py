@@ -57,6 +57,15 @@ Readings where the paper is silent (each one is listed in the design notes):
     with a positive error qualify, and an unused atom keeps its value when none
     is left.  After the last iteration the pursuit runs once more so that the
     codes belong to the final dictionary.
+  * Texture classifier (Sec. III-B, "Classifier"): a patch's "sum squared error"
+    under a class dictionary is the pursuit's own squared residual in hat
+    coordinates, ||x_hat - D_aug b||^2 (what the coder minimises; in pixels it
+    differs by a class-independent term and the basis Gram weighting).  Label =
+    the class of smallest error, ties to the smaller class index.  An image's
+    feature is its label histogram normalised to frequencies (the paper's images
+    all have one size, where counts and frequencies rank neighbours alike).
+    chi^2 terms with a[i] + b[i] = 0 are 0.  The nearest neighbour's ties go to
+    the smaller training index.
 """
 from __future__ import annotations
 
@@ -441,3 +450,53 @@ def rksvd(D_init: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, K: int, 
     code = omp(augmented_dictionary(D, R, S, T), xhat, K, M, tau)
     history.append(float(code.resid2.sum()))
     return D, code, history
+
+
+# --------------------------------------------------------------------------- classifier
+def classify(D_list, R: int, S: int, T: int, xhat: np.ndarray, K: int, tau: float = TAU):
+    """Label of every patch: the class whose dictionary codes it with the smallest
+    squared error (Sec. III-B, "Classifier"; readings in the module header).
+
+    D_list: C dictionaries [M_c, B].  Returns (label [P] int, sse [P, C])."""
+    sse = []
+    for D in D_list:
+        D = np.asarray(D, dtype=np.float64)
+        code = omp(augmented_dictionary(D, R, S, T), xhat, K, D.shape[0], tau)
+        sse.append(code.resid2)
+    sse = np.stack(sse, axis=1) if sse else np.zeros((len(xhat), 0))
+    label = np.argmin(sse, axis=1) if sse.shape[1] else np.zeros(len(xhat), np.int64)
+    return label, sse
+
+
+def label_histogram(label: np.ndarray, offsets: np.ndarray, C: int) -> np.ndarray:
+    """Per group of consecutive patches [offsets[g], offsets[g+1]): the frequencies of
+    the C labels (a group without patches has all zeros)."""
+    G = len(offsets) - 1
+    hist = np.zeros((G, C))
+    for g in range(G):
+        lab = np.asarray(label[offsets[g]:offsets[g + 1]])
+        if lab.size:
+            hist[g] = np.bincount(lab, minlength=C)[:C] / lab.size
+    return hist
+
+
+def chi2(a: np.ndarray, b: np.ndarray) -> float:
+    """d(a, b) = sum_i (a_i - b_i)^2 / (a_i + b_i) over the bins with a_i + b_i > 0."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    s = a + b
+    keep = s > 0
+    return float(np.sum((a[keep] - b[keep]) ** 2 / s[keep]))
+
+
+def nearest_chi2(train: np.ndarray, test: np.ndarray):
+    """For each test histogram, the training histogram at the smallest chi^2 distance
+    (ties: smaller training index).  Returns (index [Q], distance [Q])."""
+    idx = np.zeros(len(test), np.int64)
+    dist = np.zeros(len(test))
+    for q in range(len(test)):
+        d = [chi2(test[q], train[j]) for j in range(len(train))]
+        idx[q] = int(np.argmin(d))
+        dist[q] = d[idx[q]]
+    return idx, dist
+
