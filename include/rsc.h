@@ -337,6 +337,63 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
                            int M, int R, void* workspace, size_t ws_bytes, int32_t* atom, int32_t* angle,
                            float* coef, float* resid2, float* d_out, double* history, void* stream);
 
+/* ------------------------------------------------------------------ texture classifier
+ * Sec. III-B ("Classifier"): one dictionary per class codes every patch; a patch's
+ * label is the class whose pursuit leaves the smallest squared error (the pursuit's
+ * hat-domain residual norm, ties to the smaller class index); an image's feature is
+ * the histogram of its patches' labels as frequencies; a test image takes the class
+ * of its chi^2-nearest training image, d(a, b) = sum_i (a_i - b_i)^2 / (a_i + b_i).
+ */
+
+/*
+ * Workspace bytes of rsc_classify for P patches and K atoms per patch (one class's
+ * codes: atom, angle, coef [P, K] and the residual norms [P]).
+ */
+rsc_status rsc_classify_workspace_size(int64_t P, int K, size_t* bytes);
+
+/*
+ * Labels of P patches against C class dictionaries: for c = 0..C-1 the pursuit of
+ * rsc_omp_encode runs with classes[c]'s dictionary, and every patch keeps the class of
+ * smallest squared error.
+ *   classes     host array of C handles, each with a dictionary (RSC_E_NOT_READY
+ *               otherwise) and the same geometry (N, S, T); their precisions and
+ *               dictionary sizes may differ
+ *   C           1 <= C <= 1024
+ *   xhat        device [P, B] float32 (rsc_project of any of the handles)
+ *   P, K        as rsc_omp_encode (K <= 8 and K <= B)
+ *   workspace   device, >= rsc_classify_workspace_size(P, K) bytes, 256-byte aligned
+ *   label       device [P] int32, written: the class index
+ *   sse         device [P] float32, written: that class's squared residual norm
+ * Everything is enqueued on the stream; nothing is allocated.
+ */
+rsc_status rsc_classify(const rsc_handle* const* classes, int C, const float* xhat, int64_t P, int K,
+                        void* workspace, size_t ws_bytes, int32_t* label, float* sse, void* stream);
+
+/*
+ * Label frequencies of groups of consecutive patches (an image's windows, numbered
+ * as rsc_project_images numbers them):
+ *   label       device [P] int32; labels outside 0..C-1 are not counted (they still
+ *               count in the group size)
+ *   offset      device int64 [n_groups + 1], nondecreasing; group g is patches
+ *               offset[g] .. offset[g+1]-1 (clamped into 0..P)
+ *   n_groups    >= 0 (0 is a no-op);  C  1 <= C <= 4096
+ *   hist        device [n_groups, C] float32: count / group size (0 for an empty group)
+ */
+rsc_status rsc_label_histogram(const int32_t* label, int64_t P, const int64_t* offset, int n_groups, int C,
+                               float* hist, void* stream);
+
+/*
+ * chi^2 nearest neighbour: for every test histogram, the training histogram at the
+ * smallest d(a, b) (computed in FP64; bins with a_i + b_i = 0 add nothing; ties to the
+ * smaller training index).
+ *   train       device [n_train, C] float32, n_train >= 1
+ *   test        device [n_test, C] float32, n_test >= 0 (0 is a no-op)
+ *   nearest     device [n_test] int32, written
+ *   dist        device [n_test] float32, written (or NULL)
+ */
+rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, int n_test, int C,
+                            int32_t* nearest, float* dist, void* stream);
+
 /*
  * Counters of the BF16 / FP16 encoder, accumulated over its launches on this handle
  * (the FP32 re-scoring of candidates and the FP64 least-squares fallback described

@@ -30,6 +30,7 @@ SOURCES = [
     ("rsc_synth.hip", "hip"),
     ("rsc_images.hip", "hip"),
     ("rsc_rksvd.hip", "hip"),
+    ("rsc_classify.hip", "hip"),
 ]
 
 

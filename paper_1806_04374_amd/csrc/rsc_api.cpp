@@ -797,6 +797,87 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   return ok();
 }
 
+namespace {
+struct ClsLayout {
+  size_t atom, angle, coef, resid, total;
+};
+ClsLayout cls_layout(int64_t P, int K) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  ClsLayout L;
+  L.atom = 0;
+  L.angle = L.atom + al(sizeof(int32_t) * size_t(P) * K);
+  L.coef = L.angle + al(sizeof(int32_t) * size_t(P) * K);
+  L.resid = L.coef + al(sizeof(float) * size_t(P) * K);
+  L.total = L.resid + al(sizeof(float) * size_t(P));
+  return L;
+}
+}  // namespace
+
+rsc_status rsc_classify_workspace_size(int64_t P, int K, size_t* bytes) {
+  if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (K < 1 || K > 8) return fail(RSC_E_INVALID, "K must be in 1..8");
+  *bytes = cls_layout(P, K).total;
+  return ok();
+}
+
+rsc_status rsc_classify(const rsc_handle* const* classes, int C, const float* xhat, int64_t P, int K,
+                        void* workspace, size_t ws_bytes, int32_t* label, float* sse, void* stream) {
+  if (!classes) return fail(RSC_E_INVALID, "classes is NULL");
+  if (C < 1 || C > 1024) return fail(RSC_E_INVALID, "C must be in 1..1024");
+  for (int c = 0; c < C; ++c) {
+    if (!classes[c]) return fail(RSC_E_INVALID, "a class handle is NULL");
+    if (!classes[c]->has_dict) return fail(RSC_E_NOT_READY, "a class handle has no dictionary");
+    const rsc::HostBasis& b0 = classes[0]->basis;
+    const rsc::HostBasis& bc = classes[c]->basis;
+    if (bc.N != b0.N || bc.S != b0.S || bc.T != b0.T)
+      return fail(RSC_E_INVALID, "class handles must share the geometry (N, S, T)");
+  }
+  if (K < 1 || K > 8 || K > classes[0]->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!xhat || !workspace || !label || !sse) return fail(RSC_E_INVALID, "null device pointer");
+  const ClsLayout L = cls_layout(P, K);
+  if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
+  char* w = static_cast<char*>(workspace);
+  int32_t* atom = reinterpret_cast<int32_t*>(w + L.atom);
+  int32_t* angle = reinterpret_cast<int32_t*>(w + L.angle);
+  float* coef = reinterpret_cast<float*>(w + L.coef);
+  float* r2 = reinterpret_cast<float*>(w + L.resid);
+  for (int c = 0; c < C; ++c) {
+    rsc_status s = rsc_omp_encode(classes[c], xhat, P, K, atom, angle, coef, r2, stream);
+    if (s != RSC_OK) return s;
+    int e = rsc::launch_classify_min(r2, P, c, label, sse, stream);
+    if (e) return device_fail(e, "classify launch");
+  }
+  return ok();
+}
+
+rsc_status rsc_label_histogram(const int32_t* label, int64_t P, const int64_t* offset, int n_groups, int C,
+                               float* hist, void* stream) {
+  if (n_groups < 0) return fail(RSC_E_INVALID, "n_groups must be >= 0");
+  if (C < 1 || C > 4096) return fail(RSC_E_INVALID, "C must be in 1..4096");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (n_groups == 0) return ok();
+  if (n_groups > (1 << 30)) return fail(RSC_E_INVALID, "too many groups");
+  if (!offset || !hist || (P > 0 && !label)) return fail(RSC_E_INVALID, "null device pointer");
+  int e = rsc::launch_label_hist(label, P, offset, n_groups, C, hist, stream);
+  return e ? device_fail(e, "histogram launch") : ok();
+}
+
+rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, int n_test, int C,
+                            int32_t* nearest, float* dist, void* stream) {
+  if (n_train < 1) return fail(RSC_E_INVALID, "n_train must be >= 1");
+  if (n_test < 0) return fail(RSC_E_INVALID, "n_test must be >= 0");
+  if (C < 1 || C > 4096) return fail(RSC_E_INVALID, "C must be in 1..4096");
+  if (n_test == 0) return ok();
+  if (n_test > (1 << 30)) return fail(RSC_E_INVALID, "too many test histograms");
+  if (!train || !test || !nearest) return fail(RSC_E_INVALID, "null device pointer");
+  int e = rsc::launch_chi2_nearest(train, n_train, test, n_test, C, nearest, dist, stream);
+  return e ? device_fail(e, "nearest-neighbour launch") : ok();
+}
+
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (h->prec == RSC_FP32 || !h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "FP32 handles keep no counters");

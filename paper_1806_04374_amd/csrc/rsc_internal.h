@@ -80,6 +80,13 @@ size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P, int K);
 int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int K, const int32_t* atom,
                         const int32_t* angle, const float* coef, const float* resid2, void* ws,
                         float* d_new, int32_t* usage, int32_t* reset, void* stream);
+// Texture classifier (rsc_classify.hip).
+int launch_classify_min(const float* resid2, int64_t P, int c, int32_t* label, float* sse, void* stream);
+int launch_label_hist(const int32_t* label, int64_t P, const int64_t* offset, int n_groups, int C, float* hist,
+                      void* stream);
+int launch_chi2_nearest(const float* train, int n_train, const float* test, int n_test, int C, int32_t* nearest,
+                        float* dist, void* stream);
+
 // Sum of n floats in FP64 into out[0]; out holds kSumSlots doubles (the rest is scratch).
 constexpr int kSumBlocks = 256;
 constexpr int kSumSlots = kSumBlocks + 1;

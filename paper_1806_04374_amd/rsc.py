@@ -64,6 +64,10 @@ def lib():
         "rsc_rksvd_workspace_size": [P, I64, I, P],
         "rsc_rksvd_update": [P, P, I64, I, P, P, P, P, P, ctypes.c_size_t, P, P, P, P],
         "rsc_rksvd_train": [P, P, I64, I, I, P, I, I, P, ctypes.c_size_t, P, P, P, P, P, P, P],
+        "rsc_classify_workspace_size": [I64, I, P],
+        "rsc_classify": [P, I, P, I64, I, P, ctypes.c_size_t, P, P, P],
+        "rsc_label_histogram": [P, I64, P, I, I, P, P],
+        "rsc_chi2_nearest": [P, I, P, I, I, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -422,3 +426,61 @@ def rsc_precision_stats(h: Handle, reset: bool = False) -> dict:
 
 def rsc_sync(stream=None):
     _check(lib().rsc_sync(_stream(stream)))
+
+
+# ------------------------------------------------------------------ texture classifier
+def rsc_classify_workspace_size(P: int, K: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().rsc_classify_workspace_size(int(P), int(K), ctypes.byref(n)))
+    return n.value
+
+
+def rsc_classify(handles, xhat, K: int, workspace=None, out=None, stream=None):
+    """Labels of the patches against the class dictionaries of `handles` (one per class).
+    Returns (label [P] int32, sse [P] f32)."""
+    import torch
+    handles = list(handles)
+    if not handles:
+        raise ValueError("need at least one class handle")
+    P = xhat.shape[0]
+    _dev(xhat, torch.float32, "xhat", (P, handles[0].B))
+    nbytes = rsc_classify_workspace_size(P, K)
+    ws = workspace if workspace is not None else _workspace(nbytes, xhat.device)
+    if out is None:
+        out = (torch.empty(P, dtype=torch.int32, device=xhat.device),
+               torch.empty(P, dtype=torch.float32, device=xhat.device))
+    label, sse = out
+    _dev(label, torch.int32, "label", (P,))
+    _dev(sse, torch.float32, "sse", (P,))
+    arr = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    _check(lib().rsc_classify(arr, len(handles), _ptr(xhat), P, K, _ptr(ws), ws.numel(), _ptr(label),
+                              _ptr(sse), _stream(stream)))
+    return label, sse
+
+
+def rsc_label_histogram(label, offset, C: int, out=None, stream=None):
+    """Label frequencies per group; offset is a device int64 [n_groups + 1] tensor."""
+    import torch
+    P = label.shape[0]
+    _dev(label, torch.int32, "label", (P,))
+    G = offset.shape[0] - 1
+    _dev(offset, torch.int64, "offset", (G + 1,))
+    if out is None:
+        out = torch.empty((G, C), dtype=torch.float32, device=label.device)
+    _dev(out, torch.float32, "hist", (G, C))
+    _check(lib().rsc_label_histogram(_ptr(label), P, _ptr(offset), G, C, _ptr(out), _stream(stream)))
+    return out
+
+
+def rsc_chi2_nearest(train, test, stream=None):
+    """Returns (nearest [Q] int32, dist [Q] f32) for device [N, C] / [Q, C] float32 histograms."""
+    import torch
+    N, C = train.shape
+    Q = test.shape[0]
+    _dev(train, torch.float32, "train", (N, C))
+    _dev(test, torch.float32, "test", (Q, C))
+    nearest = torch.empty(Q, dtype=torch.int32, device=test.device)
+    dist = torch.empty(Q, dtype=torch.float32, device=test.device)
+    _check(lib().rsc_chi2_nearest(_ptr(train), N, _ptr(test), Q, C, _ptr(nearest), _ptr(dist), _stream(stream)))
+    return nearest, dist
+
