@@ -549,6 +549,180 @@ def cpu_baseline_rksvd(w, D0, X, K, R):
             "sample": f"one iteration (two pursuits and one update) on the first {len(X)} patches, {dt:.1f} s"}
 
 
+def run_texture(args, dev):
+    """Texture classification (Sec. III-B): 24 synthetic band-pass texture classes, 20
+    upright 128x128 training images per class, 20 test images per class at each of 8
+    rotations.  Setup (untimed): image draws uploaded, one R-K-SVD dictionary per class
+    (M=100, K=1, R=64, from 4,000 windows per training image), training histograms.
+    One timed step = one test rotation: projection of every window of its 480 images,
+    labels against all 24 dictionaries, histograms and chi^2 1-NN."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import texture as tx
+    w = wl.TEXTURE
+    g = w["geom"]
+    C, side, K, R = w["C"], w["side"], w["K"], w["R"]
+    n_train = w["n_train"]
+    n_test = args.images or w["n_test"]
+    rots = w["test_rot_deg"]
+    t_setup = time.perf_counter()
+    proj = rsc.rsc_create(g.N, g.S, g.T)
+    tr_images = [wl.draw_texture_image(c, i, side, w["sigma"]) for c in range(C) for i in range(n_train)]
+    tb, tpix = tx.upload_batch(tr_images, g.N, dev)
+    del tr_images
+    xh_train = rsc.rsc_project_images(proj, tpix, tb)
+    clf, learn_s = texture_learn(args, dev, xh_train, tb, R)
+    torch.cuda.synchronize()
+    print(f"texture: setup {time.perf_counter() - t_setup:.1f} s (learning {learn_s:.1f} s)", file=sys.stderr,
+          flush=True)
+    train_class = clf.train_class
+    # test batches, one per rotation
+    batches = []
+    for j, deg in enumerate(rots):
+        te = [wl.draw_texture_image(c, n_train + j * n_test + i, side, w["sigma"], np.deg2rad(deg))
+              for c in range(C) for i in range(n_test)]
+        b, pix = tx.upload_batch(te, g.N, dev)
+        batches.append((b, pix, tx.window_offsets(b, dev)))
+    P = batches[0][0].P_total
+    xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+    ws = torch.empty(rsc.rsc_classify_workspace_size(P, K), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    test_class = np.repeat(np.arange(C), n_test)
+
+    def step(j, ev=None):
+        b, pix, off = batches[j]
+        if ev:
+            ev[0].record(stream)
+        rsc.rsc_project_images(proj, pix, b, xhat=xh, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        label, _ = rsc.rsc_classify(clf.handles, xh, K, workspace=ws, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        hist = rsc.rsc_label_histogram(label, off, C, stream=stream)
+        nearest, _ = clf.predict(hist, stream=stream)
+        if ev:
+            ev[3].record(stream)
+        return nearest
+
+    for _ in range(args.warmup):
+        step(0)
+    torch.cuda.synchronize()
+    n_steps = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_steps)]
+    preds = []
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        preds.append(step(k % len(rots), evs[k]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    acc = {}
+    for k, p in enumerate(preds):
+        acc.setdefault(rots[k % len(rots)], float(np.mean(train_class[p.cpu().numpy()] == test_class)))
+    parts = {"project": [], "classify": [], "histogram_nn": []}
+    for e in evs:
+        parts["project"].append(e[0].elapsed_time(e[1]))
+        parts["classify"].append(e[1].elapsed_time(e[2]))
+        parts["histogram_nn"].append(e[2].elapsed_time(e[3]))
+    # dominant kernel: the encoder, C launches per step (events around rsc_classify)
+    cls_ms = float(np.median(parts["classify"]))
+    flops = encode_flops_per_patch(w["M"], R, g.S, g.T, K) * P * C
+    peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
+    images = batches[0][0].n
+    out = {
+        "metric": "texture windows classified per second (each coded against all C class dictionaries)",
+        "value": P * n_steps / wall, "unit": "windows/s", "n_gpus": 1, "steps": n_steps, "warmup": args.warmup,
+        "ms_per_step": wall / n_steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[args.prec], "data": "synthetic",
+        "config": {"workload": f"texture: {C} band-pass classes, {images} test images of {side}x{side} per step "
+                               f"({P} 15x15 windows), one step per rotation {list(rots)} deg; R-K-SVD "
+                               f"dictionaries M={w['M']}, K={K}, R={R} learned from {n_train} upright images "
+                               "per class", "precision": args.prec},
+        "images_per_s": images * n_steps / wall,
+        "accuracy": {"per_rotation_deg": {str(k): v for k, v in acc.items()}, "mean": float(np.mean(list(acc.values())))},
+        "parts_ms": {k: float(np.median(v)) for k, v in parts.items()},
+        "learning_s": learn_s,
+        "roofline": {"kernel": f"encoder x {C} classes (rsc_classify)", "bound": "mfma",
+                     "achieved": flops / (cls_ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / (cls_ms * 1e-3) / peak, "algorithmic_flops_per_launch": flops / C,
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    if args.compare_ksvd:
+        kclf, _ = texture_learn(args, dev, xh_train, tb, 1)
+        kacc = {}
+        for j, (b, pix, off) in enumerate(batches):
+            xk = rsc.rsc_project_images(proj, pix, b)
+            nearest, _ = kclf.predict(kclf.features(xk, off))
+            kacc[str(rots[j])] = float(np.mean(kclf.train_class[nearest.cpu().numpy()] == test_class))
+        out["ksvd_accuracy"] = {"per_rotation_deg": kacc, "mean": float(np.mean(list(kacc.values())))}
+        kclf.close()
+    del xh_train
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_texture(clf, proj, xh, batches[0], args.cpu_seconds, dev)
+    print(json.dumps(out), flush=True)
+    clf.close()
+
+
+def texture_learn(args, dev, xh_train, tb, R):
+    """One dictionary per class from 4,000 random windows of each of its training images
+    (R = 1: plain K-SVD), then the training histograms.  Returns (classifier, seconds)."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import texture as tx
+    w = wl.TEXTURE
+    g = w["geom"]
+    C, K, n_train = w["C"], w["K"], w["n_train"]
+    rng = np.random.default_rng(7)
+    per = int(tb.patches_per_image[0])
+    cls_windows = []
+    for c in range(C):
+        idx = np.concatenate([(c * n_train + j) * per + np.sort(rng.choice(per, min(per, w["train_windows"]),
+                                                                           replace=False))
+                              for j in range(n_train)])
+        cls_windows.append(xh_train.index_select(0, torch.from_numpy(idx).to(dev)).contiguous())
+    clf = tx.TextureClassifier(g.N, g.S, g.T, R, K, prec=args.prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    clf.learn(cls_windows, w["M"], w["n_iter"])
+    torch.cuda.synchronize()
+    learn_s = time.perf_counter() - t0
+    del cls_windows
+    ws = torch.empty(rsc.rsc_classify_workspace_size(xh_train.shape[0], K), dtype=torch.uint8, device=dev)
+    clf.fit(clf.features(xh_train, tx.window_offsets(tb, dev), workspace=ws), np.repeat(np.arange(C), n_train))
+    return clf, learn_s
+
+
+def cpu_baseline_texture(clf, proj, xh, batch0, target_s, dev):
+    """FP64 reference classifier (labels of windows against all class dictionaries) on the
+    first windows of the first test batch; also the device labels of the same windows."""
+    import torch
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    from paper_1806_04374_amd import rsc
+    w = wl.TEXTURE
+    g = w["geom"]
+    b, pix, _ = batch0
+    rsc.rsc_project_images(proj, pix, b, xhat=xh)
+    D = [d.astype(np.float64) for d in clf.dictionaries]
+    n0 = 96
+    X0 = xh[:n0].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    orc.classify(D, w["R"], g.S, g.T, X0, w["K"])
+    dt0 = time.perf_counter() - t0
+    n = int(min(20_000, max(n0, n0 * target_s / max(dt0, 1e-3))))
+    X = xh[:n].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    ref_label, ref_sse = orc.classify(D, w["R"], g.S, g.T, X, w["K"])
+    dt = time.perf_counter() - t0
+    label, _ = rsc.rsc_classify(clf.handles, xh[:n].contiguous(), w["K"])
+    torch.cuda.synchronize()
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "windows/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} windows of the first test batch against all {len(D)} dictionaries ({dt:.1f} s)",
+            "check": {"label_match": float(np.mean(label.cpu().numpy() == ref_label))}}
+
+
 def cpu_baseline_ragged(h, w, D, target_s, dev):
     """FP64 reference on windows of the first image (reference-synthesized pixels)."""
     import torch
@@ -585,8 +759,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd"],
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture"],
                     default="scale")
+    ap.add_argument("--compare-ksvd", action="store_true",
+                    help="texture: also learn plain K-SVD (R = 1) dictionaries and report their accuracy")
     ap.add_argument("--check-patches", type=int, default=50_000,
                     help="precision: scale-workload patches checked against the reference")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
@@ -595,7 +771,8 @@ def main():
                     help="serving: HBM budget for request pixels (<= 0: free HBM minus 8 GiB)")
     ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time leg")
     ap.add_argument("--step-windows", type=int, default=1 << 22, help="serving: windows per device step")
-    ap.add_argument("--images", type=int, default=0, help="ragged: use the first n images (testing only)")
+    ap.add_argument("--images", type=int, default=0,
+                    help="ragged: use the first n images; texture: test images per class and rotation (testing only)")
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -635,6 +812,9 @@ def main():
         return
     if args.workload == "rksvd":
         run_rksvd(args, dev)
+        return
+    if args.workload == "texture":
+        run_texture(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

@@ -202,6 +202,48 @@ SERVING = dict(name="serving", geom=GEOM15, rate=200.0, duration=30.0, side=(32,
                M=128, K=6, R=64, density=0.02, sigma=0.05)
 
 
+# Texture classification (Sec. III-B, "Classifier"; synthetic stand-in for the paper's
+# 24-class rotated texture set): C classes of stationary band-pass Gaussian fields (six
+# centre frequencies x isotropic / oriented x narrow / wide band); 128 x 128 images, 20
+# upright training images and 20 test images per class at each of 8 rotations; the
+# R-K-SVD parameters selected in the paper (M = 100, N = 15, K = 1), R = 64; 4,000
+# training windows per image.
+TEXTURE = dict(name="texture", geom=GEOM15, C=24, M=100, K=1, R=64, side=128, n_train=20, n_test=20,
+               test_rot_deg=(5, 10, 15, 30, 45, 60, 75, 90), sigma=0.05, train_windows=4000, n_iter=10,
+               freqs=(0.06, 0.09, 0.12, 0.16, 0.2, 0.25), anisotropy=0.9, bands=(0.02, 0.05))
+
+
+def texture_params(c: int, seed: int = 0, w: dict | None = None):
+    """(centre frequency in cycles/pixel, anisotropy, bandwidth, orientation) of class c:
+    frequency cycles with c, every other group of six classes is oriented, the second
+    half of the classes is wide-band; orientation U[0, pi)."""
+    w = TEXTURE if w is None else w
+    f = w["freqs"][c % len(w["freqs"])]
+    aniso = w["anisotropy"] if (c // len(w["freqs"])) % 2 else 0.0
+    bw = w["bands"][0] if c < w["C"] // 2 else w["bands"][1]
+    return f, aniso, bw, float(_rng(seed, 14, c).uniform(0.0, np.pi))
+
+
+def draw_texture_image(c: int, i: int, side: int, sigma: float, rot: float = 0.0, seed: int = 0,
+                       w: dict | None = None) -> np.ndarray:
+    """Image i of class c as it appears turned by rot radians (counter-clockwise): white
+    noise filtered by exp(-(|f| - f_c)^2 / (2 b^2)) (1 + a cos 2(phi - theta_c - rot)) on a
+    grid with 64 pixels of margin (so the periodic filtering does not wrap into the
+    image), cropped, scaled to unit variance, plus N(0, sigma^2) noise.  float64 [side, side]."""
+    f0, a, bw, th = texture_params(c, seed, w)
+    n = side + 64
+    rs = _rng(seed, 12, c, i)
+    white = rs.standard_normal((n, n))
+    fy = np.fft.fftfreq(n)[:, None]
+    fx = np.fft.fftfreq(n)[None, :]
+    fr = np.hypot(fx, fy)
+    ph = np.arctan2(fy, fx)
+    H = np.exp(-((fr - f0) ** 2) / (2 * bw * bw)) * (1.0 + a * np.cos(2.0 * (ph - th - rot)))
+    x = np.real(np.fft.ifft2(np.fft.fft2(white) * H))[:side, :side]
+    x = x / x.std()
+    return x + sigma * _rng(seed, 13, c, i).standard_normal((side, side))
+
+
 def small_draw(P: int | None = None, start: int = 0, seed: int = 0) -> tuple[np.ndarray, PatchDraw]:
     w = SMALL
     g = w["geom"]

@@ -177,3 +177,68 @@ def test_classifier_argument_errors(dev):
                              torch.zeros((2, 4), dtype=torch.float32, device=dev))
     for h in (h0, h1, h2):
         h.close()
+
+
+def test_texture_pipeline_against_reference(dev):
+    """Small band-pass texture set (4 classes, 40x40 images, test images turned by 45
+    degrees): dictionaries learned by the reference (R-K-SVD, M = 12, K = 1, R = 32) are
+    loaded on the device; the device's window labels, histograms and nearest neighbours
+    match the reference pipeline's.  The device's own learning loop then classifies the
+    test images as well as the reference does."""
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import texture as tx
+    g = wl.GEOM15
+    cfg = dict(wl.TEXTURE, C=4, freqs=(0.06, 0.2), anisotropy=0.9, bands=(0.02, 0.05))
+    C, side, M, K, R = 4, 40, 12, 1, 32
+    basis = orc.build_basis(g.N, g.S, g.T)
+    tr = [wl.draw_texture_image(c, i, side, 0.05, 0.0, w=cfg) for c in range(C) for i in range(2)]
+    te = [wl.draw_texture_image(c, 10 + i, side, 0.05, np.deg2rad(45), w=cfg) for c in range(C) for i in range(2)]
+    Xtr = [orc.project(basis, orc.image_patches(im.astype(np.float32).astype(np.float64), g.N)) for im in tr]
+    Xte = [orc.project(basis, orc.image_patches(im.astype(np.float32).astype(np.float64), g.N)) for im in te]
+    rng = np.random.default_rng(3)
+    D_ref = []
+    for c in range(C):
+        X = np.concatenate(Xtr[2 * c:2 * c + 2])
+        X = X[rng.choice(len(X), 800, replace=False)]
+        D0 = X[rng.choice(len(X), M, replace=False)]
+        D, _, _ = orc.rksvd(D0 / np.linalg.norm(D0, axis=1, keepdims=True), R, g.S, g.T, X, K, 4)
+        D_ref.append(D.astype(np.float32).astype(np.float64))
+    off = lambda Xs: np.concatenate([[0], np.cumsum([len(x) for x in Xs])])
+    lab_tr, _ = orc.classify(D_ref, R, g.S, g.T, np.concatenate(Xtr), K)
+    lab_te, sse_te = orc.classify(D_ref, R, g.S, g.T, np.concatenate(Xte), K)
+    H_tr = orc.label_histogram(lab_tr, off(Xtr), C)
+    H_te = orc.label_histogram(lab_te, off(Xte), C)
+    ref_nn, _ = orc.nearest_chi2(H_tr, H_te)
+    # device, reference dictionaries
+    hs = _handles(g, D_ref, R)
+    proj = rsc.rsc_create(g.N, g.S, g.T)
+    feats = []
+    for ims in (tr, te):
+        b, pix = tx.upload_batch(ims, g.N, dev)
+        xh = rsc.rsc_project_images(proj, pix, b)
+        label, _ = rsc.rsc_classify(hs, xh, K)
+        feats.append((label, rsc.rsc_label_histogram(label, tx.window_offsets(b, dev), C), xh))
+    nn, _ = rsc.rsc_chi2_nearest(feats[0][1], feats[1][1])
+    torch.cuda.synchronize()
+    lab_dev = feats[1][0].cpu().numpy()
+    assert np.mean(lab_dev == lab_te) >= 0.99
+    assert np.abs(feats[1][1].cpu().numpy() - H_te).sum(1).max() < 0.02
+    assert np.array_equal(nn.cpu().numpy(), ref_nn)
+    ref_acc = np.mean(np.repeat(np.arange(C), 2)[ref_nn] == np.repeat(np.arange(C), 2))
+    # device learning from the same windows
+    clf = tx.TextureClassifier(g.N, g.S, g.T, R, K)
+    xtr = feats[0][2]
+    per = (side - g.N + 1) ** 2
+    wins = [xtr[2 * c * per:(2 * c + 2) * per] for c in range(C)]
+    clf.learn([w.contiguous() for w in wins], M, 4)
+    b, pix = tx.upload_batch(tr, g.N, dev)
+    clf.fit(clf.features(rsc.rsc_project_images(proj, pix, b), tx.window_offsets(b, dev)), np.repeat(np.arange(C), 2))
+    b, pix = tx.upload_batch(te, g.N, dev)
+    nn_dev, _ = clf.predict(clf.features(rsc.rsc_project_images(proj, pix, b), tx.window_offsets(b, dev)))
+    dev_acc = np.mean(clf.train_class[nn_dev.cpu().numpy()] == np.repeat(np.arange(C), 2))
+    print("accuracy reference", ref_acc, "device-learned", dev_acc)
+    assert dev_acc >= ref_acc - 0.125
+    clf.close()
+    proj.close()
+    for h in hs:
+        h.close()
