@@ -504,35 +504,6 @@ __global__ __launch_bounds__(256) void rk_reduce_kernel(double* partial, const i
   partial[size_t(c0) * BB + i] = s;
 }
 
-// Block-wide sum of one double per thread (BT threads, scratch of BT doubles).
-template <int BT>
-__device__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = BT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// Number of eigenvalues of the symmetric tridiagonal (d, e) below x (Sturm count).
-__device__ int sturm_below(const double* d, const double* e, int n, double x, double tiny) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (q == 0.0) q = -tiny;
-  cnt += q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
-    if (q == 0.0) q = -tiny;
-    cnt += q < 0.0;
-  }
-  return cnt;
-}
-
 struct EigParams {
   const double* partial;  // [chunks][B][B]
   const int64_t* bucket;  // [M + 1]
@@ -543,188 +514,138 @@ struct EigParams {
   int32_t* usage;         // [M]
 };
 
-template <int BT>
-__global__ __launch_bounds__(BT) void rk_eig_kernel(EigParams prm) {
+constexpr int kMaxSquarings = 40;
+
+// Top eigenvector of one atom's C_m = Y_m Y_m^T (symmetric positive semidefinite), one
+// block per atom, W waves.  C is scaled to unit trace and squared repeatedly,
+// C <- C^2 / trace(C^2), on the FP64 matrix cores (16 x 16 tiles of the upper triangle,
+// the zero-padded NP x NP matrix in LDS; as C is symmetric, lane l's A operand of tile row
+// r is C[4g + l/16][16r + l%16], the same pattern as its B operand).  With the eigenvalues
+// of the scaled C written mu_i (sum 1), trace(C^2) = sum mu_i^2; it reaches 1 - 2 eps when the
+// second share is eps, so the loop stops once 1 - trace(C^2) < 1e-14 (every other direction
+// then carries a weight below 1e-14), or after kMaxSquarings.  The result is C d_old
+// (or, if d_old has no component in that eigenspace, the column of largest diagonal),
+// normalised and signed to agree with d_old.  A repeated top eigenvalue gives the
+// projection of d_old onto its eigenspace.
+template <int W>
+__global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NT = 64 * W, TW = (36 + W - 1) / W;   // at most 8 x 8 tiles, 36 in the upper triangle
   extern __shared__ double ldsd[];
-  const int n = prm.B, t = threadIdx.x, m = blockIdx.x;
-  double* A = ldsd;                 // [n][n]
-  double* v = A + n * n;            // [BT]
-  double* pw = v + BT;              // [BT]
-  double* red = pw + BT;            // [BT]
-  double* d = red + BT;             // [BT]
-  double* e = d + BT;               // [BT]
-  double* beta = e + BT;            // [BT]
-  double* z = beta + BT;            // [BT]
-  int* cnt = reinterpret_cast<int*>(z + BT);  // [BT]
-  // C_m: the sum of its chunk partials sits in its first chunk's slot
+  const int n = prm.B, m = blockIdx.x, t = threadIdx.x, lane = t % 64;
+  const int wv = __builtin_amdgcn_readfirstlane(t / 64);
+  const int NP = (n + 15) / 16 * 16, NR = NP / 16, NTILE = NR * (NR + 1) / 2;
+  double* A = ldsd;                  // [NP][NP]
+  double* red = A + NP * NP;         // [W] reduction slots, then [NP] vector
+  double* vec = red + W;
   const int used = int(prm.bucket[m + 1] - prm.bucket[m]);
-  const int c0 = prm.chunk[m];
-  if (used > 0)
-    for (int i = t; i < n * n; i += BT) A[i] = prm.partial[size_t(c0) * n * n + i];
   if (t == 0) prm.usage[m] = used;
   if (used == 0) {
-    if (t < n) prm.d_new[size_t(m) * n + t] = prm.dict_old[size_t(m) * n + t];
+    for (int i = t; i < n; i += NT) prm.d_new[size_t(m) * n + i] = prm.dict_old[size_t(m) * n + i];
     return;
   }
-  __syncthreads();
-  // Householder tridiagonalisation: A = Q T Q^T, reflector k stored in A[k+1.., k]
-  for (int k = 0; k + 2 < n; ++k) {
-    const double xv = t > k && t < n ? A[t * n + k] : 0.0;
-    const double xx = block_sum<BT>(xv * xv, red);
-    const double x0 = A[(k + 1) * n + k];
-    const double alpha = x0 >= 0.0 ? -sqrt(xx) : sqrt(xx);
-    const double vv = xx - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-    if (vv <= 0.0) {                // the column is already reduced
-      if (t == 0) {
-        e[k] = x0;
-        beta[k] = 0.0;
-      }
-      __syncthreads();
-      continue;
-    }
-    const double bt = 2.0 / vv;
-    if (t < n) v[t] = t > k + 1 ? A[t * n + k] : (t == k + 1 ? x0 - alpha : 0.0);
-    __syncthreads();
-    double pt = 0.0;
-    if (t > k && t < n) {
-      for (int j = k + 1; j < n; ++j) pt += A[t * n + j] * v[j];
-      pt *= bt;
-    }
-    const double kk = 0.5 * bt * block_sum<BT>(pt * (t < n ? v[t] : 0.0), red);
-    if (t < n) pw[t] = t > k ? pt - kk * v[t] : 0.0;
-    __syncthreads();
-    if (t > k && t < n)
-      for (int j = k + 1; j < n; ++j) A[t * n + j] -= v[t] * pw[j] + pw[t] * v[j];
-    __syncthreads();
-    if (t > k && t < n) A[t * n + k] = v[t];
-    if (t == 0) {
-      e[k] = alpha;
-      beta[k] = bt;
-    }
-    __syncthreads();
+  // load C_m (the sum of its chunk partials sits in its first chunk's slot), zero padding
+  const double* Cm = prm.partial + size_t(prm.chunk[m]) * n * n;
+  for (int i = t; i < NP * NP; i += NT) {
+    const int r = i / NP, c = i - r * NP;
+    A[i] = r < n && c < n ? Cm[size_t(r) * n + c] : 0.0;
   }
-  if (t < n) d[t] = A[t * n + t];
-  if (t == 0) {
-    if (n >= 2) e[n - 2] = A[(n - 1) * n + (n - 2)];
-    if (n >= 2) beta[n - 2] = 0.0;
+  // block sum in a fixed order: per wave a butterfly (identical bits in every lane),
+  // then the W wave sums in wave order
+  auto block_sum = [&](double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < W; ++i) s += red[i];
+    return s;
+  };
+  double tr = 0.0;
+  {
+    double p = 0.0;
+    for (int i = t; i < n; i += NT) p += A[i * NP + i];
+    tr = block_sum(p);
+  }
+  if (!(tr > 0.0)) {   // C_m = 0: nothing to fit
+    for (int i = t; i < n; i += NT) prm.d_new[size_t(m) * n + i] = prm.dict_old[size_t(m) * n + i];
+    return;
+  }
+  {
+    const double sc = 1.0 / tr;
+    for (int i = t; i < NP * NP; i += NT) A[i] *= sc;
   }
   __syncthreads();
-  // largest eigenvalue: multisection on Sturm counts inside the Gershgorin interval
-  double lo = 0.0, hi = 0.0, scale = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-    lo = i == 0 ? d[i] - r : fmin(lo, d[i] - r);
-    hi = i == 0 ? d[i] + r : fmax(hi, d[i] + r);
-    scale = fmax(scale, fabs(d[i]) + r);
+  int ta[TW], tb[TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int u = wv + W * i;
+    ta[i] = u < NTILE ? 16 * tile_r(u, NR) : -1;
+    tb[i] = u < NTILE ? 16 * tile_s(u, NR) : -1;
   }
-  const double tiny = DBL_MIN * fmax(scale, 1.0);
-  for (int iter = 0; iter < 64 && hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)); ++iter) {
-    const double x = lo + (hi - lo) * double(t + 1) / double(BT + 1);
-    cnt[t] = sturm_below(d, e, n, x, tiny);
-    __syncthreads();
-    // the largest eigenvalue lies above the last point with fewer than n eigenvalues below
-    int first = BT;
-    for (int i = 0; i < BT; ++i)
-      if (cnt[i] >= n) {
-        first = i;
-        break;
-      }
-    const double nlo = first == 0 ? lo : lo + (hi - lo) * double(first) / double(BT + 1);
-    const double nhi = first == BT ? hi : lo + (hi - lo) * double(first + 1) / double(BT + 1);
-    lo = nlo;
-    hi = nhi;
-    __syncthreads();
-  }
-  const double lam = 0.5 * (lo + hi);
-  // eigenvector of the tridiagonal matrix: inverse iteration (Gaussian elimination with
-  // partial pivoting of T - lam I), three sweeps from a constant start, one thread
-  if (t == 0) {
-    double* u1 = pw;   // super-diagonal after elimination
-    double* u2 = v;    // second super-diagonal (fill-in from pivoting)
-    double* dd = red;  // pivots
-    int* piv = cnt;
-    const double eps = DBL_EPSILON * fmax(scale, DBL_MIN);
-    // factor once
-    double a = d[0] - lam, b = n > 1 ? e[0] : 0.0;
-    for (int i = 0; i + 1 < n; ++i) {
-      const double cl = e[i], dn = d[i + 1] - lam, up = i + 2 < n ? e[i + 1] : 0.0;
-      if (fabs(a) >= fabs(cl)) {       // no swap
-        piv[i] = 0;
-        const double mlt = a != 0.0 ? cl / a : 0.0;
-        dd[i] = a != 0.0 ? a : eps;
-        u1[i] = b;
-        u2[i] = 0.0;
-        z[i] = mlt;                     // multiplier
-        a = dn - mlt * b;
-        b = up;
-      } else {                          // swap rows i and i+1
-        piv[i] = 1;
-        const double mlt = a / cl;
-        dd[i] = cl;
-        u1[i] = dn;
-        u2[i] = up;
-        z[i] = mlt;
-        a = b - mlt * dn;
-        b = -mlt * up;
+  for (int it = 0; it < kMaxSquarings; ++it) {
+    d4 acc[TW];
+#pragma unroll
+    for (int i = 0; i < TW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < NP / 4; ++g) {
+      const double* Ag = A + (4 * g + lane / 16) * NP + lane % 16;
+#pragma unroll
+      for (int i = 0; i < TW; ++i)
+        if (ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ag[ta[i]], Ag[tb[i]], acc[i], 0, 0, 0);
+    }
+    // trace of the square from the diagonal tiles: lane l register e holds row
+    // 16r + l/16 + 4e, column 16r + l%16
+    double p = 0.0;
+#pragma unroll
+    for (int i = 0; i < TW; ++i)
+      if (ta[i] >= 0 && ta[i] == tb[i])
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (lane / 16 + 4 * e == lane % 16) p += acc[i][e];
+    const double tr2 = block_sum(p);   // its barriers also end every read of A
+    const double sc = 1.0 / tr2;
+#pragma unroll
+    for (int i = 0; i < TW; ++i) {
+      if (ta[i] < 0) continue;
+      const int col = tb[i] + lane % 16;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = ta[i] + lane / 16 + 4 * e;
+        const double x = acc[i][e] * sc;
+        A[row * NP + col] = x;
+        if (ta[i] != tb[i]) A[col * NP + row] = x;
       }
     }
-    dd[n - 1] = a != 0.0 ? a : eps;
-    double* y = A;                      // row 0 of A holds no reflector: free now
-    for (int i = 0; i < n; ++i) y[i] = 1.0;
-    for (int sweep = 0; sweep < 3; ++sweep) {
-      // forward elimination on the right-hand side
-      for (int i = 0; i + 1 < n; ++i) {
-        if (piv[i]) {
-          const double tmp = y[i];
-          y[i] = y[i + 1];
-          y[i + 1] = tmp - z[i] * y[i + 1];
-        } else {
-          y[i + 1] -= z[i] * y[i];
-        }
-      }
-      // back substitution with the upper factor (diagonal dd, u1, u2)
-      for (int i = n - 1; i >= 0; --i) {
-        double s = y[i];
-        if (i + 1 < n) s -= u1[i] * y[i + 1];
-        if (i + 2 < n) s -= u2[i] * y[i + 2];
-        y[i] = s / dd[i];
-      }
-      double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
-      nrm = sqrt(nrm);
-      for (int i = 0; i < n; ++i) y[i] /= nrm;
-    }
-  }
-  __syncthreads();
-  // the eigenvector of T is in A[0][0..n-1]; back-transform through the reflectors.
-  // Row 0 of A is not part of any stored reflector (those live below the diagonal).
-  double zt = t < n ? A[t] : 0.0;
-  __syncthreads();
-  if (t < n) z[t] = zt;
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    if (beta[k] == 0.0) continue;
-    const double vt = t > k && t < n ? A[t * n + k] : 0.0;
-    const double s = beta[k] * block_sum<BT>(vt * (t < n ? z[t] : 0.0), red);
-    if (t > k && t < n) z[t] -= s * vt;
     __syncthreads();
+    if (1.0 - tr2 < 1e-14) break;
   }
-  // unit norm, sign of the old atom (largest-magnitude coordinate positive on a tie at 0)
-  const double zz = t < n ? z[t] : 0.0;
-  const double nrm = sqrt(block_sum<BT>(zz * zz, red));
-  const double dot = block_sum<BT>(t < n ? zz * double(prm.dict_old[size_t(m) * n + t]) : 0.0, red);
+  // z = C d_old, or the column of largest diagonal when d_old misses the eigenspace
+  for (int i = t; i < n; i += NT) vec[i] = double(prm.dict_old[size_t(m) * n + i]);
+  __syncthreads();
+  double zt = 0.0;
+  if (t < n)
+    for (int j = 0; j < n; ++j) zt += A[t * NP + j] * vec[j];
+  double nz = block_sum(t < n ? zt * zt : 0.0);
+  if (!(nz > 1e-20)) {
+    int jm = 0;
+    for (int j = 1; j < n; ++j)
+      if (A[j * NP + j] > A[jm * NP + jm]) jm = j;
+    zt = t < n ? A[t * NP + jm] : 0.0;
+    nz = block_sum(t < n ? zt * zt : 0.0);
+  }
+  const double dot = block_sum(t < n ? zt * vec[t] : 0.0);
   double sgn = dot < 0.0 ? -1.0 : 1.0;
-  if (dot == 0.0) {
-    if (t == 0) {
-      int im = 0;
-      for (int i = 1; i < n; ++i)
-        if (fabs(z[i]) > fabs(z[im])) im = i;
-      red[0] = z[im] < 0.0 ? -1.0 : 1.0;
-    }
+  if (dot == 0.0) {   // the largest-magnitude coordinate (the first on ties) is made positive
     __syncthreads();
-    sgn = red[0];
+    if (t < n) vec[t] = zt;
+    __syncthreads();
+    int im = 0;
+    for (int i = 1; i < n; ++i)
+      if (fabs(vec[i]) > fabs(vec[im])) im = i;
+    sgn = vec[im] < 0.0 ? -1.0 : 1.0;
   }
-  if (t < n) prm.d_new[size_t(m) * n + t] = float(sgn * zz / nrm);
+  if (t < n) prm.d_new[size_t(m) * n + t] = float(sgn * zt / sqrt(nz));
 }
 
 struct ResetParams {
@@ -878,7 +799,8 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
   const int64_t nblk = max_chunks(t.M, P, K);
   auto run = [&](auto acc_kern, auto eig_kern, int bt, int nt, int kq) -> int {
     const size_t lds1 = sizeof(double) * (size_t(kq) * bt + 2 * size_t(NQ) * t.R);
-    const size_t lds2 = sizeof(double) * (size_t(t.B) * t.B + 7 * size_t(bt)) + sizeof(int) * bt;
+    const size_t np2 = size_t((t.B + 15) / 16 * 16);
+    const size_t lds2 = sizeof(double) * (np2 * np2 + 8 + np2);
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(acc_kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1));
     if (err == hipSuccess)
@@ -894,11 +816,11 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
                        sp.chunk, BB);
     err = hipGetLastError();
     if (err != hipSuccess) return int(err);
-    hipLaunchKernelGGL(eig_kern, dim3(unsigned(t.M)), dim3(bt), lds2, st, ep);
+    hipLaunchKernelGGL(eig_kern, dim3(unsigned(t.M)), dim3(bt <= 64 ? 256 : 512), lds2, st, ep);
     return int(hipGetLastError());
   };
-  const int r = t.B <= 64 ? run(rk_accum_kernel<64, 2, 16>, rk_eig_kernel<64>, 64, 128, 16)
-                          : run(rk_accum_kernel<128, 4, 16>, rk_eig_kernel<128>, 128, 256, 16);
+  const int r = t.B <= 64 ? run(rk_accum_kernel<64, 2, 16>, rk_eig_kernel<4>, 64, 128, 16)
+                          : run(rk_accum_kernel<128, 4, 16>, rk_eig_kernel<8>, 128, 256, 16);
   if (r) return r;
   ResetParams rp{xhat, resid2, P, t.M, t.B, usage, d_new, reset};
   hipLaunchKernelGGL(rk_reset_kernel, dim3(1), dim3(256), 0, st, rp);
