@@ -66,6 +66,11 @@ Readings where the paper is silent (each one is listed in the design notes):
     all have one size, where counts and frequencies rank neighbours alike).
     chi^2 terms with a[i] + b[i] = 0 are 0.  The nearest neighbour's ties go to
     the smaller training index.
+  * Rotation by interpolation (Sec. IV, rotation speed): rotating a patch by theta
+    (counter-clockwise, about its centre pixel) sets output pixel (x, y) to the input
+    at R_{-theta}(x, y), read with nearest-neighbour interpolation (coordinates
+    rounded half up) or bicubic interpolation (Keys' cubic convolution, a = -1/2, over
+    the 4 x 4 neighbours); input pixels outside the N x N patch count as 0.
 """
 from __future__ import annotations
 
@@ -499,4 +504,57 @@ def nearest_chi2(train: np.ndarray, test: np.ndarray):
         idx[q] = int(np.argmin(d))
         dist[q] = d[idx[q]]
     return idx, dist
+
+
+# --------------------------------------------------------------------------- rotation
+def _keys(t: float, a: float = -0.5) -> float:
+    """Keys' cubic convolution kernel."""
+    t = abs(t)
+    if t <= 1.0:
+        return (a + 2.0) * t ** 3 - (a + 3.0) * t ** 2 + 1.0
+    if t < 2.0:
+        return a * t ** 3 - 5.0 * a * t ** 2 + 8.0 * a * t - 4.0 * a
+    return 0.0
+
+
+def rotation_matrix(N: int, theta: float, mode: str) -> np.ndarray:
+    """The N^2 x N^2 matrix (row-major pixels) that rotates a patch by theta with
+    nearest-neighbour or bicubic interpolation (readings in the module header)."""
+    c = (N - 1) / 2.0
+    Rm = np.zeros((N * N, N * N))
+    cs, sn = np.cos(theta), np.sin(theta)
+    for i in range(N):
+        for j in range(N):
+            x, y = j - c, c - i
+            xs, ys = cs * x + sn * y, -sn * x + cs * y        # R_{-theta} (x, y)
+            col, row = c + xs, c - ys                          # fractional source pixel
+            q = i * N + j
+            if mode == "nearest":
+                r0, c0 = int(np.floor(row + 0.5)), int(np.floor(col + 0.5))
+                if 0 <= r0 < N and 0 <= c0 < N:
+                    Rm[q, r0 * N + c0] = 1.0
+            elif mode == "bicubic":
+                r0, c0 = int(np.floor(row)), int(np.floor(col))
+                for di in range(-1, 3):
+                    for dj in range(-1, 3):
+                        rr, cc = r0 + di, c0 + dj
+                        if 0 <= rr < N and 0 <= cc < N:
+                            w = _keys(row - rr) * _keys(col - cc)
+                            if w != 0.0:
+                                Rm[q, rr * N + cc] += w
+            else:
+                raise ValueError("mode must be 'nearest' or 'bicubic'")
+    return Rm
+
+
+def rotate_interp(patches: np.ndarray, theta: float, mode: str) -> np.ndarray:
+    """Patches [P, N, N] rotated by theta (counter-clockwise) by interpolation."""
+    P, N, _ = patches.shape
+    Rm = rotation_matrix(N, theta, mode)
+    return (patches.reshape(P, N * N) @ Rm.T).reshape(P, N, N)
+
+
+def rotate_steer(basis: Basis, patches: np.ndarray, theta: float) -> np.ndarray:
+    """Steering-based rotation Phi S_theta (Phi^T Phi)^{-1} Phi^T x (Sec. IV)."""
+    return to_pixels(basis, steer(project(basis, patches), theta, basis.S, basis.T))
 
