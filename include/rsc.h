@@ -70,6 +70,7 @@ typedef enum {
 } rsc_tile;
 
 typedef struct rsc_handle rsc_handle;
+typedef struct rsc_rotation_plan rsc_rotation_plan;
 
 /*
  * Build the discrete steerable basis on the host in FP64 and upload it
@@ -393,6 +394,49 @@ rsc_status rsc_label_histogram(const int32_t* label, int64_t P, const int64_t* o
  */
 rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, int n_test, int C,
                             int32_t* nearest, float* dist, void* stream);
+
+/* ------------------------------------------------------------------ patch rotation
+ * Sec. IV (rotation speed): a batch of N x N patches turned by one angle, either by
+ * interpolation (the paper's sparse N^2 x N^2 matrices R_nearest and R_bicubic) or by
+ * steering the hat coordinates (x_hat <- S x_hat, then Phi x_hat).  Angles are in
+ * radians, counter-clockwise, about the centre pixel.
+ */
+
+/*
+ * Plan of an interpolated rotation: the rows of R (1 tap per output pixel for nearest
+ * neighbour, 16 for bicubic) built on the host in FP64 and uploaded to the current
+ * device.  Output pixel (x, y) reads the input at R_{-theta}(x, y); nearest rounds the
+ * coordinates half up; bicubic is Keys' cubic convolution (a = -1/2) over the 4 x 4
+ * neighbours; input pixels outside the patch count as 0.
+ *   N      odd, 3 <= N <= 25;  mode  0 = nearest, 1 = bicubic
+ *   plan   written; release with rsc_rotation_plan_destroy
+ */
+rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_plan** plan);
+
+/* Releases a plan's device tables (NULL is a no-op). */
+rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan);
+
+/*
+ * R x for every patch: patches and out device float32 [P, N, N] (distinct buffers).
+ */
+rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches, int64_t P, float* out,
+                             void* stream);
+
+/*
+ * Steering of hat coordinates (the diagonal S_theta of eq. (8) at any angle): harmonic k
+ * of every patch multiplied by exp(-i k theta).
+ *   xhat, out   device [P, B] float32 (may be the same buffer only if P == 0)
+ *   theta       device float32 [P] per-patch angles, or NULL to use theta0 for all
+ * Needs the handle's basis only (no dictionary).
+ */
+rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const float* theta, double theta0,
+                     float* out, void* stream);
+
+/*
+ * Phi x_hat on the N x N grid (zero off the disk), for any hat coordinates.
+ *   xhat    device [P, B] float32;  pixels  device [P, N, N] float32, written
+ */
+rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream);
 
 /*
  * Counters of the BF16 / FP16 encoder, accumulated over its launches on this handle

@@ -31,6 +31,7 @@ SOURCES = [
     ("rsc_images.hip", "hip"),
     ("rsc_rksvd.hip", "hip"),
     ("rsc_classify.hip", "hip"),
+    ("rsc_rotate.hip", "hip"),
 ]
 
 

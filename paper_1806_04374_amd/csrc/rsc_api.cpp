@@ -878,6 +878,79 @@ rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, 
   return e ? device_fail(e, "nearest-neighbour launch") : ok();
 }
 
+struct rsc_rotation_plan {
+  int N = 0, ntap = 0;
+  int32_t* src = nullptr;
+  float* w = nullptr;
+};
+
+rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_plan** plan) {
+  if (!plan) return fail(RSC_E_INVALID, "plan is NULL");
+  *plan = nullptr;
+  if (N < 3 || N > 25 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..25");
+  if (mode != 0 && mode != 1) return fail(RSC_E_INVALID, "mode must be 0 (nearest) or 1 (bicubic)");
+  if (!std::isfinite(theta)) return fail(RSC_E_INVALID, "theta must be finite");
+  std::vector<int32_t> src;
+  std::vector<float> w;
+  const int ntap = rsc::rotation_taps(N, theta, mode, src, w);
+  auto* p = new (std::nothrow) rsc_rotation_plan;
+  if (!p) return fail(RSC_E_NOMEM, "plan allocation failed");
+  p->N = N;
+  p->ntap = ntap;
+  rsc_status s = upload(p->src, src, "rotation taps");
+  if (s == RSC_OK) s = upload(p->w, w, "rotation weights");
+  if (s != RSC_OK) {
+    free_dev(p->src);
+    free_dev(p->w);
+    delete p;
+    return s;
+  }
+  *plan = p;
+  return ok();
+}
+
+rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan) {
+  if (!plan) return ok();
+  free_dev(plan->src);
+  free_dev(plan->w);
+  delete plan;
+  return ok();
+}
+
+rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches, int64_t P, float* out,
+                             void* stream) {
+  if (!plan) return fail(RSC_E_INVALID, "plan is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (P == 0) return ok();
+  if (!patches || !out) return fail(RSC_E_INVALID, "null device pointer");
+  if (patches == out) return fail(RSC_E_INVALID, "patches and out must be distinct");
+  int e = rsc::launch_rotate_taps(plan->N, plan->ntap, patches, P, plan->src, plan->w, out, stream);
+  return e ? device_fail(e, "rotation launch") : ok();
+}
+
+rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const float* theta, double theta0,
+                     float* out, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (h->dev.T > 15) return fail(RSC_E_UNSUPPORTED, "steering is compiled for T <= 15");
+  if (!theta && !std::isfinite(theta0)) return fail(RSC_E_INVALID, "theta0 must be finite");
+  if (P == 0) return ok();
+  if (!xhat || !out) return fail(RSC_E_INVALID, "null device pointer");
+  if (xhat == out) return fail(RSC_E_INVALID, "xhat and out must be distinct");
+  int e = rsc::launch_steer(h->dev, xhat, P, theta, theta0, out, stream);
+  return e ? device_fail(e, "steering launch") : ok();
+}
+
+rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "synthesis is compiled for B <= 128");
+  if (P == 0) return ok();
+  if (!xhat || !pixels) return fail(RSC_E_INVALID, "null device pointer");
+  int e = rsc::launch_synth_hat(h->dev, xhat, P, pixels, stream);
+  return e ? device_fail(e, "synthesis launch") : ok();
+}
+
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (h->prec == RSC_FP32 || !h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "FP32 handles keep no counters");

@@ -68,6 +68,11 @@ def lib():
         "rsc_classify": [P, I, P, I64, I, P, ctypes.c_size_t, P, P, P],
         "rsc_label_histogram": [P, I64, P, I, I, P, P],
         "rsc_chi2_nearest": [P, I, P, I, I, P, P, P],
+        "rsc_rotation_plan_create": [I, ctypes.c_double, I, P],
+        "rsc_rotation_plan_destroy": [P],
+        "rsc_rotate_interp": [P, P, I64, P, P],
+        "rsc_steer": [P, P, I64, P, ctypes.c_double, P, P],
+        "rsc_synthesize_hat": [P, P, I64, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -483,4 +488,63 @@ def rsc_chi2_nearest(train, test, stream=None):
     dist = torch.empty(Q, dtype=torch.float32, device=test.device)
     _check(lib().rsc_chi2_nearest(_ptr(train), N, _ptr(test), Q, C, _ptr(nearest), _ptr(dist), _stream(stream)))
     return nearest, dist
+
+
+# ------------------------------------------------------------------ patch rotation
+class RotationPlan:
+    """Interpolated rotation of N x N patches by theta (mode "nearest" or "bicubic")."""
+
+    def __init__(self, N: int, theta: float, mode: str = "bicubic"):
+        m = {"nearest": 0, "bicubic": 1}[mode]
+        ptr = ctypes.c_void_p()
+        _check(lib().rsc_rotation_plan_create(int(N), float(theta), m, ctypes.byref(ptr)))
+        self.ptr, self.N, self.theta, self.mode = ptr, int(N), float(theta), mode
+
+    def close(self):
+        if self.ptr:
+            lib().rsc_rotation_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rsc_rotate_interp(plan: RotationPlan, patches, out=None, stream=None):
+    import torch
+    P = patches.shape[0]
+    _dev(patches, torch.float32, "patches", (P, plan.N, plan.N))
+    if out is None:
+        out = torch.empty_like(patches)
+    _dev(out, torch.float32, "out", (P, plan.N, plan.N))
+    _check(lib().rsc_rotate_interp(plan.ptr, _ptr(patches), P, _ptr(out), _stream(stream)))
+    return out
+
+
+def rsc_steer(h: Handle, xhat, theta0: float = 0.0, theta=None, out=None, stream=None):
+    """S_theta x_hat: one angle theta0 for every patch, or a device float32 [P] of angles."""
+    import torch
+    P = xhat.shape[0]
+    _dev(xhat, torch.float32, "xhat", (P, h.B))
+    if theta is not None:
+        _dev(theta, torch.float32, "theta", (P,))
+    if out is None:
+        out = torch.empty_like(xhat)
+    _dev(out, torch.float32, "out", (P, h.B))
+    _check(lib().rsc_steer(h.ptr, _ptr(xhat), P, _ptr(theta), float(theta0), _ptr(out), _stream(stream)))
+    return out
+
+
+def rsc_synthesize_hat(h: Handle, xhat, out=None, stream=None):
+    """Phi x_hat on the N x N grid, zero off the disk."""
+    import torch
+    P = xhat.shape[0]
+    _dev(xhat, torch.float32, "xhat", (P, h.B))
+    if out is None:
+        out = torch.empty((P, h.N, h.N), dtype=torch.float32, device=xhat.device)
+    _dev(out, torch.float32, "pixels", (P, h.N, h.N))
+    _check(lib().rsc_synthesize_hat(h.ptr, _ptr(xhat), P, _ptr(out), _stream(stream)))
+    return out
 
