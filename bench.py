@@ -693,6 +693,104 @@ def texture_learn(args, dev, xh_train, tb, R):
     return clf, learn_s
 
 
+def run_rotate(args, dev):
+    """Rotation speed (Sec. IV): random N x N patches turned by 100 + sqrt(2) degrees with
+    the nearest and bicubic rotation matrices (R x) and by steering precomputed hat
+    coordinates (S x_hat), at N = 11 and 15 and for the paper's 50,000 patches and a
+    4,000,000-patch batch; also the full steering rotation (project, steer, synthesize).
+    Each method: median of 20 event-timed runs."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    theta = np.deg2rad(100 + np.sqrt(2))
+    stream = torch.cuda.current_stream()
+    reps = 20
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    results = {}
+    for geom in (wl.GEOM11, wl.GEOM15):
+        N = geom.N
+        h = rsc.rsc_create(N, geom.S, geom.T)
+        plans = {m: rsc.RotationPlan(N, theta, m) for m in ("nearest", "bicubic")}
+        for P in (50_000, 4_000_000):
+            rng = torch.Generator(device=dev)
+            rng.manual_seed(P + N)
+            X = torch.randn((P, N, N), generator=rng, device=dev, dtype=torch.float32)
+            Y = torch.empty_like(X)
+            xh = rsc.rsc_project(h, X)
+            xo = torch.empty_like(xh)
+            r = {}
+            for m, plan in plans.items():
+                r[m] = timed(lambda: rsc.rsc_rotate_interp(plan, X, out=Y, stream=stream))
+            r["steer"] = timed(lambda: rsc.rsc_steer(h, xh, theta, out=xo, stream=stream))
+            r["copy_of_xhat"] = timed(lambda: xo.copy_(xh))          # achievable-bandwidth reference
+            r["steer_full"] = timed(lambda: rsc.rsc_synthesize_hat(
+                h, rsc.rsc_steer(h, rsc.rsc_project(h, X, xh, stream=stream), theta, out=xo, stream=stream),
+                out=Y, stream=stream))
+            results[f"N{N}_P{P}"] = {
+                "ms": r, "B": h.B,
+                "bicubic_over_steer": r["bicubic"] / r["steer"], "nearest_over_steer": r["nearest"] / r["steer"],
+                "steer_GBps": 2 * 4 * h.B * P / (r["steer"] * 1e-3) / 1e9,
+                "bicubic_GBps": 2 * 4 * N * N * P / (r["bicubic"] * 1e-3) / 1e9,
+                "copy_GBps": 2 * 4 * h.B * P / (r["copy_of_xhat"] * 1e-3) / 1e9,
+            }
+            print(f"rotate N={N} P={P}: {json.dumps(r)}", file=sys.stderr, flush=True)
+            del X, Y, xh, xo
+            torch.cuda.empty_cache()
+        for plan in plans.values():
+            plan.close()
+        h.close()
+    main = results["N11_P4000000"]
+    bytes_steer = 2 * 4 * 55 * 4_000_000
+    out = {
+        "metric": "patch rotations per second by steering hat coordinates (S x_hat), 100 + sqrt(2) degrees",
+        "value": 4_000_000 / (main["ms"]["steer"] * 1e-3), "unit": "patches/s", "n_gpus": 1, "steps": reps,
+        "warmup": 3, "ms_per_step": main["ms"]["steer"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rotate: 4,000,000 random 11x11 patches (B = 55); also 50,000 (the paper's "
+                               "count) and 15x15; nearest / bicubic rotation matrices, steering, full "
+                               "steering rotation"},
+        "results": results,
+        "roofline": {"kernel": "steer_kernel", "bound": "hbm", "achieved": main["steer_GBps"], "peak": 8000.0,
+                     "unit": "GB/s", "frac": main["steer_GBps"] / 8000.0, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_steer},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_rotate(theta, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_rotate(theta, target_s):
+    """FP64 reference: bicubic rotation matrix product and steering on 11x11 patches."""
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    n = 50_000
+    X = np.random.default_rng(0).standard_normal((n, g.N, g.N))
+    xh = orc.project(basis, X)
+    t0 = time.perf_counter()
+    orc.steer(xh, theta, g.S, g.T)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.rotate_interp(X, theta, "bicubic")
+    dtb = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} random 11x11 patches: steering {dt:.2f} s; bicubic matrix product {dtb:.2f} s "
+                      f"({n / dtb:.0f} patches/s)"}
+
+
 def cpu_baseline_texture(clf, proj, xh, batch0, target_s, dev):
     """FP64 reference classifier (labels of windows against all class dictionaries) on the
     first windows of the first test batch; also the device labels of the same windows."""
@@ -759,7 +857,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture"],
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture", "rotate"],
                     default="scale")
     ap.add_argument("--compare-ksvd", action="store_true",
                     help="texture: also learn plain K-SVD (R = 1) dictionaries and report their accuracy")
@@ -815,6 +913,9 @@ def main():
         return
     if args.workload == "texture":
         run_texture(args, dev)
+        return
+    if args.workload == "rotate":
+        run_rotate(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

@@ -16,39 +16,49 @@
 #include <vector>
 
 #include "rsc_internal.h"
+#include "rsc_launch.h"
 
 namespace rsc {
 namespace {
 
-constexpr int kRotPatches = 16;   // patches per block pass in rotate_taps_kernel
+constexpr int kRotPatches = 32;   // patches per block pass in rotate_taps_kernel
 
-// Each block stages kRotPatches patches in LDS (coalesced), applies the taps (in LDS),
-// and writes the rotated patches (coalesced).
-template <int NTAP>
+// Thread t owns output pixels t, t + 256, ... (QPT of them) and keeps their taps in
+// registers for every patch; each block stages kRotPatches patches in LDS (coalesced),
+// applies the taps to them, and writes the rotated patches (coalesced).
+template <int NTAP, int QPT>
 __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restrict__ in, int64_t P, int NN,
                                                          const int32_t* __restrict__ src,
                                                          const float* __restrict__ wgt, float* __restrict__ out) {
-  extern __shared__ float lds[];
-  float* xs = lds;                                            // [kRotPatches][NN]
-  float* ws = xs + kRotPatches * NN;                          // [NN][NTAP]
-  int* ss = reinterpret_cast<int*>(ws + NN * NTAP);           // [NN][NTAP]
+  extern __shared__ float xs[];   // [kRotPatches][NN]
   const int t = threadIdx.x;
-  for (int i = t; i < NN * NTAP; i += 256) {
-    ws[i] = wgt[i];
-    ss[i] = src[i];
+  float w[QPT][NTAP];
+  int sidx[QPT][NTAP];
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int q = t + 256 * j < NN ? t + 256 * j : 0;
+#pragma unroll
+    for (int k = 0; k < NTAP; ++k) {
+      w[j][k] = wgt[q * NTAP + k];
+      sidx[j][k] = src[q * NTAP + k];
+    }
   }
   for (int64_t p0 = int64_t(blockIdx.x) * kRotPatches; p0 < P; p0 += int64_t(gridDim.x) * kRotPatches) {
     const int np = P - p0 < kRotPatches ? int(P - p0) : kRotPatches;
     __syncthreads();
     for (int i = t; i < np * NN; i += 256) xs[i] = in[p0 * NN + i];
     __syncthreads();
-    for (int i = t; i < np * NN; i += 256) {
-      const int p = i / NN, q = i - p * NN;
+    for (int p = 0; p < np; ++p) {
       const float* x = xs + p * NN;
-      float acc = 0.f;
 #pragma unroll
-      for (int k = 0; k < NTAP; ++k) acc += ws[q * NTAP + k] * x[ss[q * NTAP + k]];
-      out[p0 * NN + i] = acc;
+      for (int j = 0; j < QPT; ++j) {
+        const int q = t + 256 * j;
+        if (q >= NN) continue;
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < NTAP; ++k) acc += w[j][k] * x[sidx[j][k]];
+        out[(p0 + p) * NN + q] = acc;
+      }
     }
   }
 }
@@ -62,37 +72,45 @@ struct SteerParams {
   float cs[16], sn[16]; // cos, sin of k theta0 for k = 0..T (T <= 15), when theta is null
 };
 
-// One thread per coordinate: harmonic k of the packed pair (a, b) -> (a cos + b sin,
-// b cos - a sin) with angle k theta (harmonic 0 unchanged).
+// One thread per (patch, profile s, harmonic k >= 1) pair, or per harmonic-0
+// coordinate: (a, b) -> (a cos + b sin, b cos - a sin) with angle k theta.  The geometry
+// is a template parameter, so the index arithmetic is by constants.
+template <int S, int T>
 __global__ __launch_bounds__(256) void steer_kernel(SteerParams prm) {
+  constexpr int B = S * (2 * T + 1), W = S * (T + 1);   // work items per patch
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= prm.P * prm.B) return;
-  const int64_t p = i / prm.B;
-  const int b = int(i - p * prm.B), S = prm.S;
-  const float own = prm.xhat[i];
-  if (b < S) {
-    prm.out[i] = own;
+  if (i >= prm.P * W) return;
+  const int64_t p = i / W;
+  const int w = int(i - p * W);
+  const float* x = prm.xhat + p * B;
+  float* o = prm.out + p * B;
+  if (w < S) {
+    o[w] = x[w];
     return;
   }
-  const int q = b - S, k = 1 + q / (2 * S), rem = q - (k - 1) * 2 * S;
-  const bool re = rem < S;
-  const float other = prm.xhat[i + (re ? S : -S)];
-  float c, s;
+  const int k = 1 + (w - S) / S, sp = (w - S) - (k - 1) * S;
+  const int ire = S + 2 * S * (k - 1) + sp, iim = ire + S;
+  const float a = x[ire], bb = x[iim];
+  float c, sn;
   if (prm.theta) {
-    sincosf(float(k) * prm.theta[p], &s, &c);
+    sincosf(float(k) * prm.theta[p], &sn, &c);
   } else {
     c = prm.cs[k];
-    s = prm.sn[k];
+    sn = prm.sn[k];
   }
-  prm.out[i] = re ? own * c + other * s : own * c - other * s;
+  o[ire] = a * c + bb * sn;
+  o[iim] = bb * c - a * sn;
 }
 
-// Phi x_hat on the N x N grid: a block stages 8 patches' hat rows in LDS, the synthesis
-// matrix [N*N][B] is read through the caches; one thread per output pixel.
+// Phi x_hat on the N x N grid: the synthesis matrix [N*N][B] sits in LDS for the
+// block's lifetime; a block stages 8 patches' hat rows, one thread per output pixel.
 __global__ __launch_bounds__(256) void synth_hat_kernel(const float* __restrict__ xhat, int64_t P, int B, int NN,
                                                        const float* __restrict__ phi, float* __restrict__ out) {
-  __shared__ float xs[8 * 128];
+  extern __shared__ float lds[];
+  float* ph = lds;              // [NN][B]
+  float* xs = ph + NN * B;      // [8][B]
   const int t = threadIdx.x;
+  for (int i = t; i < NN * B; i += 256) ph[i] = phi[i];
   for (int64_t p0 = int64_t(blockIdx.x) * 8; p0 < P; p0 += int64_t(gridDim.x) * 8) {
     const int np = P - p0 < 8 ? int(P - p0) : 8;
     __syncthreads();
@@ -100,11 +118,16 @@ __global__ __launch_bounds__(256) void synth_hat_kernel(const float* __restrict_
     __syncthreads();
     for (int i = t; i < np * NN; i += 256) {
       const int p = i / NN, q = i - p * NN;
-      const float* ph = phi + size_t(q) * B;
+      const float* a = ph + q * B;
       const float* x = xs + p * B;
-      float acc = 0.f;
-      for (int b = 0; b < B; ++b) acc += ph[b] * x[b];
-      out[p0 * NN + i] = acc;
+      float acc0 = 0.f, acc1 = 0.f;
+      int b = 0;
+      for (; b + 1 < B; b += 2) {
+        acc0 += a[b] * x[b];
+        acc1 += a[b + 1] * x[b + 1];
+      }
+      if (b < B) acc0 += a[b] * x[b];
+      out[p0 * NN + i] = acc0 + acc1;
     }
   }
 }
@@ -152,28 +175,30 @@ int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std:
 }
 
 size_t rotate_lds_bytes(int N, int ntap) {
-  return sizeof(float) * size_t(kRotPatches) * N * N + (sizeof(float) + sizeof(int32_t)) * size_t(N) * N * ntap;
+  (void)ntap;
+  return sizeof(float) * size_t(kRotPatches) * N * N;
 }
 
 int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w, float* out,
                        void* stream) {
   const int NN = N * N;
-  const size_t lds = rotate_lds_bytes(N, ntap);
   const int64_t want = (P + kRotPatches - 1) / kRotPatches;
-  const unsigned grid = unsigned(want < 4096 ? want : 4096);
+  const int64_t cap = int64_t(num_cus()) * 8;
+  const unsigned grid = unsigned(want < cap ? want : cap);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (ntap == 1) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rotate_taps_kernel<1>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  const int qpt = (NN + 255) / 256;
+  const size_t lds = rotate_lds_bytes(N, ntap);
+  auto go = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(lds));
     if (e != hipSuccess) return int(e);
-    hipLaunchKernelGGL(rotate_taps_kernel<1>, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, out);
-  } else {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(rotate_taps_kernel<16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return int(e);
-    hipLaunchKernelGGL(rotate_taps_kernel<16>, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, out);
-  }
-  return int(hipGetLastError());
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, out);
+    return int(hipGetLastError());
+  };
+  if (ntap == 1) return qpt == 1 ? go(rotate_taps_kernel<1, 1>) : qpt == 2 ? go(rotate_taps_kernel<1, 2>)
+                                                                          : go(rotate_taps_kernel<1, 3>);
+  return qpt == 1 ? go(rotate_taps_kernel<16, 1>) : qpt == 2 ? go(rotate_taps_kernel<16, 2>)
+                                                             : go(rotate_taps_kernel<16, 3>);
 }
 
 int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const float* theta, double theta0, float* out,
@@ -189,16 +214,26 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
     prm.cs[k] = float(std::cos(k * theta0));
     prm.sn[k] = float(std::sin(k * theta0));
   }
-  hipLaunchKernelGGL(steer_kernel, dim3(unsigned((P * t.B + 255) / 256)), dim3(256), 0,
-                     reinterpret_cast<hipStream_t>(stream), prm);
+  const int64_t items = P * int64_t(t.S) * (t.T + 1);
+  const dim3 grid(unsigned((items + 255) / 256));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (t.S == 5 && t.T == 5) hipLaunchKernelGGL((steer_kernel<5, 5>), grid, dim3(256), 0, st, prm);
+  else if (t.S == 7 && t.T == 7) hipLaunchKernelGGL((steer_kernel<7, 7>), grid, dim3(256), 0, st, prm);
+  else return int(hipErrorInvalidValue);
   return int(hipGetLastError());
 }
 
 int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float* out, void* stream) {
+  const int NN = t.N * t.N;
+  const size_t lds = sizeof(float) * (size_t(NN) * t.B + 8 * size_t(t.B));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(synth_hat_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return int(e);
   const int64_t want = (P + 7) / 8;
-  const unsigned grid = unsigned(want < 8192 ? want : 8192);
-  hipLaunchKernelGGL(synth_hat_kernel, dim3(grid), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), xhat, P,
-                     t.B, t.N * t.N, t.phiPad, out);
+  const int64_t cap = int64_t(num_cus()) * 2;
+  const unsigned grid = unsigned(want < cap ? want : cap);
+  hipLaunchKernelGGL(synth_hat_kernel, dim3(grid), dim3(256), lds, reinterpret_cast<hipStream_t>(stream), xhat, P,
+                     t.B, NN, t.phiPad, out);
   return int(hipGetLastError());
 }
 
