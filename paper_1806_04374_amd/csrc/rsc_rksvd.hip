@@ -34,6 +34,7 @@ namespace rsc {
 namespace {
 
 constexpr int kSortBlocks = 1024;
+constexpr size_t kResidLdsPaired = 96 * 1024;   // above this the residual kernel keeps single values
 constexpr int kChunkTarget = 4096;
 constexpr int kChunkMin = 256;
 
@@ -297,20 +298,27 @@ struct ResidParams {
 // order; an absent entry adds 0 d_0), in FP64; coordinates B..BP-1 are zero.  The
 // dictionary and the rotation table sit in LDS; a block of G BP threads strides over
 // the patches G at a time, thread (g, b) owning coordinate b of one patch.
-template <int KMAX>
+// PAIRED: the dictionary in LDS as (own, partner) pairs, one read per atom and
+// coordinate; otherwise as single values (half the LDS, for large M B), two reads.
+template <int KMAX, bool PAIRED>
 __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   extern __shared__ double ldsd[];
   const int B = prm.B, BP = prm.BP, R = prm.R, M = prm.M, K = prm.K, NQ = prm.T + 1;
   double2* sc = reinterpret_cast<double2*>(ldsd);            // [R][NQ] (cos, sin)
-  float2* sd = reinterpret_cast<float2*>(sc + R * NQ);        // [M][B] (d_b, d_partner(b))
+  float2* sd = reinterpret_cast<float2*>(sc + R * NQ);        // [M][B] (d_b, d_partner(b)) if PAIRED
+  float* sd1 = reinterpret_cast<float*>(sc + R * NQ);         // [M][B] otherwise
   const int t = threadIdx.x, nt = blockDim.x, G = nt / BP;
   for (int i = t; i < R * NQ; i += nt) {
     const int r = i / NQ, k = i - r * NQ;
     sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
   }
   for (int i = t; i < M * B; i += nt) {
-    const int a = i / B, bb = i - a * B;
-    sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.S).partner]};
+    if constexpr (PAIRED) {
+      const int a = i / B, bb = i - a * B;
+      sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.S).partner]};
+    } else {
+      sd1[i] = prm.dict[i];
+    }
   }
   __syncthreads();
   const int g = __builtin_amdgcn_readfirstlane(t / BP), b = t - g * BP, bc = b < B ? b : 0;
@@ -342,7 +350,13 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
         const float cj = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cv[u]), j));
         // an angle outside 0..R-1 (not produced by the pursuit) reads angle 0, in bounds
         const bool use = j < K && aj >= 0 && aj < M;
-        const float2 dd = sd[(use ? aj : 0) * B + bc];
+        float2 dd;
+        if constexpr (PAIRED) {
+          dd = sd[(use ? aj : 0) * B + bc];
+        } else {
+          const float* d = sd1 + (use ? aj : 0) * B;
+          dd = float2{d[bc], d[cd.partner]};
+        }
         const double2 cs = sc[(use && unsigned(rj) < unsigned(R) ? rj : 0) * NQ + cd.k];
         r[u] = fma(-double(use ? cj : 0.f), rot(dd.x, dd.y, cs.x, cs.y, sig), r[u]);
       }
@@ -550,6 +564,7 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
     const int r = i / NP, c = i - r * NP;
     A[i] = r < n && c < n ? Cm[size_t(r) * n + c] : 0.0;
   }
+  __syncthreads();   // the trace below reads diagonal entries other threads wrote
   // block sum in a fixed order: per wave a butterfly (identical bits in every lane),
   // then the W wave sums in wave order
   auto block_sum = [&](double v) {
@@ -782,10 +797,13 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
   ResidParams qp{xhat, atom, angle, coef, t.dictHat, t.cs64, P, K, t.M, t.R, t.B, BP, t.S, t.T, resid};
   {
     const int G = 256 / BP, nt = G * BP;
-    const size_t lds = sizeof(double) * 2 * size_t(t.R) * (t.T + 1) + sizeof(float) * 2 * size_t(t.M) * t.B;
+    const size_t table = sizeof(double) * 2 * size_t(t.R) * (t.T + 1);
+    const bool paired = table + sizeof(float) * 2 * size_t(t.M) * t.B <= kResidLdsPaired;
+    const size_t lds = table + sizeof(float) * (paired ? 2 : 1) * size_t(t.M) * t.B;
     const int64_t want = (P + G - 1) / G;
     const unsigned grid = unsigned(want < 2048 ? want : 2048);
-    auto kern = K <= 4 ? rk_resid_kernel<4> : rk_resid_kernel<8>;
+    auto kern = paired ? (K <= 4 ? rk_resid_kernel<4, true> : rk_resid_kernel<8, true>)
+                       : (K <= 4 ? rk_resid_kernel<4, false> : rk_resid_kernel<8, false>);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return int(e);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), lds, st, qp);

@@ -125,6 +125,21 @@ def test_update_with_more_than_four_slots(dev):
     print("worst atom difference", _check_update(g, Dp, R, K, X, dev))
 
 
+def test_update_largest_dictionary(dev):
+    """M = 256 atoms at B = 105: the residual kernel's dictionary no longer fits in LDS as
+    pairs and takes the single-value layout."""
+    g = wl.GEOM15
+    M, R, K = 256, 32, 2
+    D = wl.draw_dictionary(M, g.B, seed=28).astype(np.float32).astype(np.float64)
+    basis = orc.build_basis(g.N, g.S, g.T)
+    d = wl.draw_mixtures(1500, g.N, M, 2, 0.05, seed=28)
+    X = orc.project(basis, orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
+    X = X.astype(np.float32).astype(np.float64)
+    Dp = D + 0.2 * np.random.default_rng(29).standard_normal(D.shape)
+    Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
+    print("worst atom difference", _check_update(g, Dp, R, K, X, dev))
+
+
 def test_update_over_many_chunks_matches_reference(dev):
     """Scale geometry (M=64, R=64, K=4) on 12,000 patches: about 750 pairs per atom,
     so every bucket spans several 256-pair chunks and the chunk partials are summed;
