@@ -697,8 +697,9 @@ def run_rotate(args, dev):
     """Rotation speed (Sec. IV): random N x N patches turned by 100 + sqrt(2) degrees with
     the nearest and bicubic rotation matrices (R x) and by steering precomputed hat
     coordinates (S x_hat), at N = 11 and 15 and for the paper's 50,000 patches and a
-    4,000,000-patch batch; also the full steering rotation (project, steer, synthesize).
-    Each method: median of 20 event-timed runs."""
+    4,000,000-patch batch; also steering with the low-pass basis (T halved) and the full
+    steering rotation (project, steer, synthesize).  Each method: median of 20 event-timed
+    runs."""
     import torch
     from paper_1806_04374_amd import rsc
     theta = np.deg2rad(100 + np.sqrt(2))
@@ -720,6 +721,7 @@ def run_rotate(args, dev):
     for geom in (wl.GEOM11, wl.GEOM15):
         N = geom.N
         h = rsc.rsc_create(N, geom.S, geom.T)
+        hl = rsc.rsc_create(N, geom.S, geom.T // 2)
         plans = {m: rsc.RotationPlan(N, theta, m) for m in ("nearest", "bicubic")}
         for P in (50_000, 4_000_000):
             rng = torch.Generator(device=dev)
@@ -728,27 +730,31 @@ def run_rotate(args, dev):
             Y = torch.empty_like(X)
             xh = rsc.rsc_project(h, X)
             xo = torch.empty_like(xh)
+            xl = rsc.rsc_project(hl, X)
+            xlo = torch.empty_like(xl)
             r = {}
             for m, plan in plans.items():
                 r[m] = timed(lambda: rsc.rsc_rotate_interp(plan, X, out=Y, stream=stream))
             r["steer"] = timed(lambda: rsc.rsc_steer(h, xh, theta, out=xo, stream=stream))
             r["copy_of_xhat"] = timed(lambda: xo.copy_(xh))          # achievable-bandwidth reference
+            r["steer_low"] = timed(lambda: rsc.rsc_steer(hl, xl, theta, out=xlo, stream=stream))
             r["steer_full"] = timed(lambda: rsc.rsc_synthesize_hat(
                 h, rsc.rsc_steer(h, rsc.rsc_project(h, X, xh, stream=stream), theta, out=xo, stream=stream),
                 out=Y, stream=stream))
             results[f"N{N}_P{P}"] = {
-                "ms": r, "B": h.B,
+                "ms": r, "B": h.B, "B_low": hl.B,
                 "bicubic_over_steer": r["bicubic"] / r["steer"], "nearest_over_steer": r["nearest"] / r["steer"],
                 "steer_GBps": 2 * 4 * h.B * P / (r["steer"] * 1e-3) / 1e9,
                 "bicubic_GBps": 2 * 4 * N * N * P / (r["bicubic"] * 1e-3) / 1e9,
                 "copy_GBps": 2 * 4 * h.B * P / (r["copy_of_xhat"] * 1e-3) / 1e9,
             }
             print(f"rotate N={N} P={P}: {json.dumps(r)}", file=sys.stderr, flush=True)
-            del X, Y, xh, xo
+            del X, Y, xh, xo, xl, xlo
             torch.cuda.empty_cache()
         for plan in plans.values():
             plan.close()
         h.close()
+        hl.close()
     main = results["N11_P4000000"]
     bytes_steer = 2 * 4 * 55 * 4_000_000
     out = {
@@ -757,10 +763,10 @@ def run_rotate(args, dev):
         "warmup": 3, "ms_per_step": main["ms"]["steer"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "rotate: 4,000,000 random 11x11 patches (B = 55); also 50,000 (the paper's "
-                               "count) and 15x15; nearest / bicubic rotation matrices, steering, full "
-                               "steering rotation"},
+                               "count) and 15x15; nearest / bicubic rotation matrices, steering, low-pass "
+                               "steering (T halved), full steering rotation"},
         "results": results,
-        "roofline": {"kernel": "steer_kernel", "bound": "hbm", "achieved": main["steer_GBps"], "peak": 8000.0,
+        "roofline": {"kernel": "steer_stream_kernel", "bound": "hbm", "achieved": main["steer_GBps"], "peak": 8000.0,
                      "unit": "GB/s", "frac": main["steer_GBps"] / 8000.0, "traffic": None,
                      "algorithmic_bytes_per_launch": bytes_steer},
         "cpu_baseline": None,

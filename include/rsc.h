@@ -85,8 +85,10 @@ typedef struct rsc_rotation_plan rsc_rotation_plan;
  * Cholesky factorisation.
  *
  *   N        odd patch side, 3 <= N <= 31
- *   S, T     radial profiles and largest harmonic; (S, T) must be one of the
- *            compiled geometries (5, 5) or (7, 7), and B = S(2T+1) <= n_pix
+ *   S, T     radial profiles and largest harmonic; B = S(2T+1) <= min(n_pix, 128),
+ *            T <= 15.  The pursuit (rsc_set_dictionary and everything that needs a
+ *            dictionary) is compiled for (S, T) = (5, 5) and (7, 7); handles of other
+ *            geometries (FP32 only) serve projection, steering and synthesis
  *   centres  host array [S] of profile centres in pixels, or NULL for
  *            centres[s] = (s+1) (N/2)/S
  *   sigma    profile width in pixels, or <= 0 for (N/2)/S (used only when

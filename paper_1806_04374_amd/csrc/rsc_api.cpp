@@ -58,6 +58,27 @@ rsc_status upload(X*& dst, const std::vector<X>& src, const char* what) {
   return RSC_OK;
 }
 
+// Packs host tables into one staging buffer at 256-byte aligned offsets; bind() then points
+// each registered device pointer into the arena (nullptr for an empty table).
+struct Arena {
+  std::vector<char> staging;
+  std::vector<std::pair<void**, size_t>> slots;  // (pointer to set, offset), offset ~0 for empty
+  template <class X>
+  void add(X*& dst, const std::vector<X>& src) {
+    if (src.empty()) {
+      slots.emplace_back(reinterpret_cast<void**>(&dst), ~size_t(0));
+      return;
+    }
+    const size_t off = (staging.size() + 255) & ~size_t(255);
+    staging.resize(off + src.size() * sizeof(X));
+    std::memcpy(staging.data() + off, src.data(), src.size() * sizeof(X));
+    slots.emplace_back(reinterpret_cast<void**>(&dst), off);
+  }
+  void bind(char* base) {
+    for (auto& sl : slots) *sl.first = (base && sl.second != ~size_t(0)) ? base + sl.second : nullptr;
+  }
+};
+
 // Round to the nearest BF16 / FP16 value (ties to even); returns the bit pattern.
 uint16_t to_bf16(float f) {
   uint32_t u;
@@ -99,9 +120,11 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   *out = nullptr;
   if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
   if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
-  if (!rsc::encode_supported(S, T))
-    return fail(RSC_E_UNSUPPORTED, "(S, T) must be (5, 5) or (7, 7) in this build");
+  if (S * (2 * T + 1) > 128) return fail(RSC_E_UNSUPPORTED, "B = S(2T+1) must be <= 128 in this build");
+  if (T > 15) return fail(RSC_E_UNSUPPORTED, "T must be <= 15 in this build");
   if (prec != RSC_FP32 && prec != RSC_BF16 && prec != RSC_FP16) return fail(RSC_E_INVALID, "unknown precision");
+  if (!rsc::encode_supported(S, T) && prec != RSC_FP32)
+    return fail(RSC_E_UNSUPPORTED, "16-bit handles need (S, T) = (5, 5) or (7, 7)");
   if (centres) {
     for (int s = 0; s < S; ++s)
       if (!std::isfinite(centres[s])) return fail(RSC_E_INVALID, "non-finite profile centre");
@@ -233,18 +256,7 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.pinvI);
   free_dev(d.dpixI);
   free_dev(d.phiPad);
-  free_dev(d.dictA);
-  free_dev(d.dictHat);
-  free_dev(d.dftA32);
-  free_dev(d.dftA16);
-  free_dev(d.dftA16s);
-  free_dev(d.cs);
-  free_dev(d.gramH);
-  free_dev(d.lpA);
-  free_dev(d.lpF16);
-  free_dev(d.lpF32);
-  free_dev(d.gramH64);
-  free_dev(d.cs64);
+  free_dev(d.dictArena);
   free_dev(d.lpStats);
   free_dev(d.lpPinv);
   free_dev(d.lpPix16);
@@ -274,6 +286,10 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   if (R < 1 || R > 128) return fail(RSC_E_INVALID, "R must be in 1..128");
   rsc::DeviceTables& d = h->dev;
   const int S = d.S, T = d.T, B = d.B;
+  if (!rsc::encode_supported(S, T))
+    return fail(RSC_E_UNSUPPORTED,
+                "the encoders are compiled for (S, T) = (5, 5) and (7, 7); this geometry supports "
+                "projection, steering and synthesis only");
   for (int m = 0; m < M; ++m) {
     double n2 = 0.0;
     for (int b = 0; b < B; ++b) {
@@ -467,20 +483,42 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
   if (!lp && rsc::encode_lds_bytes(d, RSC_TILE_16) > 160 * 1024)
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
-  rsc_status s = upload(d.dictA, dictA, "dictionary operand");
-  if (s == RSC_OK) s = upload(d.dictHat, hat, "dictionary");
-  if (s == RSC_OK) s = upload(d.dftA32, dftA32, "angle DFT operand");
-  if (s == RSC_OK) s = upload(d.dftA16, dftA16, "angle DFT operand");
-  if (s == RSC_OK) s = upload(d.dftA16s, dftA16s, "angle DFT operand");
-  if (s == RSC_OK) s = upload(d.cs, cs, "steering table");
-  if (s == RSC_OK) s = upload(d.gramH, gramH, "pair table");
-  if (s == RSC_OK) s = upload(d.lpA, lpA, "16-bit dictionary operand");
-  if (s == RSC_OK) s = upload(d.lpF16, lpF16, "16-bit angle DFT operand");
-  if (s == RSC_OK) s = upload(d.lpF32, lpF32, "angle DFT operand");
-  if (s == RSC_OK) s = upload(d.gramH64, gramH64, "FP64 pair table");
-  if (s == RSC_OK) s = upload(d.cs64, cs64, "FP64 steering table");
-  h->has_dict = s == RSC_OK;
-  return s == RSC_OK ? ok() : s;
+  // one host staging buffer, one device arena (kept across uploads), one copy
+  Arena arena;
+  arena.add(d.dictA, dictA);
+  arena.add(d.dictHat, hat);
+  arena.add(d.dftA32, dftA32);
+  arena.add(d.dftA16, dftA16);
+  arena.add(d.dftA16s, dftA16s);
+  arena.add(d.cs, cs);
+  arena.add(d.gramH, gramH);
+  arena.add(d.lpA, lpA);
+  arena.add(d.lpF16, lpF16);
+  arena.add(d.lpF32, lpF32);
+  arena.add(d.gramH64, gramH64);
+  arena.add(d.cs64, cs64);
+  // kernels still in flight on any stream may read the current tables
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return device_fail(int(e), "device synchronisation before the dictionary upload");
+  if (d.dictArenaBytes < arena.staging.size()) {
+    free_dev(d.dictArena);
+    d.dictArenaBytes = 0;
+    e = hipMalloc(&d.dictArena, arena.staging.size());
+    if (e != hipSuccess) {
+      d.dictArena = nullptr;
+      arena.bind(nullptr);
+      return fail(RSC_E_NOMEM, "hipMalloc for the dictionary tables failed");
+    }
+    d.dictArenaBytes = arena.staging.size();
+  }
+  arena.bind(static_cast<char*>(d.dictArena));
+  e = hipMemcpy(d.dictArena, arena.staging.data(), arena.staging.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    arena.bind(nullptr);
+    return device_fail(int(e), "dictionary tables");
+  }
+  h->has_dict = true;
+  return ok();
 }
 
 rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile) {
@@ -665,8 +703,10 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
     return fail(RSC_E_INVALID, "null device pointer");
   if (ws_bytes < rsc::images_workspace_bytes(n_images)) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(RSC_E_INVALID, "workspace not 8-byte aligned");
-  if (!((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)))
-    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for N = 11 and N = 15");
+  if (!((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
+      !rsc::encode_supported(h->dev.S, h->dev.T))
+    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
+                                   "geometries");
   int e = rsc::launch_project_images(h->dev, pixels, img_offset, H, W, n_images, P_total, workspace, xhat,
                                      stream);
   return e ? device_fail(e, "image projection launch") : ok();

@@ -40,6 +40,10 @@ struct DeviceTables {
   float* pinvI = nullptr;    // image projection operand over disk pixels [2 or 4][ceil(n_pix/2)][64]
   int* dpixI = nullptr;      // (dy << 8 | dx) of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
+  // Dictionary tables (dictA .. cs64 below) live in one device arena, refilled in place by
+  // every dictionary upload of the same or a smaller size.
+  void* dictArena = nullptr;
+  size_t dictArenaBytes = 0;
   float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
   float* dictHat = nullptr;  // dictionary rows [16*ceil(M/16)][B] (zero rows past M)
   float* dftA32 = nullptr;   // 32x32-tile stage-2 operand, angles r < R/2 [T+1][64] (even R <= 64)

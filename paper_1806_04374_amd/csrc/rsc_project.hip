@@ -300,7 +300,7 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
   if (P <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int NN = t.N * t.N;
-  if (t.prec != RSC_FP32 && t.N == 11 && t.B <= 64 && t.lpPinv) {
+  if (t.prec != RSC_FP32 && t.N == 11 && t.S == 5 && t.T == 5 && t.lpPinv) {
     constexpr int kNN = 121, kKS = 7;
     if ((t.n_pix + 15) / 16 != kKS) return int(hipErrorInvalidValue);
     const size_t lds = project_lp_lds_bytes(t.N, t.n_pix, t.prec);
@@ -318,7 +318,8 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
                        reinterpret_cast<const uint4*>(t.lpPinv), t.lpPix16, t.lpPinvUnscale, vin, vout, xhat);
     return int(hipGetLastError());
   }
-  if (t.N == 11 && t.B <= 64 && t.pinvD) {
+  // the tiled kernel is compiled for the 11x11, S = T = 5 geometry (B = 55)
+  if (t.N == 11 && t.S == 5 && t.T == 5 && t.pinvD) {
     constexpr int kNN = 121, kKPD = 49;
     if ((t.n_pix + 1) / 2 != kKPD) return int(hipErrorInvalidValue);
     const size_t lds = project_tiled_lds_bytes(t.N, t.n_pix);

@@ -13,6 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "rsc_internal.h"
@@ -23,20 +26,24 @@ namespace {
 
 constexpr int kRotPatches = 32;   // patches per block pass in rotate_taps_kernel
 
-// Thread t owns output pixels t, t + 256, ... (QPT of them) and keeps their taps in
-// registers for every patch; each block stages kRotPatches patches in LDS (coalesced),
-// applies the taps to them, and writes the rotated patches (coalesced).
-template <int NTAP, int QPT>
+// The block's threads form 256 / G groups of G lanes; lane g of a group owns output
+// pixels g, g + G, ... (QPT of them) and keeps their taps in registers.  Each block stages
+// kRotPatches patches in LDS (coalesced, 16-byte loads where aligned), group h applies the
+// taps to patches h, h + 256 / G, ..., and writes them (coalesced).  G is the smallest of
+// 64, 128, 256 that covers N*N (256 for N*N > 256), so few lanes idle.
+template <int NTAP, int QPT, int G>
 __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restrict__ in, int64_t P, int NN,
                                                          const int32_t* __restrict__ src,
-                                                         const float* __restrict__ wgt, float* __restrict__ out) {
+                                                         const float* __restrict__ wgt, bool vec,
+                                                         float* __restrict__ out) {
+  constexpr int NSUB = 256 / G;
   extern __shared__ float xs[];   // [kRotPatches][NN]
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, g = t % G, sub = t / G;
   float w[QPT][NTAP];
   int sidx[QPT][NTAP];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int q = t + 256 * j < NN ? t + 256 * j : 0;
+    const int q = g + G * j < NN ? g + G * j : 0;
 #pragma unroll
     for (int k = 0; k < NTAP; ++k) {
       w[j][k] = wgt[q * NTAP + k];
@@ -46,18 +53,86 @@ __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restric
   for (int64_t p0 = int64_t(blockIdx.x) * kRotPatches; p0 < P; p0 += int64_t(gridDim.x) * kRotPatches) {
     const int np = P - p0 < kRotPatches ? int(P - p0) : kRotPatches;
     __syncthreads();
-    for (int i = t; i < np * NN; i += 256) xs[i] = in[p0 * NN + i];
+    if (vec && np == kRotPatches) {
+      const float4* s4 = reinterpret_cast<const float4*>(in + p0 * NN);
+      for (int i = t; i < kRotPatches * NN / 4; i += 256) reinterpret_cast<float4*>(xs)[i] = s4[i];
+    } else {
+      for (int i = t; i < np * NN; i += 256) xs[i] = in[p0 * NN + i];
+    }
     __syncthreads();
-    for (int p = 0; p < np; ++p) {
+    for (int p = sub; p < np; p += NSUB) {
       const float* x = xs + p * NN;
 #pragma unroll
       for (int j = 0; j < QPT; ++j) {
-        const int q = t + 256 * j;
+        const int q = g + G * j;
         if (q >= NN) continue;
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < NTAP; ++k) acc += w[j][k] * x[sidx[j][k]];
         out[(p0 + p) * NN + q] = acc;
+      }
+    }
+  }
+}
+
+// The same for N*N = NNC known at compile time (NNC <= 256, one output pixel per lane,
+// G = 128 or 256), whole chunks only, 16-byte aligned input: the next chunk is loaded into
+// registers while the current one is computed, and every LDS gather uses the lane's tap
+// offset plus an immediate patch offset (no address arithmetic per tap).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int NTAP, int NNC, int G>
+__global__ __launch_bounds__(256, 4) void rotate_taps_fixed_kernel(const float* __restrict__ in, int64_t nchunk,
+                                                               const int32_t* __restrict__ src,
+                                                               const float* __restrict__ wgt,
+                                                               float* __restrict__ out) {
+  constexpr int NSUB = 256 / G, PPG = kRotPatches / NSUB;   // patches per lane group and chunk
+  constexpr int NV = kRotPatches * NNC / 4, VPT = (NV + 255) / 256;
+  static_assert(NNC <= G && kRotPatches % NSUB == 0, "one output pixel per lane");
+  __shared__ v4f xs4[VPT * 256];   // NV used; the rest takes the clamped loads' copies
+  const float* xs = reinterpret_cast<const float*>(xs4);
+  const int t = threadIdx.x, g = t % G, sub = t / G;
+  const bool own = g < NNC;
+  const int q = own ? g : 0;
+  float w[NTAP];
+  const float* base[NTAP];
+#pragma unroll
+  for (int k = 0; k < NTAP; ++k) {
+    w[k] = wgt[q * NTAP + k];
+    base[k] = xs + sub * NNC + src[q * NTAP + k];
+  }
+  // loads clamped to the chunk's last float4 (unconditional, so nothing waits on them early)
+  int vi[VPT];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) vi[v] = t + 256 * v < NV ? t + 256 * v : NV - 1;
+  // the launch has at most nchunk blocks, so every block starts on a chunk
+  v4f nxt[VPT];
+  int64_t c = blockIdx.x;
+  {
+    const v4f* s4 = reinterpret_cast<const v4f*>(in + c * kRotPatches * NNC);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+  }
+  for (; c < nchunk; c += gridDim.x) {
+    __syncthreads();   // the previous chunk's gathers are done
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) xs4[t + 256 * v] = nxt[v];
+    __syncthreads();
+    {
+      // the next chunk (the last one re-reads its own, unused)
+      const int64_t cn = c + gridDim.x < nchunk ? c + gridDim.x : c;
+      const v4f* s4 = reinterpret_cast<const v4f*>(in + cn * kRotPatches * NNC);
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+    }
+    if (own) {
+      float* o = out + c * kRotPatches * NNC + sub * NNC + g;
+#pragma unroll
+      for (int i = 0; i < PPG; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < NTAP; ++k) acc += w[k] * base[k][i * NSUB * NNC];
+        o[i * NSUB * NNC] = acc;
       }
     }
   }
@@ -78,6 +153,94 @@ struct SteerParams {
 template <int S, int T>
 __global__ __launch_bounds__(256) void steer_kernel(SteerParams prm) {
   constexpr int B = S * (2 * T + 1), W = S * (T + 1);   // work items per patch
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= prm.P * W) return;
+  const int64_t p = i / W;
+  const int w = int(i - p * W);
+  const float* x = prm.xhat + p * B;
+  float* o = prm.out + p * B;
+  if (w < S) {
+    o[w] = x[w];
+    return;
+  }
+  const int k = 1 + (w - S) / S, sp = (w - S) - (k - 1) * S;
+  const int ire = S + 2 * S * (k - 1) + sp, iim = ire + S;
+  const float a = x[ire], bb = x[iim];
+  float c, sn;
+  if (prm.theta) {
+    sincosf(float(k) * prm.theta[p], &sn, &c);
+  } else {
+    c = prm.cs[k];
+    sn = prm.sn[k];
+  }
+  o[ire] = a * c + bb * sn;
+  o[iim] = bb * c - a * sn;
+}
+
+// One angle for all patches, compiled geometry: the array is streamed in chunks of
+// kSteerChunk whole patches (kSteerChunk * B floats, a multiple of 4) with 16-byte loads
+// and stores.  A chunk is staged in LDS, where each output element finds its partner
+// (Re <-> Im, S apart).  Since a chunk holds whole patches, the coordinate of each of a
+// thread's elements is the same in every chunk, so its coefficients are set up once:
+//   out[c] = alpha_c x[c] + beta_c x[c + delta_c],
+// alpha = 1, beta = 0 on harmonic 0; alpha = cos k theta, beta = +sin k theta, delta = +S
+// on Re; alpha = cos k theta, beta = -sin k theta, delta = -S on Im.
+constexpr int kSteerChunk = 64;
+
+template <int S, int T>
+__global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int64_t nchunk) {
+  constexpr int B = S * (2 * T + 1), CF = kSteerChunk * B, NV = CF / 4, VPT = (NV + 255) / 256;
+  static_assert(CF % 4 == 0, "a chunk must be whole float4s");
+  __shared__ float buf[CF];
+  const int t = threadIdx.x;
+  float alpha[VPT][4], beta[VPT][4];
+  int partner[VPT][4];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = 4 * (t + 256 * v) + j;   // element of the chunk
+      const int c = e % B;                   // its coordinate in the patch
+      float a = 1.f, b = 0.f;
+      int d = 0;
+      if (c >= S && e < CF) {
+        const int cc = c - S, k = 1 + cc / (2 * S), im = (cc % (2 * S)) >= S;
+        a = prm.cs[k];
+        b = im ? -prm.sn[k] : prm.sn[k];
+        d = im ? -S : S;
+      }
+      alpha[v][j] = a;
+      beta[v][j] = b;
+      partner[v][j] = e < CF ? e + d : 0;
+    }
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const float4* src = reinterpret_cast<const float4*>(prm.xhat + ch * CF);
+    float4 x[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) x[v] = src[t + 256 * v];
+    __syncthreads();   // the previous chunk's partner reads are done
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) reinterpret_cast<float4*>(buf)[t + 256 * v] = x[v];
+    __syncthreads();
+    float4* dst = reinterpret_cast<float4*>(prm.out + ch * CF);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) {
+        float4 o;
+        o.x = alpha[v][0] * x[v].x + beta[v][0] * buf[partner[v][0]];
+        o.y = alpha[v][1] * x[v].y + beta[v][1] * buf[partner[v][1]];
+        o.z = alpha[v][2] * x[v].z + beta[v][2] * buf[partner[v][2]];
+        o.w = alpha[v][3] * x[v].w + beta[v][3] * buf[partner[v][3]];
+        dst[t + 256 * v] = o;
+      }
+  }
+}
+
+// The same for any geometry (index arithmetic at run time).
+__global__ __launch_bounds__(256) void steer_any_kernel(SteerParams prm, int T) {
+  const int S = prm.S, B = prm.B, W = S * (T + 1);
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= prm.P * W) return;
   const int64_t p = i / W;
@@ -132,6 +295,69 @@ __global__ __launch_bounds__(256) void synth_hat_kernel(const float* __restrict_
   }
 }
 
+// Phi x_hat for N*N <= 256, B <= 128: lane g of a G-lane group owns output pixel g and
+// keeps row g of Phi in registers (BV float4, zero past B); a block stages kSynP patches'
+// hat rows in LDS at a padded stride of 4 BV floats (the pads stay zero), and group h
+// forms patches h, h + 256 / G, ... with one broadcast 16-byte LDS read per 4 FMAs.
+constexpr int kSynP = 32;
+
+template <int BV, int G>
+__global__ __launch_bounds__(256) void synth_reg_kernel(const float* __restrict__ xhat, int64_t P, int B, int NN,
+                                                       const float* __restrict__ phi, float* __restrict__ out) {
+  constexpr int NSUB = 256 / G, BP = 4 * BV;
+  __shared__ float4 xs4[kSynP * BV];
+  float* xs = reinterpret_cast<float*>(xs4);
+  const int t = threadIdx.x, g = t % G, sub = t / G, lane = t & 63, wave = t >> 6;
+  const bool own = g < NN;
+  float4 ph[BV];
+#pragma unroll
+  for (int v = 0; v < BV; ++v) {
+    float e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = (own && 4 * v + i < B) ? phi[g * B + 4 * v + i] : 0.f;
+    ph[v] = make_float4(e[0], e[1], e[2], e[3]);
+  }
+  for (int i = t; i < kSynP * BP; i += 256) xs[i] = 0.f;
+  for (int64_t p0 = int64_t(blockIdx.x) * kSynP; p0 < P; p0 += int64_t(gridDim.x) * kSynP) {
+    const int np = P - p0 < kSynP ? int(P - p0) : kSynP;
+    __syncthreads();   // also orders the zero fill before the first staging
+    for (int pp = wave; pp < np; pp += 4)
+      for (int c = lane; c < B; c += 64) xs[pp * BP + c] = xhat[(p0 + pp) * B + c];
+    __syncthreads();
+    if (own) {
+      for (int p = sub; p < np; p += NSUB) {
+        const float4* x = xs4 + p * BV;
+        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+        for (int v = 0; v < BV; ++v) {
+          const float4 xv = x[v];
+          a0 += ph[v].x * xv.x;
+          a1 += ph[v].y * xv.y;
+          a0 += ph[v].z * xv.z;
+          a1 += ph[v].w * xv.w;
+        }
+        out[(p0 + p) * NN + g] = a0 + a1;
+      }
+    }
+  }
+}
+
+// Blocks of 256 threads (no dynamic LDS) that fit on the whole chip at once: a grid of
+// this size runs in one round, each block looping over its share of chunks.
+// Cached per kernel (the query is host work on every launch otherwise).
+template <class Kern>
+int64_t resident_blocks(Kern kern) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int64_t> cache;
+  const void* key = reinterpret_cast<const void*>(kern);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 4;
+  return cache[key] = int64_t(num_cus()) * per_cu;
+}
+
 double keys(double t) {
   const double a = -0.5;
   t = std::fabs(t);
@@ -182,23 +408,51 @@ size_t rotate_lds_bytes(int N, int ntap) {
 int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w, float* out,
                        void* stream) {
   const int NN = N * N;
-  const int64_t want = (P + kRotPatches - 1) / kRotPatches;
   const int64_t cap = int64_t(num_cus()) * 8;
-  const unsigned grid = unsigned(want < cap ? want : cap);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int qpt = (NN + 255) / 256;
   const size_t lds = rotate_lds_bytes(N, ntap);
+  const bool vec = (reinterpret_cast<uintptr_t>(in) & 15) == 0;   // kRotPatches * NN is a multiple of 4
+  // 11x11 and 15x15: whole chunks by the pipelined kernel, the rest by the general one
+  const int64_t nfull = vec && (NN == 121 || NN == 225) ? P / kRotPatches : 0;
+  if (nfull > 0) {
+    // one resident round of blocks (as many as fit on every CU at once), each looping
+    // over chunks, so no CU idles on a partial second round
+    auto fixed = [&](auto kern) {
+      const int64_t blocks = resident_blocks(kern);
+      hipLaunchKernelGGL(kern, dim3(unsigned(nfull < blocks ? nfull : blocks)), dim3(256), 0, st, in, nfull, src,
+                         w, out);
+      return hipGetLastError();
+    };
+    hipError_t e;
+    if (NN == 121) e = ntap == 1 ? fixed(rotate_taps_fixed_kernel<1, 121, 128>) : fixed(rotate_taps_fixed_kernel<16, 121, 128>);
+    else e = ntap == 1 ? fixed(rotate_taps_fixed_kernel<1, 225, 256>) : fixed(rotate_taps_fixed_kernel<16, 225, 256>);
+    if (e != hipSuccess) return int(e);
+    const int64_t done = nfull * kRotPatches;
+    if (done == P) return 0;
+    in += done * NN;
+    out += done * NN;
+    P -= done;
+  }
+  const int64_t want = (P + kRotPatches - 1) / kRotPatches;
+  const unsigned grid = unsigned(want < cap ? want : cap);
   auto go = [&](auto kern) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(lds));
     if (e != hipSuccess) return int(e);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, out);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, vec, out);
     return int(hipGetLastError());
   };
-  if (ntap == 1) return qpt == 1 ? go(rotate_taps_kernel<1, 1>) : qpt == 2 ? go(rotate_taps_kernel<1, 2>)
-                                                                          : go(rotate_taps_kernel<1, 3>);
-  return qpt == 1 ? go(rotate_taps_kernel<16, 1>) : qpt == 2 ? go(rotate_taps_kernel<16, 2>)
-                                                             : go(rotate_taps_kernel<16, 3>);
+  if (ntap == 1) {
+    if (NN <= 64) return go(rotate_taps_kernel<1, 1, 64>);
+    if (NN <= 128) return go(rotate_taps_kernel<1, 1, 128>);
+    return qpt == 1 ? go(rotate_taps_kernel<1, 1, 256>) : qpt == 2 ? go(rotate_taps_kernel<1, 2, 256>)
+                                                                : go(rotate_taps_kernel<1, 3, 256>);
+  }
+  if (NN <= 64) return go(rotate_taps_kernel<16, 1, 64>);
+  if (NN <= 128) return go(rotate_taps_kernel<16, 1, 128>);
+  return qpt == 1 ? go(rotate_taps_kernel<16, 1, 256>) : qpt == 2 ? go(rotate_taps_kernel<16, 2, 256>)
+                                                               : go(rotate_taps_kernel<16, 3, 256>);
 }
 
 int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const float* theta, double theta0, float* out,
@@ -214,17 +468,66 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
     prm.cs[k] = float(std::cos(k * theta0));
     prm.sn[k] = float(std::sin(k * theta0));
   }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // one angle, compiled geometry, 16-byte aligned buffers: whole chunks streamed, the
+  // remaining patches (fewer than a chunk) by the per-coordinate kernel below
+  const bool aligned = ((reinterpret_cast<uintptr_t>(xhat) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  const int64_t nchunk = (!theta && aligned) ? P / kSteerChunk : 0;
+  const int geo = t.S == 5 && t.T == 5 ? 0 : t.S == 7 && t.T == 7 ? 1 : t.S == 5 && t.T == 2 ? 2
+                : t.S == 7 && t.T == 3 ? 3 : -1;
+  if (nchunk > 0 && geo >= 0) {
+    auto go = [&](auto kern) {
+      const int64_t blocks = resident_blocks(kern);
+      hipLaunchKernelGGL(kern, dim3(unsigned(nchunk < blocks ? nchunk : blocks)), dim3(256), 0, st, prm, nchunk);
+      return hipGetLastError();
+    };
+    hipError_t e = geo == 0 ? go(steer_stream_kernel<5, 5>) : geo == 1 ? go(steer_stream_kernel<7, 7>)
+                 : geo == 2 ? go(steer_stream_kernel<5, 2>) : go(steer_stream_kernel<7, 3>);
+    if (e != hipSuccess) return int(e);
+    const int64_t done = nchunk * kSteerChunk;
+    if (done == P) return 0;
+    prm.xhat = xhat + done * t.B;
+    prm.out = out + done * t.B;
+    prm.P = P - done;
+    P = prm.P;
+  }
   const int64_t items = P * int64_t(t.S) * (t.T + 1);
   const dim3 grid(unsigned((items + 255) / 256));
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (t.S == 5 && t.T == 5) hipLaunchKernelGGL((steer_kernel<5, 5>), grid, dim3(256), 0, st, prm);
   else if (t.S == 7 && t.T == 7) hipLaunchKernelGGL((steer_kernel<7, 7>), grid, dim3(256), 0, st, prm);
-  else return int(hipErrorInvalidValue);
+  else if (t.S == 5 && t.T == 2) hipLaunchKernelGGL((steer_kernel<5, 2>), grid, dim3(256), 0, st, prm);
+  else if (t.S == 7 && t.T == 3) hipLaunchKernelGGL((steer_kernel<7, 3>), grid, dim3(256), 0, st, prm);
+  else hipLaunchKernelGGL(steer_any_kernel, grid, dim3(256), 0, st, prm, t.T);
   return int(hipGetLastError());
 }
 
 int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float* out, void* stream) {
   const int NN = t.N * t.N;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (NN <= 256 && t.B <= 128) {
+    const int bv = (t.B + 3) / 4;
+    const int64_t want = (P + kSynP - 1) / kSynP;
+    const int64_t cap = int64_t(num_cus()) * 8;
+    const dim3 grid(unsigned(want < cap ? want : cap));
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, xhat, P, t.B, NN, t.phiPad, out);
+      return int(hipGetLastError());
+    };
+    // exact row lengths of the compiled geometries, else rounded up (zero pads)
+    auto pick = [&](auto g_tag) -> int {
+      constexpr int G = decltype(g_tag)::value;
+      switch (bv) {
+        case 7: return go(synth_reg_kernel<7, G>);
+        case 13: return go(synth_reg_kernel<13, G>);
+        case 14: return go(synth_reg_kernel<14, G>);
+        case 27: return go(synth_reg_kernel<27, G>);
+        default: return bv <= 16 ? go(synth_reg_kernel<16, G>) : go(synth_reg_kernel<32, G>);
+      }
+    };
+    if (NN <= 64) return pick(std::integral_constant<int, 64>{});
+    if (NN <= 128) return pick(std::integral_constant<int, 128>{});
+    return pick(std::integral_constant<int, 256>{});
+  }
   const size_t lds = sizeof(float) * (size_t(NN) * t.B + 8 * size_t(t.B));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(synth_hat_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -232,8 +535,7 @@ int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float*
   const int64_t want = (P + 7) / 8;
   const int64_t cap = int64_t(num_cus()) * 2;
   const unsigned grid = unsigned(want < cap ? want : cap);
-  hipLaunchKernelGGL(synth_hat_kernel, dim3(grid), dim3(256), lds, reinterpret_cast<hipStream_t>(stream), xhat, P,
-                     t.B, NN, t.phiPad, out);
+  hipLaunchKernelGGL(synth_hat_kernel, dim3(grid), dim3(256), lds, st, xhat, P, t.B, NN, t.phiPad, out);
   return int(hipGetLastError());
 }
 

@@ -66,7 +66,9 @@ def test_argument_errors_without_device(L):
     h = ctypes.c_void_p()
     assert L.rsc_create(10, 5, 5, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_INVALID
     assert b"odd" in L.rsc_last_error()
-    assert L.rsc_create(11, 4, 4, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED
+    assert L.rsc_create(15, 7, 9, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED   # B = 133
+    assert L.rsc_create(31, 1, 16, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED   # T > 15
+    assert L.rsc_create(11, 5, 2, None, 0.0, 1, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED    # 16-bit
     assert L.rsc_create(11, 5, 5, None, 0.0, 0, None) == rsc.RSC_E_INVALID
     assert L.rsc_create(11, 5, 5, None, 0.0, 7, ctypes.byref(h)) == rsc.RSC_E_INVALID
     assert L.rsc_precision_stats(None, None, 0) == rsc.RSC_E_INVALID

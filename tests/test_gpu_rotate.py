@@ -94,3 +94,73 @@ def test_rotation_argument_errors(dev):
     with pytest.raises(rsc.RscError, match="distinct"):
         rsc.rsc_rotate_interp(plan, x, out=x)
     plan.close()
+
+
+@pytest.mark.parametrize("N,S,T", [(11, 5, 2), (15, 7, 3), (9, 3, 4)])
+def test_basis_only_geometries(dev, N, S, T):
+    """Handles of geometries the pursuit is not compiled for (here the low-pass bases with T
+    halved) project, steer and synthesize like the reference; a dictionary is refused."""
+    from paper_1806_04374_amd import rsc
+    basis = orc.build_basis(N, S, T)
+    h = rsc.rsc_create(N, S, T)
+    with pytest.raises(rsc.RscError) as e:
+        rsc.rsc_set_dictionary(h, np.ones((2, h.B), np.float32), 8)
+    assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    rng = np.random.default_rng(N + T)
+    X = rng.standard_normal((301, N, N)).astype(np.float32)
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev))
+    ref = orc.project(basis, X.astype(np.float64))
+    assert np.abs(xh.cpu().numpy() - ref).max() < 2e-5 * np.abs(ref).max()
+    rot = rsc.rsc_synthesize_hat(h, rsc.rsc_steer(h, xh, THETA)).cpu().numpy()
+    ref = orc.rotate_steer(basis, X.astype(np.float64), THETA)
+    assert np.abs(rot - ref).max() < 1e-4 * np.abs(ref).max()
+    h.close()
+
+
+@pytest.mark.parametrize("geom", [wl.GEOM11, wl.GEOM15])
+@pytest.mark.parametrize("P", [1, 63, 64, 128, 64 * 2048 + 5])
+def test_steer_chunk_edges(dev, geom, P):
+    """One angle for all patches: whole 64-patch chunks are streamed and the rest handled
+    per coordinate; both parts, and a buffer offset by one float (not 16-byte aligned),
+    agree with the reference."""
+    from paper_1806_04374_amd import rsc
+    h = rsc.rsc_create(geom.N, geom.S, geom.T)
+    xh = np.random.default_rng(P).standard_normal((P, geom.B)).astype(np.float32)
+    ref = orc.steer(xh.astype(np.float64), THETA, geom.S, geom.T)
+    out = rsc.rsc_steer(h, torch.from_numpy(xh).to(dev), THETA).cpu().numpy()
+    assert np.abs(out - ref).max() < 1e-6 * np.abs(ref).max()
+    flat = torch.zeros(P * geom.B + 1, dtype=torch.float32, device=dev)
+    flat[1:] = torch.from_numpy(xh.ravel()).to(dev)
+    out = rsc.rsc_steer(h, flat[1:].view(P, geom.B), THETA).cpu().numpy()
+    assert np.abs(out - ref).max() < 1e-6 * np.abs(ref).max()
+    h.close()
+
+
+@pytest.mark.parametrize("N", [5, 11, 15])
+def test_interp_unaligned_input(dev, N):
+    """A patch buffer that is not 16-byte aligned takes the scalar staging path."""
+    from paper_1806_04374_amd import rsc
+    P = 100
+    X = np.random.default_rng(N + 7).standard_normal((P, N, N)).astype(np.float32)
+    flat = torch.zeros(P * N * N + 1, dtype=torch.float32, device=dev)
+    flat[1:] = torch.from_numpy(X.ravel()).to(dev)
+    plan = rsc.RotationPlan(N, THETA, "bicubic")
+    out = rsc.rsc_rotate_interp(plan, flat[1:].view(P, N, N)).cpu().numpy()
+    ref = orc.rotate_interp(X.astype(np.float64), THETA, "bicubic")
+    assert np.abs(out - ref).max() < 1e-5 * np.abs(X).max()
+    plan.close()
+
+
+@pytest.mark.parametrize("N,S,T,P", [(7, 2, 3, 77), (9, 3, 4, 1000), (11, 5, 5, 33), (15, 7, 7, 65),
+                                     (15, 3, 5, 40), (17, 3, 3, 50)])
+def test_synthesis_geometries(dev, N, S, T, P):
+    """Phi x_hat for pixel counts in each lane-group size (N*N <= 64, <= 128, <= 256) and
+    above 256 (the LDS kernel), with row lengths B both compiled exactly and padded."""
+    from paper_1806_04374_amd import rsc
+    basis = orc.build_basis(N, S, T)
+    h = rsc.rsc_create(N, S, T)
+    xh = np.random.default_rng(N * S + T).standard_normal((P, h.B)).astype(np.float32)
+    pix = rsc.rsc_synthesize_hat(h, torch.from_numpy(xh).to(dev)).cpu().numpy()
+    ref = orc.to_pixels(basis, xh.astype(np.float64))
+    assert np.abs(pix - ref).max() < 1e-5 * np.abs(ref).max()
+    h.close()
