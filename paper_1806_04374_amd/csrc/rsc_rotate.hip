@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void steer_kernel(SteerParams prm) {
 constexpr int kSteerChunk = 64;
 
 template <int S, int T>
-__global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int64_t nchunk) {
+__global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int64_t nchunk, int tail) {
   constexpr int B = S * (2 * T + 1), CF = kSteerChunk * B, NV = CF / 4, VPT = (NV + 255) / 256;
   static_assert(CF % 4 == 0, "a chunk must be whole float4s");
   __shared__ float buf[CF];
@@ -235,6 +235,25 @@ __global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int6
         o.w = alpha[v][3] * x[v].w + beta[v][3] * buf[partner[v][3]];
         dst[t + 256 * v] = o;
       }
+  }
+  // the last tail (< kSteerChunk) patches, element by element
+  if (tail > 0 && blockIdx.x == nchunk % gridDim.x) {
+    const int nel = tail * B;
+    const float* src = prm.xhat + nchunk * CF;
+    __syncthreads();   // the block's last chunk's partner reads are done
+    for (int e = t; e < nel; e += 256) buf[e] = src[e];
+    __syncthreads();
+    float* dst = prm.out + nchunk * CF;
+    for (int e = t; e < nel; e += 256) {   // coefficients recomputed: the arrays above are dead here
+      const int c = e % B;
+      float o = buf[e];
+      if (c >= S) {
+        const int cc = c - S, k = 1 + cc / (2 * S);
+        const bool im = (cc % (2 * S)) >= S;
+        o = prm.cs[k] * o + (im ? -prm.sn[k] * buf[e - S] : prm.sn[k] * buf[e + S]);
+      }
+      dst[e] = o;
+    }
   }
 }
 
@@ -469,27 +488,24 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
     prm.sn[k] = float(std::sin(k * theta0));
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  // one angle, compiled geometry, 16-byte aligned buffers: whole chunks streamed, the
-  // remaining patches (fewer than a chunk) by the per-coordinate kernel below
+  // one angle, compiled geometry, 16-byte aligned buffers: the streaming kernel; otherwise
+  // the per-coordinate kernels below
   const bool aligned = ((reinterpret_cast<uintptr_t>(xhat) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-  const int64_t nchunk = (!theta && aligned) ? P / kSteerChunk : 0;
   const int geo = t.S == 5 && t.T == 5 ? 0 : t.S == 7 && t.T == 7 ? 1 : t.S == 5 && t.T == 2 ? 2
                 : t.S == 7 && t.T == 3 ? 3 : -1;
-  if (nchunk > 0 && geo >= 0) {
+  if (!theta && aligned && geo >= 0) {
+    // whole chunks streamed, the last partial chunk by one block of the same launch
+    const int64_t nchunk = P / kSteerChunk;
+    const int tail = int(P - nchunk * kSteerChunk);
+    const int64_t work = nchunk + (tail > 0);
     auto go = [&](auto kern) {
       const int64_t blocks = resident_blocks(kern);
-      hipLaunchKernelGGL(kern, dim3(unsigned(nchunk < blocks ? nchunk : blocks)), dim3(256), 0, st, prm, nchunk);
+      hipLaunchKernelGGL(kern, dim3(unsigned(work < blocks ? work : blocks)), dim3(256), 0, st, prm, nchunk, tail);
       return hipGetLastError();
     };
     hipError_t e = geo == 0 ? go(steer_stream_kernel<5, 5>) : geo == 1 ? go(steer_stream_kernel<7, 7>)
                  : geo == 2 ? go(steer_stream_kernel<5, 2>) : go(steer_stream_kernel<7, 3>);
-    if (e != hipSuccess) return int(e);
-    const int64_t done = nchunk * kSteerChunk;
-    if (done == P) return 0;
-    prm.xhat = xhat + done * t.B;
-    prm.out = out + done * t.B;
-    prm.P = P - done;
-    P = prm.P;
+    return int(e);
   }
   const int64_t items = P * int64_t(t.S) * (t.T + 1);
   const dim3 grid(unsigned((items + 255) / 256));
