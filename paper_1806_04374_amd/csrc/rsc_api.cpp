@@ -158,10 +158,10 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   const int KPD = (b.n_pix + 1) / 2;
   std::vector<float> pinvD;
   std::vector<int> pixD;
+  pixD.assign(size_t(2) * KPD, -1);
+  for (int i = 0; i < b.n_pix; ++i) pixD[i] = b.pix[i];
   if (b.B <= 64) {
     pinvD.assign(size_t(2) * KPD * 64, 0.f);
-    pixD.assign(size_t(2) * KPD, -1);
-    for (int i = 0; i < b.n_pix; ++i) pixD[i] = b.pix[i];
     for (int t = 0; t < 2; ++t)
       for (int j = 0; j < KPD; ++j)
         for (int l = 0; l < 64; ++l) {
@@ -184,10 +184,23 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
       }
   std::vector<float> phiPad(size_t(NN) * b.B);
   for (size_t i = 0; i < phiPad.size(); ++i) phiPad[i] = float(b.phi[i]);
+  // synthesis MFMA operand: row = output pixel, contraction = hat coordinate
+  std::vector<float> synA;
+  if (NN <= 256) {
+    const int NTT = (NN + 31) / 32, KB = (b.B + 1) / 2;
+    synA.assign(size_t(NTT) * KB * 64, 0.f);
+    for (int tt = 0; tt < NTT; ++tt)
+      for (int j = 0; j < KB; ++j)
+        for (int l = 0; l < 64; ++l) {
+          const int q = 32 * tt + l % 32, c = 2 * j + l / 32;
+          if (q < NN && c < b.B) synA[(size_t(tt) * KB + j) * 64 + l] = phiPad[size_t(q) * b.B + c];
+        }
+  }
   rsc_status s = upload(d.pinvA, pinvA, "projection table");
   if (s == RSC_OK) s = upload(d.pinvD, pinvD, "projection table");
   if (s == RSC_OK) s = upload(d.pixD, pixD, "pixel table");
   if (s == RSC_OK) s = upload(d.phiPad, phiPad, "synthesis table");
+  if (s == RSC_OK) s = upload(d.synA, synA, "synthesis operand");
   if (s == RSC_OK) s = upload(d.pinvI, pinvI, "image projection table");
   if (s == RSC_OK) s = upload(d.dpixI, dpixI, "image pixel table");
   d.prec = prec;
@@ -256,6 +269,7 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.pinvI);
   free_dev(d.dpixI);
   free_dev(d.phiPad);
+  free_dev(d.synA);
   free_dev(d.dictArena);
   free_dev(d.lpStats);
   free_dev(d.lpPinv);

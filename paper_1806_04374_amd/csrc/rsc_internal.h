@@ -36,10 +36,11 @@ struct DeviceTables {
   int enc_bpc = 0;           // encoder blocks per CU (0: as many as fit)
   float* pinvA = nullptr;    // projection operand over the grid [RTB][ceil(N*N/2)][64]
   float* pinvD = nullptr;    // projection operand over disk pixels [2][ceil(n_pix/2)][64] (B <= 64)
-  int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
+  int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)] (every B)
   float* pinvI = nullptr;    // image projection operand over disk pixels [2 or 4][ceil(n_pix/2)][64]
   int* dpixI = nullptr;      // (dy << 8 | dx) of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
+  float* synA = nullptr;     // synthesis MFMA operand [ceil(N*N/32)][ceil(B/2)][64] (N*N <= 256)
   // Dictionary tables (dictA .. cs64 below) live in one device arena, refilled in place by
   // every dictionary upload of the same or a smaller size.
   void* dictArena = nullptr;

@@ -227,6 +227,78 @@ __global__ __launch_bounds__(64 * kProjWavesLp) void project_tiled_lp_kernel(
   }
 }
 
+// 15x15 patch arrays (N*N = NNC, B <= 32 NT): block of NT waves, wave w computes hat
+// coordinates 32w..32w+31 and keeps its operand rows (KPD contraction steps over disk
+// pixels) in registers.  The block takes 32 patches at a time: the chunk is staged in LDS,
+// the next one is loaded into registers while the current one is contracted, and the
+// results leave through an LDS staging tile with coalesced 16-byte stores.
+constexpr int kProjRegPatches = 32;
+
+template <int NNC, int KPD, int NT>
+__global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __restrict__ patches, int64_t nchunk,
+                                                             int B, const float* __restrict__ pinvI,
+                                                             const int* __restrict__ pix, bool vec_out,
+                                                             float* __restrict__ xhat) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NTH = 64 * NT, NV = kProjRegPatches * NNC / 4, VPT = (NV + NTH - 1) / NTH;
+  __shared__ v4f tile4[VPT * NTH];               // [32][NNC] used; the rest takes clamped copies
+  __shared__ int sPix[2 * KPD];
+  __shared__ float stage[kProjRegPatches * 32 * NT];   // [32 patches][B] used
+  const float* tile = reinterpret_cast<const float*>(tile4);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, col = lane & 31, u = lane >> 5;
+  float a[KPD];
+#pragma unroll
+  for (int j = 0; j < KPD; ++j) a[j] = pinvI[(w * KPD + j) * 64 + lane];
+  // contraction slots past the disk have zero operand rows: point them at disk pixel 0
+  // (any finite pixel gives the same sum), so the gathers need no condition
+  for (int i = t; i < 2 * KPD; i += NTH) sPix[i] = pix[i] >= 0 ? pix[i] : pix[0];
+  int vi[VPT];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) vi[v] = t + NTH * v < NV ? t + NTH * v : NV - 1;
+  // the launch has at most nchunk blocks, so every block starts on a chunk
+  v4f nxt[VPT];
+  int64_t c = blockIdx.x;
+  {
+    const v4f* s4 = reinterpret_cast<const v4f*>(patches + c * kProjRegPatches * NNC);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+  }
+  const float* mine = tile + col * NNC;
+  const int nout = kProjRegPatches * B;
+  for (; c < nchunk; c += gridDim.x) {
+    __syncthreads();   // the previous chunk's reads of the tile and the staging tile are done
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) tile4[t + NTH * v] = nxt[v];
+    __syncthreads();
+    {
+      const int64_t cn = c + gridDim.x < nchunk ? c + gridDim.x : c;   // the last re-reads its own
+      const v4f* s4 = reinterpret_cast<const v4f*>(patches + cn * kProjRegPatches * NNC);
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+    }
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KPD; ++j) {
+      acc = mfma32(a[j], mine[sPix[2 * j + u]], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = 32 * w + 8 * (v / 4) + 4 * u + (v % 4);
+      if (r < B) stage[col * B + r] = acc[v];
+    }
+    __syncthreads();
+    float* dst = xhat + c * nout;
+    if (vec_out) {
+      const v4f* s4 = reinterpret_cast<const v4f*>(stage);
+      for (int i = t; i < nout / 4; i += NTH) reinterpret_cast<v4f*>(dst)[i] = s4[i];
+    } else {
+      for (int i = t; i < nout; i += NTH) dst[i] = stage[i];
+    }
+  }
+}
+
 // Generic fallback: one block = 2 waves = 64 patches, operand from global memory.
 template <int RTB>
 __global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ patches, int64_t P, int NN,
@@ -335,6 +407,27 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
     hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * kProjWaves), lds, st, patches, P, t.B,
                        t.pinvD, t.pixD, vin, vout, xhat);
     return int(hipGetLastError());
+  }
+  // 15x15, B in 97..128 (4 row tiles), 16-byte aligned patches: whole 32-patch chunks by
+  // the register-operand kernel, the rest by the generic one
+  const int64_t nreg = (t.N == 15 && t.n_pix == 177 && t.B > 96 && t.B <= 128 && t.pinvI && t.pixD &&
+                        (reinterpret_cast<uintptr_t>(patches) & 15) == 0)
+                           ? P / kProjRegPatches : 0;
+  if (nreg > 0) {
+    auto kern = project_reg_kernel<225, 89, 4>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t cap = int64_t(cus()) * per_cu;
+    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (kProjRegPatches * t.B) % 4 == 0;
+    hipLaunchKernelGGL(kern, dim3(unsigned(nreg < cap ? nreg : cap)), dim3(256), 0, st, patches, nreg, t.B,
+                       t.pinvI, t.pixD, vout, xhat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return int(e);
+    const int64_t done = nreg * kProjRegPatches;
+    if (done == P) return 0;
+    patches += done * NN;
+    xhat += done * t.B;
+    P -= done;
   }
   const int64_t blocks = (P + 63) / 64;
   const size_t lds = sizeof(float) * 64 * size_t(NN > t.B ? NN : t.B);

@@ -18,6 +18,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "rsc_device.h"
 #include "rsc_internal.h"
 #include "rsc_launch.h"
 
@@ -377,6 +378,84 @@ int64_t resident_blocks(Kern kern) {
   return cache[key] = int64_t(num_cus()) * per_cu;
 }
 
+// Phi x_hat on FP32 MFMA for the compiled geometries (N*N = NNC, B = BB): rows = output
+// pixels (tiles of 32; wave w owns tiles w*TPW .. w*TPW+TPW-1 with its rows of Phi in
+// registers), columns = 32 patches, contraction over hat coordinates in steps of 2.  The
+// block takes 32 patches at a time: their hat rows are staged in LDS (the next chunk's
+// loaded into registers meanwhile) and the pixels leave through an LDS staging tile with
+// coalesced 16-byte stores.  synA: [NTT][KB][64], lane l of step j in tile tt holds
+// Phi[32 tt + l % 32][2 j + l / 32] (zero past N*N or B).
+constexpr int kSynMP = 32;
+
+template <int NNC, int BB, int TPW>
+__global__ __launch_bounds__(256) void synth_mfma_kernel(const float* __restrict__ xhat, int64_t nchunk,
+                                                        const float* __restrict__ synA, bool vec_out,
+                                                        float* __restrict__ out) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int KB = (BB + 1) / 2, NV = kSynMP * BB / 4, VPT = (NV + 255) / 256;
+  static_assert((kSynMP * BB) % 4 == 0 && (kSynMP * NNC) % 4 == 0, "chunks of whole float4s");
+  static_assert(4 * TPW * 32 >= NNC, "row tiles must cover the pixels");
+  __shared__ v4f xs4[VPT * 256];                 // [32][BB] used; the rest takes clamped copies
+  __shared__ v4f st4[kSynMP * NNC / 4];          // [32 patches][NNC]
+  const float* xs = reinterpret_cast<const float*>(xs4);
+  float* st = reinterpret_cast<float*>(st4);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, col = lane & 31, u = lane >> 5;
+  float a[TPW][KB];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int j = 0; j < KB; ++j) a[i][j] = synA[((w * TPW + i) * KB + j) * 64 + lane];
+  int vi[VPT];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) vi[v] = t + 256 * v < NV ? t + 256 * v : NV - 1;
+  // the launch has at most nchunk blocks, so every block starts on a chunk
+  v4f nxt[VPT];
+  int64_t c = blockIdx.x;
+  {
+    const v4f* s4 = reinterpret_cast<const v4f*>(xhat + c * kSynMP * BB);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+  }
+  const float* mine = xs + col * BB + u;
+  for (; c < nchunk; c += gridDim.x) {
+    __syncthreads();   // the previous chunk's hat and staging reads are done
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) xs4[t + 256 * v] = nxt[v];
+    __syncthreads();
+    {
+      const int64_t cn = c + gridDim.x < nchunk ? c + gridDim.x : c;   // the last re-reads its own
+      const v4f* s4 = reinterpret_cast<const v4f*>(xhat + cn * kSynMP * BB);
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+    }
+    f32x16 acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const float b = 2 * j + u < BB ? mine[2 * j] : 0.f;   // odd B: the last slot is padding
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = mfma32(a[i][j], b, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int q = 32 * (w * TPW + i) + 8 * (r / 4) + 4 * u + (r % 4);
+        if (q < NNC) st[col * NNC + q] = acc[i][r];
+      }
+    __syncthreads();
+    float* dst = out + c * kSynMP * NNC;
+    if (vec_out) {
+      for (int i = t; i < kSynMP * NNC / 4; i += 256) reinterpret_cast<v4f*>(dst)[i] = st4[i];
+    } else {
+      for (int i = t; i < kSynMP * NNC; i += 256) dst[i] = st[i];
+    }
+  }
+}
+
 double keys(double t) {
   const double a = -0.5;
   t = std::fabs(t);
@@ -520,6 +599,25 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
 int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float* out, void* stream) {
   const int NN = t.N * t.N;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // compiled geometries, 16-byte aligned hat rows: whole 32-patch chunks on MFMA, the rest below
+  const int geo = NN == 121 && t.B == 55 ? 0 : NN == 225 && t.B == 105 ? 1 : -1;
+  const int64_t nm = (geo >= 0 && t.synA && (reinterpret_cast<uintptr_t>(xhat) & 15) == 0) ? P / kSynMP : 0;
+  if (nm > 0) {
+    const bool vout = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    auto go = [&](auto kern) {
+      const int64_t blocks = resident_blocks(kern);
+      hipLaunchKernelGGL(kern, dim3(unsigned(nm < blocks ? nm : blocks)), dim3(256), 0, st, xhat, nm, t.synA, vout,
+                         out);
+      return hipGetLastError();
+    };
+    hipError_t e = geo == 0 ? go(synth_mfma_kernel<121, 55, 1>) : go(synth_mfma_kernel<225, 105, 2>);
+    if (e != hipSuccess) return int(e);
+    const int64_t done = nm * kSynMP;
+    if (done == P) return 0;
+    xhat += done * t.B;
+    out += done * NN;
+    P -= done;
+  }
   if (NN <= 256 && t.B <= 128) {
     const int bv = (t.B + 3) / 4;
     const int64_t want = (P + kSynP - 1) / kSynP;

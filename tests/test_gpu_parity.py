@@ -295,3 +295,33 @@ def test_dictionary_reload_on_one_handle(dev, prec):
         rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
         assert rep.match_rate >= MATCH, (M, R, K, str(rep))
     h.close()
+
+
+@pytest.mark.parametrize("P", [1, 31, 32, 33, 2000, 64 * 1024 + 7])
+def test_projection_15x15_patch_arrays(dev, P):
+    """15x15 patch arrays: whole 32-patch chunks by the register-operand MFMA kernel, the rest
+    by the generic kernel; also from a buffer that is not 16-byte aligned (generic kernel
+    only) and into an output that is not (scalar stores)."""
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM15
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    h = rsc.rsc_create(geom.N, geom.S, geom.T)
+    X = np.random.default_rng(P).standard_normal((P, geom.N, geom.N)).astype(np.float32)
+    n = min(P, 3000)
+    ref = orc.project(basis, X[:n].astype(np.float64))
+    tol = 2e-5 * np.abs(ref).max()
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev)).cpu().numpy()
+    assert np.abs(xh[:n] - ref).max() < tol
+    if P > n:   # the rest: the same rows through the reference at a sample of indices
+        idx = np.random.default_rng(1).choice(P, 500, replace=False)
+        ref_s = orc.project(basis, X[idx].astype(np.float64))
+        assert np.abs(xh[idx] - ref_s).max() < 2e-5 * np.abs(ref_s).max()
+    flat = torch.zeros(P * geom.N * geom.N + 1, dtype=torch.float32, device=dev)
+    flat[1:] = torch.from_numpy(X.ravel()).to(dev)
+    out = torch.zeros(P * geom.B + 1, dtype=torch.float32, device=dev)
+    rsc.rsc_project(h, flat[1:].view(P, geom.N, geom.N), out[1:].view(P, geom.B))
+    assert np.abs(out[1:].view(P, geom.B).cpu().numpy()[:n] - ref).max() < tol
+    xo = torch.zeros(P * geom.B + 1, dtype=torch.float32, device=dev)
+    rsc.rsc_project(h, torch.from_numpy(X).to(dev), xo[1:].view(P, geom.B))
+    assert np.abs(xo[1:].view(P, geom.B).cpu().numpy()[:n] - ref).max() < tol
+    h.close()

@@ -164,3 +164,31 @@ def test_synthesis_geometries(dev, N, S, T, P):
     ref = orc.to_pixels(basis, xh.astype(np.float64))
     assert np.abs(pix - ref).max() < 1e-5 * np.abs(ref).max()
     h.close()
+
+
+@pytest.mark.parametrize("geom", [wl.GEOM11, wl.GEOM15])
+@pytest.mark.parametrize("P", [32, 64 * 700 + 3])
+def test_synthesis_chunks_and_alignment(dev, geom, P):
+    """Phi x_hat through the MFMA kernel (whole 32-patch chunks, aligned hat rows), the
+    register kernel (remainder, or hat rows not 16-byte aligned), and scalar stores into an
+    output that is not 16-byte aligned, all equal to the reference."""
+    from paper_1806_04374_amd import rsc
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    h = rsc.rsc_create(geom.N, geom.S, geom.T)
+    xh = np.random.default_rng(P + geom.N).standard_normal((P, geom.B)).astype(np.float32)
+    n = min(P, 2000)
+    ref = orc.to_pixels(basis, xh[:n].astype(np.float64))
+    tol = 1e-5 * np.abs(ref).max()
+    x = torch.from_numpy(xh).to(dev)
+    assert np.abs(rsc.rsc_synthesize_hat(h, x).cpu().numpy()[:n] - ref).max() < tol
+    flat = torch.zeros(P * geom.B + 1, dtype=torch.float32, device=dev)
+    flat[1:] = x.ravel()
+    assert np.abs(rsc.rsc_synthesize_hat(h, flat[1:].view(P, geom.B)).cpu().numpy()[:n] - ref).max() < tol
+    o = torch.zeros(P * geom.N * geom.N + 1, dtype=torch.float32, device=dev)
+    rsc.rsc_synthesize_hat(h, x, o[1:].view(P, geom.N, geom.N))
+    assert np.abs(o[1:].view(P, geom.N, geom.N).cpu().numpy()[:n] - ref).max() < tol
+    if P > n:
+        idx = np.random.default_rng(2).choice(P, 300, replace=False)
+        ref_s = orc.to_pixels(basis, xh[idx].astype(np.float64))
+        assert np.abs(rsc.rsc_synthesize_hat(h, x).cpu().numpy()[idx] - ref_s).max() < 1e-5 * np.abs(ref_s).max()
+    h.close()
