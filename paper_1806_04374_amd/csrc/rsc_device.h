@@ -58,6 +58,21 @@ __device__ __forceinline__ float max_halves(float x) {
   return fmaxf(a, b);
 }
 
+// The same for x >= 0 (a maximum of absolute values): non-negative floats order like their
+// bit patterns, so an integer maximum needs none of the NaN quieting a float maximum of
+// cross-lane values costs (a NaN, if any, wins instead of being dropped).
+__device__ __forceinline__ float max_halves_nonneg(float x) {
+  float a = x, b = x;
+  swap32(a, b);
+  return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+
+__device__ __forceinline__ float max_quarters_nonneg(float x) {
+  float a = x, b = x;
+  swap16(a, b);
+  return max_halves_nonneg(__uint_as_float(max(__float_as_uint(a), __float_as_uint(b))));
+}
+
 // Maximum of x over the four quarter-waves.
 __device__ __forceinline__ float max_quarters(float x) {
   float a = x, b = x;

@@ -152,7 +152,11 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           for (int q = parity; q < NQ; q += 2) o = mfma32(F[q], acc[q][vreg(a)], o);
           return o;
         };
+        // the winner inside the group is kept as a constant (ba) and a lane mask (upd), and
+        // turned into the atom index once per group
         f32x16 e_cur = chain(0, 0), o_cur = chain(0, 1);
+        int ba = 0;
+        bool upd = false;
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
           f32x16 e_next;
@@ -160,10 +164,11 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           float am = fabsf(e_cur[0]) + fabsf(o_cur[0]);
 #pragma unroll
           for (int i = 1; i < 16; ++i) am = fmaxf(am, fabsf(e_cur[i]) + fabsf(o_cur[i]));
-          am = max_halves(am);
+          am = max_halves_nonneg(am);
           const bool gt = am > best;
           best = gt ? am : best;
-          bm = gt ? g * 16 + a : bm;
+          ba = gt ? a : ba;
+          upd = upd || gt;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][vreg(a)] : bop[q];
           if (a + 1 < 16) {
@@ -171,6 +176,7 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
             e_cur = e_next;
           }
         }
+        bm = upd ? g * 16 + ba : bm;
       }
       // ---------------- (b) pass 2: angles of the best atom, same arithmetic
       int rs;
@@ -340,6 +346,8 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
             }
         };
         chains(0, ob[0]);
+        int ba = 0;
+        bool upd = false;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           if (a + 1 < 8) chains(a + 1, ob[(a + 1) & 1]);
@@ -350,13 +358,15 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
               am = fmaxf(am, SPLIT ? fabsf(o[0][t][i]) + fabsf(o[1][t][i]) : fabsf(o[0][t][i]));
-          am = max_quarters(am);
+          am = max_quarters_nonneg(am);
           const bool gt = am > best;
           best = gt ? am : best;
-          bm = gt ? g * 8 + a : bm;
+          ba = gt ? a : ba;
+          upd = upd || gt;
 #pragma unroll
           for (int q = 0; q < NS; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
         }
+        bm = upd ? g * 8 + ba : bm;
       }
       int rs;
       float cval;
