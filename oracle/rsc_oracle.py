@@ -66,6 +66,16 @@ Readings where the paper is silent (each one is listed in the design notes):
     all have one size, where counts and frequencies rank neighbours alike).
     chi^2 terms with a[i] + b[i] = 0 are 0.  The nearest neighbour's ties go to
     the smaller training index.
+  * The paper's own annular basis (eq. (5)-(7), Sec. II-D) for rotation: S = floor(N/2)
+    annuli N(s-1)/(2S) <= r < N s/(2S); harmonics -T_s..T_s on annulus s with T_s the
+    half circumference floor(pi r_mid) (r_mid the annulus' middle radius, which gives the
+    (1, 5, 8) of the paper's basis figure at N = 11), lowered where needed to the largest
+    value whose 2 T_s + 1 harmonic columns are linearly independent on the annulus' pixels
+    (taken as it is, the rule asks the 8-pixel second annulus at N = 11 for 11 columns,
+    and (Phi^* Phi)^{-1} would not exist).  The low-pass basis halves these T_s (floor).
+    The centre pixel is 0 for t != 0, as above; columns are normalised and need no
+    orthonormalisation (annuli are disjoint).  Packed real coordinates as above,
+    harmonic-major, with the annuli whose T_s >= k in each harmonic-k block.
   * Rotation by interpolation (Sec. IV, rotation speed): rotating a patch by theta
     (counter-clockwise, about its centre pixel) sets output pixel (x, y) to the input
     at R_{-theta}(x, y), read with nearest-neighbour interpolation (coordinates
@@ -153,6 +163,124 @@ def build_basis(N: int, S: int, T: int, centres=None, sigma=None) -> Basis:
     # biorthogonal partner (Phi^T Phi)^{-1} Phi^T, Sec. II-D
     pinv = np.linalg.solve(phi.T @ phi, phi.T)
     return Basis(N, S, T, mask, phi_c, phi, pinv)
+
+
+# --------------------------------------------------------------------------- annular basis
+def _annulus_columns(rho: np.ndarray, theta: np.ndarray, T: int) -> np.ndarray:
+    """Complex columns exp(i t theta), t = -T..T, on the given pixels (eq. (5)); the centre
+    pixel (rho = 0) is 0 for t != 0."""
+    t = np.arange(-T, T + 1)
+    A = np.exp(1j * np.outer(theta, t))
+    A[(rho == 0)[:, None] & (t != 0)[None, :]] = 0.0
+    return A
+
+
+def annular_cutoffs(N: int, lowpass: bool = False, cap: bool = True) -> list:
+    """Per-annulus cut-offs T_s, s = 1..floor(N/2) (Sec. II-D): half the circumference,
+    floor(pi r_mid); with cap, lowered to the largest T whose columns t = -T..T are linearly
+    independent on the annulus (smallest singular value above 1e-6 of the largest); the
+    low-pass basis halves them (Sec. IV)."""
+    S = N // 2
+    _, rho, theta = disk_grid(N)
+    out = []
+    for s in range(1, S + 1):
+        lo, hi = N * (s - 1) / (2 * S), N * s / (2 * S)
+        ring = (rho >= lo) & (rho < hi)
+        half = int(np.floor(np.pi * (lo + hi) / 2))
+        T = half
+        if cap:
+            T = -1
+            for t in range(half + 1):
+                A = _annulus_columns(rho[ring], theta[ring], t)
+                if A.shape[1] > A.shape[0]:
+                    break
+                sv = np.linalg.svd(A, compute_uv=False)
+                if sv[-1] <= 1e-6 * sv[0]:
+                    break
+                T = t
+        out.append(T // 2 if lowpass else T)
+    return out
+
+
+@dataclasses.dataclass
+class AnnularBasis:
+    N: int
+    Ts: list                  # cut-off of annulus s = 1..S
+    mask: np.ndarray          # [N, N] disk
+    phi: np.ndarray           # [n_pix, B] packed real synthesis matrix
+    pinv: np.ndarray          # [B, n_pix] (Phi^T Phi)^{-1} Phi^T
+
+    @property
+    def S(self) -> int:
+        return len(self.Ts)
+
+    @property
+    def T(self) -> int:
+        return max(self.Ts)
+
+    @property
+    def Sk(self) -> list:
+        """Number of annuli carrying harmonic k, k = 0..T."""
+        return [sum(1 for t in self.Ts if t >= k) for k in range(self.T + 1)]
+
+    @property
+    def B(self) -> int:
+        return self.phi.shape[1]
+
+    @property
+    def n_pix(self) -> int:
+        return int(self.mask.sum())
+
+
+def build_annular_basis(N: int, lowpass: bool = False) -> AnnularBasis:
+    """The paper's discrete steerable basis, eq. (5)-(7), with the cut-offs above."""
+    mask, rho, theta = disk_grid(N)
+    S = N // 2
+    Ts = annular_cutoffs(N, lowpass)
+    blocks = []
+    for k in range(max(Ts) + 1):
+        cols = []
+        for s in range(1, S + 1):
+            if Ts[s - 1] < k:
+                continue
+            lo, hi = N * (s - 1) / (2 * S), N * s / (2 * S)
+            col = np.where((rho >= lo) & (rho < hi), np.exp(1j * k * theta), 0.0)
+            if k != 0:
+                col[rho == 0] = 0.0
+            cols.append(col / np.linalg.norm(col))
+        C = np.array(cols).T                                # [n_pix, annuli with T_s >= k]
+        if k == 0:
+            blocks.append(C.real)
+        else:
+            blocks.append(np.sqrt(2.0) * C.real)
+            blocks.append(-np.sqrt(2.0) * C.imag)
+    phi = np.concatenate(blocks, axis=1)
+    pinv = np.linalg.solve(phi.T @ phi, phi.T)
+    return AnnularBasis(N, Ts, mask, phi, pinv)
+
+
+def steer_ragged(xhat: np.ndarray, theta, Sk: list) -> np.ndarray:
+    """Steering (eq. (8)) in the harmonic-major layout with Sk[k] annuli in harmonic k:
+    the complex coefficient (Re + i Im) of harmonic k is multiplied by exp(-i k theta)."""
+    xhat = np.asarray(xhat, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    out = xhat.copy()
+    off = Sk[0]
+    for k in range(1, len(Sk)):
+        n = Sk[k]
+        re, im = slice(off, off + n), slice(off + n, off + 2 * n)
+        z = (xhat[..., re] + 1j * xhat[..., im]) * np.exp(-1j * k * theta)[..., None]
+        out[..., re] = z.real
+        out[..., im] = z.imag
+        off += 2 * n
+    return out
+
+
+def steer_basis(basis, xhat: np.ndarray, theta) -> np.ndarray:
+    """Steering for either basis: the full (S, T) grid or the annular basis' ragged one."""
+    if isinstance(basis, AnnularBasis):
+        return steer_ragged(xhat, theta, basis.Sk)
+    return steer(xhat, theta, basis.S, basis.T)
 
 
 # --------------------------------------------------------------------------- coordinates
@@ -555,6 +683,6 @@ def rotate_interp(patches: np.ndarray, theta: float, mode: str) -> np.ndarray:
 
 
 def rotate_steer(basis: Basis, patches: np.ndarray, theta: float) -> np.ndarray:
-    """Steering-based rotation Phi S_theta (Phi^T Phi)^{-1} Phi^T x (Sec. IV)."""
-    return to_pixels(basis, steer(project(basis, patches), theta, basis.S, basis.T))
+    """Steering-based rotation Phi S_theta (Phi^T Phi)^{-1} Phi^T x (Sec. IV), in either basis."""
+    return to_pixels(basis, steer_basis(basis, project(basis, patches), theta))
 
