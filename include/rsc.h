@@ -112,6 +112,35 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma,
 rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sigma,
                           double* phi, double* pinv, int* n_pix, int* B, double* cond_gram);
 
+/*
+ * A handle on the paper's own discrete steerable basis (eq. (5)-(7), Sec. II-D): S =
+ * floor(N/2) annuli N(s-1)/(2S) <= r < N s/(2S) on the disk grid, harmonics
+ * exp(i t theta), |t| <= T_s, on annulus s, T_s = half the annulus' circumference,
+ * floor(pi r_mid) (Sec. II-D's anti-aliasing rule), lowered to the largest value whose
+ * 2 T_s + 1 harmonic columns are linearly independent on the annulus' pixels (as printed,
+ * the 8-pixel second annulus at N = 11 would get 11 columns and Phi^T Phi would be
+ * singular).  lowpass != 0 halves the cut-offs (the low-pass basis of Sec. IV).  The
+ * centre pixel is 0 for t != 0; columns are normalised; packed real coordinates are
+ * harmonic-major with the annuli whose T_s >= k in block k ([Re][Im] for k >= 1, the
+ * convention of rsc_create).  B = sum_s (2 T_s + 1) (81 at N = 11, 39 low-pass).
+ * The handle is FP32 and serves rsc_project, rsc_steer, rsc_synthesize_hat,
+ * rsc_basis_info and rsc_get_basis; rsc_set_dictionary and image projection return
+ * RSC_E_UNSUPPORTED.
+ *   N      odd, 3 <= N <= 31;  out  receives the handle
+ * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 128 or some T_s > 15, e.g.
+ * the full basis at N = 15, B = 153), RSC_E_NOMEM, RSC_E_DEVICE.
+ */
+rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out);
+
+/*
+ * The same annular basis on the host only (no device needed).
+ *   phi   host [N*N, B] or NULL;  pinv  host [B, N*N] or NULL;  Ts  host [N/2] or NULL
+ *   (the cut-off of each annulus);  B, cond_gram may be NULL.  Call once with phi and
+ *   pinv NULL to learn B.  N odd, 3 <= N <= 63.
+ */
+rsc_status rsc_annular_basis_host(int N, int lowpass, double* phi, double* pinv, int* Ts, int* B,
+                                  double* cond_gram);
+
 /* Release the handle and its device copies.  NULL is accepted. */
 rsc_status rsc_destroy(rsc_handle* h);
 

@@ -18,6 +18,8 @@ struct rsc_handle {
   rsc_precision prec = RSC_FP32;
   rsc_tile tile = RSC_TILE_AUTO;
   bool has_dict = false;
+  bool annular = false;      // the paper's annular basis (projection, steering, synthesis only)
+  std::vector<int> Ts;       // its per-annulus cut-offs
 };
 
 namespace {
@@ -108,34 +110,9 @@ float from_f16(uint16_t b) {
   return float(h);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* rsc_last_error(void) { return g_err.c_str(); }
-
-rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, rsc_precision prec,
-                      rsc_handle** out) {
-  if (!out) return fail(RSC_E_INVALID, "out is NULL");
-  *out = nullptr;
-  if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
-  if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
-  if (S * (2 * T + 1) > 128) return fail(RSC_E_UNSUPPORTED, "B = S(2T+1) must be <= 128 in this build");
-  if (T > 15) return fail(RSC_E_UNSUPPORTED, "T must be <= 15 in this build");
-  if (prec != RSC_FP32 && prec != RSC_BF16 && prec != RSC_FP16) return fail(RSC_E_INVALID, "unknown precision");
-  if (!rsc::encode_supported(S, T) && prec != RSC_FP32)
-    return fail(RSC_E_UNSUPPORTED, "16-bit handles need (S, T) = (5, 5) or (7, 7)");
-  if (centres) {
-    for (int s = 0; s < S; ++s)
-      if (!std::isfinite(centres[s])) return fail(RSC_E_INVALID, "non-finite profile centre");
-  }
-  rsc_handle* h = new (std::nothrow) rsc_handle();
-  if (!h) return fail(RSC_E_NOMEM, "handle allocation failed");
-  std::string err;
-  if (!rsc::build_basis(N, S, T, centres, sigma, h->basis, err)) {
-    delete h;
-    return fail(RSC_E_INVALID, "basis construction failed: " + err);
-  }
+// Device tables of a handle whose host basis is built (shared by every kind of handle).
+// On failure the handle is destroyed.
+rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
   const rsc::HostBasis& b = h->basis;
   h->prec = prec;
   rsc::DeviceTables& d = h->dev;
@@ -240,7 +217,101 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
     rsc_destroy(h);
     return s;
   }
+  return RSC_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+const char* rsc_last_error(void) { return g_err.c_str(); }
+
+rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, rsc_precision prec,
+                      rsc_handle** out) {
+  if (!out) return fail(RSC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
+  if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
+  if (S * (2 * T + 1) > 128) return fail(RSC_E_UNSUPPORTED, "B = S(2T+1) must be <= 128 in this build");
+  if (T > 15) return fail(RSC_E_UNSUPPORTED, "T must be <= 15 in this build");
+  if (prec != RSC_FP32 && prec != RSC_BF16 && prec != RSC_FP16) return fail(RSC_E_INVALID, "unknown precision");
+  if (!rsc::encode_supported(S, T) && prec != RSC_FP32)
+    return fail(RSC_E_UNSUPPORTED, "16-bit handles need (S, T) = (5, 5) or (7, 7)");
+  if (centres) {
+    for (int s = 0; s < S; ++s)
+      if (!std::isfinite(centres[s])) return fail(RSC_E_INVALID, "non-finite profile centre");
+  }
+  rsc_handle* h = new (std::nothrow) rsc_handle();
+  if (!h) return fail(RSC_E_NOMEM, "handle allocation failed");
+  std::string err;
+  if (!rsc::build_basis(N, S, T, centres, sigma, h->basis, err)) {
+    delete h;
+    return fail(RSC_E_INVALID, "basis construction failed: " + err);
+  }
+  rsc_status st = init_tables(h, N, S, T, prec);
+  if (st != RSC_OK) return st;
   *out = h;
+  return ok();
+}
+
+rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out) {
+  if (!out) return fail(RSC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
+  rsc_handle* h = new (std::nothrow) rsc_handle();
+  if (!h) return fail(RSC_E_NOMEM, "handle allocation failed");
+  std::string err;
+  if (!rsc::build_annular_basis(N, lowpass != 0, h->basis, h->Ts, err)) {
+    delete h;
+    return fail(RSC_E_INVALID, "basis construction failed: " + err);
+  }
+  const rsc::HostBasis& b = h->basis;
+  if (b.B > 128 || b.T > 15) {
+    delete h;
+    return fail(RSC_E_UNSUPPORTED, "annular basis with B = " + std::to_string(b.B) + ", T = " +
+                                       std::to_string(b.T) + ": this build handles B <= 128 and T <= 15");
+  }
+  h->annular = true;
+  rsc_status st = init_tables(h, N, b.S, b.T, RSC_FP32);
+  if (st != RSC_OK) return st;
+  // steering table: coordinate -> (harmonic k, offset of its Re/Im partner)
+  std::vector<int> tab(b.B);
+  int col = 0;
+  for (int k = 0; k <= b.T; ++k) {
+    int nk = 0;
+    for (int t : h->Ts) nk += t >= k ? 1 : 0;
+    for (int i = 0; i < nk; ++i) {
+      if (k == 0) {
+        tab[col + i] = 32768;
+      } else {
+        tab[col + i] = (k << 16) | (nk + 32768);
+        tab[col + nk + i] = (k << 16) | (-nk + 32768);
+      }
+    }
+    col += k == 0 ? nk : 2 * nk;
+  }
+  st = upload(h->dev.steerTab, tab, "steering table");
+  if (st != RSC_OK) {
+    rsc_destroy(h);
+    return st;
+  }
+  *out = h;
+  return ok();
+}
+
+rsc_status rsc_annular_basis_host(int N, int lowpass, double* phi, double* pinv, int* Ts, int* B, double* cond_gram) {
+  if (N < 3 || N > 63 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..63");
+  rsc::HostBasis b;
+  std::vector<int> ts;
+  std::string err;
+  if (!rsc::build_annular_basis(N, lowpass != 0, b, ts, err))
+    return fail(RSC_E_INVALID, "basis construction failed: " + err);
+  if (phi) std::memcpy(phi, b.phi.data(), b.phi.size() * sizeof(double));
+  if (pinv) std::memcpy(pinv, b.pinv.data(), b.pinv.size() * sizeof(double));
+  if (Ts) std::memcpy(Ts, ts.data(), ts.size() * sizeof(int));
+  if (B) *B = b.B;
+  if (cond_gram) *cond_gram = b.cond;
   return ok();
 }
 
@@ -270,6 +341,7 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.dpixI);
   free_dev(d.phiPad);
   free_dev(d.synA);
+  free_dev(d.steerTab);
   free_dev(d.dictArena);
   free_dev(d.lpStats);
   free_dev(d.lpPinv);
@@ -300,6 +372,7 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   if (R < 1 || R > 128) return fail(RSC_E_INVALID, "R must be in 1..128");
   rsc::DeviceTables& d = h->dev;
   const int S = d.S, T = d.T, B = d.B;
+  if (h->annular) return fail(RSC_E_UNSUPPORTED, "the annular basis serves projection, steering and synthesis only");
   if (!rsc::encode_supported(S, T))
     return fail(RSC_E_UNSUPPORTED,
                 "the encoders are compiled for (S, T) = (5, 5) and (7, 7); this geometry supports "
@@ -717,7 +790,7 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
     return fail(RSC_E_INVALID, "null device pointer");
   if (ws_bytes < rsc::images_workspace_bytes(n_images)) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(RSC_E_INVALID, "workspace not 8-byte aligned");
-  if (!((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
+  if (h->annular || !((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
       !rsc::encode_supported(h->dev.S, h->dev.T))
     return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
                                    "geometries");

@@ -4,7 +4,9 @@
 // Plain C++ with no device code; the GPU kernels only ever see FP32 copies.
 #include "rsc_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <utility>
 #include <vector>
 
 namespace rsc {
@@ -66,6 +68,62 @@ bool cholesky(int n, std::vector<double>& A) {
     }
     for (int k = j + 1; k < n; ++k) A[size_t(j) * n + k] = 0.0;
   }
+  return true;
+}
+
+// Gram matrix, condition number and biorthogonal partner of a packed real synthesis
+// matrix phid [n][B] over the disk pixels pix; fills out (except S and T).
+bool finish_basis(int N, const std::vector<int>& pix, const std::vector<double>& phid, int B, HostBasis& out,
+                  std::string& err) {
+  const int n = int(pix.size());
+  // Gram, its Cholesky factor, eigenvalues for the condition number
+  std::vector<double> G(size_t(B) * B, 0.0);
+  for (int a = 0; a < B; ++a)
+    for (int b = 0; b <= a; ++b) {
+      double v = 0.0;
+      for (int p = 0; p < n; ++p) v += phid[size_t(p) * B + a] * phid[size_t(p) * B + b];
+      G[size_t(a) * B + b] = G[size_t(b) * B + a] = v;
+    }
+  std::vector<double> w, V;
+  jacobi_eig(B, G, w, V);
+  double wmin = w[0], wmax = w[0];
+  for (double x : w) {
+    wmin = std::min(wmin, x);
+    wmax = std::max(wmax, x);
+  }
+  std::vector<double> L = G;
+  if (!(wmin > 0.0) || !cholesky(B, L)) {
+    err = "basis Gram matrix is not positive definite";
+    return false;
+  }
+  // pinv_d = G^{-1} Phi_d^T : solve L L^T X = Phi_d^T column by column (pixel by pixel)
+  std::vector<double> pinvd(size_t(B) * n);
+  std::vector<double> y(B);
+  for (int p = 0; p < n; ++p) {
+    for (int i = 0; i < B; ++i) {
+      double v = phid[size_t(p) * B + i];
+      for (int k = 0; k < i; ++k) v -= L[size_t(i) * B + k] * y[k];
+      y[i] = v / L[size_t(i) * B + i];
+    }
+    for (int i = B - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < B; ++k) v -= L[size_t(k) * B + i] * y[k];
+      y[i] = v / L[size_t(i) * B + i];
+    }
+    for (int i = 0; i < B; ++i) pinvd[size_t(i) * n + p] = y[i];
+  }
+  out.N = N;
+  out.B = B;
+  out.n_pix = n;
+  out.cond = wmax / wmin;
+  out.pix = pix;
+  out.phi.assign(size_t(N) * N * B, 0.0);
+  out.pinv.assign(size_t(B) * N * N, 0.0);
+  for (int p = 0; p < n; ++p)
+    for (int b = 0; b < B; ++b) {
+      out.phi[size_t(pix[p]) * B + b] = phid[size_t(p) * B + b];
+      out.pinv[size_t(b) * N * N + pix[p]] = pinvd[size_t(b) * n + p];
+    }
   return true;
 }
 
@@ -182,56 +240,131 @@ bool build_basis(int N, int S, int T, const double* centres_in, double sigma_in,
       }
     }
   }
-  // Gram, its Cholesky factor, eigenvalues for the condition number
-  std::vector<double> G(size_t(B) * B, 0.0);
-  for (int a = 0; a < B; ++a)
-    for (int b = 0; b <= a; ++b) {
-      double v = 0.0;
-      for (int p = 0; p < n; ++p) v += phid[size_t(p) * B + a] * phid[size_t(p) * B + b];
-      G[size_t(a) * B + b] = G[size_t(b) * B + a] = v;
-    }
-  std::vector<double> w, V;
-  jacobi_eig(B, G, w, V);
-  double wmin = w[0], wmax = w[0];
-  for (double x : w) {
-    wmin = std::min(wmin, x);
-    wmax = std::max(wmax, x);
-  }
-  std::vector<double> L = G;
-  if (!(wmin > 0.0) || !cholesky(B, L)) {
-    err = "basis Gram matrix is not positive definite";
-    return false;
-  }
-  // pinv_d = G^{-1} Phi_d^T : solve L L^T X = Phi_d^T column by column (pixel by pixel)
-  std::vector<double> pinvd(size_t(B) * n);
-  std::vector<double> y(B);
-  for (int p = 0; p < n; ++p) {
-    for (int i = 0; i < B; ++i) {
-      double v = phid[size_t(p) * B + i];
-      for (int k = 0; k < i; ++k) v -= L[size_t(i) * B + k] * y[k];
-      y[i] = v / L[size_t(i) * B + i];
-    }
-    for (int i = B - 1; i >= 0; --i) {
-      double v = y[i];
-      for (int k = i + 1; k < B; ++k) v -= L[size_t(k) * B + i] * y[k];
-      y[i] = v / L[size_t(i) * B + i];
-    }
-    for (int i = 0; i < B; ++i) pinvd[size_t(i) * n + p] = y[i];
-  }
-  out.N = N;
+  if (!finish_basis(N, pix, phid, B, out, err)) return false;
   out.S = S;
   out.T = T;
-  out.B = B;
-  out.n_pix = n;
-  out.cond = wmax / wmin;
-  out.pix = pix;
-  out.phi.assign(size_t(N) * N * B, 0.0);
-  out.pinv.assign(size_t(B) * N * N, 0.0);
-  for (int p = 0; p < n; ++p)
-    for (int b = 0; b < B; ++b) {
-      out.phi[size_t(pix[p]) * B + b] = phid[size_t(p) * B + b];
-      out.pinv[size_t(b) * N * N + pix[p]] = pinvd[size_t(b) * n + p];
+  return true;
+}
+
+// The paper's annular basis (eq. (5)-(7)): annulus s = 1..S (S = floor(N/2)) is
+// N(s-1)/(2S) <= r < N s/(2S); its cut-off is half its circumference, floor(pi r_mid),
+// lowered to the largest T for which its 2T + 1 real harmonic columns (the indicator,
+// cos k theta and sin k theta for k = 1..T, which span the same space as the complex
+// exp(i t theta), |t| <= T) are linearly independent on the annulus' pixels: the smallest
+// eigenvalue of their Gram matrix (columns normalised) above 1e-12 of the largest.  The
+// low-pass basis halves the cut-offs.  Columns are normalised on the disk; the centre
+// pixel is 0 for k != 0.  Packed layout: harmonic-major, the annuli with T_s >= k in
+// block k ([Re][Im] for k >= 1, sqrt 2 Re and -sqrt 2 Im of the normalised complex column).
+bool build_annular_basis(int N, bool lowpass, HostBasis& out, std::vector<int>& Ts, std::string& err) {
+  const int S = N / 2;
+  const double half = 0.5 * N, c0 = 0.5 * (N - 1);
+  const double pi = 3.14159265358979323846;
+  if (S < 1) {
+    err = "N must be at least 3";
+    return false;
+  }
+  std::vector<int> pix, ring;
+  std::vector<double> rho, th;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const double x = j - c0, y = c0 - i, r = std::sqrt(x * x + y * y);
+      if (r < half) {
+        pix.push_back(i * N + j);
+        rho.push_back(r);
+        th.push_back(std::atan2(y, x));
+        int s = int(std::floor(r * 2.0 * S / N)) + 1;   // N(s-1)/(2S) <= r < N s/(2S)
+        if (s > S) s = S;
+        if (s > 1 && r < N * (s - 1) / (2.0 * S)) --s;  // guard the boundary against rounding
+        if (s < S && r >= N * s / (2.0 * S)) ++s;
+        ring.push_back(s);
+      }
     }
+  const int n = int(pix.size());
+  // real harmonic value of column (k, part) at pixel p: part 0 cos, part 1 sin
+  auto val = [&](int k, int part, int p) -> double {
+    if (k == 0) return part == 0 ? 1.0 : 0.0;
+    if (rho[p] == 0.0) return 0.0;
+    return part == 0 ? std::cos(k * th[p]) : std::sin(k * th[p]);
+  };
+  Ts.assign(S, 0);
+  for (int s = 1; s <= S; ++s) {
+    std::vector<int> ps;
+    for (int p = 0; p < n; ++p)
+      if (ring[p] == s) ps.push_back(p);
+    const int cap = int(std::floor(pi * (N * (s - 0.5) / (2.0 * S))));
+    int T = -1;
+    for (int t = 0; t <= cap; ++t) {
+      const int m = 2 * t + 1;
+      if (m > int(ps.size())) break;
+      // columns: (0, cos), then (k, cos), (k, sin) for k = 1..t, each normalised
+      std::vector<std::pair<int, int>> cols{{0, 0}};
+      for (int k = 1; k <= t; ++k) {
+        cols.push_back({k, 0});
+        cols.push_back({k, 1});
+      }
+      std::vector<double> nrm(m, 0.0);
+      for (int a = 0; a < m; ++a)
+        for (int p : ps) nrm[a] += val(cols[a].first, cols[a].second, p) * val(cols[a].first, cols[a].second, p);
+      bool zero = false;
+      for (int a = 0; a < m; ++a) zero = zero || !(nrm[a] > 0.0);
+      if (zero) break;
+      std::vector<double> G(size_t(m) * m);
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+          double v = 0.0;
+          for (int p : ps) v += val(cols[a].first, cols[a].second, p) * val(cols[b].first, cols[b].second, p);
+          G[size_t(a) * m + b] = v / std::sqrt(nrm[a] * nrm[b]);
+        }
+      std::vector<double> w, V;
+      jacobi_eig(m, G, w, V);
+      double wmin = w[0], wmax = w[0];
+      for (double x : w) {
+        wmin = std::min(wmin, x);
+        wmax = std::max(wmax, x);
+      }
+      if (!(wmin > 1e-12 * wmax)) break;
+      T = t;
+    }
+    if (T < 0) {
+      err = "an annulus holds no pixel";
+      return false;
+    }
+    Ts[s - 1] = lowpass ? T / 2 : T;
+  }
+  int Tmax = 0, B = 0;
+  for (int t : Ts) {
+    Tmax = std::max(Tmax, t);
+    B += 2 * t + 1;
+  }
+  // packed real synthesis matrix on the disk
+  std::vector<double> phid(size_t(n) * B, 0.0);
+  const double r2 = std::sqrt(2.0);
+  int col = 0;
+  for (int k = 0; k <= Tmax; ++k) {
+    std::vector<int> rs;
+    for (int s = 1; s <= S; ++s)
+      if (Ts[s - 1] >= k) rs.push_back(s);
+    const int nk = int(rs.size());
+    for (int i = 0; i < nk; ++i) {
+      double nrm = 0.0;   // |exp(i k theta)| = 1 on the annulus, 0 at the centre for k != 0
+      for (int p = 0; p < n; ++p)
+        if (ring[p] == rs[i] && (k == 0 || rho[p] != 0.0)) nrm += 1.0;
+      nrm = std::sqrt(nrm);
+      for (int p = 0; p < n; ++p) {
+        if (ring[p] != rs[i]) continue;
+        if (k == 0) {
+          phid[size_t(p) * B + col + i] = 1.0 / nrm;
+        } else {
+          phid[size_t(p) * B + col + i] = r2 * val(k, 0, p) / nrm;
+          phid[size_t(p) * B + col + nk + i] = -r2 * val(k, 1, p) / nrm;
+        }
+      }
+    }
+    col += k == 0 ? nk : 2 * nk;
+  }
+  if (!finish_basis(N, pix, phid, B, out, err)) return false;
+  out.S = S;
+  out.T = Tmax;
   return true;
 }
 

@@ -21,6 +21,8 @@ struct HostBasis {
 
 bool build_basis(int N, int S, int T, const double* centres, double sigma, HostBasis& out,
                  std::string& err);
+// The paper's annular basis; Ts receives the cut-off of each annulus.
+bool build_annular_basis(int N, bool lowpass, HostBasis& out, std::vector<int>& Ts, std::string& err);
 
 // Geometry-dependent constants of the encoder.  Stage-1 contraction steps: the
 // k = 0 block pairs profiles (s, s+1) per step, every k >= 1 block uses one step
@@ -39,6 +41,8 @@ struct DeviceTables {
   int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)] (every B)
   float* pinvI = nullptr;    // image projection operand over disk pixels [2 or 4][ceil(n_pix/2)][64]
   int* dpixI = nullptr;      // (dy << 8 | dx) of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
+  int* steerTab = nullptr;   // annular basis: per coordinate, harmonic k and partner offset
+                             // ((k << 16) | (offset + 32768)); null for the full (S, T) grid
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
   float* synA = nullptr;     // synthesis MFMA operand [ceil(N*N/32)][ceil(B/2)][64] (N*N <= 256)
   // Dictionary tables (dictA .. cs64 below) live in one device arena, refilled in place by

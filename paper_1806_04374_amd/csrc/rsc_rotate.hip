@@ -258,6 +258,98 @@ __global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int6
   }
 }
 
+// Steering in a layout given by a table (the annular basis): tab[c] = (k << 16) | (off +
+// 32768) for coordinate c of harmonic k whose Re/Im partner sits off floats away (off > 0
+// for a Re coordinate, < 0 for an Im one, 0 on harmonic 0).  One angle for all patches:
+// the chunk pipeline of steer_stream_kernel with B at run time (chunk = 64 patches in
+// dynamic LDS, VPT >= 16 B / 256 float4 per thread) and coefficients from the table.
+__device__ __forceinline__ void steer_coef(const SteerParams& prm, int code, float& a, float& b, int& off) {
+  const int k = code >> 16;
+  off = (code & 0xffff) - 32768;
+  a = prm.cs[k];
+  b = off > 0 ? prm.sn[k] : off < 0 ? -prm.sn[k] : 0.f;
+}
+
+template <int VPT>
+__global__ __launch_bounds__(256) void steer_table_stream_kernel(SteerParams prm, const int* __restrict__ tab,
+                                                                int64_t nchunk, int tail) {
+  extern __shared__ float buf[];   // [kSteerChunk * B]
+  const int B = prm.B, CF = kSteerChunk * B, NV = CF / 4;
+  const int t = threadIdx.x;
+  float alpha[VPT][4], beta[VPT][4];
+  int partner[VPT][4];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = 4 * (t + 256 * v) + j;
+      float a = 0.f, b = 0.f;
+      int off = 0;
+      if (e < CF) steer_coef(prm, tab[e % B], a, b, off);
+      alpha[v][j] = a;
+      beta[v][j] = b;
+      partner[v][j] = e < CF ? e + off : 0;
+    }
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const float4* src = reinterpret_cast<const float4*>(prm.xhat + ch * CF);
+    float4 x[VPT];
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) x[v] = src[t + 256 * v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) reinterpret_cast<float4*>(buf)[t + 256 * v] = x[v];
+    __syncthreads();
+    float4* dst = reinterpret_cast<float4*>(prm.out + ch * CF);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v)
+      if (t + 256 * v < NV) {
+        float4 o;
+        o.x = alpha[v][0] * x[v].x + beta[v][0] * buf[partner[v][0]];
+        o.y = alpha[v][1] * x[v].y + beta[v][1] * buf[partner[v][1]];
+        o.z = alpha[v][2] * x[v].z + beta[v][2] * buf[partner[v][2]];
+        o.w = alpha[v][3] * x[v].w + beta[v][3] * buf[partner[v][3]];
+        dst[t + 256 * v] = o;
+      }
+  }
+  if (tail > 0 && blockIdx.x == nchunk % gridDim.x) {
+    const int nel = tail * B;
+    const float* src = prm.xhat + nchunk * CF;
+    __syncthreads();
+    for (int e = t; e < nel; e += 256) buf[e] = src[e];
+    __syncthreads();
+    float* dst = prm.out + nchunk * CF;
+    for (int e = t; e < nel; e += 256) {
+      float a, b;
+      int off;
+      steer_coef(prm, tab[e % B], a, b, off);
+      dst[e] = a * buf[e] + b * buf[e + off];
+    }
+  }
+}
+
+// Table layout, any buffers, per-patch angles or one angle: one thread per coordinate.
+__global__ __launch_bounds__(256) void steer_table_kernel(SteerParams prm, const int* __restrict__ tab) {
+  const int B = prm.B;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= prm.P * B) return;
+  const int64_t p = i / B;
+  const int c = int(i - p * B);
+  const int code = tab[c];
+  const int k = code >> 16, off = (code & 0xffff) - 32768;
+  float a, b;
+  if (prm.theta) {
+    float sn;
+    sincosf(float(k) * prm.theta[p], &sn, &a);
+    b = off > 0 ? sn : off < 0 ? -sn : 0.f;
+  } else {
+    int o2;
+    steer_coef(prm, code, a, b, o2);
+  }
+  prm.out[i] = a * prm.xhat[i] + b * prm.xhat[i + off];
+}
+
 // The same for any geometry (index arithmetic at run time).
 __global__ __launch_bounds__(256) void steer_any_kernel(SteerParams prm, int T) {
   const int S = prm.S, B = prm.B, W = S * (T + 1);
@@ -567,6 +659,28 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
     prm.sn[k] = float(std::sin(k * theta0));
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (t.steerTab) {
+    // table layout: chunks streamed for one angle and 16-byte aligned buffers, else one
+    // thread per coordinate
+    const bool al = ((reinterpret_cast<uintptr_t>(xhat) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    if (!theta && al && t.B <= 128) {
+      const int64_t nchunk = P / kSteerChunk;
+      const int tail = int(P - nchunk * kSteerChunk);
+      const int64_t work = nchunk + (tail > 0);
+      const size_t lds = sizeof(float) * kSteerChunk * size_t(t.B);
+      auto go = [&](auto kern) {
+        const int64_t blocks = int64_t(num_cus()) * 4;
+        hipLaunchKernelGGL(kern, dim3(unsigned(work < blocks ? work : blocks)), dim3(256), lds, st, prm,
+                           static_cast<const int*>(t.steerTab), nchunk, tail);
+        return hipGetLastError();
+      };
+      return int(t.B <= 64 ? go(steer_table_stream_kernel<4>) : go(steer_table_stream_kernel<8>));
+    }
+    const int64_t items = P * int64_t(t.B);
+    hipLaunchKernelGGL(steer_table_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, prm,
+                       static_cast<const int*>(t.steerTab));
+    return int(hipGetLastError());
+  }
   // one angle, compiled geometry, 16-byte aligned buffers: the streaming kernel; otherwise
   // the per-coordinate kernels below
   const bool aligned = ((reinterpret_cast<uintptr_t>(xhat) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;

@@ -43,6 +43,8 @@ def lib():
     sig = {
         "rsc_create": [I, I, I, P, D, I, ctypes.POINTER(ctypes.c_void_p)],
         "rsc_basis_host": [I, I, I, P, D, P, P, P, P, P],
+        "rsc_create_annular": [I, I, ctypes.POINTER(ctypes.c_void_p)],
+        "rsc_annular_basis_host": [I, I, P, P, P, P, P],
         "rsc_destroy": [P],
         "rsc_basis_info": [P, P, P, P],
         "rsc_get_basis": [P, P, P],
@@ -165,6 +167,31 @@ def rsc_basis_host(N: int, S: int, T: int, centres=None, sigma: float = 0.0):
                                 float(sigma), phi.ctypes.data_as(ctypes.c_void_p),
                                 pinv.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(cond)))
     return phi, pinv, cond.value
+
+
+def rsc_annular_basis_host(N: int, lowpass: bool = False):
+    """The library's FP64 annular basis built on the host: (phi [N*N, B], pinv [B, N*N],
+    per-annulus cut-offs T_s, cond)."""
+    B = ctypes.c_int()
+    Ts = np.zeros(N // 2, dtype=np.int32)
+    _check(lib().rsc_annular_basis_host(N, int(bool(lowpass)), None, None, Ts.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(B), None))
+    phi = np.zeros((N * N, B.value))
+    pinv = np.zeros((B.value, N * N))
+    cond = ctypes.c_double()
+    _check(lib().rsc_annular_basis_host(N, int(bool(lowpass)), phi.ctypes.data_as(ctypes.c_void_p),
+                                        pinv.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(cond)))
+    return phi, pinv, [int(t) for t in Ts], cond.value
+
+
+def rsc_create_annular(N: int, lowpass: bool = False) -> Handle:
+    """FP32 handle on the paper's annular basis (projection, steering, synthesis)."""
+    _, _, Ts, _ = rsc_annular_basis_host(N, lowpass)
+    h = ctypes.c_void_p()
+    _check(lib().rsc_create_annular(N, int(bool(lowpass)), ctypes.byref(h)))
+    hd = Handle(h, N, N // 2, max(Ts), "fp32")
+    hd.Ts = Ts
+    return hd
 
 
 def rsc_get_basis(h: Handle):

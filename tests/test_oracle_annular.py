@@ -99,3 +99,21 @@ def test_lowpass_columns_are_columns_of_the_full_basis(N):
     assert low.Ts == [t // 2 for t in full.Ts]
     for j in range(low.B):
         assert np.min(np.abs(full.phi - low.phi[:, j : j + 1]).max(axis=0)) < 1e-15
+
+
+@pytest.mark.parametrize("N,lowpass", [(11, False), (11, True), (15, False), (15, True), (21, False), (9, True)])
+def test_library_host_basis_matches_reference(N, lowpass):
+    """The library builds the annular basis with its own code (real cos/sin columns, a
+    Jacobi rank test); cut-offs, Phi and its partner equal the reference's."""
+    from paper_1806_04374_amd import rsc
+    phi, pinv, Ts, cond = rsc.rsc_annular_basis_host(N, lowpass)
+    b = orc.build_annular_basis(N, lowpass)
+    assert Ts == b.Ts
+    ref = np.zeros((N * N, b.B))
+    ref[b.mask.ravel()] = b.phi
+    assert np.abs(phi - ref).max() < 1e-13
+    refp = np.zeros((b.B, N * N))
+    refp[:, b.mask.ravel()] = b.pinv
+    assert np.abs(pinv - refp).max() < 1e-9 * np.abs(refp).max()
+    w = np.linalg.eigvalsh(b.phi.T @ b.phi)
+    assert abs(cond - w[-1] / w[0]) < 1e-8 * cond
