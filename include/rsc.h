@@ -127,8 +127,9 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * rsc_basis_info and rsc_get_basis; rsc_set_dictionary and image projection return
  * RSC_E_UNSUPPORTED.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
- * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 128 or some T_s > 15, e.g.
- * the full basis at N = 15, B = 153), RSC_E_NOMEM, RSC_E_DEVICE.
+ * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
+ * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 192 or some T_s > 31),
+ * RSC_E_NOMEM, RSC_E_DEVICE.
  */
 rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out);
 

@@ -121,7 +121,7 @@ rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
   d.T = T;
   d.B = b.B;
   const int NN = N * N, KP = (NN + 1) / 2;
-  const int RTB = (b.B + 31) / 32 <= 2 ? 2 : 4;  // row tiles of the compiled projection kernels
+  const int RTB = (b.B + 31) / 32 <= 2 ? 2 : (b.B + 31) / 32 <= 4 ? 4 : 6;  // row tiles of the projection kernels
   // projection A operand: row = hat coordinate, contraction = grid pixel
   std::vector<float> pinvA(size_t(RTB) * KP * 64, 0.f);
   for (int t = 0; t < RTB; ++t)
@@ -267,10 +267,10 @@ rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out) {
     return fail(RSC_E_INVALID, "basis construction failed: " + err);
   }
   const rsc::HostBasis& b = h->basis;
-  if (b.B > 128 || b.T > 15) {
+  if (b.B > 192 || b.T > 31) {
     delete h;
     return fail(RSC_E_UNSUPPORTED, "annular basis with B = " + std::to_string(b.B) + ", T = " +
-                                       std::to_string(b.T) + ": this build handles B <= 128 and T <= 15");
+                                       std::to_string(b.T) + ": this build handles B <= 192 and T <= 31");
   }
   h->annular = true;
   rsc_status st = init_tables(h, N, b.S, b.T, RSC_FP32);
@@ -1059,7 +1059,7 @@ rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const fl
                      float* out, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
-  if (h->dev.T > 15) return fail(RSC_E_UNSUPPORTED, "steering is compiled for T <= 15");
+  if (h->dev.T > 31) return fail(RSC_E_UNSUPPORTED, "steering is compiled for T <= 31");
   if (!theta && !std::isfinite(theta0)) return fail(RSC_E_INVALID, "theta0 must be finite");
   if (P == 0) return ok();
   if (!xhat || !out) return fail(RSC_E_INVALID, "null device pointer");
@@ -1071,7 +1071,7 @@ rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const fl
 rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
-  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "synthesis is compiled for B <= 128");
+  if (h->dev.B > 192) return fail(RSC_E_UNSUPPORTED, "synthesis is compiled for B <= 192");
   if (P == 0) return ok();
   if (!xhat || !pixels) return fail(RSC_E_INVALID, "null device pointer");
   int e = rsc::launch_synth_hat(h->dev, xhat, P, pixels, stream);

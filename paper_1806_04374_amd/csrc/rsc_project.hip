@@ -438,6 +438,9 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
   else if (rtb <= 4)
     hipLaunchKernelGGL(project_kernel<4>, dim3(unsigned(blocks)), dim3(128), lds, st, patches, P, NN, t.B,
                        t.pinvA, xhat);
+  else if (rtb <= 6)
+    hipLaunchKernelGGL(project_kernel<6>, dim3(unsigned(blocks)), dim3(128), lds, st, patches, P, NN, t.B,
+                       t.pinvA, xhat);
   else
     return int(hipErrorInvalidValue);
   return int(hipGetLastError());

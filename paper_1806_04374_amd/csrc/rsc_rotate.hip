@@ -145,7 +145,7 @@ struct SteerParams {
   int64_t P;
   int B, S;
   const float* theta;   // per patch, or null
-  float cs[16], sn[16]; // cos, sin of k theta0 for k = 0..T (T <= 15), when theta is null
+  float cs[32], sn[32]; // cos, sin of k theta0 for k = 0..T (T <= 31), when theta is null
 };
 
 // One thread per (patch, profile s, harmonic k >= 1) pair, or per harmonic-0
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256) void synth_hat_kernel(const float* __restrict_
   }
 }
 
-// Phi x_hat for N*N <= 256, B <= 128: lane g of a G-lane group owns output pixel g and
+// Phi x_hat for N*N <= 256, B <= 192: lane g of a G-lane group owns output pixel g and
 // keeps row g of Phi in registers (BV float4, zero past B); a block stages kSynP patches'
 // hat rows in LDS at a padded stride of 4 BV floats (the pads stay zero), and group h
 // forms patches h, h + 256 / G, ... with one broadcast 16-byte LDS read per 4 FMAs.
@@ -654,7 +654,7 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
   prm.B = t.B;
   prm.S = t.S;
   prm.theta = theta;
-  for (int k = 0; k <= t.T && k < 16; ++k) {
+  for (int k = 0; k <= t.T && k < 32; ++k) {
     prm.cs[k] = float(std::cos(k * theta0));
     prm.sn[k] = float(std::sin(k * theta0));
   }
@@ -663,7 +663,7 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
     // table layout: chunks streamed for one angle and 16-byte aligned buffers, else one
     // thread per coordinate
     const bool al = ((reinterpret_cast<uintptr_t>(xhat) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    if (!theta && al && t.B <= 128) {
+    if (!theta && al && t.B <= 192) {
       const int64_t nchunk = P / kSteerChunk;
       const int tail = int(P - nchunk * kSteerChunk);
       const int64_t work = nchunk + (tail > 0);
@@ -674,7 +674,8 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
                            static_cast<const int*>(t.steerTab), nchunk, tail);
         return hipGetLastError();
       };
-      return int(t.B <= 64 ? go(steer_table_stream_kernel<4>) : go(steer_table_stream_kernel<8>));
+      return int(t.B <= 64 ? go(steer_table_stream_kernel<4>) : t.B <= 128 ? go(steer_table_stream_kernel<8>)
+                                                                         : go(steer_table_stream_kernel<12>));
     }
     const int64_t items = P * int64_t(t.B);
     hipLaunchKernelGGL(steer_table_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, prm,
@@ -732,7 +733,7 @@ int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float*
     out += done * NN;
     P -= done;
   }
-  if (NN <= 256 && t.B <= 128) {
+  if (NN <= 256 && t.B <= 192) {
     const int bv = (t.B + 3) / 4;
     const int64_t want = (P + kSynP - 1) / kSynP;
     const int64_t cap = int64_t(num_cus()) * 8;
@@ -749,7 +750,8 @@ int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float*
         case 13: return go(synth_reg_kernel<13, G>);
         case 14: return go(synth_reg_kernel<14, G>);
         case 27: return go(synth_reg_kernel<27, G>);
-        default: return bv <= 16 ? go(synth_reg_kernel<16, G>) : go(synth_reg_kernel<32, G>);
+        default: return bv <= 16 ? go(synth_reg_kernel<16, G>) : bv <= 32 ? go(synth_reg_kernel<32, G>)
+                                                                         : go(synth_reg_kernel<48, G>);
       }
     };
     if (NN <= 64) return pick(std::integral_constant<int, 64>{});

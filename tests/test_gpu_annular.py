@@ -25,7 +25,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("N,lowpass", [(11, False), (11, True), (15, True), (9, False)])
+@pytest.mark.parametrize("N,lowpass", [(11, False), (11, True), (15, False), (15, True), (9, False)])
 def test_annular_rotation_path(dev, N, lowpass):
     from paper_1806_04374_amd import rsc
     b = orc.build_annular_basis(N, lowpass)
@@ -80,7 +80,7 @@ def test_annular_steering_chunk_edges_and_alignment(dev, P):
 def test_annular_refusals(dev):
     from paper_1806_04374_amd import rsc
     with pytest.raises(rsc.RscError) as e:
-        rsc.rsc_create_annular(15)           # B = 153
+        rsc.rsc_create_annular(17)           # B = 204
     assert e.value.status == rsc.RSC_E_UNSUPPORTED
     h = rsc.rsc_create_annular(11)
     with pytest.raises(rsc.RscError) as e:
