@@ -722,6 +722,8 @@ def run_rotate(args, dev):
         N = geom.N
         h = rsc.rsc_create(N, geom.S, geom.T)
         hl = rsc.rsc_create(N, geom.S, geom.T // 2)
+        ha = rsc.rsc_create_annular(N)            # the paper's annular basis and its low-pass form
+        hal = rsc.rsc_create_annular(N, lowpass=True)
         plans = {m: rsc.RotationPlan(N, theta, m) for m in ("nearest", "bicubic")}
         for P in (50_000, 4_000_000):
             rng = torch.Generator(device=dev)
@@ -741,20 +743,33 @@ def run_rotate(args, dev):
             r["steer_full"] = timed(lambda: rsc.rsc_synthesize_hat(
                 h, rsc.rsc_steer(h, rsc.rsc_project(h, X, xh, stream=stream), theta, out=xo, stream=stream),
                 out=Y, stream=stream))
+            del xl, xlo
+            xa = rsc.rsc_project(ha, X)
+            xao = torch.empty_like(xa)
+            r["steer_annular"] = timed(lambda: rsc.rsc_steer(ha, xa, theta, out=xao, stream=stream))
+            del xa, xao
+            xa = rsc.rsc_project(hal, X)
+            xao = torch.empty_like(xa)
+            r["steer_annular_low"] = timed(lambda: rsc.rsc_steer(hal, xa, theta, out=xao, stream=stream))
+            del xa, xao
             results[f"N{N}_P{P}"] = {
-                "ms": r, "B": h.B, "B_low": hl.B,
+                "ms": r, "B": h.B, "B_low": hl.B, "B_annular": ha.B, "B_annular_low": hal.B,
+                "bicubic_over_steer_annular": r["bicubic"] / r["steer_annular"],
+                "steer_annular_GBps": 2 * 4 * ha.B * P / (r["steer_annular"] * 1e-3) / 1e9,
                 "bicubic_over_steer": r["bicubic"] / r["steer"], "nearest_over_steer": r["nearest"] / r["steer"],
                 "steer_GBps": 2 * 4 * h.B * P / (r["steer"] * 1e-3) / 1e9,
                 "bicubic_GBps": 2 * 4 * N * N * P / (r["bicubic"] * 1e-3) / 1e9,
                 "copy_GBps": 2 * 4 * h.B * P / (r["copy_of_xhat"] * 1e-3) / 1e9,
             }
             print(f"rotate N={N} P={P}: {json.dumps(r)}", file=sys.stderr, flush=True)
-            del X, Y, xh, xo, xl, xlo
+            del X, Y, xh, xo
             torch.cuda.empty_cache()
         for plan in plans.values():
             plan.close()
         h.close()
         hl.close()
+        ha.close()
+        hal.close()
     main = results["N11_P4000000"]
     bytes_steer = 2 * 4 * 55 * 4_000_000
     out = {
@@ -764,7 +779,8 @@ def run_rotate(args, dev):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "rotate: 4,000,000 random 11x11 patches (B = 55); also 50,000 (the paper's "
                                "count) and 15x15; nearest / bicubic rotation matrices, steering, low-pass "
-                               "steering (T halved), full steering rotation"},
+                               "steering (T halved), steering in the paper's annular basis and its "
+                               "low-pass form, full steering rotation"},
         "results": results,
         "roofline": {"kernel": "steer_stream_kernel", "bound": "hbm", "achieved": main["steer_GBps"], "peak": 8000.0,
                      "unit": "GB/s", "frac": main["steer_GBps"] / 8000.0, "traffic": None,

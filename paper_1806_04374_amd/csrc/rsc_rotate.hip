@@ -262,7 +262,8 @@ __global__ __launch_bounds__(256) void steer_stream_kernel(SteerParams prm, int6
 // 32768) for coordinate c of harmonic k whose Re/Im partner sits off floats away (off > 0
 // for a Re coordinate, < 0 for an Im one, 0 on harmonic 0).  One angle for all patches:
 // the chunk pipeline of steer_stream_kernel with B at run time (chunk = 64 patches in
-// dynamic LDS, VPT >= 16 B / 256 float4 per thread) and coefficients from the table.
+// dynamic LDS, NT threads with VPT >= 16 B / NT float4 each; larger B takes larger blocks
+// rather than more registers per thread) and coefficients from the table.
 __device__ __forceinline__ void steer_coef(const SteerParams& prm, int code, float& a, float& b, int& off) {
   const int k = code >> 16;
   off = (code & 0xffff) - 32768;
@@ -270,8 +271,8 @@ __device__ __forceinline__ void steer_coef(const SteerParams& prm, int code, flo
   b = off > 0 ? prm.sn[k] : off < 0 ? -prm.sn[k] : 0.f;
 }
 
-template <int VPT>
-__global__ __launch_bounds__(256) void steer_table_stream_kernel(SteerParams prm, const int* __restrict__ tab,
+template <int VPT, int NT>
+__global__ __launch_bounds__(NT) void steer_table_stream_kernel(SteerParams prm, const int* __restrict__ tab,
                                                                 int64_t nchunk, int tail) {
   extern __shared__ float buf[];   // [kSteerChunk * B]
   const int B = prm.B, CF = kSteerChunk * B, NV = CF / 4;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void steer_table_stream_kernel(SteerParams prm
   for (int v = 0; v < VPT; ++v)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int e = 4 * (t + 256 * v) + j;
+      const int e = 4 * (t + NT * v) + j;
       float a = 0.f, b = 0.f;
       int off = 0;
       if (e < CF) steer_coef(prm, tab[e % B], a, b, off);
@@ -295,32 +296,32 @@ __global__ __launch_bounds__(256) void steer_table_stream_kernel(SteerParams prm
     float4 x[VPT];
 #pragma unroll
     for (int v = 0; v < VPT; ++v)
-      if (t + 256 * v < NV) x[v] = src[t + 256 * v];
+      if (t + NT * v < NV) x[v] = src[t + NT * v];
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < VPT; ++v)
-      if (t + 256 * v < NV) reinterpret_cast<float4*>(buf)[t + 256 * v] = x[v];
+      if (t + NT * v < NV) reinterpret_cast<float4*>(buf)[t + NT * v] = x[v];
     __syncthreads();
     float4* dst = reinterpret_cast<float4*>(prm.out + ch * CF);
 #pragma unroll
     for (int v = 0; v < VPT; ++v)
-      if (t + 256 * v < NV) {
+      if (t + NT * v < NV) {
         float4 o;
         o.x = alpha[v][0] * x[v].x + beta[v][0] * buf[partner[v][0]];
         o.y = alpha[v][1] * x[v].y + beta[v][1] * buf[partner[v][1]];
         o.z = alpha[v][2] * x[v].z + beta[v][2] * buf[partner[v][2]];
         o.w = alpha[v][3] * x[v].w + beta[v][3] * buf[partner[v][3]];
-        dst[t + 256 * v] = o;
+        dst[t + NT * v] = o;
       }
   }
   if (tail > 0 && blockIdx.x == nchunk % gridDim.x) {
     const int nel = tail * B;
     const float* src = prm.xhat + nchunk * CF;
     __syncthreads();
-    for (int e = t; e < nel; e += 256) buf[e] = src[e];
+    for (int e = t; e < nel; e += NT) buf[e] = src[e];
     __syncthreads();
     float* dst = prm.out + nchunk * CF;
-    for (int e = t; e < nel; e += 256) {
+    for (int e = t; e < nel; e += NT) {
       float a, b;
       int off;
       steer_coef(prm, tab[e % B], a, b, off);
@@ -668,14 +669,20 @@ int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const floa
       const int tail = int(P - nchunk * kSteerChunk);
       const int64_t work = nchunk + (tail > 0);
       const size_t lds = sizeof(float) * kSteerChunk * size_t(t.B);
-      auto go = [&](auto kern) {
-        const int64_t blocks = int64_t(num_cus()) * 4;
-        hipLaunchKernelGGL(kern, dim3(unsigned(work < blocks ? work : blocks)), dim3(256), lds, st, prm,
+      auto go = [&](auto kern, int nt) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds) != hipSuccess || per_cu < 1)
+          per_cu = 1;
+        const int64_t blocks = int64_t(num_cus()) * per_cu;
+        hipLaunchKernelGGL(kern, dim3(unsigned(work < blocks ? work : blocks)), dim3(nt), lds, st, prm,
                            static_cast<const int*>(t.steerTab), nchunk, tail);
         return hipGetLastError();
       };
-      return int(t.B <= 64 ? go(steer_table_stream_kernel<4>) : t.B <= 128 ? go(steer_table_stream_kernel<8>)
-                                                                         : go(steer_table_stream_kernel<12>));
+      // NV = 16 B float4 per chunk: B <= 64 -> 4 x 256, <= 96 -> 3 x 512, <= 128 -> 4 x 512, else 3 x 1024
+      return int(t.B <= 64   ? go(steer_table_stream_kernel<4, 256>, 256)
+                 : t.B <= 96 ? go(steer_table_stream_kernel<3, 512>, 512)
+                 : t.B <= 128 ? go(steer_table_stream_kernel<4, 512>, 512)
+                              : go(steer_table_stream_kernel<3, 1024>, 1024));
     }
     const int64_t items = P * int64_t(t.B);
     hipLaunchKernelGGL(steer_table_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, st, prm,
