@@ -19,6 +19,8 @@
 //    by a power of two that puts its largest value in [2^10, 2^11) (the operand is
 //    pre-scaled the same way on the host), keeping the remainders normal; the
 //    scales are exact and removed per column after the accumulation.
+//  * project_reg_kernel (15x15 patch arrays, B in 97..128): the operand in registers,
+//    one 32-row tile per wave, 32-patch chunks with the next one prefetched.
 //  * project_kernel (any size): blocks of 64 patches, operand read from global.
 #include <hip/hip_runtime.h>
 

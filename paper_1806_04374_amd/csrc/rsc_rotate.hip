@@ -2,14 +2,18 @@
 //
 // Interpolation: a plan holds the rotation as a table of taps, the rows of the paper's
 // N^2 x N^2 matrix R_nearest or R_bicubic (at most 1 or 16 nonzeros per output pixel),
-// built once on the host in FP64; rotate_taps_kernel applies it to a batch of patches.
+// built once on the host in FP64; rotate_taps_kernel / rotate_taps_fixed_kernel (11x11,
+// 15x15) apply it to a batch of patches.
 //   Output pixel (x, y) (x = col - c, y = c - row, c = (N-1)/2) reads the input at
 //   R_{-theta}(x, y): nearest-neighbour (coordinates rounded half up) or bicubic (Keys'
 //   cubic convolution, a = -1/2, over the 4 x 4 neighbours); input pixels outside the
 //   patch count as 0.
-// Steering: steer_kernel multiplies harmonic k of hat coordinates by exp(-i k theta)
-// (the diagonal S of eq. (8), at any angle); synth_hat_kernel maps hat coordinates back
-// to pixels, Phi x_hat (zero off the disk).
+// Steering multiplies harmonic k of hat coordinates by exp(-i k theta) (the diagonal S of
+// eq. (8), at any angle): steer_stream_kernel (compiled geometries, one angle),
+// steer_kernel / steer_any_kernel (per-patch angles, other geometries), and the
+// table-driven steer_table_*_kernel for the annular basis' ragged layout.  Synthesis maps
+// hat coordinates back to pixels, Phi x_hat (zero off the disk): synth_mfma_kernel
+// (compiled geometries), synth_reg_kernel (N*N <= 256), synth_hat_kernel (larger).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
