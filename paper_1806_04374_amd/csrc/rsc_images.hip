@@ -3,10 +3,11 @@
 //  * images_plan_kernel: per-image patch and wave-tile prefix sums, computed on the
 //    device from device arrays of image sizes, so a batch needs no host round trip
 //    and can be captured in a HIP graph.
-//  * project_images_kernel: persistent im2col projection (Sec. II-E step 2).  A wave
-//    owns 32 consecutive window origins of one image row; lanes read the disk pixels
-//    of their windows straight from the image (consecutive lanes = consecutive
-//    columns), the (Phi^T Phi)^{-1} Phi^T operand stays in LDS for the whole launch.
+//  * project_images_reg_kernel: persistent im2col projection (Sec. II-E step 2).  A
+//    block takes tiles of 32 consecutive window origins of one image row; the tile's
+//    pixel region is staged in LDS, each wave keeps one 32-row tile of the
+//    (Phi^T Phi)^{-1} Phi^T operand in registers, and the results leave as contiguous
+//    runs of x_hat rows.
 //  * stamp_kernel: adds amplitude * Phi S_theta d_m stamps into images (synthetic
 //    inputs), one block per stamp.
 #include <hip/hip_runtime.h>
@@ -18,7 +19,6 @@ namespace rsc {
 namespace {
 
 constexpr int kPlanThreads = 1024;
-constexpr int kImgWaves = 8;
 
 // ws: int64 patch_start[n+1], tile_start[n+1] (exclusive prefix sums).
 __global__ __launch_bounds__(kPlanThreads) void images_plan_kernel(const int32_t* __restrict__ H,
@@ -63,64 +63,136 @@ __global__ __launch_bounds__(kPlanThreads) void images_plan_kernel(const int32_t
   }
 }
 
-// pinvD: [RTB][KPD][64] operand over disk pixels; dpix: [2*KPD] (dy << 8 | dx) or -1.
-template <int N, int KPD, int RTB>
-__global__ __launch_bounds__(64 * kImgWaves) void project_images_kernel(
-    const float* __restrict__ pixels, const int64_t* __restrict__ img_offset, const int32_t* __restrict__ H,
-    const int32_t* __restrict__ W, int n, const int64_t* __restrict__ ws, int64_t P_total, int B,
-    const float* __restrict__ pinvD, const int* __restrict__ dpix, float* __restrict__ xhat) {
-  extern __shared__ float lds[];
-  float* sA = lds;                                            // [RTB][KPD][64]
-  int* sPix = reinterpret_cast<int*>(sA + RTB * KPD * 64);    // [2*KPD]
-  for (int i = threadIdx.x; i < RTB * KPD * 64; i += blockDim.x) sA[i] = pinvD[i];
-  for (int i = threadIdx.x; i < 2 * KPD; i += blockDim.x) sPix[i] = dpix[i];
-  __syncthreads();
-  const int64_t* patch_start = ws;
-  const int64_t* tile_start = ws + n + 1;
-  const int64_t ntiles = tile_start[n];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 31, u = lane >> 5;
-  for (int64_t wt = int64_t(blockIdx.x) * kImgWaves + wave; wt < ntiles; wt += int64_t(gridDim.x) * kImgWaves) {
-    // keeps the operand reads from LDS inside the loop (hoisting them all out of it
-    // would need hundreds of registers)
-    asm volatile("" ::: "memory");
-    int lo = 0, hi = n - 1;                  // last image with tile_start <= wt
+// Wave tile wt -> (image, window row y, first window column x0) through the plan.
+struct ImgTile {
+  int img, w, wp, y, x0;
+};
+
+// from: an image index whose tile_start <= wt (the previous tile's), or -1 for a binary
+// search; tiles only move forward, so the walk from the previous image is usually short.
+template <int N>
+__device__ __forceinline__ ImgTile img_tile(const int64_t* __restrict__ tile_start, const int32_t* __restrict__ W,
+                                            int n, int64_t wt, int from) {
+  int lo = 0;                              // last image with tile_start <= wt
+  if (from < 0) {
+    int hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (tile_start[mid] <= wt) lo = mid;
       else hi = mid - 1;
     }
-    const int img = lo;
-    const int w = W[img];
-    const int wp = w - N + 1;
-    const int tpr = (wp + 31) >> 5;
-    const int local = int(wt - tile_start[img]);      // < H * tpr, fits in 32 bits
-    const int y = local / tpr;
-    const int x = (local - y * tpr) * 32 + col;
-    const bool valid = x < wp;
-    const float* base = pixels + img_offset[img] + int64_t(y) * w + (valid ? x : 0);
-    f32x16 acc[RTB];
+  } else {
+    lo = from;
+    while (lo + 1 < n && tile_start[lo + 1] <= wt) ++lo;
+  }
+  ImgTile r;
+  r.img = lo;
+  r.w = W[lo];
+  r.wp = r.w - N + 1;
+  const int tpr = (r.wp + 31) >> 5;
+  const int local = int(wt - tile_start[lo]);   // < H * tpr, fits in 32 bits
+  r.y = local / tpr;
+  r.x0 = (local - r.y * tpr) * 32;
+  return r;
+}
+
+// The same projection with the operand in registers: a block of NT waves takes TPB tiles of
+// 32 windows at a time (wave w computes hat coordinates 32w..32w+31 from its KPD operand
+// steps in registers, one accumulator per tile, so the tiles' MFMA chains interleave).  Each
+// tile's pixels, an N x (32 + N - 1) region of one image (zero past its right edge), are
+// staged in LDS, the next tiles' regions are loaded into registers while the current ones
+// are contracted, and the 32 x B results of a tile leave through an LDS staging tile as one
+// contiguous run of x_hat rows (consecutive windows are consecutive rows).
+template <int N, int KPD, int NT, int TPB>
+__global__ __launch_bounds__(64 * NT) void project_images_reg_kernel(
+    const float* __restrict__ pixels, const int64_t* __restrict__ img_offset, const int32_t* __restrict__ H,
+    const int32_t* __restrict__ W, int n, const int64_t* __restrict__ ws, int64_t P_total, int B,
+    const float* __restrict__ pinvI, const int* __restrict__ dpix, float* __restrict__ xhat) {
+  constexpr int NTH = 64 * NT, RW = 32 + N - 1, RSZ = N * RW, RPT = (RSZ + NTH - 1) / NTH;
+  __shared__ float region[TPB][RSZ];
+  __shared__ int sPix[2 * KPD];
+  __shared__ float stage[TPB][32 * 32 * NT];     // [32 windows][B] per tile, B <= 32 NT
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, col = lane & 31, u = lane >> 5;
+  float a[KPD];
 #pragma unroll
-    for (int t = 0; t < RTB; ++t)
+  for (int j = 0; j < KPD; ++j) a[j] = pinvI[(w * KPD + j) * 64 + lane];
+  // slots past the disk have zero operand rows: point them at disk pixel 0
+  for (int i = t; i < 2 * KPD; i += NTH) sPix[i] = dpix[i] >= 0 ? dpix[i] : dpix[0];
+  const int64_t* patch_start = ws;
+  const int64_t* tile_start = ws + n + 1;
+  const int64_t ntiles = tile_start[n];
+  // region element e of a tile: row e / RW, column e % RW (fixed per thread)
+  int er[RPT], ec[RPT];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
-#pragma unroll 8
+  for (int v = 0; v < RPT; ++v) {
+    const int e = t + NTH * v;
+    er[v] = e < RSZ ? e / RW : 0;
+    ec[v] = e < RSZ ? e - (e / RW) * RW : 0;
+  }
+  float nxt[TPB][RPT];
+  ImgTile cur[TPB];
+  bool has[TPB];
+  const int64_t stride = int64_t(gridDim.x) * TPB;
+  // decode tiles wt0 .. wt0 + TPB - 1 (those below ntiles) and load their regions
+  auto fetch = [&](int64_t wt0, bool first) {
+#pragma unroll
+    for (int k = 0; k < TPB; ++k) {
+      has[k] = wt0 + k < ntiles;
+      if (has[k]) {
+        cur[k] = img_tile<N>(tile_start, W, n, wt0 + k, first ? -1 : cur[k].img);
+        const float* img = pixels + img_offset[cur[k].img] + int64_t(cur[k].y) * cur[k].w + cur[k].x0;
+#pragma unroll
+        for (int v = 0; v < RPT; ++v)
+          nxt[k][v] = (t + NTH * v < RSZ && cur[k].x0 + ec[v] < cur[k].w) ? img[er[v] * cur[k].w + ec[v]] : 0.f;
+      }
+    }
+  };
+  int64_t wt0 = int64_t(blockIdx.x) * TPB;
+  if (wt0 < ntiles) fetch(wt0, true);
+  for (; wt0 < ntiles; wt0 += stride) {
+    __syncthreads();   // the previous tiles' region and staging reads are done
+#pragma unroll
+    for (int k = 0; k < TPB; ++k)
+#pragma unroll
+      for (int v = 0; v < RPT; ++v)
+        if (t + NTH * v < RSZ) region[k][t + NTH * v] = has[k] ? nxt[k][v] : 0.f;
+    __syncthreads();
+    ImgTile now[TPB];
+    bool nhas[TPB];
+#pragma unroll
+    for (int k = 0; k < TPB; ++k) {
+      now[k] = cur[k];
+      nhas[k] = has[k];
+    }
+    if (wt0 + stride < ntiles) fetch(wt0 + stride, false);
+    f32x16 acc[TPB];
+#pragma unroll
+    for (int k = 0; k < TPB; ++k)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[k][i] = 0.f;
+#pragma unroll
     for (int j = 0; j < KPD; ++j) {
       const int q = sPix[2 * j + u];
-      const float b = (valid && q >= 0) ? base[(q >> 8) * w + (q & 255)] : 0.f;
+      const int off = (q >> 8) * RW + (q & 255) + col;
 #pragma unroll
-      for (int t = 0; t < RTB; ++t) acc[t] = mfma32(sA[(t * KPD + j) * 64 + lane], b, acc[t]);
+      for (int k = 0; k < TPB; ++k) acc[k] = mfma32(a[j], region[k][off], acc[k]);
     }
-    const int64_t pidx = patch_start[img] + int64_t(y) * wp + x;
-    if (valid && pidx < P_total) {
-      float* dst = xhat + pidx * B;
 #pragma unroll
-      for (int t = 0; t < RTB; ++t)
+    for (int k = 0; k < TPB; ++k)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int c = 32 * t + 8 * (v / 4) + 4 * u + (v % 4);
-          if (c < B) dst[c] = acc[t][v];
-        }
+      for (int v = 0; v < 16; ++v) {
+        const int r = 32 * w + 8 * (v / 4) + 4 * u + (v % 4);
+        if (r < B) stage[k][col * B + r] = acc[k][v];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TPB; ++k) {
+      if (!nhas[k]) continue;
+      const int nv = now[k].wp - now[k].x0 < 32 ? now[k].wp - now[k].x0 : 32;   // valid windows
+      const int64_t p0 = patch_start[now[k].img] + int64_t(now[k].y) * now[k].wp + now[k].x0;
+      const int64_t np = p0 + nv <= P_total ? nv : (P_total > p0 ? P_total - p0 : 0);
+      float* dst = xhat + p0 * B;
+      for (int i = t; i < int(np) * B; i += NTH) dst[i] = stage[k][i];
     }
   }
 }
@@ -183,12 +255,6 @@ __global__ __launch_bounds__(256) void stamp_kernel(StampParams p) {
 
 size_t images_workspace_bytes(int n_images) { return sizeof(int64_t) * 2 * (size_t(n_images) + 1); }
 
-size_t project_images_lds_bytes(const DeviceTables& t) {
-  const int kpd = (t.n_pix + 1) / 2;
-  const int rtb = (t.B + 31) / 32 <= 2 ? 2 : 4;
-  return sizeof(float) * (size_t(rtb) * kpd * 64 + 2 * size_t(kpd));
-}
-
 int launch_project_images(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
                           const int32_t* H, const int32_t* W, int n, int64_t P_total, void* ws, float* xhat,
                           void* stream) {
@@ -198,7 +264,6 @@ int launch_project_images(const DeviceTables& t, const float* pixels, const int6
                      reinterpret_cast<int64_t*>(ws));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return int(e);
-  const size_t lds = project_images_lds_bytes(t);
   static int cus = -1;
   if (cus < 0) {
     int dev = 0;
@@ -206,27 +271,21 @@ int launch_project_images(const DeviceTables& t, const float* pixels, const int6
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
   }
-  auto go = [&](auto kern) -> int {
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e2 != hipSuccess) return int(e2);
-      attr = true;
-    }
+  // two 32-window tiles per block step, grid of one resident round
+  auto go_reg = [&](auto kern, int nt) -> int {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kImgWaves, lds) != hipSuccess ||
-        per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * nt, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
-    const int64_t max_tiles = (P_total + 31) / 32 + int64_t(n);   // upper bound on wave tiles
-    int64_t blocks = (max_tiles + kImgWaves - 1) / kImgWaves;
+    const int64_t max_tiles = (P_total + 31) / 32 + int64_t(n);   // upper bound on tiles
+    int64_t blocks = (max_tiles + 1) / 2;                          // two tiles per block step
     if (blocks > int64_t(cus) * per_cu) blocks = int64_t(cus) * per_cu;
-    hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * kImgWaves), lds, st, pixels, img_offset, H, W,
-                       n, reinterpret_cast<const int64_t*>(ws), P_total, t.B, t.pinvI, t.dpixI, xhat);
+    hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * nt), 0, st, pixels, img_offset, H, W, n,
+                       reinterpret_cast<const int64_t*>(ws), P_total, t.B, t.pinvI, t.dpixI, xhat);
     return int(hipGetLastError());
   };
-  if (t.N == 11 && t.n_pix == 97) return go(project_images_kernel<11, 49, 2>);
-  if (t.N == 15 && t.n_pix == 177) return go(project_images_kernel<15, 89, 4>);
+  if (t.N == 11 && t.n_pix == 97 && t.B <= 64) return go_reg(project_images_reg_kernel<11, 49, 2, 2>, 2);
+  if (t.N == 15 && t.n_pix == 177 && t.B > 64 && t.B <= 128)
+    return go_reg(project_images_reg_kernel<15, 89, 4, 2>, 4);
   return int(hipErrorInvalidValue);
 }
 
