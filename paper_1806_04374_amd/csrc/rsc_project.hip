@@ -3,7 +3,12 @@
 // an FP32 MFMA GEMM with rows = hat coordinates, columns = patches and the
 // contraction over disk pixels.
 //
-//  * project_tiled_kernel (N*N <= 128): one block of 8 waves per CU loops over
+//  * project_reg_kernel (11x11 with B <= 64, 15x15 with B in 97..128; 16-byte aligned
+//    patches): the operand in registers, one 32-row tile per wave, 32-patch chunks staged
+//    in LDS with the next one prefetched into registers, the partial last chunk in the
+//    same launch.
+//  * project_tiled_kernel (11x11 patches that are not 16-byte aligned): one block of 8
+//    waves per CU loops over
 //    tiles of 8 x 32 patches.  Each wave copies its 32 contiguous patches to its
 //    own LDS tile with 16-byte loads, the (Phi^T Phi)^{-1} Phi^T operand stays in
 //    LDS for the whole launch, and the results leave through the same tile as
@@ -19,8 +24,6 @@
 //    by a power of two that puts its largest value in [2^10, 2^11) (the operand is
 //    pre-scaled the same way on the host), keeping the remainders normal; the
 //    scales are exact and removed per column after the accumulation.
-//  * project_reg_kernel (15x15 patch arrays, B in 97..128): the operand in registers,
-//    one 32-row tile per wave, 32-patch chunks with the next one prefetched.
 //  * project_kernel (any size): blocks of 64 patches, operand read from global.
 #include <hip/hip_runtime.h>
 
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(64 * kProjWavesLp) void project_tiled_lp_kernel(
   }
 }
 
-// 15x15 patch arrays (N*N = NNC, B <= 32 NT): block of NT waves, wave w computes hat
+// Patch arrays (N*N = NNC, B <= 32 NT): block of NT waves, wave w computes hat
 // coordinates 32w..32w+31 and keeps its operand rows (KPD contraction steps over disk
 // pixels) in registers.  The block takes 32 patches at a time: the chunk is staged in LDS,
 // the next one is loaded into registers while the current one is contracted, and the
@@ -237,8 +240,8 @@ __global__ __launch_bounds__(64 * kProjWavesLp) void project_tiled_lp_kernel(
 constexpr int kProjRegPatches = 32;
 
 template <int NNC, int KPD, int NT>
-__global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __restrict__ patches, int64_t nchunk,
-                                                             int B, const float* __restrict__ pinvI,
+__global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __restrict__ patches, int64_t nfull,
+                                                             int tail, int B, const float* __restrict__ pinvI,
                                                              const int* __restrict__ pix, bool vec_out,
                                                              float* __restrict__ xhat) {
   typedef float v4f __attribute__((ext_vector_type(4)));
@@ -257,23 +260,33 @@ __global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __res
   int vi[VPT];
 #pragma unroll
   for (int v = 0; v < VPT; ++v) vi[v] = t + NTH * v < NV ? t + NTH * v : NV - 1;
-  // the launch has at most nchunk blocks, so every block starts on a chunk
+  // chunks 0..nfull-1 hold 32 patches, chunk nfull (if tail > 0) the last tail patches; the
+  // launch has at most nfull + (tail > 0) blocks, so every block starts on a chunk.  Whole
+  // chunks go through the 16-byte register prefetch, the partial one is staged directly.
+  const int64_t nchunk = nfull + (tail > 0 ? 1 : 0);
   v4f nxt[VPT];
   int64_t c = blockIdx.x;
-  {
-    const v4f* s4 = reinterpret_cast<const v4f*>(patches + c * kProjRegPatches * NNC);
+  if (nfull > 0) {
+    const int64_t c0 = c < nfull ? c : nfull - 1;
+    const v4f* s4 = reinterpret_cast<const v4f*>(patches + c0 * kProjRegPatches * NNC);
 #pragma unroll
     for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
   }
   const float* mine = tile + col * NNC;
-  const int nout = kProjRegPatches * B;
   for (; c < nchunk; c += gridDim.x) {
     __syncthreads();   // the previous chunk's reads of the tile and the staging tile are done
+    if (c < nfull) {
 #pragma unroll
-    for (int v = 0; v < VPT; ++v) tile4[t + NTH * v] = nxt[v];
+      for (int v = 0; v < VPT; ++v) tile4[t + NTH * v] = nxt[v];
+    } else {
+      const float* src = patches + c * kProjRegPatches * NNC;
+      float* tw = reinterpret_cast<float*>(tile4);
+      for (int i = t; i < kProjRegPatches * NNC; i += NTH) tw[i] = i < tail * NNC ? src[i] : 0.f;
+    }
     __syncthreads();
-    {
-      const int64_t cn = c + gridDim.x < nchunk ? c + gridDim.x : c;   // the last re-reads its own
+    if (nfull > 0) {
+      // the next whole chunk (otherwise the block's last whole one again, unused)
+      const int64_t nx = c + gridDim.x, cn = nx < nfull ? nx : (c < nfull ? c : nfull - 1);
       const v4f* s4 = reinterpret_cast<const v4f*>(patches + cn * kProjRegPatches * NNC);
 #pragma unroll
       for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
@@ -291,8 +304,9 @@ __global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __res
       if (r < B) stage[col * B + r] = acc[v];
     }
     __syncthreads();
-    float* dst = xhat + c * nout;
-    if (vec_out) {
+    const int nout = (c < nfull ? kProjRegPatches : tail) * B;
+    float* dst = xhat + c * kProjRegPatches * B;
+    if (vec_out && c < nfull) {
       const v4f* s4 = reinterpret_cast<const v4f*>(stage);
       for (int i = t; i < nout / 4; i += NTH) reinterpret_cast<v4f*>(dst)[i] = s4[i];
     } else {
@@ -392,7 +406,25 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
                        reinterpret_cast<const uint4*>(t.lpPinv), t.lpPix16, t.lpPinvUnscale, vin, vout, xhat);
     return int(hipGetLastError());
   }
-  // the tiled kernel is compiled for the 11x11, S = T = 5 geometry (B = 55)
+  // register-operand kernel (16-byte aligned patches): 11x11 with B <= 64 (2 row tiles) and
+  // 15x15 with B in 97..128 (4 row tiles); whole 32-patch chunks and the partial last one
+  const bool aligned = (reinterpret_cast<uintptr_t>(patches) & 15) == 0;
+  const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (kProjRegPatches * t.B) % 4 == 0;
+  auto go_reg = [&](auto kern, int nt) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * nt, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    const int64_t nfull = P / kProjRegPatches, tail = P - nfull * kProjRegPatches;
+    const int64_t work = nfull + (tail > 0), cap = int64_t(cus()) * per_cu;
+    hipLaunchKernelGGL(kern, dim3(unsigned(work < cap ? work : cap)), dim3(64 * nt), 0, st, patches, nfull,
+                       int(tail), t.B, t.pinvI, t.pixD, vout, xhat);
+    return int(hipGetLastError());
+  };
+  if (aligned && t.N == 11 && t.n_pix == 97 && t.B <= 64 && t.pinvI && t.pixD)
+    return go_reg(project_reg_kernel<121, 49, 2>, 2);
+  if (aligned && t.N == 15 && t.n_pix == 177 && t.B > 96 && t.B <= 128 && t.pinvI && t.pixD)
+    return go_reg(project_reg_kernel<225, 89, 4>, 4);
+  // unaligned 11x11 input (S = T = 5): the LDS-operand tiled kernel
   if (t.N == 11 && t.S == 5 && t.T == 5 && t.pinvD) {
     constexpr int kNN = 121, kKPD = 49;
     if ((t.n_pix + 1) / 2 != kKPD) return int(hipErrorInvalidValue);
@@ -404,32 +436,9 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
     const int64_t ntile = (P + 31) / 32;
     int64_t blocks = (ntile + kProjWaves - 1) / kProjWaves;
     if (blocks > cus()) blocks = cus();
-    const bool vin = (reinterpret_cast<uintptr_t>(patches) & 15) == 0;
-    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (t.B * 32) % 4 == 0;
     hipLaunchKernelGGL(kern, dim3(unsigned(blocks)), dim3(64 * kProjWaves), lds, st, patches, P, t.B,
-                       t.pinvD, t.pixD, vin, vout, xhat);
+                       t.pinvD, t.pixD, aligned, vout, xhat);
     return int(hipGetLastError());
-  }
-  // 15x15, B in 97..128 (4 row tiles), 16-byte aligned patches: whole 32-patch chunks by
-  // the register-operand kernel, the rest by the generic one
-  const int64_t nreg = (t.N == 15 && t.n_pix == 177 && t.B > 96 && t.B <= 128 && t.pinvI && t.pixD &&
-                        (reinterpret_cast<uintptr_t>(patches) & 15) == 0)
-                           ? P / kProjRegPatches : 0;
-  if (nreg > 0) {
-    auto kern = project_reg_kernel<225, 89, 4>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-    const int64_t cap = int64_t(cus()) * per_cu;
-    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (kProjRegPatches * t.B) % 4 == 0;
-    hipLaunchKernelGGL(kern, dim3(unsigned(nreg < cap ? nreg : cap)), dim3(256), 0, st, patches, nreg, t.B,
-                       t.pinvI, t.pixD, vout, xhat);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return int(e);
-    const int64_t done = nreg * kProjRegPatches;
-    if (done == P) return 0;
-    patches += done * NN;
-    xhat += done * t.B;
-    P -= done;
   }
   const int64_t blocks = (P + 63) / 64;
   const size_t lds = sizeof(float) * 64 * size_t(NN > t.B ? NN : t.B);

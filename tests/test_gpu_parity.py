@@ -297,13 +297,13 @@ def test_dictionary_reload_on_one_handle(dev, prec):
     h.close()
 
 
+@pytest.mark.parametrize("geom", [wl.GEOM11, wl.GEOM15])
 @pytest.mark.parametrize("P", [1, 31, 32, 33, 2000, 64 * 1024 + 7])
-def test_projection_15x15_patch_arrays(dev, P):
-    """15x15 patch arrays: whole 32-patch chunks by the register-operand MFMA kernel, the rest
-    by the generic kernel; also from a buffer that is not 16-byte aligned (generic kernel
-    only) and into an output that is not (scalar stores)."""
+def test_projection_patch_arrays(dev, geom, P):
+    """Patch arrays: whole 32-patch chunks and the partial last one by the register-operand
+    MFMA kernel; also from a buffer that is not 16-byte aligned (another kernel) and into an
+    output that is not (scalar stores)."""
     from paper_1806_04374_amd import rsc
-    geom = wl.GEOM15
     basis = orc.build_basis(geom.N, geom.S, geom.T)
     h = rsc.rsc_create(geom.N, geom.S, geom.T)
     X = np.random.default_rng(P).standard_normal((P, geom.N, geom.N)).astype(np.float32)
