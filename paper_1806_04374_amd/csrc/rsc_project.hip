@@ -13,7 +13,8 @@
 //    own LDS tile with 16-byte loads, the (Phi^T Phi)^{-1} Phi^T operand stays in
 //    LDS for the whole launch, and the results leave through the same tile as
 //    contiguous 16-byte stores; the waves need no block-wide barrier.
-//  * project_tiled_lp_kernel: the same tiling (6 waves per block) with 16-bit MFMA
+//  * project_reg_lp_kernel / project_tiled_lp_kernel (aligned / unaligned 11x11 input of
+//    16-bit handles): the layouts above (6 waves per block for the tiled one) with 16-bit MFMA
 //    operands (v_mfma_f32_32x32x16_{bf16,f16}, contraction over 16 disk pixels per
 //    step) in compensated form: the patch values and the operand are split into
 //    16-bit parts and the products down to FP32 order are accumulated in FP32 --
@@ -315,6 +316,130 @@ __global__ __launch_bounds__(64 * NT) void project_reg_kernel(const float* __res
   }
 }
 
+// The compensated 16-bit projection (as project_tiled_lp_kernel) with the structure of
+// project_reg_kernel: a block of two waves (one 32-row operand tile each, its NP 16-bit
+// parts in registers) takes 32 patches at a time from LDS, the next chunk is prefetched
+// into registers, the partial last chunk is staged element-wise, and the results leave
+// through an LDS staging tile.  Both waves gather and split the same patch values.
+template <int NNC, int KS, int PREC>
+__global__ __launch_bounds__(128) void project_reg_lp_kernel(const float* __restrict__ patches, int64_t nfull,
+                                                            int tail, int B, const uint4* __restrict__ pinvP,
+                                                            const int* __restrict__ pix16, float a_unscale,
+                                                            bool vec_out, float* __restrict__ xhat) {
+  using Pr = Lp<PREC>;
+  using V8 = typename Pr::V8;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NP = PREC == RSC_BF16 ? 3 : 2;
+  constexpr int NTH = 128, NV = kProjRegPatches * NNC / 4, VPT = (NV + NTH - 1) / NTH;
+  __shared__ v4f tile4[VPT * NTH];                   // [32][NNC] used; the rest takes clamped copies
+  __shared__ int sPix[16 * KS];
+  __shared__ float stage[kProjRegPatches * 64];      // [32 patches][B], B <= 64
+  const float* tile = reinterpret_cast<const float*>(tile4);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, col = lane & 31, u = lane >> 5;
+  uint4 a[NP][KS];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < KS; ++j) a[p][j] = pinvP[((p * 2 + w) * KS + j) * 64 + lane];
+  // slots past the disk have zero operand parts: point them at disk pixel 0, a pixel the
+  // patch's scale already covers, so the gathers need no condition
+  for (int i = t; i < 16 * KS; i += NTH) sPix[i] = pix16[i] >= 0 ? pix16[i] : pix16[0];
+  int vi[VPT];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) vi[v] = t + NTH * v < NV ? t + NTH * v : NV - 1;
+  const int64_t nchunk = nfull + (tail > 0 ? 1 : 0);
+  v4f nxt[VPT];
+  int64_t c = blockIdx.x;
+  if (nfull > 0) {
+    const int64_t c0 = c < nfull ? c : nfull - 1;
+    const v4f* s4 = reinterpret_cast<const v4f*>(patches + c0 * kProjRegPatches * NNC);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+  }
+  const float* mine = tile + col * NNC;
+  for (; c < nchunk; c += gridDim.x) {
+    __syncthreads();   // the previous chunk's reads of the tile and the staging tile are done
+    if (c < nfull) {
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) tile4[t + NTH * v] = nxt[v];
+    } else {
+      const float* src = patches + c * kProjRegPatches * NNC;
+      float* tw = reinterpret_cast<float*>(tile4);
+      for (int i = t; i < kProjRegPatches * NNC; i += NTH) tw[i] = i < tail * NNC ? src[i] : 0.f;
+    }
+    __syncthreads();
+    if (nfull > 0) {
+      const int64_t nx = c + gridDim.x, cn = nx < nfull ? nx : (c < nfull ? c : nfull - 1);
+      const v4f* s4 = reinterpret_cast<const v4f*>(patches + cn * kProjRegPatches * NNC);
+#pragma unroll
+      for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
+    }
+    float xs[KS][8];
+#pragma unroll
+    for (int j = 0; j < KS; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) xs[j][i] = mine[sPix[16 * j + 8 * u + i]];
+    float unscale = a_unscale;
+    if (NP == 2) {
+      // power-of-two scale of this patch (both half-waves of the column agree)
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(xs[j][i]));
+      m = max_halves(m);
+      int ex = 0;
+      (void)frexpf(m, &ex);                 // m in [2^(ex-1), 2^ex)
+      const int e = m > 0.f ? 11 - ex : 0;  // largest value in [2^10, 2^11)
+      const float sc = ldexpf(1.f, e);
+      unscale = ldexpf(a_unscale, -e);
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[j][i] *= sc;
+    }
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      if (NP == 3) {
+        V8 xh, xm, xl;
+        split8x3<Pr>(xs[j], xh, xm, xl);
+        const V8 a0 = __builtin_bit_cast(V8, a[0][j]), a1 = __builtin_bit_cast(V8, a[1][j]),
+                 a2 = __builtin_bit_cast(V8, a[NP - 1][j]);
+        acc = Pr::mfma(a0, xh, acc);
+        acc = Pr::mfma(a0, xm, acc);
+        acc = Pr::mfma(a1, xh, acc);
+        acc = Pr::mfma(a0, xl, acc);
+        acc = Pr::mfma(a2, xh, acc);
+        acc = Pr::mfma(a1, xm, acc);
+      } else {
+        V8 xh, xl;
+        split8<Pr>(xs[j], xh, xl);
+        const V8 a0 = __builtin_bit_cast(V8, a[0][j]), a1 = __builtin_bit_cast(V8, a[1][j]);
+        acc = Pr::mfma(a0, xh, acc);
+        acc = Pr::mfma(a0, xl, acc);
+        acc = Pr::mfma(a1, xh, acc);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = 32 * w + 8 * (v / 4) + 4 * u + (v % 4);
+      if (r < B) stage[col * B + r] = acc[v] * unscale;
+    }
+    __syncthreads();
+    const int nout = (c < nfull ? kProjRegPatches : tail) * B;
+    float* dst = xhat + c * kProjRegPatches * B;
+    if (vec_out && c < nfull) {
+      const v4f* s4 = reinterpret_cast<const v4f*>(stage);
+      for (int i = t; i < nout / 4; i += NTH) reinterpret_cast<v4f*>(dst)[i] = s4[i];
+    } else {
+      for (int i = t; i < nout; i += NTH) dst[i] = stage[i];
+    }
+  }
+}
+
 // Generic fallback: one block = 2 waves = 64 patches, operand from global memory.
 template <int RTB>
 __global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ patches, int64_t P, int NN,
@@ -388,6 +513,22 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
   if (P <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int NN = t.N * t.N;
+  if (t.prec != RSC_FP32 && t.N == 11 && t.S == 5 && t.T == 5 && t.lpPinv &&
+      (reinterpret_cast<uintptr_t>(patches) & 15) == 0) {
+    // 16-byte aligned patches: the register-operand form, whole chunks and the partial last one
+    constexpr int kNN = 121, kKS = 7;
+    if ((t.n_pix + 15) / 16 != kKS) return int(hipErrorInvalidValue);
+    auto kern = t.prec == RSC_BF16 ? project_reg_lp_kernel<kNN, kKS, RSC_BF16>
+                                   : project_reg_lp_kernel<kNN, kKS, RSC_FP16>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 128, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t nfull = P / kProjRegPatches, tail = P - nfull * kProjRegPatches;
+    const int64_t work = nfull + (tail > 0), cap = int64_t(cus()) * per_cu;
+    const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (kProjRegPatches * t.B) % 4 == 0;
+    hipLaunchKernelGGL(kern, dim3(unsigned(work < cap ? work : cap)), dim3(128), 0, st, patches, nfull, int(tail),
+                       t.B, reinterpret_cast<const uint4*>(t.lpPinv), t.lpPix16, t.lpPinvUnscale, vout, xhat);
+    return int(hipGetLastError());
+  }
   if (t.prec != RSC_FP32 && t.N == 11 && t.S == 5 && t.T == 5 && t.lpPinv) {
     constexpr int kNN = 121, kKS = 7;
     if ((t.n_pix + 15) / 16 != kKS) return int(hipErrorInvalidValue);
