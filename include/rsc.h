@@ -165,9 +165,12 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
  *          Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID)
  *   M      1 <= M <= 256 (BF16 / FP16 handles: M <= 128)
  *   R      1 <= R <= 128 (BF16 / FP16 handles: R <= 64)
- * Synchronous (the copy to the device completes before return).
+ * Synchronous: it first waits for the whole device (launches in flight on any stream
+ * may still read the previous tables, which are refilled in place when the new ones fit),
+ * and the copy to the device completes before return.
  * Errors: RSC_E_INVALID (arguments), RSC_E_UNSUPPORTED (sizes beyond the compiled
- * limits of the handle's precision, or tables beyond the 160 KiB LDS of a CU).
+ * limits of the handle's precision, tables beyond the 160 KiB LDS of a CU, or a handle
+ * of rsc_create_annular or of a geometry the pursuit is not compiled for).
  */
 rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
 
