@@ -903,8 +903,8 @@ def main():
                     help="copy: only a plain 1 GiB device copy, to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the coding path has no cross-GPU step, see the design notes for how it shards.",
+        print(f"bench.py: runs on one GPU (asked for --gpus {args.gpus}); the coding path has no "
+              "cross-GPU step: patches, images or requests shard over independent per-GPU processes.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -51,7 +51,7 @@ typedef enum {
   RSC_E_INVALID = -1,      /* bad argument: null pointer, size out of range, wrong state */
   RSC_E_NOMEM = -2,        /* the library could not allocate its own resident copies */
   RSC_E_DEVICE = -3,       /* a HIP call or kernel launch failed */
-  RSC_E_UNSUPPORTED = -4,  /* valid request that this build does not implement */
+  RSC_E_UNSUPPORTED = -4,  /* valid request that the library does not implement */
   RSC_E_NOT_READY = -5     /* the handle has no dictionary yet (rsc_set_dictionary) */
 } rsc_status;
 

@@ -20,7 +20,7 @@ Paper: McCann, Andrearczyk, Unser, Depeursinge, "Fast Rotational Sparse Coding"
   Sec. II-E  proposed algorithm: basis, hat coordinates, R-K-SVD with S_r in
            place of R_r, back to pixels with Phi.
 
-Readings where the paper is silent (each one is listed in the design notes):
+Readings where the paper is silent:
   * Grid axes: pixel (row i, col j) sits at x = j - c, y = c - i (y up),
     c = (N-1)/2; angles are atan2(y, x), counter-clockwise.
   * Disk: pixels with radius < N/2 (97 pixels at N = 11, as printed in III-A).

@@ -233,8 +233,8 @@ rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, 
   *out = nullptr;
   if (N < 3 || N > 31 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..31");
   if (S < 1 || T < 0) return fail(RSC_E_INVALID, "S must be >= 1 and T >= 0");
-  if (S * (2 * T + 1) > 128) return fail(RSC_E_UNSUPPORTED, "B = S(2T+1) must be <= 128 in this build");
-  if (T > 15) return fail(RSC_E_UNSUPPORTED, "T must be <= 15 in this build");
+  if (S * (2 * T + 1) > 128) return fail(RSC_E_UNSUPPORTED, "B = S(2T+1) must be <= 128");
+  if (T > 15) return fail(RSC_E_UNSUPPORTED, "T must be <= 15");
   if (prec != RSC_FP32 && prec != RSC_BF16 && prec != RSC_FP16) return fail(RSC_E_INVALID, "unknown precision");
   if (!rsc::encode_supported(S, T) && prec != RSC_FP32)
     return fail(RSC_E_UNSUPPORTED, "16-bit handles need (S, T) = (5, 5) or (7, 7)");
@@ -270,7 +270,7 @@ rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out) {
   if (b.B > 192 || b.T > 31) {
     delete h;
     return fail(RSC_E_UNSUPPORTED, "annular basis with B = " + std::to_string(b.B) + ", T = " +
-                                       std::to_string(b.T) + ": this build handles B <= 192 and T <= 31");
+                                       std::to_string(b.T) + ": the library handles B <= 192 and T <= 31");
   }
   h->annular = true;
   rsc_status st = init_tables(h, N, b.S, b.T, RSC_FP32);
@@ -505,7 +505,7 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   bool split = false;
   if (lp) {
     if (!rsc::encode_lp_supported(S, T, M, R))
-      return fail(RSC_E_UNSUPPORTED, "16-bit encoder: needs M <= 128 and R <= 64 in this build");
+      return fail(RSC_E_UNSUPPORTED, "16-bit encoder: needs M <= 128 and R <= 64");
     auto cvt = [&](float v) { return h->prec == RSC_BF16 ? to_bf16(v) : to_f16(v); };
     // stage 1: lane l gives row l % 32 = (atom 4(row/8) + row%4, Re/Im = (row/4)%2) and
     // contraction slots 8(l/32)..+7: the residual's harmonic-k block, Re parts (k = 0:
