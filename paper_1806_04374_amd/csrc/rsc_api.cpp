@@ -223,6 +223,49 @@ rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
 
 }  // namespace
 
+namespace {
+
+// Workspace of the dictionary update: partial covariances, per-chunk counts, the FP64
+// sum slot, then (for training) the new dictionary, usage and reset arrays.
+struct RkLayout {
+  size_t update = 0, dnew = 0, usage = 0, reset = 0, total = 0;
+};
+
+RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P, int K) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  RkLayout L;
+  L.update = al(rsc::rksvd_workspace_bytes(d, P, K));
+  L.dnew = L.update;
+  L.usage = L.dnew + al(sizeof(float) * size_t(d.M) * d.B);
+  L.reset = L.usage + al(sizeof(int32_t) * size_t(d.M));
+  L.total = L.reset + al(sizeof(int32_t) * size_t(d.M));
+  return L;
+}
+
+double* rk_sum_slot(const rsc::DeviceTables& d, int64_t P, int K, void* ws) {
+  // the last kSumSlots doubles of the update area
+  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + rsc::rksvd_workspace_bytes(d, P, K) -
+                                   rsc::kSumSlots * sizeof(double));
+}
+
+}  // namespace
+
+namespace {
+struct ClsLayout {
+  size_t atom, angle, coef, resid, total;
+};
+ClsLayout cls_layout(int64_t P, int K) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  ClsLayout L;
+  L.atom = 0;
+  L.angle = L.atom + al(sizeof(int32_t) * size_t(P) * K);
+  L.coef = L.angle + al(sizeof(int32_t) * size_t(P) * K);
+  L.resid = L.coef + al(sizeof(float) * size_t(P) * K);
+  L.total = L.resid + al(sizeof(float) * size_t(P));
+  return L;
+}
+}  // namespace
+
 extern "C" {
 
 const char* rsc_last_error(void) { return g_err.c_str(); }
@@ -814,32 +857,6 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
   return e ? device_fail(e, "stamp launch") : ok();
 }
 
-namespace {
-
-// Workspace of the dictionary update: partial covariances, per-chunk counts, the FP64
-// sum slot, then (for training) the new dictionary, usage and reset arrays.
-struct RkLayout {
-  size_t update = 0, dnew = 0, usage = 0, reset = 0, total = 0;
-};
-
-RkLayout rk_layout(const rsc::DeviceTables& d, int64_t P, int K) {
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  RkLayout L;
-  L.update = al(rsc::rksvd_workspace_bytes(d, P, K));
-  L.dnew = L.update;
-  L.usage = L.dnew + al(sizeof(float) * size_t(d.M) * d.B);
-  L.reset = L.usage + al(sizeof(int32_t) * size_t(d.M));
-  L.total = L.reset + al(sizeof(int32_t) * size_t(d.M));
-  return L;
-}
-
-double* rk_sum_slot(const rsc::DeviceTables& d, int64_t P, int K, void* ws) {
-  // the last kSumSlots doubles of the update area
-  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + rsc::rksvd_workspace_bytes(d, P, K) -
-                                   rsc::kSumSlots * sizeof(double));
-}
-
-}  // namespace
 
 rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, int K, size_t* bytes) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
@@ -924,21 +941,6 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   return ok();
 }
 
-namespace {
-struct ClsLayout {
-  size_t atom, angle, coef, resid, total;
-};
-ClsLayout cls_layout(int64_t P, int K) {
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  ClsLayout L;
-  L.atom = 0;
-  L.angle = L.atom + al(sizeof(int32_t) * size_t(P) * K);
-  L.coef = L.angle + al(sizeof(int32_t) * size_t(P) * K);
-  L.resid = L.coef + al(sizeof(float) * size_t(P) * K);
-  L.total = L.resid + al(sizeof(float) * size_t(P));
-  return L;
-}
-}  // namespace
 
 rsc_status rsc_classify_workspace_size(int64_t P, int K, size_t* bytes) {
   if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
