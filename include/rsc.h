@@ -219,9 +219,11 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
 
 /*
  * Projection onto the basis (Sec. II-E step 2): xhat_p = (Phi^T Phi)^{-1} Phi^T x_p.
- *   patches  device [P, N, N] float32 row-major; off-disk pixels ignored
+ *   patches  device [P, N, N] float32 row-major; off-disk pixels ignored (they must be
+ *            finite: a few kernels read one of them with a zero weight)
  *   P        number of patches, >= 0 (0 is a no-op)
  *   xhat     device [P, B] float32 row-major, written
+ * Asynchronous on stream.  16-byte aligned patches take the fastest kernels.
  */
 rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat,
                        void* stream);
@@ -460,16 +462,22 @@ rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches
 /*
  * Steering of hat coordinates (the diagonal S_theta of eq. (8) at any angle): harmonic k
  * of every patch multiplied by exp(-i k theta).
- *   xhat, out   device [P, B] float32 (may be the same buffer only if P == 0)
+ *   xhat, out   device [P, B] float32, distinct buffers (RSC_E_INVALID if equal)
  *   theta       device float32 [P] per-patch angles, or NULL to use theta0 for all
- * Needs the handle's basis only (no dictionary).
+ * Needs the handle's basis only (no dictionary); in the layout of the handle's basis (the
+ * full (S, T) grid, or the annular basis' harmonic-major blocks of rsc_create_annular).
+ * Asynchronous on stream.  Errors: RSC_E_INVALID (arguments, non-finite theta0),
+ * RSC_E_UNSUPPORTED (a harmonic above 31), RSC_E_DEVICE.
  */
 rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const float* theta, double theta0,
                      float* out, void* stream);
 
 /*
- * Phi x_hat on the N x N grid (zero off the disk), for any hat coordinates.
+ * Phi x_hat on the N x N grid (zero off the disk), for any hat coordinates (Sec. II-E
+ * step 4 without the dictionary).
  *   xhat    device [P, B] float32;  pixels  device [P, N, N] float32, written
+ * Asynchronous on stream.  Errors: RSC_E_INVALID (arguments), RSC_E_UNSUPPORTED (B > 192),
+ * RSC_E_DEVICE.
  */
 rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream);
 
