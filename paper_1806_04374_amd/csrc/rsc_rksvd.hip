@@ -330,18 +330,34 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   constexpr int U = 2;
   const int64_t stride = int64_t(gridDim.x) * G;
   const int lane = t % 64, jl = lane < K ? lane : 0;
-  for (int64_t p0 = int64_t(blockIdx.x) * G + g; p0 < prm.P; p0 += U * stride) {
+  // the next pass's codes and coordinates are loaded while this pass is computed (indices
+  // clamped to the last patch, so the loads need no branch)
+  int an[U], rn[U];
+  float cn[U], xn[U];
+  auto fetch = [&](int64_t q0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = q0 + u * stride < prm.P ? q0 + u * stride : prm.P - 1;
+      an[u] = prm.atom[p * K + jl];
+      rn[u] = prm.angle[p * K + jl];
+      cn[u] = prm.coef[p * K + jl];
+      xn[u] = prm.xhat[p * B + bc];
+    }
+  };
+  int64_t p0 = int64_t(blockIdx.x) * G + g;
+  if (p0 < prm.P) fetch(p0);
+  for (; p0 < prm.P; p0 += U * stride) {
     int av[U], rv[U];
     float cv[U];
     double r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t p = p0 + u * stride < prm.P ? p0 + u * stride : p0;
-      av[u] = prm.atom[p * K + jl];
-      rv[u] = prm.angle[p * K + jl];
-      cv[u] = prm.coef[p * K + jl];
-      r[u] = prm.xhat[p * B + bc];
+      av[u] = an[u];
+      rv[u] = rn[u];
+      cv[u] = cn[u];
+      r[u] = xn[u];
     }
+    fetch(p0 + U * stride);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
