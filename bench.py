@@ -80,6 +80,36 @@ def make_inputs(h, w, P, dev):
     return X
 
 
+def host_info() -> dict:
+    """CPU model and logical core count of the host the reference is timed on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count()}
+
+
+def oracle_rate_one_thread(run, X, target_s: float) -> dict:
+    """The reference's rate with its BLAS pools held to one thread, on a prefix of X sized
+    from a 64-patch pilot to take about target_s seconds."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        n0 = min(64, len(X))
+        t0 = time.perf_counter()
+        run(X[:n0].astype(np.float64))
+        dt0 = time.perf_counter() - t0
+        n = int(min(len(X), max(n0, n0 * target_s / max(dt0, 1e-3))))
+        t0 = time.perf_counter()
+        run(X[:n].astype(np.float64))
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "cores": 1, "sample": f"first {n} patches of the same sample ({dt:.1f} s)"}
+
+
 def cpu_baseline(h, w, D, target_s: float, dev):
     """Time the FP64 reference (as it stands) on a bounded sample of the workload."""
     import torch
@@ -107,6 +137,7 @@ def cpu_baseline(h, w, D, target_s: float, dev):
     _, code = orc.encode(basis, D, w["R"], X.astype(np.float64), w["K"])
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    one = oracle_rate_one_thread(lambda Xs: orc.encode(basis, D, w["R"], Xs, w["K"]), X, target_s=8.0)
     # device codes of the same sample: selection match and matched MSE
     xd = torch.from_numpy(X).to(dev)
     xh = rsc.rsc_project(h, xd)
@@ -123,6 +154,7 @@ def cpu_baseline(h, w, D, target_s: float, dev):
     return {
         "value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
         "sample": f"first {n} patches of the same workload (FP64 reference, {dt:.1f} s)",
+        "one_thread": one, "host": host_info(),
         "check": {"selection_match": float(match), "mse_device": mse_dev, "mse_oracle": mse_ref,
                   "mse_rel_diff": abs(mse_dev - mse_ref) / mse_ref},
     }
