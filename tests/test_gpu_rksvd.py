@@ -155,6 +155,19 @@ def test_update_over_many_chunks_matches_reference(dev):
     print("worst atom difference", _check_update(g, Dp, w["R"], w["K"], X, dev, repeat=True))
 
 
+@pytest.mark.parametrize("geom,M,R,K,P", [(wl.GEOM11, 16, 32, 2, 1), (wl.GEOM11, 16, 32, 2, 2),
+                                          (wl.GEOM11, 16, 32, 2, 5), (wl.GEOM15, 8, 64, 3, 3)])
+def test_update_tiny_inputs(dev, geom, M, R, K, P):
+    """A handful of patches: every bucket is shorter than one batch of pairs, and more
+    atoms go unused than there are patches to reset them to (the rest keep -1)."""
+    D = wl.draw_dictionary(M, geom.B, seed=41).astype(np.float32).astype(np.float64)
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    d = wl.draw_mixtures(P, geom.N, M, 2, 0.05, seed=41)
+    X = orc.project(basis, orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
+    X = X.astype(np.float32).astype(np.float64)
+    _check_update(geom, D, R, K, X, dev, repeat=True)
+
+
 def test_unused_atoms_are_reset_on_device(dev):
     """Atoms in harmonics that no patch contains are never selected and take the
     worst-coded patches, in index order."""
