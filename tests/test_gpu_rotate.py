@@ -192,3 +192,26 @@ def test_synthesis_chunks_and_alignment(dev, geom, P):
         ref_s = orc.to_pixels(basis, xh[idx].astype(np.float64))
         assert np.abs(rsc.rsc_synthesize_hat(h, x).cpu().numpy()[idx] - ref_s).max() < 1e-5 * np.abs(ref_s).max()
     h.close()
+
+
+def test_empty_and_negative_sizes(dev):
+    """P = 0 is a no-op that reads no pointer (null pointers are accepted); P < 0 and
+    a non-finite common angle are refused; the binding returns empty outputs."""
+    from paper_1806_04374_amd import rsc
+    L = rsc.lib()
+    h = rsc.rsc_create(11, 5, 5)
+    plan = rsc.RotationPlan(11, THETA)
+    assert L.rsc_rotate_interp(plan.ptr, None, 0, None, None) == rsc.RSC_OK
+    assert L.rsc_steer(h.ptr, None, 0, None, 0.3, None, None) == rsc.RSC_OK
+    assert L.rsc_synthesize_hat(h.ptr, None, 0, None, None) == rsc.RSC_OK
+    assert L.rsc_rotate_interp(plan.ptr, None, -1, None, None) == rsc.RSC_E_INVALID
+    assert L.rsc_steer(h.ptr, None, -1, None, 0.3, None, None) == rsc.RSC_E_INVALID
+    assert L.rsc_synthesize_hat(h.ptr, None, -1, None, None) == rsc.RSC_E_INVALID
+    assert L.rsc_steer(h.ptr, None, 0, None, float("nan"), None, None) == rsc.RSC_E_INVALID
+    e = torch.empty((0, 11, 11), dtype=torch.float32, device=dev)
+    assert rsc.rsc_rotate_interp(plan, e).shape == (0, 11, 11)
+    xe = torch.empty((0, h.B), dtype=torch.float32, device=dev)
+    assert rsc.rsc_steer(h, xe, THETA).shape == (0, h.B)
+    assert rsc.rsc_synthesize_hat(h, xe).shape == (0, 11, 11)
+    plan.close()
+    h.close()
