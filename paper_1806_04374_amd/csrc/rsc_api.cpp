@@ -1009,8 +1009,9 @@ rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, 
 
 struct rsc_rotation_plan {
   int N = 0, ntap = 0;
-  int32_t* src = nullptr;
+  int32_t* src = nullptr;   // [N*N][ntap] in lane order
   float* w = nullptr;
+  int32_t* pix = nullptr;   // output pixel of each lane
 };
 
 rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_plan** plan) {
@@ -1019,18 +1020,20 @@ rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_
   if (N < 3 || N > 25 || N % 2 == 0) return fail(RSC_E_INVALID, "N must be odd, 3..25");
   if (mode != 0 && mode != 1) return fail(RSC_E_INVALID, "mode must be 0 (nearest) or 1 (bicubic)");
   if (!std::isfinite(theta)) return fail(RSC_E_INVALID, "theta must be finite");
-  std::vector<int32_t> src;
+  std::vector<int32_t> src, pix;
   std::vector<float> w;
-  const int ntap = rsc::rotation_taps(N, theta, mode, src, w);
+  const int ntap = rsc::rotation_taps(N, theta, mode, src, w, pix);
   auto* p = new (std::nothrow) rsc_rotation_plan;
   if (!p) return fail(RSC_E_NOMEM, "plan allocation failed");
   p->N = N;
   p->ntap = ntap;
   rsc_status s = upload(p->src, src, "rotation taps");
   if (s == RSC_OK) s = upload(p->w, w, "rotation weights");
+  if (s == RSC_OK) s = upload(p->pix, pix, "rotation lane order");
   if (s != RSC_OK) {
     free_dev(p->src);
     free_dev(p->w);
+    free_dev(p->pix);
     delete p;
     return s;
   }
@@ -1042,6 +1045,7 @@ rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan) {
   if (!plan) return ok();
   free_dev(plan->src);
   free_dev(plan->w);
+  free_dev(plan->pix);
   delete plan;
   return ok();
 }
@@ -1053,7 +1057,7 @@ rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches
   if (P == 0) return ok();
   if (!patches || !out) return fail(RSC_E_INVALID, "null device pointer");
   if (patches == out) return fail(RSC_E_INVALID, "patches and out must be distinct");
-  int e = rsc::launch_rotate_taps(plan->N, plan->ntap, patches, P, plan->src, plan->w, out, stream);
+  int e = rsc::launch_rotate_taps(plan->N, plan->ntap, patches, P, plan->src, plan->w, plan->pix, out, stream);
   return e ? device_fail(e, "rotation launch") : ok();
 }
 

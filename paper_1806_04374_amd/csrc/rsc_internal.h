@@ -90,10 +90,11 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
                         const int32_t* angle, const float* coef, const float* resid2, void* ws,
                         float* d_new, int32_t* usage, int32_t* reset, void* stream);
 // Patch rotation (rsc_rotate.hip).
-int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std::vector<float>& w);
+int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std::vector<float>& w,
+                  std::vector<int32_t>& pix);
 size_t rotate_lds_bytes(int N, int ntap);
-int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w, float* out,
-                       void* stream);
+int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w,
+                       const int32_t* pix, float* out, void* stream);
 int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const float* theta, double theta0, float* out,
                  void* stream);
 int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float* out, void* stream);

@@ -16,6 +16,7 @@
 // (compiled geometries), synth_reg_kernel (N*N <= 256), synth_hat_kernel (larger).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <type_traits>
@@ -31,24 +32,27 @@ namespace {
 
 constexpr int kRotPatches = 32;   // patches per block pass in rotate_taps_kernel
 
-// The block's threads form 256 / G groups of G lanes; lane g of a group owns output
-// pixels g, g + G, ... (QPT of them) and keeps their taps in registers.  Each block stages
+// The block's threads form 256 / G groups of G lanes; lane g of a group owns the output
+// pixels pix[g], pix[g + G], ... (QPT of them; pix is the plan's lane order) and keeps
+// their taps in registers.  Each block stages
 // kRotPatches patches in LDS (coalesced, 16-byte loads where aligned), group h applies the
 // taps to patches h, h + 256 / G, ..., and writes them (coalesced).  G is the smallest of
 // 64, 128, 256 that covers N*N (256 for N*N > 256), so few lanes idle.
 template <int NTAP, int QPT, int G>
 __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restrict__ in, int64_t P, int NN,
                                                          const int32_t* __restrict__ src,
-                                                         const float* __restrict__ wgt, bool vec,
+                                                         const float* __restrict__ wgt,
+                                                         const int32_t* __restrict__ pix, bool vec,
                                                          float* __restrict__ out) {
   constexpr int NSUB = 256 / G;
   extern __shared__ float xs[];   // [kRotPatches][NN]
   const int t = threadIdx.x, g = t % G, sub = t / G;
   float w[QPT][NTAP];
-  int sidx[QPT][NTAP];
+  int sidx[QPT][NTAP], qo[QPT];
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
     const int q = g + G * j < NN ? g + G * j : 0;
+    qo[j] = pix[q];
 #pragma unroll
     for (int k = 0; k < NTAP; ++k) {
       w[j][k] = wgt[q * NTAP + k];
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restric
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < NTAP; ++k) acc += w[j][k] * x[sidx[j][k]];
-        out[(p0 + p) * NN + q] = acc;
+        out[(p0 + p) * NN + qo[j]] = acc;
       }
     }
   }
@@ -90,6 +94,7 @@ template <int NTAP, int NNC, int G>
 __global__ __launch_bounds__(256, 4) void rotate_taps_fixed_kernel(const float* __restrict__ in, int64_t nchunk,
                                                                const int32_t* __restrict__ src,
                                                                const float* __restrict__ wgt,
+                                                               const int32_t* __restrict__ pix,
                                                                float* __restrict__ out) {
   constexpr int NSUB = 256 / G, PPG = kRotPatches / NSUB;   // patches per lane group and chunk
   constexpr int NV = kRotPatches * NNC / 4, VPT = (NV + 255) / 256;
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(256, 4) void rotate_taps_fixed_kernel(const float* 
   const float* xs = reinterpret_cast<const float*>(xs4);
   const int t = threadIdx.x, g = t % G, sub = t / G;
   const bool own = g < NNC;
-  const int q = own ? g : 0;
+  const int q = own ? g : 0, qo = pix[q];
   float w[NTAP];
   const float* base[NTAP];
 #pragma unroll
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(256, 4) void rotate_taps_fixed_kernel(const float* 
       for (int v = 0; v < VPT; ++v) nxt[v] = s4[vi[v]];
     }
     if (own) {
-      float* o = out + c * kRotPatches * NNC + sub * NNC + g;
+      float* o = out + c * kRotPatches * NNC + sub * NNC + qo;
 #pragma unroll
       for (int i = 0; i < PPG; ++i) {
         float acc = 0.f;
@@ -563,10 +568,12 @@ double keys(double t) {
 
 }  // namespace
 
-int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std::vector<float>& w) {
+int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std::vector<float>& w,
+                  std::vector<int32_t>& pix) {
   const int NN = N * N, ntap = mode == 0 ? 1 : 16;
   src.assign(size_t(NN) * ntap, 0);
   w.assign(size_t(NN) * ntap, 0.f);
+  std::vector<int64_t> key(NN);
   const double c = (N - 1) / 2.0, cs = std::cos(theta), sn = std::sin(theta);
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) {
@@ -574,6 +581,7 @@ int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std:
       const double xs = cs * x + sn * y, ys = -sn * x + cs * y;   // R_{-theta} (x, y)
       const double col = c + xs, row = c - ys;
       const int q = i * N + j;
+      key[q] = int64_t(std::floor(row)) * N + int64_t(std::floor(col));
       if (mode == 0) {
         const int r0 = int(std::floor(row + 0.5)), c0 = int(std::floor(col + 0.5));
         if (r0 >= 0 && r0 < N && c0 >= 0 && c0 < N) {
@@ -592,6 +600,26 @@ int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std:
           }
       }
     }
+  // Lane order.  Bicubic with N*N <= 128 (lane groups of 64 or 128): output pixels sorted
+  // by the input position they read (row-major), so that neighbouring lanes gather from
+  // neighbouring LDS words and a wave's 16 gathers per pixel spread over the banks instead
+  // of striding across the patch (at 11x11 this takes the kernel from bank-conflict bound
+  // to about 0.6 of its time).  Elsewhere the natural order: with one tap, or with 256-lane
+  // groups, the scattered stores of a sorted order cost more than the conflicts they save.
+  // pix[g] is the output pixel of lane g; the tap rows are stored in lane order.
+  pix.resize(NN);
+  for (int q = 0; q < NN; ++q) pix[q] = q;
+  if (mode == 1 && NN <= 128)
+    std::stable_sort(pix.begin(), pix.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  std::vector<int32_t> src2(src.size());
+  std::vector<float> w2(w.size());
+  for (int g = 0; g < NN; ++g)
+    for (int k = 0; k < ntap; ++k) {
+      src2[size_t(g) * ntap + k] = src[size_t(pix[g]) * ntap + k];
+      w2[size_t(g) * ntap + k] = w[size_t(pix[g]) * ntap + k];
+    }
+  src.swap(src2);
+  w.swap(w2);
   return ntap;
 }
 
@@ -600,8 +628,8 @@ size_t rotate_lds_bytes(int N, int ntap) {
   return sizeof(float) * size_t(kRotPatches) * N * N;
 }
 
-int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w, float* out,
-                       void* stream) {
+int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w,
+                       const int32_t* pix, float* out, void* stream) {
   const int NN = N * N;
   const int64_t cap = int64_t(num_cus()) * 8;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -616,7 +644,7 @@ int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_
     auto fixed = [&](auto kern) {
       const int64_t blocks = resident_blocks(kern);
       hipLaunchKernelGGL(kern, dim3(unsigned(nfull < blocks ? nfull : blocks)), dim3(256), 0, st, in, nfull, src,
-                         w, out);
+                         w, pix, out);
       return hipGetLastError();
     };
     hipError_t e;
@@ -635,7 +663,7 @@ int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(lds));
     if (e != hipSuccess) return int(e);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, vec, out);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, in, P, NN, src, w, pix, vec, out);
     return int(hipGetLastError());
   };
   if (ntap == 1) {
