@@ -34,10 +34,10 @@ constexpr int kRotPatches = 32;   // patches per block pass in rotate_taps_kerne
 
 // The block's threads form 256 / G groups of G lanes; lane g of a group owns the output
 // pixels pix[g], pix[g + G], ... (QPT of them; pix is the plan's lane order) and keeps
-// their taps in registers.  Each block stages
-// kRotPatches patches in LDS (coalesced, 16-byte loads where aligned), group h applies the
-// taps to patches h, h + 256 / G, ..., and writes them (coalesced).  G is the smallest of
-// 64, 128, 256 that covers N*N (256 for N*N > 256), so few lanes idle.
+// their taps in registers.  Each block stages kRotPatches patches in LDS (coalesced,
+// 16-byte loads where aligned), group h applies the taps to patches h, h + 256 / G, ...,
+// and writes them (a wave's stores stay within one patch).  G is the smallest of 64, 128,
+// 256 that covers N*N (256 for N*N > 256), so few lanes idle.
 template <int NTAP, int QPT, int G>
 __global__ __launch_bounds__(256) void rotate_taps_kernel(const float* __restrict__ in, int64_t P, int NN,
                                                          const int32_t* __restrict__ src,
