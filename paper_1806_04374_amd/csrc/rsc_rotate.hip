@@ -604,8 +604,9 @@ int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std:
   // by the input position they read (row-major), so that neighbouring lanes gather from
   // neighbouring LDS words and a wave's 16 gathers per pixel spread over the banks instead
   // of striding across the patch (at 11x11 this takes the kernel from bank-conflict bound
-  // to about 0.6 of its time).  Elsewhere the natural order: with one tap, or with 256-lane
-  // groups, the scattered stores of a sorted order cost more than the conflicts they save.
+  // to about 0.6 of its time).  Elsewhere the natural order, which measured faster: with one
+  // tap there are few gathers to spread, and with 256-lane groups (15x15) the sorted order
+  // was slower even with its stores staged through LDS.
   // pix[g] is the output pixel of lane g; the tap rows are stored in lane order.
   pix.resize(NN);
   for (int q = 0; q < NN; ++q) pix[q] = q;
