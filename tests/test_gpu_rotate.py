@@ -42,11 +42,15 @@ def test_interp_matches_reference(dev, mode, N, P):
         plan.close()
 
 
-def test_interp_quarter_turn_exact(dev):
+@pytest.mark.parametrize("N", [5, 11, 15])
+def test_interp_quarter_turn_exact(dev, N):
+    """A quarter turn is np.rot90 for both modes: at 5x5 and 11x11 bicubic runs in the
+    plan's sorted lane order (through the general and the fixed kernel), at 15x15 in the
+    natural one; 64 + 7 patches cover whole chunks and a partial one."""
     from paper_1806_04374_amd import rsc
-    X = np.random.default_rng(1).standard_normal((64, 15, 15)).astype(np.float32)
+    X = np.random.default_rng(1).standard_normal((71, N, N)).astype(np.float32)
     for mode in ("nearest", "bicubic"):
-        plan = rsc.RotationPlan(15, np.pi / 2, mode)
+        plan = rsc.RotationPlan(N, np.pi / 2, mode)
         out = rsc.rsc_rotate_interp(plan, torch.from_numpy(X).to(dev)).cpu().numpy()
         assert np.allclose(out, np.rot90(X, 1, axes=(1, 2)), atol=1e-6)
         plan.close()
