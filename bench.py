@@ -39,6 +39,7 @@ DTYPE = {"fp32": "f32", "bf16": "bf16 (FP32 accumulation, FP32 re-score)",
 TRAFFIC = {
     "scale-fp32": {"read": 227.0e6, "write": 54.1e6},      # algorithmic 220.0e6 / 52.0e6
     "ragged-images": {"read": 12.81e9, "write": 2.22e9},   # algorithmic 12.21e9 / 2.21e9
+    "rotate-steer-11": {"read": 880.1e6, "write": 880.0e6},  # algorithmic 880e6 / 880e6 (4M x 55 x 4 B)
 }
 
 
@@ -815,7 +816,7 @@ def run_rotate(args, dev):
                                "low-pass form, full steering rotation"},
         "results": results,
         "roofline": {"kernel": "steer_stream_kernel", "bound": "hbm", "achieved": main["steer_GBps"], "peak": 8000.0,
-                     "unit": "GB/s", "frac": main["steer_GBps"] / 8000.0, "traffic": None,
+                     "unit": "GB/s", "frac": main["steer_GBps"] / 8000.0, "traffic": traffic("rotate-steer-11"),
                      "algorithmic_bytes_per_launch": bytes_steer},
         "cpu_baseline": None,
     }
