@@ -758,6 +758,8 @@ def run_rotate(args, dev):
         ha = rsc.rsc_create_annular(N)            # the paper's annular basis and its low-pass form
         hal = rsc.rsc_create_annular(N, lowpass=True)
         plans = {m: rsc.RotationPlan(N, theta, m) for m in ("nearest", "bicubic")}
+        if N == 11:   # Phi S_theta Phi^+ as one operator on the matrix cores
+            plans["steer_one_pass"] = rsc.RotationPlan.steer(h, theta)
         for P in (50_000, 4_000_000):
             rng = torch.Generator(device=dev)
             rng.manual_seed(P + N)

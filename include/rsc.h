@@ -450,6 +450,21 @@ rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, 
  */
 rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_plan** plan);
 
+/*
+ * Rotation of 11x11 pixel patches through the steerable basis in one pass (eq. (6)-(8):
+ * project onto the handle's basis, steer by theta, synthesize).  The plan holds
+ * Phi S_theta Phi^+ as one 121 x 97 operator from the disk pixels to the grid (zero off the
+ * disk, built in FP64 on the host, applied in FP32 on the matrix cores by rsc_rotate_interp);
+ * the result equals rsc_project, rsc_steer and rsc_synthesize_hat in turn up to rounding.
+ *   h      a handle of rsc_create with N = 11 (only its basis is used; it may be destroyed
+ *          after this call)
+ *   plan   written; release with rsc_rotation_plan_destroy
+ * rsc_rotate_interp with such a plan needs 16-byte aligned patches (RSC_E_INVALID otherwise).
+ * Errors: RSC_E_INVALID (arguments, non-finite theta), RSC_E_UNSUPPORTED (N != 11 or the
+ * annular basis), RSC_E_NOMEM, RSC_E_DEVICE.
+ */
+rsc_status rsc_rotation_plan_create_steer(const rsc_handle* h, double theta, rsc_rotation_plan** plan);
+
 /* Releases a plan's device tables (NULL is a no-op). */
 rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan);
 

@@ -1012,6 +1012,8 @@ struct rsc_rotation_plan {
   int32_t* src = nullptr;   // [N*N][ntap] in lane order
   float* w = nullptr;
   int32_t* pix = nullptr;   // output pixel of each lane
+  float* op = nullptr;      // steering plans: Phi S_theta Phi^+ as 4 row tiles x 49 x 64 operands
+  int* opPix = nullptr;     // its contraction order (disk pixels, -1 past the disk)
 };
 
 rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_plan** plan) {
@@ -1041,11 +1043,67 @@ rsc_status rsc_rotation_plan_create(int N, double theta, int mode, rsc_rotation_
   return ok();
 }
 
+rsc_status rsc_rotation_plan_create_steer(const rsc_handle* h, double theta, rsc_rotation_plan** plan) {
+  if (!plan) return fail(RSC_E_INVALID, "plan is NULL");
+  *plan = nullptr;
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!std::isfinite(theta)) return fail(RSC_E_INVALID, "theta must be finite");
+  const rsc::HostBasis& b = h->basis;
+  if (h->annular || b.N != 11 || b.n_pix != 97)
+    return fail(RSC_E_UNSUPPORTED, "steering plans are compiled for 11x11 handles of rsc_create");
+  const int NN = b.N * b.N, S = b.S, T = b.T, B = b.B, KPD = 49;
+  // column i of the operator: Phi (S_theta (column pix[i] of Phi^+)); harmonic k >= 1 of the
+  // packed coordinates (Re block, then Im block, S profiles each) turns by k theta
+  std::vector<double> M(size_t(NN) * b.n_pix, 0.0), v(B), sv(B);
+  for (int i = 0; i < b.n_pix; ++i) {
+    for (int c = 0; c < B; ++c) v[c] = b.pinv[size_t(c) * NN + b.pix[i]];
+    for (int c = 0; c < S; ++c) sv[c] = v[c];
+    for (int k = 1; k <= T; ++k) {
+      const double ck = std::cos(k * theta), sk = std::sin(k * theta);
+      for (int s = 0; s < S; ++s) {
+        const int re = S + 2 * S * (k - 1) + s, im = re + S;
+        sv[re] = v[re] * ck + v[im] * sk;
+        sv[im] = v[im] * ck - v[re] * sk;
+      }
+    }
+    for (int q = 0; q < NN; ++q) {
+      double acc = 0.0;
+      for (int c = 0; c < B; ++c) acc += b.phi[size_t(q) * B + c] * sv[c];
+      M[size_t(q) * b.n_pix + i] = acc;
+    }
+  }
+  std::vector<float> op(size_t(4) * KPD * 64, 0.f);
+  for (int t = 0; t < 4; ++t)
+    for (int j = 0; j < KPD; ++j)
+      for (int l = 0; l < 64; ++l) {
+        const int row = 32 * t + (l % 32), i = 2 * j + l / 32;
+        if (row < NN && i < b.n_pix) op[(size_t(t) * KPD + j) * 64 + l] = float(M[size_t(row) * b.n_pix + i]);
+      }
+  std::vector<int> opPix(size_t(2) * KPD, -1);
+  for (int i = 0; i < b.n_pix; ++i) opPix[i] = b.pix[i];
+  auto* p = new (std::nothrow) rsc_rotation_plan;
+  if (!p) return fail(RSC_E_NOMEM, "plan allocation failed");
+  p->N = b.N;
+  p->ntap = 0;
+  rsc_status st = upload(p->op, op, "steering operator");
+  if (st == RSC_OK) st = upload(p->opPix, opPix, "steering operator pixels");
+  if (st != RSC_OK) {
+    free_dev(p->op);
+    free_dev(p->opPix);
+    delete p;
+    return st;
+  }
+  *plan = p;
+  return ok();
+}
+
 rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan) {
   if (!plan) return ok();
   free_dev(plan->src);
   free_dev(plan->w);
   free_dev(plan->pix);
+  free_dev(plan->op);
+  free_dev(plan->opPix);
   delete plan;
   return ok();
 }
@@ -1057,6 +1115,12 @@ rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches
   if (P == 0) return ok();
   if (!patches || !out) return fail(RSC_E_INVALID, "null device pointer");
   if (patches == out) return fail(RSC_E_INVALID, "patches and out must be distinct");
+  if (plan->op) {
+    if ((reinterpret_cast<uintptr_t>(patches) & 15) != 0)
+      return fail(RSC_E_INVALID, "steering plans need 16-byte aligned patches");
+    const int e = rsc::launch_rotate_operator(plan->op, plan->opPix, patches, P, out, stream);
+    return e ? device_fail(e, "rotation launch") : ok();
+  }
   int e = rsc::launch_rotate_taps(plan->N, plan->ntap, patches, P, plan->src, plan->w, plan->pix, out, stream);
   return e ? device_fail(e, "rotation launch") : ok();
 }

@@ -95,6 +95,8 @@ int rotation_taps(int N, double theta, int mode, std::vector<int32_t>& src, std:
 size_t rotate_lds_bytes(int N, int ntap);
 int launch_rotate_taps(int N, int ntap, const float* in, int64_t P, const int32_t* src, const float* w,
                        const int32_t* pix, float* out, void* stream);
+int launch_rotate_operator(const float* op, const int* pix, const float* patches, int64_t P, float* out,
+                           void* stream);
 int launch_steer(const DeviceTables& t, const float* xhat, int64_t P, const float* theta, double theta0, float* out,
                  void* stream);
 int launch_synth_hat(const DeviceTables& t, const float* xhat, int64_t P, float* out, void* stream);

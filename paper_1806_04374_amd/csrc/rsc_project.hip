@@ -598,4 +598,23 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
   return int(hipGetLastError());
 }
 
+
+// Rotation of 11x11 patches by a fixed operator from the 97 disk pixels to the 121 grid
+// pixels (Phi S_theta Phi^+, built by the plan): the register-operand projection kernel
+// with 121 output rows in four 32-row tiles.  16-byte aligned patches only.
+int launch_rotate_operator(const float* op, const int* pix, const float* patches, int64_t P, float* out,
+                           void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if ((reinterpret_cast<uintptr_t>(patches) & 15) != 0) return int(hipErrorInvalidValue);
+  auto kern = project_reg_kernel<121, 49, 4>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t nfull = P / kProjRegPatches, tail = P - nfull * kProjRegPatches;
+  const int64_t work = nfull + (tail > 0), cap = int64_t(cus()) * per_cu;
+  const bool vout = (reinterpret_cast<uintptr_t>(out) & 15) == 0;   // 32 x 121 floats per chunk: whole float4s
+  hipLaunchKernelGGL(kern, dim3(unsigned(work < cap ? work : cap)), dim3(256), 0, st, patches, nfull, int(tail), 121,
+                     op, pix, vout, out);
+  return int(hipGetLastError());
+}
+
 }  // namespace rsc

@@ -71,6 +71,7 @@ def lib():
         "rsc_label_histogram": [P, I64, P, I, I, P, P],
         "rsc_chi2_nearest": [P, I, P, I, I, P, P, P],
         "rsc_rotation_plan_create": [I, ctypes.c_double, I, P],
+        "rsc_rotation_plan_create_steer": [P, ctypes.c_double, P],
         "rsc_rotation_plan_destroy": [P],
         "rsc_rotate_interp": [P, P, I64, P, P],
         "rsc_steer": [P, P, I64, P, ctypes.c_double, P, P],
@@ -519,13 +520,23 @@ def rsc_chi2_nearest(train, test, stream=None):
 
 # ------------------------------------------------------------------ patch rotation
 class RotationPlan:
-    """Interpolated rotation of N x N patches by theta (mode "nearest" or "bicubic")."""
+    """Rotation of N x N patches by theta: interpolated (mode "nearest" or "bicubic"), or
+    through a handle's steerable basis in one pass (RotationPlan.steer, 11x11)."""
 
     def __init__(self, N: int, theta: float, mode: str = "bicubic"):
         m = {"nearest": 0, "bicubic": 1}[mode]
         ptr = ctypes.c_void_p()
         _check(lib().rsc_rotation_plan_create(int(N), float(theta), m, ctypes.byref(ptr)))
         self.ptr, self.N, self.theta, self.mode = ptr, int(N), float(theta), mode
+
+    @classmethod
+    def steer(cls, h: "Handle", theta: float) -> "RotationPlan":
+        """Phi S_theta Phi^+ of the handle's basis as one operator (rsc_rotation_plan_create_steer)."""
+        ptr = ctypes.c_void_p()
+        _check(lib().rsc_rotation_plan_create_steer(h.ptr, float(theta), ctypes.byref(ptr)))
+        plan = cls.__new__(cls)
+        plan.ptr, plan.N, plan.theta, plan.mode = ptr, h.N, float(theta), "steer"
+        return plan
 
     def close(self):
         if self.ptr:

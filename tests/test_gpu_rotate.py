@@ -235,3 +235,52 @@ def test_interp_unaligned_output(dev, N):
     ref = orc.rotate_interp(X.astype(np.float64), THETA, "bicubic")
     assert np.abs(o[1:].view(P, N, N).cpu().numpy() - ref).max() < 1e-5 * np.abs(X).max()
     plan.close()
+
+
+@pytest.mark.parametrize("P", [1, 31, 32, 33, 777, 32 * 2100 + 7])
+def test_steer_plan_one_pass(dev, P):
+    """The one-pass steering plan (Phi S_theta Phi^+ as one operator) against the reference's
+    projection, steering and synthesis, and against the device's three calls; whole 32-patch
+    chunks, the partial last one, and an output not 16-byte aligned."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    h = rsc.rsc_create(g.N, g.S, g.T)
+    plan = rsc.RotationPlan.steer(h, THETA)
+    X = np.random.default_rng(P + 3).standard_normal((P, g.N, g.N)).astype(np.float32)
+    x = torch.from_numpy(X).to(dev)
+    out = rsc.rsc_rotate_interp(plan, x).cpu().numpy()
+    n = min(P, 2000)
+    ref = orc.rotate_steer(basis, X[:n].astype(np.float64), THETA)
+    assert np.abs(out[:n] - ref).max() < 1e-4 * np.abs(ref).max()
+    three = rsc.rsc_synthesize_hat(h, rsc.rsc_steer(h, rsc.rsc_project(h, x), THETA)).cpu().numpy()
+    assert np.abs(out - three).max() < 2e-5 * np.abs(three).max()
+    o = torch.zeros(P * g.N * g.N + 1, dtype=torch.float32, device=dev)
+    rsc.rsc_rotate_interp(plan, x, o[1:].view(P, g.N, g.N))
+    assert np.array_equal(o[1:].view(P, g.N, g.N).cpu().numpy(), out)
+    plan.close()
+    h.close()
+
+
+def test_steer_plan_refusals(dev):
+    """Steering plans: 11x11 handles of rsc_create only, finite angles, aligned patches."""
+    from paper_1806_04374_amd import rsc
+    h15 = rsc.rsc_create(15, 7, 7)
+    with pytest.raises(rsc.RscError) as e:
+        rsc.RotationPlan.steer(h15, THETA)
+    assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    ha = rsc.rsc_create_annular(11)
+    with pytest.raises(rsc.RscError) as e:
+        rsc.RotationPlan.steer(ha, THETA)
+    assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    h = rsc.rsc_create(11, 5, 5)
+    with pytest.raises(rsc.RscError, match="finite"):
+        rsc.RotationPlan.steer(h, float("inf"))
+    plan = rsc.RotationPlan.steer(h, THETA)
+    flat = torch.zeros(10 * 121 + 1, dtype=torch.float32, device=dev)
+    with pytest.raises(rsc.RscError, match="aligned"):
+        rsc.rsc_rotate_interp(plan, flat[1:].view(10, 11, 11))
+    plan.close()
+    h.close()
+    ha.close()
+    h15.close()
