@@ -469,7 +469,10 @@ rsc_status rsc_rotation_plan_create_steer(const rsc_handle* h, double theta, rsc
 rsc_status rsc_rotation_plan_destroy(rsc_rotation_plan* plan);
 
 /*
- * R x for every patch: patches and out device float32 [P, N, N] (distinct buffers).
+ * R x for every patch: patches and out device float32 [P, N, N] (distinct buffers); R is the
+ * plan's interpolation matrix, or Phi S_theta Phi^+ for a plan of
+ * rsc_rotation_plan_create_steer (whose patches must be 16-byte aligned).  P = 0 is a no-op.
+ * Asynchronous on stream.  Errors: RSC_E_INVALID (arguments, alignment), RSC_E_DEVICE.
  */
 rsc_status rsc_rotate_interp(const rsc_rotation_plan* plan, const float* patches, int64_t P, float* out,
                              void* stream);
