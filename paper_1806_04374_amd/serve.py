@@ -5,7 +5,8 @@ Requests carry one image each.  Every window of an image is a patch to code
 
 * admits requests in arrival order while their pixels fit the HBM budget (an arena
   preallocated once; step buffers are preallocated too, so nothing is allocated on
-  the device per request or per step),
+  the device per request or per step); requests that can never fit the budget, or
+  whose window row is wider than a step, are rejected,
 * cuts admitted images into row ranges ("chunks") and fills each device step with
   up to ``step_windows`` windows: every ready request first gets an equal share of
   the step, the rest goes to the oldest ones, so requests that arrive while others
@@ -40,6 +41,7 @@ class Request:
     windows: int = 0
     done_rows: int = 0             # window rows handed to steps
     coded_rows: int = 0            # window rows whose codes reached the host
+    served_step: int = -1          # last step that coded rows of it (admission step at first)
     t_admit: float | None = None
     t_done: float | None = None
     slot: object = None            # backend memory handle
@@ -149,23 +151,28 @@ class Scheduler:
             while self.queue:
                 req = self.queue[0]
                 need = self.be.request_elems(req)
-                if need > self.arena.capacity:
+                row = req.W - self.be.N + 1
+                if need > self.arena.capacity or (req.windows > 0 and row > self.step_windows):
                     self.queue.popleft()
-                    self.rejected.append(req)          # can never fit the budget
+                    self.rejected.append(req)          # can never fit the budget or one step
                     continue
                 block = self.arena.alloc(need)
                 if block is None:
                     break                              # wait for memory (arrival order kept)
                 self.queue.popleft()
                 req.slot = block
+                req.served_step = self.steps
                 req.t_admit = self.now()
                 self.be.upload(req, block)
                 self.active.append(req)
         self.max_active = max(self.max_active, len(self.active))
 
     def _next_chunks(self) -> list[Chunk]:
-        """Fill one step: every ready request first gets an equal share of the step
-        (at least one window row), then the rest goes to the oldest requests."""
+        """Fill one step of at most ``step_windows`` windows: every ready request first
+        gets an equal share of the step (at least one window row while a row still fits),
+        then the rest goes to the oldest requests.  Shares are handed out longest-unserved
+        first; admission rejects images whose window row is wider than a step, so the first
+        of them always gets a row and no request waits behind others for ever."""
         n = self.be.N
         ready = []
         for req in self.active:                        # oldest first
@@ -177,14 +184,16 @@ class Scheduler:
         budget = self.step_windows
         share = max(budget // len(ready), 1)
         take = {}
-        for req in ready:
+        age = {req.rid: i for i, req in enumerate(ready)}
+        for req in sorted(ready, key=lambda r: (r.served_step, age[r.rid])):
             if budget <= 0:
                 break
             wc = req.W - n + 1
             left = req.H - n + 1 - req.done_rows
-            rows = min(left, max(min(share, budget) // wc, 1))
-            take[req.rid] = rows
-            budget -= rows * wc
+            rows = min(left, max(min(share, budget) // wc, 1 if wc <= budget else 0))
+            if rows > 0:
+                take[req.rid] = rows
+                budget -= rows * wc
         for req in ready:
             if budget <= 0:
                 break
@@ -201,6 +210,7 @@ class Scheduler:
                 wc = req.W - n + 1
                 chunks.append(Chunk(req, req.done_rows, rows, req.done_rows * wc))
                 req.done_rows += rows
+                req.served_step = self.steps
         return chunks
 
     def _retire(self, chunks: list[Chunk]):

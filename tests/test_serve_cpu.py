@@ -10,8 +10,9 @@ class FakeBackend(serve.Backend):
     """Codes a window by a deterministic function of its pixels; steps finish after
     ``lag`` polls; uploads become visible after ``upload_lag`` queries."""
 
-    def __init__(self, N=3, K=2, lag=1, upload_lag=0):
+    def __init__(self, N=3, K=2, lag=1, upload_lag=0, capacity=None):
         self.N, self.K, self.lag, self.upload_lag = N, K, lag, upload_lag
+        self.capacity = capacity          # windows a step buffer holds (as the device slots)
         self.pixels = {}
         self.queries = {}
         self.steps = []
@@ -34,7 +35,10 @@ class FakeBackend(serve.Backend):
         return np.array([s * (j + 1) + win[0, 0] for j in range(K)])
 
     def launch(self, chunks):
-        self.steps.append(sum(c.rows * (c.req.W - self.N + 1) for c in chunks))
+        n = sum(c.rows * (c.req.W - self.N + 1) for c in chunks)
+        if self.capacity is not None and n > self.capacity:
+            raise ValueError(f"step of {n} windows exceeds the slot capacity {self.capacity}")
+        self.steps.append(n)
         for c in chunks:
             img = self.pixels[c.req.rid]
             wc = c.req.W - self.N + 1
@@ -71,7 +75,7 @@ def make_requests(n, seed=0, lo=1, hi=40):
 
 
 def test_every_window_coded_once_and_equal_alone():
-    be = FakeBackend(lag=2, upload_lag=1)
+    be = FakeBackend(lag=2, upload_lag=1, capacity=300)
     sch = serve.Scheduler(be, budget_elems=10_000, step_windows=300, clock=lambda: 0.0)
     reqs = make_requests(40)
     for r in reqs:
@@ -83,7 +87,28 @@ def test_every_window_coded_once_and_equal_alone():
             assert np.array_equal(r.codes, alone(be, r.pixels))
         assert r.done_rows == max(r.H - be.N + 1, 0) or r.windows == 0
     assert sch.arena.used == 0
-    assert max(be.steps) <= 300 + 40            # at most one extra row past the step size
+    assert max(be.steps) <= 300                  # never past the step size
+
+
+@pytest.mark.parametrize("step,shapes", [
+    (2100, [(200, 114), (20, 2048)]),        # wide rows that used to overshoot the step
+    (3000, [(20, 4000)]),                    # one row wider than a step: rejected
+    (50, [(9, 40), (9, 45), (12, 50), (5, 52)]),
+])
+def test_steps_never_exceed_the_slot_capacity(step, shapes):
+    be = FakeBackend(N=3, lag=1, capacity=step)
+    sch = serve.Scheduler(be, budget_elems=10**7, step_windows=step, clock=lambda: 0.0)
+    rng = np.random.default_rng(5)
+    reqs = [serve.Request(i, 0.0, rng.standard_normal(s), s[0], s[1]) for i, s in enumerate(shapes)]
+    for r in reqs:
+        sch.submit(r)
+    sch.drain(len(reqs))
+    wide = {r.rid for r in reqs if r.W - be.N + 1 > step}
+    assert {r.rid for r in sch.rejected} == wide
+    assert max(be.steps, default=0) <= step
+    for r in reqs:
+        if r.rid not in wide:
+            assert np.array_equal(r.codes, alone(be, r.pixels))
 
 
 def test_admission_respects_budget_and_order():
@@ -156,3 +181,20 @@ def test_latency_report_and_replay():
     sch.drain(len(reqs))
     rep = serve.latency_report(reqs)
     assert rep["requests"] == 5 and rep["p99_s"] >= rep["p50_s"] >= 0
+
+
+def test_wide_request_not_starved_by_a_stream_of_small_ones():
+    be = FakeBackend(N=3, lag=0, capacity=100)
+    sch = serve.Scheduler(be, budget_elems=10**7, step_windows=100, clock=lambda: 0.0)
+    wide = serve.Request(0, 0.0, np.ones((12, 92)), 12, 92)        # 10 rows of 90 windows
+    sch.submit(wide)
+    rid = 1
+    for _ in range(200):                                          # a new small request every round
+        sch.submit(serve.Request(rid, 0.0, np.ones((6, 8)), 6, 8))
+        rid += 1
+        sch.poll()
+        if wide in sch.finished:
+            break
+    assert wide in sch.finished
+    assert sch.steps <= 40                                        # served at least every other step
+    assert max(be.steps) <= 100
