@@ -727,7 +727,7 @@ def texture_learn(args, dev, xh_train, tb, R):
 
 
 def run_rotate(args, dev):
-    """Rotation speed (Sec. IV): random N x N patches turned by 100 + sqrt(2) degrees with
+    """Rotation speed (Sec. III-C): random N x N patches turned by 100 + sqrt(2) degrees with
     the nearest and bicubic rotation matrices (R x) and by steering precomputed hat
     coordinates (S x_hat), at N = 11 and 15 and for the paper's 50,000 patches and a
     4,000,000-patch batch; also steering with the low-pass basis (T halved) and the full

@@ -119,7 +119,7 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * floor(pi r_mid) (Sec. II-D's anti-aliasing rule), lowered to the largest value whose
  * 2 T_s + 1 harmonic columns are linearly independent on the annulus' pixels (as printed,
  * the 8-pixel second annulus at N = 11 would get 11 columns and Phi^T Phi would be
- * singular).  lowpass != 0 halves the cut-offs (the low-pass basis of Sec. IV).  The
+ * singular).  lowpass != 0 halves the cut-offs (the low-pass basis of Sec. III-C).  The
  * centre pixel is 0 for t != 0; columns are normalised; packed real coordinates are
  * harmonic-major with the annuli whose T_s >= k in block k ([Re][Im] for k >= 1, the
  * convention of rsc_create).  B = sum_s (2 T_s + 1) (81 at N = 11, 39 low-pass).
@@ -433,7 +433,7 @@ rsc_status rsc_chi2_nearest(const float* train, int n_train, const float* test, 
                             int32_t* nearest, float* dist, void* stream);
 
 /* ------------------------------------------------------------------ patch rotation
- * Sec. IV (rotation speed): a batch of N x N patches turned by one angle, either by
+ * Sec. III-C (rotation speed): a batch of N x N patches turned by one angle, either by
  * interpolation (the paper's sparse N^2 x N^2 matrices R_nearest and R_bicubic) or by
  * steering the hat coordinates (x_hat <- S x_hat, then Phi x_hat).  Angles are in
  * radians, counter-clockwise, about the centre pixel.

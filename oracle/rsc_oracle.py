@@ -76,7 +76,7 @@ Readings where the paper is silent:
     The centre pixel is 0 for t != 0, as above; columns are normalised and need no
     orthonormalisation (annuli are disjoint).  Packed real coordinates as above,
     harmonic-major, with the annuli whose T_s >= k in each harmonic-k block.
-  * Rotation by interpolation (Sec. IV, rotation speed): rotating a patch by theta
+  * Rotation by interpolation (Sec. III-C, rotation speed): rotating a patch by theta
     (counter-clockwise, about its centre pixel) sets output pixel (x, y) to the input
     at R_{-theta}(x, y), read with nearest-neighbour interpolation (coordinates
     rounded half up) or bicubic interpolation (Keys' cubic convolution, a = -1/2, over
@@ -179,7 +179,7 @@ def annular_cutoffs(N: int, lowpass: bool = False, cap: bool = True) -> list:
     """Per-annulus cut-offs T_s, s = 1..floor(N/2) (Sec. II-D): half the circumference,
     floor(pi r_mid); with cap, lowered to the largest T whose columns t = -T..T are linearly
     independent on the annulus (smallest singular value above 1e-6 of the largest); the
-    low-pass basis halves them (Sec. IV)."""
+    low-pass basis halves them (Sec. III-C)."""
     S = N // 2
     _, rho, theta = disk_grid(N)
     out = []
@@ -683,6 +683,6 @@ def rotate_interp(patches: np.ndarray, theta: float, mode: str) -> np.ndarray:
 
 
 def rotate_steer(basis: Basis, patches: np.ndarray, theta: float) -> np.ndarray:
-    """Steering-based rotation Phi S_theta (Phi^T Phi)^{-1} Phi^T x (Sec. IV), in either basis."""
+    """Steering-based rotation Phi S_theta (Phi^T Phi)^{-1} Phi^T x (Sec. III-C), in either basis."""
     return to_pixels(basis, steer_basis(basis, project(basis, patches), theta))
 

@@ -1,4 +1,4 @@
-// Patch rotation (Sec. IV, rotation speed): by interpolation, and by steering.
+// Patch rotation (Sec. III-C, rotation speed): by interpolation, and by steering.
 //
 // Interpolation: a plan holds the rotation as a table of taps, the rows of the paper's
 // N^2 x N^2 matrix R_nearest or R_bicubic (at most 1 or 16 nonzeros per output pixel),

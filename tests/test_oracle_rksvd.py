@@ -245,7 +245,7 @@ def _toy_crosses(R, P, seed=40):
 
 
 def test_toy_two_rotations_of_one_atom():
-    """The paper's toy experiment (Fig. toyCoding, Sec. IV, synthetic images): patches are
+    """The paper's toy experiment (Fig. toyCoding, Sec. III-A, synthetic patches): patches are
     the sum of two random rotations of one atom.  R-K-SVD with M = 1, K = 2 recovers the
     atom up to a rotation; plain K-SVD (R = 1) with M = 1, K = 1 or M = 2, K = 2 learns
     angular averages and codes far worse.  Greedy pursuit does not separate two nearby

@@ -1,4 +1,4 @@
-"""Pins of the reference patch rotations (Sec. IV, rotation speed), CPU only.
+"""Pins of the reference patch rotations (Sec. III-C, rotation speed), CPU only.
 
 Interpolation: identity at 0, exact quarter and half turns, exact reproduction of
 quadratics by the bicubic kernel where its support lies inside the patch, nearest
