@@ -48,16 +48,44 @@ def traffic(name: str):
     return None if t is None else t["read"] + t["write"]
 
 
-def encode_flops_per_patch(M: int, R: int, S: int, T: int, K: int) -> float:
-    """Algorithmic flops of the pursuit for one patch doing all K steps.
+def encode_flops_per_patch(M: int, R: int, S: int, T: int, K: int, split: bool = False) -> float:
+    """Flops of the pursuit for one patch doing all K steps.
 
-    Correlation (per step): per-harmonic inner products 2*M*S*(1+4T) plus the angle
-    DFT 2*M*R*(2T+1).  Least squares and residual (step k): 2*(2*k*B + k^2).
+    Correlation (per step): per-harmonic inner products 2*M*S*(1+4T) plus the angle DFT
+    2*M*R*(2T+1).  With split=True the DFT is counted as the FP32 encoder computes it for
+    even R: split once by harmonic parity, the even and odd partial sums are formed for R/2
+    angle rows only, M*R*(2T+1).  Least squares and residual (step k): 2*(2*k*B + k^2).
     """
     B = S * (2 * T + 1)
-    corr = 2.0 * (M * S * (1 + 4 * T) + M * R * (2 * T + 1))
+    dft = 2.0 * M * R * (2 * T + 1) * (0.5 if split else 1.0)
+    corr = 2.0 * M * S * (1 + 4 * T) + dft
     ls = sum(2.0 * (2 * k * B + k * k) for k in range(1, K + 1))
     return K * corr + ls
+
+
+def encoder_roofline(h, prec: str, M: int, R: int, S: int, T: int, K: int, P: int, enc_s: float,
+                     traffic_bytes=None) -> dict:
+    """Roofline of one encoder launch over P patches that took enc_s seconds.
+
+    frac counts the arithmetic the encoder itself performs: the FP32 encoder splits the
+    angle DFT by harmonic parity for even R; the 16-bit encoder forms the whole DFT in 16-bit
+    (its FP32 re-score of candidates is data-dependent and not counted).  Beside it: the same
+    work with the direct R-angle DFT (what the split saves is counted as if done), and the
+    matrix-core work actually executed (padding and recomputation included).
+    """
+    from paper_1806_04374_amd import rsc
+    split = prec == "fp32" and R % 2 == 0
+    own = encode_flops_per_patch(M, R, S, T, K, split=split) * P
+    direct = encode_flops_per_patch(M, R, S, T, K, split=False) * P
+    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
+    peak = FP32_MFMA_PEAK if prec == "fp32" else HALF_MFMA_PEAK
+    return {"kernel": "encode_kernel" if prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
+            "achieved": own / enc_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": own / enc_s / peak,
+            "traffic": traffic_bytes, "algorithmic_flops_per_launch": own, "dft_split": split,
+            "launch_ms": enc_s * 1e3,
+            "frac_direct_dft_equivalent": direct / enc_s / peak,
+            "executed_mfma_tflops": mfma_pp * P / enc_s / 1e12, "executed_mfma_frac": mfma_pp * P / enc_s / peak,
+            "tile": tile_used}
 
 
 def make_inputs(h, w, P, dev):
@@ -139,26 +167,33 @@ def cpu_baseline(h, w, D, target_s: float, dev):
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     one = oracle_rate_one_thread(lambda Xs: orc.encode(basis, D, w["R"], Xs, w["K"]), X, target_s=8.0)
-    # device codes of the same sample: selection match and matched MSE
-    xd = torch.from_numpy(X).to(dev)
-    xh = rsc.rsc_project(h, xd)
-    atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, w["K"])
-    rec = rsc.rsc_reconstruct(h, atom, angle, coef)
-    torch.cuda.synchronize()
-    a, r = atom.cpu().numpy(), angle.cpu().numpy()
-    match = np.mean([
-        {(x, y) for x, y in zip(a[p], r[p]) if x >= 0} ==
-        {(int(x), int(y)) for x, y in zip(code.atom[p], code.angle[p]) if x >= 0}
-        for p in range(n)])
-    mse_dev = orc.mse(basis, X, rec.cpu().numpy().astype(np.float64))
-    mse_ref = orc.mse(basis, X, orc.reconstruct(basis, D, w["R"], code))
+    ref = {"X": X, "code": code, "mse": orc.mse(basis, X, orc.reconstruct(basis, D, w["R"], code)),
+           "basis": basis}
     return {
         "value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
         "sample": f"first {n} patches of the same workload (FP64 reference, {dt:.1f} s)",
         "one_thread": one, "host": host_info(),
-        "check": {"selection_match": float(match), "mse_device": mse_dev, "mse_oracle": mse_ref,
-                  "mse_rel_diff": abs(mse_dev - mse_ref) / mse_ref},
-    }
+        "check": device_check(h, ref, D, w["R"], w["K"], dev),
+    }, ref
+
+
+def device_check(h, ref, D, R, K, dev) -> dict:
+    """Device codes of the reference's sample: selection match, coefficient error of the
+    matched patches and matched MSE against the FP64 reference."""
+    import torch
+    from oracle import rsc_oracle as orc
+    from paper_1806_04374_amd import rsc
+    from tests.parity import compare_codes
+    X, code, basis = ref["X"], ref["code"], ref["basis"]
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev))
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, K)
+    rec = rsc.rsc_reconstruct(h, atom, angle, coef)
+    torch.cuda.synchronize()
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code)
+    mse_dev = orc.mse(basis, X, rec.cpu().numpy().astype(np.float64))
+    return {"patches": int(len(X)), "selection_match": rep.match_rate, "coef_rel_err_max": rep.coef_err_max,
+            "coef_bad": rep.coef_bad, "mse_device": mse_dev, "mse_oracle": ref["mse"],
+            "mse_rel_diff": abs(mse_dev - ref["mse"]) / ref["mse"]}
 
 
 def run_ragged(args, dev):
@@ -233,11 +268,6 @@ def run_ragged(args, dev):
         kp.append(e0.elapsed_time(e1))
         ke.append(e1.elapsed_time(e2))
     ms = wall * 1e3 / args.steps
-    flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
-    achieved = flops / (np.mean(ke) * 1e-3)
-    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
-    executed = mfma_pp * P / (np.mean(ke) * 1e-3)
-    peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     out = {
         "metric": METRIC, "value": P / (ms * 1e-3), "unit": "patches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -251,12 +281,8 @@ def run_ragged(args, dev):
                    "precision": args.prec},
         "autotune": tuned,
         "kernels_ms": {"project_images_mean": float(np.mean(kp)), "encode_mean": float(np.mean(ke))},
-        "roofline": {"kernel": "encode_kernel" if args.prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
-                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic(w["name"]) if args.prec == "fp32" else None,
-                     "algorithmic_flops_per_launch": flops,
-                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / peak,
-                     "tile": tile_used},
+        "roofline": encoder_roofline(h, args.prec, w["M"], w["R"], g.S, g.T, K, P, np.mean(ke) * 1e-3,
+                                     traffic(w["name"]) if args.prec == "fp32" else None),
         "cpu_baseline": None,
     }
     if args.prec != "fp32":
@@ -659,7 +685,7 @@ def run_texture(args, dev):
         parts["histogram_nn"].append(e[2].elapsed_time(e[3]))
     # dominant kernel: the encoder, C launches per step (events around rsc_classify)
     cls_ms = float(np.median(parts["classify"]))
-    flops = encode_flops_per_patch(w["M"], R, g.S, g.T, K) * P * C
+    flops = encode_flops_per_patch(w["M"], R, g.S, g.T, K, split=args.prec == "fp32" and R % 2 == 0) * P * C
     peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     images = batches[0][0].n
     out = {
@@ -681,15 +707,6 @@ def run_texture(args, dev):
                      "traffic": None},
         "cpu_baseline": None,
     }
-    if args.compare_ksvd:
-        kclf, _ = texture_learn(args, dev, xh_train, tb, 1)
-        kacc = {}
-        for j, (b, pix, off) in enumerate(batches):
-            xk = rsc.rsc_project_images(proj, pix, b)
-            nearest, _ = kclf.predict(kclf.features(xk, off))
-            kacc[str(rots[j])] = float(np.mean(kclf.train_class[nearest.cpu().numpy()] == test_class))
-        out["ksvd_accuracy"] = {"per_rotation_deg": kacc, "mean": float(np.mean(list(kacc.values())))}
-        kclf.close()
     del xh_train
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_texture(clf, proj, xh, batches[0], args.cpu_seconds, dev)
@@ -916,8 +933,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture", "rotate"],
                     default="scale")
-    ap.add_argument("--compare-ksvd", action="store_true",
-                    help="texture: also learn plain K-SVD (R = 1) dictionaries and report their accuracy")
     ap.add_argument("--check-patches", type=int, default=50_000,
                     help="precision: scale-workload patches checked against the reference")
     ap.add_argument("--duration", type=float, default=30.0, help="serving: trace length (s)")
@@ -930,6 +945,8 @@ def main():
                     help="ragged: use the first n images; texture: test images per class and rotation (testing only)")
     ap.add_argument("--patches", type=int, default=0, help="override P (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="scale: skip the BF16 / FP16 forms and the small-workload latency")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", choices=["auto", "16", "32"], default="auto")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32",
@@ -1013,11 +1030,6 @@ def main():
     proj_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
     enc_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
     ms = wall * 1e3 / args.steps
-    flops = encode_flops_per_patch(w["M"], w["R"], g.S, g.T, K) * P
-    achieved = flops / (enc_ms.mean() * 1e-3)
-    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
-    executed = mfma_pp * P / (enc_ms.mean() * 1e-3)
-    peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     out = {
         "metric": METRIC,
         "value": P / (ms * 1e-3),
@@ -1039,20 +1051,101 @@ def main():
                    "P": P, "N": g.N, "S": g.S, "T": g.T, "M": w["M"], "K": K, "R": w["R"],
                    "tile": args.tile, "precision": args.prec},
         "kernels_ms": {"project_mean": float(proj_ms.mean()), "encode_mean": float(enc_ms.mean())},
-        "roofline": {"kernel": "encode_kernel" if args.prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
-                     "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": traffic(w["name"]) if args.prec == "fp32" else None,
-                     "algorithmic_flops_per_launch": flops,
-                     "executed_mfma_tflops": executed / 1e12, "executed_mfma_frac": executed / peak,
-                     "tile": tile_used},
+        "roofline": encoder_roofline(h, args.prec, w["M"], w["R"], g.S, g.T, K, P, enc_ms.mean() * 1e-3,
+                                     traffic(w["name"]) if args.prec == "fp32" else None),
         "cpu_baseline": None,
     }
     if args.prec != "fp32":
         out["precision_stats"] = rsc.rsc_precision_stats(h)
+    ref = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(h, w, D, args.cpu_seconds, dev)
+        out["cpu_baseline"], ref = cpu_baseline(h, w, D, args.cpu_seconds, dev)
+    if w["name"] == "scale-fp32" and args.prec == "fp32" and not args.no_extras and not args.patches:
+        out["precision_forms"] = precision_forms(D, w, X, ref, ms, args, dev)
+        out["small_latency"] = small_latency(dev)
     print(json.dumps(out), flush=True)
+
+
+def precision_forms(D, w, X, ref, fp32_ms: float, args, dev) -> dict:
+    """The BF16 and FP16 forms of the encoder on the same input as the FP32 line: step time,
+    speedup over FP32 and, on the reference's sample, selection match and MSE."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    g, K, P = w["geom"], w["K"], X.shape[0]
+    res = {}
+    for prec in ("bf16", "fp16"):
+        h = rsc.rsc_create(g.N, g.S, g.T, prec=prec)
+        rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+        xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+        outs = (torch.empty((P, K), dtype=torch.int32, device=dev), torch.empty((P, K), dtype=torch.int32, device=dev),
+                torch.empty((P, K), dtype=torch.float32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev))
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            rsc.rsc_project(h, X, xh, stream=stream)
+            rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+        n = max(10, args.steps)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b, c in ev:
+            a.record(stream)
+            rsc.rsc_project(h, X, xh, stream=stream)
+            b.record(stream)
+            rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+            c.record(stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n
+        enc = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+        r = {"ms_per_step": ms, "patches_per_s": P / (ms * 1e-3), "speedup_vs_fp32": fp32_ms / ms,
+             "encode_mean_ms": enc,
+             "roofline": encoder_roofline(h, prec, w["M"], w["R"], g.S, g.T, K, P, enc * 1e-3)}
+        if ref is not None:
+            r["check"] = device_check(h, ref, D, w["R"], K, dev)
+        r["precision_stats"] = rsc.rsc_precision_stats(h)
+        res[prec] = r
+        h.close()
+    return res
+
+
+def small_latency(dev, runs: int = 100) -> dict:
+    """The small workload (2,000 11x11 patches, M=16, K=2, R=32): latency of one project +
+    encode over `runs` runs, HIP events on the launch stream, and its codes against the
+    FP64 reference (all 2,000 patches)."""
+    import torch
+    from oracle import rsc_oracle as orc
+    from paper_1806_04374_amd import rsc
+    w = wl.SMALL
+    g, K = w["geom"], w["K"]
+    D, draw = wl.small_draw()
+    basis = orc.build_basis(g.N, g.S, g.T)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    _, code = orc.encode(basis, D, w["R"], X.astype(np.float64), K)
+    ref = {"X": X, "code": code, "mse": orc.mse(basis, X, orc.reconstruct(basis, D, w["R"], code)), "basis": basis}
+    res = {"workload": f"{w['name']}: {w['P']} 11x11 patches, M={w['M']}, K={K}, R={w['R']}", "runs": runs}
+    for prec in ("fp32", "bf16", "fp16"):
+        h = rsc.rsc_create(g.N, g.S, g.T, prec=prec)
+        rsc.rsc_set_dictionary(h, D.astype(np.float32), w["R"])
+        x = torch.from_numpy(X).to(dev)
+        xh = torch.empty((len(X), g.B), dtype=torch.float32, device=dev)
+        outs = (torch.empty((len(X), K), dtype=torch.int32, device=dev),
+                torch.empty((len(X), K), dtype=torch.int32, device=dev),
+                torch.empty((len(X), K), dtype=torch.float32, device=dev), None)
+        stream = torch.cuda.current_stream()
+        lat = []
+        for i in range(runs + 5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            rsc.rsc_project(h, x, xh, stream=stream)
+            rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            if i >= 5:
+                lat.append(a.elapsed_time(b) * 1e3)
+        res[prec] = {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+                     "check": device_check(h, ref, D, w["R"], K, dev)}
+        h.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -13,12 +13,15 @@
  *  - Every function returns rsc_status: 0 on success, a negative code on error.
  *    Nothing aborts or prints.  rsc_last_error() gives a thread-local message for
  *    the last failure on the calling thread.
+ *  - Device faults are sticky per handle: once a launch, copy or synchronisation on a
+ *    handle fails, every later call on that handle (and rsc_sync with it) returns
+ *    RSC_E_DEVICE with the first fault's message.  Such a handle can only be destroyed.
  *  - Device pointers are HIP device (or managed) addresses owned by the caller.
  *    The library owns only the handle and its resident copies of the basis,
  *    dictionary and tables.  Host arrays are copied before the call returns.
  *  - "stream" is a hipStream_t passed as void*; NULL is the default stream.  The
  *    compute calls only enqueue work and return; argument errors are reported
- *    synchronously, launch errors as RSC_E_DEVICE.  rsc_sync() waits.
+ *    synchronously, launch errors as RSC_E_DEVICE.  rsc_sync() is the call that waits.
  *  - Compute calls never allocate device memory.
  *  - Calls that use the dictionary (encode, reconstruct, synthesis, autotuning,
  *    encoder info) return RSC_E_NOT_READY until rsc_set_dictionary succeeds.
@@ -161,18 +164,27 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
 /*
  * Load the dictionary D_hat (Sec. II-C; hat coordinates, Sec. II-E step 3) and the
  * angle grid size R.
- *   d_hat  HOST array [M, B] float32, packed hat coordinates, each row of unit
- *          Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID)
- *   M      1 <= M <= 256 (BF16 / FP16 handles: M <= 128)
- *   R      1 <= R <= 128 (BF16 / FP16 handles: R <= 64)
- * Synchronous: it first waits for the whole device (launches in flight on any stream
- * may still read the previous tables, which are refilled in place when the new ones fit),
- * and the copy to the device completes before return.
+ *   d_hat   HOST array [M, B] float32, packed hat coordinates, each row of unit
+ *           Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID); copied before
+ *           the call returns
+ *   M       1 <= M <= 256 (BF16 / FP16 handles: M <= 128)
+ *   R       1 <= R <= 128 (BF16 / FP16 handles: R <= 64)
+ *   stream  the upload is enqueued on it (hipStream_t as void*)
+ * Stream-ordered, without a device-wide wait: the handle keeps two device copies of its
+ * tables and the upload fills the one not in use.  Launches enqueued before this call
+ * (on any stream) keep the previous dictionary; launches enqueued after it return use
+ * the new one (on another stream they are ordered after the upload by the library).  The
+ * upload waits on the device for the launches that read the copy it overwrites (the
+ * dictionary before the previous one).  A HIP graph keeps the tables bound when it was
+ * captured: capture again after an upload.  Blocks the host only when a copy must grow
+ * or its staging buffer still feeds an earlier upload.
+ * On any error the handle keeps its previous dictionary.
  * Errors: RSC_E_INVALID (arguments), RSC_E_UNSUPPORTED (sizes beyond the compiled
  * limits of the handle's precision, tables beyond the 160 KiB LDS of a CU, or a handle
- * of rsc_create_annular or of a geometry the pursuit is not compiled for).
+ * of rsc_create_annular or of a geometry the pursuit is not compiled for), RSC_E_NOMEM,
+ * RSC_E_DEVICE (sticky).
  */
-rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R);
+rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, void* stream);
 
 /*
  * Select the encoder tile shape for later rsc_omp_encode calls on this handle.
@@ -227,6 +239,15 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
  */
 rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, float* xhat,
                        void* stream);
+
+/*
+ * Device workspace that rsc_omp_encode needs for P patches and K atoms per patch: always
+ * 0 bytes, because every per-patch value of the pursuit (residual, Cholesky factor,
+ * coefficients, selections) stays in registers; admission and graph-capture code query it
+ * like the other workspace sizes.  Errors: RSC_E_INVALID (null h or bytes, P < 0, K
+ * outside 1..min(8, B)).
+ */
+rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size_t* bytes);
 
 /*
  * Rotational OMP over the augmented dictionary [S_0 D, ..., S_{R-1} D]
@@ -513,11 +534,27 @@ rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P,
  */
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset);
 
-/* Wait for all work on the stream; reports RSC_E_DEVICE for a failed kernel. */
-rsc_status rsc_sync(void* stream);
+/*
+ * Wait for all work on the stream.  RSC_E_DEVICE if the wait reports a failed kernel (the
+ * fault then becomes sticky on h) or if h already carries a sticky fault.  h may be NULL
+ * (only the stream is checked).
+ */
+rsc_status rsc_sync(rsc_handle* h, void* stream);
 
-/* Message for the last failure on this thread ("" if none).  Valid until the next call. */
-const char* rsc_last_error(void);
+/*
+ * Message for the last failure on this thread; when there is none and h carries a sticky
+ * fault, that fault's message; else "".  h may be NULL.  Valid until the next call.
+ */
+const char* rsc_last_error(const rsc_handle* h);
+
+/*
+ * Marks h as failed, as a device fault on it would (for callers that detect a fault of
+ * their own on work that shares the handle's streams, and for tests of error handling):
+ * every later call on h returns RSC_E_DEVICE with msg (NULL: a generic message).  A
+ * handle that already carries a fault keeps its first message.  Errors: RSC_E_INVALID
+ * (null h).
+ */
+rsc_status rsc_set_fault(rsc_handle* h, const char* msg);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,19 @@
 #include "rsc.h"
 #include "rsc_internal.h"
 
+// One of the two device arenas that hold a handle's dictionary tables.  Uploads go to the
+// arena that is not bound, so tables that launches in flight still read are never
+// overwritten; before an arena is refilled, the upload stream waits for every launch that
+// read it (an event per stream, recorded after each launch).
+struct DictSlot {
+  void* arena = nullptr;
+  size_t bytes = 0;
+  void* pinned = nullptr;            // page-locked host staging of the upload
+  size_t pinned_bytes = 0;
+  hipEvent_t copied = nullptr;       // recorded after the upload's copy
+  std::vector<std::pair<hipStream_t, hipEvent_t>> users;   // launches that read this arena
+};
+
 struct rsc_handle {
   rsc::HostBasis basis;
   rsc::DeviceTables dev;
@@ -20,6 +33,13 @@ struct rsc_handle {
   bool has_dict = false;
   bool annular = false;      // the paper's annular basis (projection, steering, synthesis only)
   std::vector<int> Ts;       // its per-annulus cut-offs
+  // Sticky device fault: a failed launch, copy or synchronisation on this handle makes
+  // every later call on it return RSC_E_DEVICE with this message.
+  mutable rsc_status fault = RSC_OK;
+  mutable std::string fault_msg;
+  mutable DictSlot slot[2];
+  int cur = -1;                          // slot whose tables are bound (-1: none)
+  hipStream_t dict_stream = nullptr;     // stream of the last upload
 };
 
 namespace {
@@ -38,6 +58,85 @@ rsc_status ok() {
 
 rsc_status device_fail(int e, const char* what) {
   return fail(RSC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(hipError_t(e)));
+}
+
+// A device failure on a handle: reported now and on every later call (sticky).
+rsc_status handle_fail(const rsc_handle* h, int e, const char* what) {
+  const std::string msg = std::string(what) + ": " + hipGetErrorString(hipError_t(e));
+  if (h && h->fault == RSC_OK) {
+    h->fault = RSC_E_DEVICE;
+    h->fault_msg = msg;
+  }
+  return fail(RSC_E_DEVICE, msg);
+}
+
+// RSC_E_DEVICE if the handle carries a sticky fault.
+rsc_status check_fault(const rsc_handle* h) {
+  if (h && h->fault != RSC_OK) return fail(h->fault, "earlier device fault on this handle: " + h->fault_msg);
+  return RSC_OK;
+}
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Before a launch that reads the dictionary tables: order it after the upload when the
+// upload ran on another stream and may still be in flight.
+rsc_status dict_before(const rsc_handle* h, void* stream) {
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const DictSlot& s = h->slot[h->cur];
+  if (st != h->dict_stream && s.copied && !capturing(st) && hipEventQuery(s.copied) == hipErrorNotReady) {
+    const hipError_t e = hipStreamWaitEvent(st, s.copied, 0);
+    if (e != hipSuccess) return handle_fail(h, int(e), "stream wait on the dictionary upload");
+  }
+  return RSC_OK;
+}
+
+// After a launch that reads the dictionary tables: mark the stream as a reader of the bound
+// arena (not under graph capture: a captured graph reads the tables bound at capture time).
+rsc_status dict_after(const rsc_handle* h, void* stream) {
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (capturing(st)) return RSC_OK;
+  DictSlot& s = h->slot[h->cur];
+  hipEvent_t ev = nullptr;
+  for (auto& u : s.users)
+    if (u.first == st) ev = u.second;
+  if (!ev) {
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return handle_fail(h, int(e), "event creation");
+    s.users.emplace_back(st, ev);
+  }
+  const hipError_t e = hipEventRecord(ev, st);
+  return e == hipSuccess ? RSC_OK : handle_fail(h, int(e), "event record after a launch");
+}
+
+// A launch that reads the dictionary: fault check, ordering, launch, reader mark.
+template <class F>
+rsc_status dict_launch(const rsc_handle* h, void* stream, const char* what, F launch) {
+  rsc_status s = dict_before(h, stream);
+  if (s != RSC_OK) return s;
+  const int e = launch();
+  if (e) return handle_fail(h, e, what);
+  s = dict_after(h, stream);
+  return s != RSC_OK ? s : ok();
+}
+
+// Wait for every launch recorded against the slot and for its upload, then release it.
+void release_slot(DictSlot& s) {
+  for (auto& u : s.users) {
+    (void)hipEventSynchronize(u.second);
+    (void)hipEventDestroy(u.second);
+  }
+  s.users.clear();
+  if (s.copied) {
+    (void)hipEventSynchronize(s.copied);
+    (void)hipEventDestroy(s.copied);
+    s.copied = nullptr;
+  }
+  if (s.arena) (void)hipFree(s.arena);
+  if (s.pinned) (void)hipHostFree(s.pinned);
+  s = DictSlot();
 }
 
 template <class X>
@@ -268,7 +367,10 @@ ClsLayout cls_layout(int64_t P, int K) {
 
 extern "C" {
 
-const char* rsc_last_error(void) { return g_err.c_str(); }
+const char* rsc_last_error(const rsc_handle* h) {
+  if (g_err.empty() && h && h->fault != RSC_OK) return h->fault_msg.c_str();
+  return g_err.c_str();
+}
 
 rsc_status rsc_create(int N, int S, int T, const double* centres, double sigma, rsc_precision prec,
                       rsc_handle** out) {
@@ -385,7 +487,9 @@ rsc_status rsc_destroy(rsc_handle* h) {
   free_dev(d.phiPad);
   free_dev(d.synA);
   free_dev(d.steerTab);
-  free_dev(d.dictArena);
+  release_slot(h->slot[0]);
+  release_slot(h->slot[1]);
+  d.dictArena = nullptr;
   free_dev(d.lpStats);
   free_dev(d.lpPinv);
   free_dev(d.lpPix16);
@@ -408,8 +512,9 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv) {
   return ok();
 }
 
-rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
+rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, void* stream) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (rsc_status f = check_fault(h)) return f;
   if (!d_hat) return fail(RSC_E_INVALID, "d_hat is NULL");
   if (M < 1 || M > 256) return fail(RSC_E_INVALID, "M must be in 1..256");
   if (R < 1 || R > 128) return fail(RSC_E_INVALID, "R must be in 1..128");
@@ -604,16 +709,18 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
       cs64[size_t(k) * R + r] = std::cos(two_pi * double(k) * double(r) / double(R));
       cs64[size_t(NQ + k) * R + r] = std::sin(two_pi * double(k) * double(r) / double(R));
     }
-  d.M = M;
-  d.R = R;
-  d.NG = NG;
-  d.lpSplit = split;
-  h->has_dict = false;
-  if (lp && rsc::encode_lp_lds_bytes(d) > 160 * 1024)
+  // the new tables must fit a CU's LDS; checked before the handle changes, so a refused
+  // upload leaves the current dictionary in place
+  rsc::DeviceTables nd = d;
+  nd.M = M;
+  nd.R = R;
+  nd.NG = NG;
+  nd.lpSplit = split;
+  if (lp && rsc::encode_lp_lds_bytes(nd) > 160 * 1024)
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
-  if (!lp && rsc::encode_lds_bytes(d, RSC_TILE_16) > 160 * 1024)
+  if (!lp && rsc::encode_lds_bytes(nd, RSC_TILE_16) > 160 * 1024)
     return fail(RSC_E_UNSUPPORTED, "dictionary tables exceed the 160 KiB LDS of a CU");
-  // one host staging buffer, one device arena (kept across uploads), one copy
+  // one host staging buffer, one copy into the arena that is not bound
   Arena arena;
   arena.add(d.dictA, dictA);
   arena.add(d.dictHat, hat);
@@ -627,26 +734,55 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R) {
   arena.add(d.lpF32, lpF32);
   arena.add(d.gramH64, gramH64);
   arena.add(d.cs64, cs64);
-  // kernels still in flight on any stream may read the current tables
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return device_fail(int(e), "device synchronisation before the dictionary upload");
-  if (d.dictArenaBytes < arena.staging.size()) {
-    free_dev(d.dictArena);
-    d.dictArenaBytes = 0;
-    e = hipMalloc(&d.dictArena, arena.staging.size());
-    if (e != hipSuccess) {
-      d.dictArena = nullptr;
-      arena.bind(nullptr);
+  const size_t need = arena.staging.size();
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DictSlot& sl = h->slot[h->cur < 0 ? 0 : 1 - h->cur];
+  hipError_t e = hipSuccess;
+  if (sl.copied && (e = hipEventSynchronize(sl.copied)) != hipSuccess)   // staging of its last upload
+    return handle_fail(h, int(e), "wait for an earlier dictionary upload");
+  if (sl.pinned_bytes < need) {
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    sl.pinned = nullptr;
+    sl.pinned_bytes = 0;
+    if (hipHostMalloc(&sl.pinned, need, hipHostMallocDefault) != hipSuccess) {
+      sl.pinned = nullptr;
+      return fail(RSC_E_NOMEM, "hipHostMalloc for the dictionary staging failed");
+    }
+    sl.pinned_bytes = need;
+  }
+  if (sl.bytes < need) {
+    // launches in flight may still read the arena: wait for them before it is freed
+    for (auto& u : sl.users)
+      if ((e = hipEventSynchronize(u.second)) != hipSuccess) return handle_fail(h, int(e), "wait for readers");
+    if (sl.arena) (void)hipFree(sl.arena);
+    sl.arena = nullptr;
+    sl.bytes = 0;
+    if (hipMalloc(&sl.arena, need) != hipSuccess) {
+      sl.arena = nullptr;
       return fail(RSC_E_NOMEM, "hipMalloc for the dictionary tables failed");
     }
-    d.dictArenaBytes = arena.staging.size();
+    sl.bytes = need;
   }
-  arena.bind(static_cast<char*>(d.dictArena));
-  e = hipMemcpy(d.dictArena, arena.staging.data(), arena.staging.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    arena.bind(nullptr);
-    return device_fail(int(e), "dictionary tables");
-  }
+  if (!sl.copied && (e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming)) != hipSuccess)
+    return handle_fail(h, int(e), "event creation");
+  std::memcpy(sl.pinned, arena.staging.data(), need);
+  // the copy waits for every launch that read this arena (events recorded after them)
+  for (auto& u : sl.users)
+    if ((e = hipStreamWaitEvent(st, u.second, 0)) != hipSuccess)
+      return handle_fail(h, int(e), "stream wait before the dictionary upload");
+  if ((e = hipMemcpyAsync(sl.arena, sl.pinned, need, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return handle_fail(h, int(e), "dictionary upload");
+  if ((e = hipEventRecord(sl.copied, st)) != hipSuccess) return handle_fail(h, int(e), "event record");
+  // later launches read the new arena
+  arena.bind(static_cast<char*>(sl.arena));
+  d.M = M;
+  d.R = R;
+  d.NG = NG;
+  d.lpSplit = split;
+  d.dictArena = sl.arena;
+  d.dictArenaBytes = need;
+  h->cur = int(&sl - h->slot);
+  h->dict_stream = st;
   h->has_dict = true;
   return ok();
 }
@@ -677,6 +813,8 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
   if (P < 1 || !xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "need a non-empty sample");
   if (reps < 1 || reps > 100) return fail(RSC_E_INVALID, "reps must be in 1..100");
+  if (rsc_status f = check_fault(h)) return f;
+  if (rsc_status f = dict_before(h, stream)) return f;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool lp = h->prec != RSC_FP32;
   int tiles[2] = {lp ? RSC_TILE_32 : RSC_TILE_16, RSC_TILE_32};
@@ -699,12 +837,12 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
     for (int bpc = 1; bpc <= 4 && status == RSC_OK; ++bpc) {
       h->dev.enc_bpc = bpc;
       int e = run(tiles[ti]);
-      if (e) { status = device_fail(e, "autotune launch"); break; }
+      if (e) { status = handle_fail(h, e, "autotune launch"); break; }
       std::vector<float> ms(reps);
       for (int r = 0; r < reps && status == RSC_OK; ++r) {
         if (hipEventRecord(e0, st) != hipSuccess) { status = fail(RSC_E_DEVICE, "event record"); break; }
         e = run(tiles[ti]);
-        if (e) { status = device_fail(e, "autotune launch"); break; }
+        if (e) { status = handle_fail(h, e, "autotune launch"); break; }
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms[r], e0, e1) != hipSuccess) {
           status = fail(RSC_E_DEVICE, "event timing");
@@ -729,6 +867,7 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (status == RSC_OK) status = dict_after(h, stream);
   if (status != RSC_OK) {
     h->dev.enc_bpc = saved_bpc;
     return status;
@@ -767,8 +906,9 @@ rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, flo
   if (P == 0) return ok();
   if (!patches || !xhat) return fail(RSC_E_INVALID, "null device pointer");
   if (P > (int64_t(1) << 31) * 64) return fail(RSC_E_INVALID, "P too large");
+  if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_project(h->dev, patches, P, xhat, stream);
-  return e ? device_fail(e, "projection launch") : ok();
+  return e ? handle_fail(h, e, "projection launch") : ok();
 }
 
 rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
@@ -779,13 +919,15 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
   if (!xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "null device pointer");
-  if (h->prec != RSC_FP32) {
-    int e = rsc::launch_encode_lp(h->dev, h->prec, xhat, P, K, atom, angle, coef, resid2, stream);
-    return e ? device_fail(e, "encode launch") : ok();
-  }
+  if (rsc_status f = check_fault(h)) return f;
+  if (h->prec != RSC_FP32)
+    return dict_launch(h, stream, "encode launch", [&] {
+      return rsc::launch_encode_lp(h->dev, h->prec, xhat, P, K, atom, angle, coef, resid2, stream);
+    });
   const int tile = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
-  int e = rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, resid2, stream);
-  return e ? device_fail(e, "encode launch") : ok();
+  return dict_launch(h, stream, "encode launch", [&] {
+    return rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, resid2, stream);
+  });
 }
 
 rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32_t* angle,
@@ -797,8 +939,10 @@ rsc_status rsc_reconstruct(const rsc_handle* h, const int32_t* atom, const int32
   if (P == 0) return ok();
   if (!atom || !angle || !coef || !out) return fail(RSC_E_INVALID, "null device pointer");
   if (P > (int64_t(1) << 31) * 8) return fail(RSC_E_INVALID, "P too large");
-  int e = rsc::launch_synthesize(h->dev, atom, angle, nullptr, coef, P, K, nullptr, out, stream);
-  return e ? device_fail(e, "reconstruct launch") : ok();
+  if (rsc_status f = check_fault(h)) return f;
+  return dict_launch(h, stream, "reconstruct launch", [&] {
+    return rsc::launch_synthesize(h->dev, atom, angle, nullptr, coef, P, K, nullptr, out, stream);
+  });
 }
 
 rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float* theta,
@@ -811,8 +955,10 @@ rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float*
   if (P == 0) return ok();
   if (!atom || !theta || !weight || !out) return fail(RSC_E_INVALID, "null device pointer");
   if (P > (int64_t(1) << 31) * 8) return fail(RSC_E_INVALID, "P too large");
-  int e = rsc::launch_synthesize(h->dev, atom, nullptr, theta, weight, P, J, noise, out, stream);
-  return e ? device_fail(e, "synthesize launch") : ok();
+  if (rsc_status f = check_fault(h)) return f;
+  return dict_launch(h, stream, "synthesize launch", [&] {
+    return rsc::launch_synthesize(h->dev, atom, nullptr, theta, weight, P, J, noise, out, stream);
+  });
 }
 
 rsc_status rsc_images_workspace_size(int n_images, size_t* bytes) {
@@ -837,9 +983,10 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
       !rsc::encode_supported(h->dev.S, h->dev.T))
     return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
                                    "geometries");
+  if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_project_images(h->dev, pixels, img_offset, H, W, n_images, P_total, workspace, xhat,
                                      stream);
-  return e ? device_fail(e, "image projection launch") : ok();
+  return e ? handle_fail(h, e, "image projection launch") : ok();
 }
 
 rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const float* theta,
@@ -852,9 +999,11 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
   if (n_stamps == 0) return ok();
   if (!atom || !theta || !amplitude || !centre || !image || !img_offset || !H || !W || !pixels)
     return fail(RSC_E_INVALID, "null device pointer");
-  int e = rsc::launch_stamps(h->dev, atom, theta, amplitude, centre, image, n_stamps, img_offset, H, W,
-                             n_images, pixels, stream);
-  return e ? device_fail(e, "stamp launch") : ok();
+  if (rsc_status f = check_fault(h)) return f;
+  return dict_launch(h, stream, "stamp launch", [&] {
+    return rsc::launch_stamps(h->dev, atom, theta, amplitude, centre, image, n_stamps, img_offset, H, W,
+                              n_images, pixels, stream);
+  });
 }
 
 
@@ -882,9 +1031,11 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
   int32_t* rs = reset ? reset : reinterpret_cast<int32_t*>(reinterpret_cast<char*>(workspace) + L.reset);
-  int e = rsc::launch_rksvd_update(h->dev, xhat, P, K, atom, angle, coef, resid2, workspace, d_new, usage, rs,
-                                   stream);
-  return e ? device_fail(e, "dictionary update launch") : ok();
+  if (rsc_status f = check_fault(h)) return f;
+  return dict_launch(h, stream, "dictionary update launch", [&] {
+    return rsc::launch_rksvd_update(h->dev, xhat, P, K, atom, angle, coef, resid2, workspace, d_new, usage, rs,
+                                    stream);
+  });
 }
 
 rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, int n_iter, const float* d_init,
@@ -897,7 +1048,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   if (P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
     return fail(RSC_E_INVALID, "null device pointer or empty input");
-  rsc_status s = rsc_set_dictionary(h, d_init, M, R);
+  rsc_status s = rsc_set_dictionary(h, d_init, M, R, stream);
   if (s != RSC_OK) return s;
   const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
@@ -911,10 +1062,10 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
     if (!history) return RSC_OK;
     double* slot = rk_sum_slot(h->dev, P, K, workspace);
     int e = rsc::launch_sum(resid2, P, slot, stream);
-    if (e) return device_fail(e, "sum launch");
+    if (e) return handle_fail(h, e, "sum launch");
     hipError_t he = hipMemcpyAsync(&history[at], slot, sizeof(double), hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
-    return he == hipSuccess ? RSC_OK : device_fail(int(he), "history copy");
+    return he == hipSuccess ? RSC_OK : handle_fail(h, int(he), "history copy");
   };
   for (int it = 0; it <= n_iter; ++it) {
     s = rsc_omp_encode(h, xhat, P, K, atom, angle, coef, resid2, stream);
@@ -924,7 +1075,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
     if (s != RSC_OK) break;
     hipError_t he = hipMemcpyAsync(host.data(), dn, host.size() * sizeof(float), hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) return device_fail(int(he), "dictionary copy");
+    if (he != hipSuccess) return handle_fail(h, int(he), "dictionary copy");
     // rows leave the device at unit norm up to FP32 rounding; renormalise in FP64
     for (int m = 0; m < M; ++m) {
       double n2 = 0.0;
@@ -933,7 +1084,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
       for (int b = 0; b < h->dev.B; ++b)
         host[size_t(m) * h->dev.B + b] = float(host[size_t(m) * h->dev.B + b] * inv);
     }
-    s = rsc_set_dictionary(h, host.data(), M, R);
+    s = rsc_set_dictionary(h, host.data(), M, R, stream);
     if (s != RSC_OK) break;
   }
   if (s != RSC_OK) return s;
@@ -978,7 +1129,7 @@ rsc_status rsc_classify(const rsc_handle* const* classes, int C, const float* xh
     rsc_status s = rsc_omp_encode(classes[c], xhat, P, K, atom, angle, coef, r2, stream);
     if (s != RSC_OK) return s;
     int e = rsc::launch_classify_min(r2, P, c, label, sse, stream);
-    if (e) return device_fail(e, "classify launch");
+    if (e) return handle_fail(classes[c], e, "classify launch");
   }
   return ok();
 }
@@ -1134,8 +1285,9 @@ rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const fl
   if (P == 0) return ok();
   if (!xhat || !out) return fail(RSC_E_INVALID, "null device pointer");
   if (xhat == out) return fail(RSC_E_INVALID, "xhat and out must be distinct");
+  if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_steer(h->dev, xhat, P, theta, theta0, out, stream);
-  return e ? device_fail(e, "steering launch") : ok();
+  return e ? handle_fail(h, e, "steering launch") : ok();
 }
 
 rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream) {
@@ -1144,31 +1296,52 @@ rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P,
   if (h->dev.B > 192) return fail(RSC_E_UNSUPPORTED, "synthesis is compiled for B <= 192");
   if (P == 0) return ok();
   if (!xhat || !pixels) return fail(RSC_E_INVALID, "null device pointer");
+  if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_synth_hat(h->dev, xhat, P, pixels, stream);
-  return e ? device_fail(e, "synthesis launch") : ok();
+  return e ? handle_fail(h, e, "synthesis launch") : ok();
 }
 
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (h->prec == RSC_FP32 || !h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "FP32 handles keep no counters");
+  if (rsc_status f = check_fault(h)) return f;
   hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return device_fail(int(e), "device synchronize");
+  if (e != hipSuccess) return handle_fail(h, int(e), "device synchronize");
   unsigned long long v[4];
   e = hipMemcpy(v, h->dev.lpStats, sizeof(v), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return device_fail(int(e), "counter read");
+  if (e != hipSuccess) return handle_fail(h, int(e), "counter read");
   if (out)
     for (int i = 0; i < 4; ++i) out[i] = int64_t(v[i]);
   if (reset) {
     e = hipMemset(h->dev.lpStats, 0, sizeof(v));
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return device_fail(int(e), "counter reset");
+    if (e != hipSuccess) return handle_fail(h, int(e), "counter reset");
   }
   return ok();
 }
 
-rsc_status rsc_sync(void* stream) {
+rsc_status rsc_sync(rsc_handle* h, void* stream) {
   hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return device_fail(int(e), "stream synchronize");
+  if (e != hipSuccess) return handle_fail(h, int(e), "stream synchronize");
+  if (rsc_status f = check_fault(h)) return f;
+  return ok();
+}
+
+rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size_t* bytes) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
+  if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
+  if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  *bytes = 0;   // every per-patch value of the pursuit stays in registers
+  return ok();
+}
+
+rsc_status rsc_set_fault(rsc_handle* h, const char* msg) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (h->fault == RSC_OK) {
+    h->fault = RSC_E_DEVICE;
+    h->fault_msg = msg ? msg : "fault set by the caller";
+  }
   return ok();
 }
 

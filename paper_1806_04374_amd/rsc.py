@@ -48,7 +48,9 @@ def lib():
         "rsc_destroy": [P],
         "rsc_basis_info": [P, P, P, P],
         "rsc_get_basis": [P, P, P],
-        "rsc_set_dictionary": [P, P, I, I],
+        "rsc_set_dictionary": [P, P, I, I, P],
+        "rsc_encode_workspace_size": [P, I64, I, P],
+        "rsc_set_fault": [P, ctypes.c_char_p],
         "rsc_set_tile": [P, I],
         "rsc_set_launch": [P, I, I],
         "rsc_get_launch": [P, P, P],
@@ -58,7 +60,7 @@ def lib():
         "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
         "rsc_reconstruct": [P, P, P, P, I64, I, P, P],
         "rsc_synthesize": [P, P, P, P, I64, I, P, P, P],
-        "rsc_sync": [P],
+        "rsc_sync": [P, P],
         "rsc_images_workspace_size": [I, P],
         "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
         "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
@@ -81,7 +83,7 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
-    L.rsc_last_error.argtypes = []
+    L.rsc_last_error.argtypes = [P]
     L.rsc_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
@@ -96,7 +98,7 @@ def header_functions(path: str = HEADER) -> list[str]:
 
 def _check(status: int):
     if status != RSC_OK:
-        raise RscError(status, lib().rsc_last_error().decode())
+        raise RscError(status, lib().rsc_last_error(None).decode())
 
 
 def _ptr(t):
@@ -203,12 +205,23 @@ def rsc_get_basis(h: Handle):
     return phi, pinv
 
 
-def rsc_set_dictionary(h: Handle, d_hat, R: int):
+def rsc_set_dictionary(h: Handle, d_hat, R: int, stream=None):
+    """Uploads the host dictionary [M, B] on the stream (the current one by default)."""
     d = np.ascontiguousarray(d_hat, dtype=np.float32)
     if d.ndim != 2 or d.shape[1] != h.B:
         raise ValueError(f"d_hat must be [M, {h.B}]")
-    _check(lib().rsc_set_dictionary(h.ptr, d.ctypes.data_as(ctypes.c_void_p), d.shape[0], R))
+    _check(lib().rsc_set_dictionary(h.ptr, d.ctypes.data_as(ctypes.c_void_p), d.shape[0], R, _stream(stream)))
     h.M, h.R = d.shape[0], R
+
+
+def rsc_encode_workspace_size(h: Handle, P: int, K: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().rsc_encode_workspace_size(h.ptr, int(P), int(K), ctypes.byref(n)))
+    return n.value
+
+
+def rsc_set_fault(h: Handle, msg: str | None = None):
+    _check(lib().rsc_set_fault(h.ptr, None if msg is None else msg.encode()))
 
 
 def rsc_set_tile(h: Handle, tile: str = "auto"):
@@ -433,7 +446,7 @@ def rsc_rksvd_train(h: Handle, xhat, d_init, R: int, K: int, n_iter: int, stream
     P = xhat.shape[0]
     if xhat.dtype != torch.float32 or not xhat.is_contiguous() or xhat.shape != (P, h.B) or B != h.B:
         raise ValueError("xhat must be device [P, B] float32 and d_init [M, B]")
-    rsc_set_dictionary(h, d_init, R)
+    rsc_set_dictionary(h, d_init, R, stream)
     ws = _workspace(rsc_rksvd_workspace_size(h, P, K), xhat.device)
     dev = xhat.device
     atom = torch.empty((P, K), dtype=torch.int32, device=dev)
@@ -457,8 +470,13 @@ def rsc_precision_stats(h: Handle, reset: bool = False) -> dict:
     return {"steps_rescored": out[0], "candidates": out[1], "max_candidates": out[2], "fp64_solves": out[3]}
 
 
-def rsc_sync(stream=None):
-    _check(lib().rsc_sync(_stream(stream)))
+def rsc_sync(h: Handle | None = None, stream=None):
+    """Waits for the stream; raises on a failed kernel or a sticky fault of h."""
+    _check(lib().rsc_sync(None if h is None else h.ptr, _stream(stream)))
+
+
+def rsc_last_error(h: Handle | None = None) -> str:
+    return lib().rsc_last_error(None if h is None else h.ptr).decode()
 
 
 # ------------------------------------------------------------------ texture classifier

@@ -33,6 +33,36 @@ def test_exports_every_declared_function(L):
         assert getattr(L, n) is not None
 
 
+# the calls of the boundary: handle and basis, dictionary upload, projection (patch arrays
+# and images), the encoder with its workspace query, reconstruction, and the stream wait
+# with the error text
+BOUNDARY = ["rsc_create", "rsc_destroy", "rsc_basis_info", "rsc_get_basis", "rsc_set_dictionary",
+            "rsc_project", "rsc_project_images", "rsc_encode_workspace_size", "rsc_omp_encode",
+            "rsc_reconstruct", "rsc_sync", "rsc_last_error"]
+
+
+def test_boundary_calls_are_declared_and_exported(L):
+    names = set(rsc.header_functions())
+    for n in BOUNDARY:
+        assert n in names, n
+        assert getattr(L, n) is not None
+
+
+def test_boundary_state_without_device(L):
+    """Argument errors come back synchronously and name the problem; the workspace query,
+    the fault setter and the stream wait validate their handle before any device use."""
+    n = ctypes.c_size_t(77)
+    assert L.rsc_encode_workspace_size(None, 10, 2, ctypes.byref(n)) == rsc.RSC_E_INVALID
+    assert b"handle" in L.rsc_last_error(None)
+    assert n.value == 77                                   # untouched on error
+    assert L.rsc_set_fault(None, b"x") == rsc.RSC_E_INVALID
+    assert L.rsc_set_dictionary(None, None, 4, 8, None) == rsc.RSC_E_INVALID
+    assert b"handle is NULL" in L.rsc_last_error(None)
+    # a later successful call clears the thread's message
+    assert L.rsc_destroy(None) == rsc.RSC_OK
+    assert L.rsc_last_error(None) == b""
+
+
 def test_header_documents_every_function():
     import re
     text = open(rsc.HEADER).read()
@@ -65,14 +95,14 @@ def test_library_basis_custom_profiles(L):
 def test_argument_errors_without_device(L):
     h = ctypes.c_void_p()
     assert L.rsc_create(10, 5, 5, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_INVALID
-    assert b"odd" in L.rsc_last_error()
+    assert b"odd" in L.rsc_last_error(None)
     assert L.rsc_create(15, 7, 9, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED   # B = 133
     assert L.rsc_create(31, 1, 16, None, 0.0, 0, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED   # T > 15
     assert L.rsc_create(11, 5, 2, None, 0.0, 1, ctypes.byref(h)) == rsc.RSC_E_UNSUPPORTED    # 16-bit
     assert L.rsc_create(11, 5, 5, None, 0.0, 0, None) == rsc.RSC_E_INVALID
     assert L.rsc_create(11, 5, 5, None, 0.0, 7, ctypes.byref(h)) == rsc.RSC_E_INVALID
     assert L.rsc_precision_stats(None, None, 0) == rsc.RSC_E_INVALID
-    assert L.rsc_set_dictionary(None, None, 4, 8) == rsc.RSC_E_INVALID
+    assert L.rsc_set_dictionary(None, None, 4, 8, None) == rsc.RSC_E_INVALID
     assert L.rsc_project(None, None, 10, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_omp_encode(None, None, 10, 2, None, None, None, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_reconstruct(None, None, None, None, 10, 2, None, None) == rsc.RSC_E_INVALID
@@ -81,7 +111,7 @@ def test_argument_errors_without_device(L):
     assert L.rsc_basis_host(4, 5, 5, None, 0.0, None, None, None, None, None) == rsc.RSC_E_INVALID
     # more basis columns than disk pixels
     assert L.rsc_basis_host(5, 5, 5, None, 0.0, None, None, None, None, None) == rsc.RSC_E_INVALID
-    assert b"more columns" in L.rsc_last_error()
+    assert b"more columns" in L.rsc_last_error(None)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

@@ -63,7 +63,7 @@ def test_small_ragged_batch(dev, geom, M, R, K):
     assert err.max() < 2e-5
     rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code)
     print(f"ragged N={geom.N}", rep, flush=True)
-    assert rep.match_rate >= 0.999 and rep.coef_bad <= int(0.001 * rep.n)
+    assert rep.match_rate >= 0.999 and rep.coef_bad == 0, str(rep)
     h.close()
 
 
@@ -135,7 +135,7 @@ def test_batch_in_hip_graph(dev):
 
 def test_full_ragged_batch_sampled(dev):
     """All windows of the 256-image batch in one projection + one encode launch;
-    1,200 sampled windows checked against the reference."""
+    20,000 sampled windows checked against the reference."""
     from paper_1806_04374_amd import rsc
     w = wl.RAGGED
     geom = w["geom"]
@@ -150,7 +150,7 @@ def test_full_ragged_batch_sampled(dev):
     atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, w["K"])
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
-    idx = np.sort(rng.choice(batch.P_total, 1200, replace=False))
+    idx = np.sort(rng.choice(batch.P_total, 20000, replace=False))
     starts = np.concatenate([[0], np.cumsum(batch.patches_per_image)])
     patches = []
     for p in idx:
@@ -161,5 +161,5 @@ def test_full_ragged_batch_sampled(dev):
     _, code = orc.encode(basis, D, w["R"], np.stack(patches), w["K"])
     rep = compare_codes(atom.cpu().numpy()[idx], angle.cpu().numpy()[idx], coef.cpu().numpy()[idx], code)
     print("ragged-full-sampled", rep, flush=True)
-    assert rep.match_rate >= 0.995 and rep.coef_bad <= 2
+    assert rep.match_rate >= 0.999 and rep.coef_bad == 0, str(rep)
     h.close()

@@ -58,7 +58,7 @@ def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True, tile="auto"):
     rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
     print(label, rep, flush=True)
     assert rep.match_rate >= MATCH, (label, str(rep))
-    assert rep.coef_bad <= int((1 - MATCH) * rep.n), (label, str(rep))
+    assert rep.coef_bad == 0, (label, str(rep))
     if mse:
         rec = rsc.rsc_reconstruct(h, atom, angle, coef)
         torch.cuda.synchronize()
@@ -97,7 +97,8 @@ def test_scale_workload_ragged_slice(dev, tile):
 
 
 def test_scale_workload_full_size_sampled(dev):
-    """All 1,000,000 scale patches encoded in one launch; 1,500 sampled patches checked."""
+    """All 1,000,000 scale patches encoded in one launch (the benchmark's launch); 20,000
+    sampled patches and the last one checked against the reference."""
     from paper_1806_04374_amd import rsc
     w = wl.SCALE
     geom = w["geom"]
@@ -106,13 +107,13 @@ def test_scale_workload_full_size_sampled(dev):
     X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
     h = _handle(geom, D, w["R"])
     xh, atom, angle, coef, r2 = _encode(h, X, w["K"], dev)
-    idx = np.sort(np.random.default_rng(0).choice(len(X), 1500, replace=False))
+    idx = np.sort(np.random.default_rng(0).choice(len(X) - 1, 20000, replace=False))
     idx = np.concatenate([idx, [len(X) - 1]])
     _, code = orc.encode(basis, D, w["R"], X[idx].astype(np.float64), w["K"])
     rep = compare_codes(atom.cpu().numpy()[idx], angle.cpu().numpy()[idx], coef.cpu().numpy()[idx], code)
     print("scale-full-sampled", rep, flush=True)
-    assert rep.match_rate >= 0.995          # 1,501 samples: allows 7 near-tie mismatches
-    assert rep.coef_bad <= 2
+    assert rep.match_rate >= MATCH, str(rep)
+    assert rep.coef_bad == 0, str(rep)
     h.close()
 
 
@@ -199,7 +200,9 @@ def test_batch_position_invariance(dev, tile):
 
 
 def test_rotation_equivariance_on_device(dev):
-    """Rotating a patch inside the basis span by r0 grid steps shifts every angle by r0."""
+    """Rotating a patch inside the basis span by r0 grid steps shifts every angle by r0
+    (eq. (3)): exactly, on every patch whose reference top-2 gap stays above 1e-6 at each
+    step (a closer pair is decided by rounding)."""
     from paper_1806_04374_amd import rsc
     geom = wl.GEOM11
     M, R, K = 16, 32, 2
@@ -212,6 +215,9 @@ def test_rotation_equivariance_on_device(dev):
     h = _handle(geom, D, R)
     base = rsc.rsc_omp_encode(h, torch.from_numpy(v.astype(np.float32)).to(dev), K)
     torch.cuda.synchronize()
+    ref = orc.omp(orc.augmented_dictionary(D, R, 5, 5), v.astype(np.float32).astype(np.float64), K, M)
+    clear = np.array([np.all(ref.gap[p][ref.atom[p] >= 0] >= 1e-6) for p in range(len(v))])
+    assert clear.mean() > 0.95
     ok = tot = 0
     for r0 in (1, 8, 13):
         vr = orc.steer(v, 2 * np.pi * r0 / R, 5, 5).astype(np.float32)
@@ -219,12 +225,12 @@ def test_rotation_equivariance_on_device(dev):
         torch.cuda.synchronize()
         a0, g0 = base[0].cpu().numpy(), base[1].cpu().numpy()
         a1, g1 = rot[0].cpu().numpy(), rot[1].cpu().numpy()
-        for p in range(len(v)):
+        for p in np.flatnonzero(clear):
             tot += 1
             s0 = {(int(a), (int(g) + r0) % R) for a, g in zip(a0[p], g0[p]) if a >= 0}
             s1 = {(int(a), int(g)) for a, g in zip(a1[p], g1[p]) if a >= 0}
             ok += s0 == s1
-    assert ok >= 0.995 * tot, (ok, tot)
+    assert ok == tot, (ok, tot)
     h.close()
 
 
@@ -325,3 +331,27 @@ def test_projection_patch_arrays(dev, geom, P):
     rsc.rsc_project(h, torch.from_numpy(X).to(dev), xo[1:].view(P, geom.B))
     assert np.abs(xo[1:].view(P, geom.B).cpu().numpy()[:n] - ref).max() < tol
     h.close()
+
+
+@pytest.mark.parametrize("tile", ["16", "32"])
+def test_duplicate_atom_ties_go_to_smaller_index(dev, tile):
+    """Atom 1 is a copy of atom 0: every column of atom 1 ties exactly with the same column
+    of atom 0, so the smaller atom index must win every time.  The codes then equal, bit
+    for bit, those of the dictionary without the copy (indices above 1 shifted)."""
+    from paper_1806_04374_amd import rsc
+    geom = wl.GEOM11
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    M, R, K = 16, 32, 2
+    D = wl.draw_dictionary(M, geom.B, seed=7)
+    D[1] = D[0]
+    Dm = np.delete(D, 1, axis=0)
+    draw = wl.draw_mixtures(3000, geom.N, M, 2, 0.02, seed=7)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    h, hm = _handle(geom, D, R, tile), _handle(geom, Dm, R, tile)
+    a, g, c = (t.cpu().numpy() for t in _encode(h, X, K, dev)[1:4])
+    am, gm, cm = (t.cpu().numpy() for t in _encode(hm, X, K, dev)[1:4])
+    assert (a == 1).sum() == 0 and (a == 0).sum() > 0
+    assert np.array_equal(a, np.where(am >= 1, am + 1, am))
+    assert np.array_equal(g, gm) and np.array_equal(c, cm)
+    h.close()
+    hm.close()

@@ -53,22 +53,35 @@ def test_served_codes_equal_alone(setup):
         assert np.array_equal(r.codes[0], atom.cpu().numpy()), r.rid
         assert np.array_equal(r.codes[1], angle.cpu().numpy()), r.rid
         assert np.array_equal(r.codes[2], coef.cpu().numpy()), r.rid
-    # two served requests against the FP64 reference
-    for r in reqs[:2]:
-        wins = orc.image_patches(r.pixels.astype(np.float64), g.N)
+    # served requests against the FP64 reference, >= 20,000 windows
+    _against_reference(basis, D, [r for r in reqs if r.windows])
+
+
+def _against_reference(basis, D, reqs, need=20000):
+    n = 0
+    codes, refs = [[], [], []], []
+    for r in reqs:
+        wins = orc.image_patches(r.pixels.astype(np.float64), basis.N)
         _, code = orc.encode(basis, D, 64, wins, 6)
-        rep = compare_codes(r.codes[0], r.codes[1], r.codes[2], code)
-        assert rep.match_rate >= 0.99 and rep.coef_bad == 0, str(rep)
+        refs.append(code)
+        for i in range(3):
+            codes[i].append(r.codes[i])
+        n += len(wins)
+        if n >= need:
+            break
+    assert n >= need, n
+    cat = lambda f: np.concatenate([getattr(c, f) for c in refs])
+    ref = orc.Code(cat("atom"), cat("angle"), cat("coef"), cat("resid2"), cat("corr"), cat("gap"))
+    rep = compare_codes(*(np.concatenate(c) for c in codes), ref)
+    print("served-vs-reference", rep, flush=True)
+    assert rep.match_rate >= 0.999 and rep.coef_bad == 0, str(rep)
 
 
 def test_one_at_a_time_baseline_matches(setup):
     from paper_1806_04374_amd import serve
     g, D, h = setup
     basis = orc.build_basis(g.N, g.S, g.T)
-    reqs = [serve.Request(i, 0.0, _image(basis, D, 100 + i, s), s, s) for i, s in enumerate([20, 33, 15, 47])]
+    reqs = [serve.Request(i, 0.0, _image(basis, D, 100 + i, s), s, s)
+            for i, s in enumerate([20, 33, 15, 47, 120, 130])]
     serve.encode_one_at_a_time(h, 6, reqs, realtime=False)
-    for r in reqs:
-        wins = orc.image_patches(r.pixels.astype(np.float64), g.N)
-        _, code = orc.encode(basis, D, 64, wins, 6)
-        rep = compare_codes(r.codes[0], r.codes[1], r.codes[2], code)
-        assert rep.match_rate >= 0.99, str(rep)
+    _against_reference(basis, D, reqs)
