@@ -55,7 +55,8 @@ def _check(label, X32, D, R, K, geom, dev, basis=None, mse=True, tile="auto"):
     # projection parity (FP32 GEMM against FP64 least squares)
     err = np.abs(xh.cpu().numpy() - xh_ref).max(axis=1) / np.maximum(np.linalg.norm(xh_ref, axis=1), 1e-30)
     assert err.max() < 2e-5, (label, err.max())
-    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL,
+                        xnorm=np.linalg.norm(xh_ref, axis=1))
     print(label, rep, flush=True)
     assert rep.match_rate >= MATCH, (label, str(rep))
     assert rep.coef_bad == 0, (label, str(rep))

@@ -59,8 +59,9 @@ def _check(label, X32, D, R, K, geom, dev, prec, basis=None):
     rsc.rsc_precision_stats(h, reset=True)
     atom, angle, coef, r2 = _run(h, X32, K, dev, basis)
     stats = rsc.rsc_precision_stats(h)
-    _, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
-    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    xh_ref, code = orc.encode(basis, D, R, X32.astype(np.float64), K)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL,
+                        xnorm=np.linalg.norm(xh_ref, axis=1))
     print(label, prec, rep, stats, flush=True)
     assert rep.match_rate >= MATCH, (label, prec, str(rep))
     assert rep.coef_bad == 0, (label, prec, str(rep))

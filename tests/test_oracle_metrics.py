@@ -184,3 +184,21 @@ def test_planted_angle_first_tie_rule_is_caught():
     absc[0 * M + 1] = absc[2 * M + 0] = 1.0
     angle_first = int(np.flatnonzero(absc == absc.max())[0])     # smallest j = r M + m
     assert angle_first != _pick_ref(list(absc), M)
+
+
+# ----------------------------------------------------------------------------- parity helper
+def test_parity_floor_for_coefficients_tiny_against_their_patch():
+    """The coefficient check of the device tests: 1e-4 relative, floored at 1e-3 of the
+    largest coefficient and, when given, at 1e-2 of the patch's coordinate norm."""
+    from tests.parity import compare_codes
+    ref = orc.Code(np.array([[0, -1], [1, 2]]), np.array([[3, -1], [0, 5]]),
+                   np.array([[8e-4, 0.0], [1.0, 0.5]]), np.zeros(2), np.zeros((2, 2)), np.zeros((2, 2)))
+    atom, angle = ref.atom.copy(), ref.angle.copy()
+    coef = ref.coef.copy()
+    coef[0, 0] += 3e-7                                  # 3.75e-4 of itself, 2e-7 of ||x_hat|| = 1.4
+    assert compare_codes(atom, angle, coef, ref).coef_bad == 1
+    assert compare_codes(atom, angle, coef, ref, xnorm=np.array([1.4, 1.2])).coef_bad == 0
+    coef[1, 1] += 1e-4                                  # 2e-4 relative on a coefficient of 0.5
+    assert compare_codes(atom, angle, coef, ref, xnorm=np.array([1.4, 1.2])).coef_bad == 1
+    coef[0, 0] += 3e-5                                  # now 2e-5 of ||x_hat||: beyond the floor
+    assert compare_codes(atom, angle, coef, ref, xnorm=np.array([1.4, 1.2])).coef_bad == 2
