@@ -330,6 +330,19 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
                               void* workspace, size_t ws_bytes, float* xhat, void* stream);
 
 /*
+ * rsc_project_images without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the per-image plan lives in a static device array of the library
+ * (1 MiB per device, held until the process ends), so this call allocates nothing.
+ * Arguments, numbering and results as rsc_project_images; n_images <= 65535
+ * (RSC_E_INVALID above).  Every call on one device shares that array: calls that overlap
+ * on one device (concurrent streams or threads) race and must be ordered by the caller.
+ */
+rsc_status rsc_project_images_noalloc(const rsc_handle* h, const float* pixels, const int64_t* img_offset,
+                                      const int32_t* H, const int32_t* W, int n_images, int64_t P_total,
+                                      float* xhat, void* stream);
+
+/*
  * Adds synthetic stamps to images: for stamp s, amplitude[s] * Phi S(theta[s]) d_{atom[s]}
  * (an N x N patch, zero off the disk) is added with its centre pixel at
  * centre[s] = (row, col) of image image[s], clipped at the image borders.  pixels must be

@@ -989,6 +989,25 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
   return e ? handle_fail(h, e, "image projection launch") : ok();
 }
 
+rsc_status rsc_project_images_noalloc(const rsc_handle* h, const float* pixels, const int64_t* img_offset,
+                                      const int32_t* H, const int32_t* W, int n_images, int64_t P_total,
+                                      float* xhat, void* stream) {
+  if (!h) return fail(RSC_E_INVALID, "handle is NULL");
+  if (n_images < 0 || n_images > rsc::kNoAllocMaxImages)
+    return fail(RSC_E_INVALID, "n_images must be in 0.." + std::to_string(rsc::kNoAllocMaxImages) +
+                                   " (the size of the library's static plan buffer)");
+  if (P_total < 0) return fail(RSC_E_INVALID, "P_total must be >= 0");
+  if (n_images == 0 || P_total == 0) return ok();
+  if (!pixels || !img_offset || !H || !W || !xhat) return fail(RSC_E_INVALID, "null device pointer");
+  if (h->annular || !((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
+      !rsc::encode_supported(h->dev.S, h->dev.T))
+    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
+                                   "geometries");
+  if (rsc_status f = check_fault(h)) return f;
+  int e = rsc::launch_project_images_noalloc(h->dev, pixels, img_offset, H, W, n_images, P_total, xhat, stream);
+  return e ? handle_fail(h, e, "image projection launch") : ok();
+}
+
 rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const float* theta,
                                  const float* amplitude, const int32_t* centre, const int32_t* image,
                                  int64_t n_stamps, const int64_t* img_offset, const int32_t* H,

@@ -12,6 +12,8 @@
 //    inputs), one block per stamp.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "rsc_device.h"
 #include "rsc_internal.h"
 
@@ -287,6 +289,49 @@ int launch_project_images(const DeviceTables& t, const float* pixels, const int6
   if (t.N == 15 && t.n_pix == 177 && t.B > 64 && t.B <= 128)
     return go_reg(project_images_reg_kernel<15, 89, 4, 2>, 4);
   return int(hipErrorInvalidValue);
+}
+
+// Plan of rsc_project_images_noalloc: the two prefix-sum arrays of images_plan_kernel for
+// up to kNoAllocMaxImages images (1 MiB), held by every device the library runs on until
+// the process ends.  Every call on a device shares its copy: the plan kernel writes every
+// entry the projection reads, so nothing needs clearing, and calls that overlap on one
+// device race.  In host code `scratch` is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) int64_t scratch[2 * (kNoAllocMaxImages + 1)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up on the first call per device).
+int scratch_address(int64_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return int(e);
+  if (dev < 0 || dev >= kMaxDevices) return int(hipErrorInvalidDevice);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return int(e);
+    if (!p) return int(hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = static_cast<int64_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+}  // namespace
+
+int launch_project_images_noalloc(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
+                                  const int32_t* H, const int32_t* W, int n, int64_t P_total, float* xhat,
+                                  void* stream) {
+  if (n > kNoAllocMaxImages) return int(hipErrorInvalidValue);
+  if (n <= 0 || P_total <= 0) return 0;
+  int64_t* ws = nullptr;
+  const int e = scratch_address(&ws);
+  if (e) return e;
+  return launch_project_images(t, pixels, img_offset, H, W, n, P_total, ws, xhat, stream);
 }
 
 int launch_stamps(const DeviceTables& t, const int32_t* atom, const float* theta, const float* amplitude,

@@ -45,8 +45,8 @@ struct DeviceTables {
                              // ((k << 16) | (offset + 32768)); null for the full (S, T) grid
   float* phiPad = nullptr;   // synthesis matrix [N*N][B]
   float* synA = nullptr;     // synthesis MFMA operand [ceil(N*N/32)][ceil(B/2)][64] (N*N <= 256)
-  // Dictionary tables (dictA .. cs64 below) live in one device arena, refilled in place by
-  // every dictionary upload of the same or a smaller size.
+  // Dictionary tables (dictA .. cs64 below) point into the bound one of the handle's two
+  // device copies (dictArena, dictArenaBytes); each upload fills the other copy.
   void* dictArena = nullptr;
   size_t dictArenaBytes = 0;
   float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
@@ -118,6 +118,11 @@ double encode_lp_mfma_flops_per_patch(const DeviceTables& t, int K);
 int launch_encode_lp(const DeviceTables& t, int prec, const float* xhat, int64_t P, int K, int32_t* atom,
                      int32_t* angle, float* coef, float* resid2, void* stream);
 size_t images_workspace_bytes(int n_images);
+// rsc_project_images_noalloc: the plan in a static device array of this many images.
+constexpr int kNoAllocMaxImages = 65535;
+int launch_project_images_noalloc(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
+                                  const int32_t* H, const int32_t* W, int n, int64_t P_total, float* xhat,
+                                  void* stream);
 int launch_project_images(const DeviceTables& t, const float* pixels, const int64_t* img_offset,
                           const int32_t* H, const int32_t* W, int n, int64_t P_total, void* ws, float* xhat,
                           void* stream);

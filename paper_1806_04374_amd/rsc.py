@@ -63,6 +63,7 @@ def lib():
         "rsc_sync": [P, P],
         "rsc_images_workspace_size": [I, P],
         "rsc_project_images": [P, P, P, P, P, I, I64, P, ctypes.c_size_t, P, P],
+        "rsc_project_images_noalloc": [P, P, P, P, P, I, I64, P, P],
         "rsc_synthesize_images": [P, P, P, P, P, P, I64, P, P, P, I, P, P],
         "rsc_precision_stats": [P, P, I],
         "rsc_rksvd_workspace_size": [P, I64, I, P],
@@ -381,6 +382,21 @@ def rsc_project_images(h: Handle, pixels, batch: "ImageBatch", xhat=None, stream
     _check(lib().rsc_project_images(h.ptr, _ptr(pixels), _ptr(batch.d_offset), _ptr(batch.d_H),
                                     _ptr(batch.d_W), batch.n, batch.P_total, _ptr(batch.workspace),
                                     batch.ws_bytes, _ptr(xhat), _stream(stream)))
+    return xhat
+
+
+def rsc_project_images_noalloc(h: Handle, pixels, batch: "ImageBatch", xhat, stream=None):
+    """rsc_project_images through the entry point that allocates nothing (the plan lives
+    in the library's static device buffer; batch.workspace is not used).  xhat must be
+    given: device [P_total, B] float32."""
+    import torch
+    _dev(pixels, torch.float32, "pixels")
+    if pixels.dim() != 1 or pixels.shape[0] < batch.min_pixels:
+        raise ValueError(f"pixels must be 1-D with at least {batch.min_pixels} elements")
+    _dev(xhat, torch.float32, "xhat", (batch.P_total, h.B))
+    _check(lib().rsc_project_images_noalloc(h.ptr, _ptr(pixels), _ptr(batch.d_offset), _ptr(batch.d_H),
+                                            _ptr(batch.d_W), batch.n, batch.P_total, _ptr(xhat),
+                                            _stream(stream)))
     return xhat
 
 

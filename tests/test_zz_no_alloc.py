@@ -1,0 +1,54 @@
+"""rsc_project_images_noalloc (the entry point that allocates nothing) against
+rsc_project_images with a caller workspace: bit-identical coordinates on two calls in a
+row, the second with a smaller batch, and the size limit of its static plan buffer."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1806_04374_amd import rsc
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _batch(sizes, N, seed):
+    rng = np.random.default_rng(seed)
+    b = rsc.ImageBatch(sizes, N, DEV)
+    pix = torch.from_numpy(rng.standard_normal(b.total_pixels).astype(np.float32)).to(DEV)
+    return b, pix
+
+
+@pytest.mark.parametrize("geom", [(11, 5, 5), (15, 7, 7)])
+def test_noalloc_matches_workspace_projection(geom):
+    N, S, T = geom
+    h = rsc.rsc_create(N, S, T)
+    rng = np.random.default_rng(N)
+    big = [(int(a), int(b)) for a, b in rng.integers(N - 2, 300, (300, 2))] + [(N, N), (5, 400), (400, 5)]
+    small = [(int(a), int(b)) for a, b in rng.integers(N, 90, (7, 2))]
+    for sizes, seed in ((big, 1), (small, 2)):             # the second call: fewer, smaller images
+        b, pix = _batch(sizes, N, seed)
+        ref = rsc.rsc_project_images(h, pix, b)
+        out = torch.full((b.P_total, h.B), float("nan"), dtype=torch.float32, device=DEV)
+        rsc.rsc_project_images_noalloc(h, pix, b, out)
+        torch.cuda.synchronize()
+        assert b.P_total > 0
+        assert torch.equal(out, ref)
+    h.close()
+
+
+def test_noalloc_limits():
+    h = rsc.rsc_create(11, 5, 5)
+    b, pix = _batch([(20, 20)], 11, 3)
+    out = torch.empty((b.P_total, h.B), dtype=torch.float32, device=DEV)
+    L = rsc.lib()
+    args = (rsc._ptr(pix), rsc._ptr(b.d_offset), rsc._ptr(b.d_H), rsc._ptr(b.d_W))
+    # more images than the static plan holds: refused before anything is launched
+    st = L.rsc_project_images_noalloc(h.ptr, *args, 65536, b.P_total, rsc._ptr(out), rsc._stream(None))
+    assert st == rsc.RSC_E_INVALID
+    assert "65535" in rsc.rsc_last_error()
+    assert L.rsc_project_images_noalloc(h.ptr, *args, -1, b.P_total, rsc._ptr(out), rsc._stream(None)) \
+        == rsc.RSC_E_INVALID
+    # nothing to do is a no-op
+    assert L.rsc_project_images_noalloc(h.ptr, *args, 0, 0, rsc._ptr(out), rsc._stream(None)) == rsc.RSC_OK
+    h.close()
