@@ -538,24 +538,27 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
   const int NG = (M + 15) / 16;
   const int K0 = rsc::k0_steps(S), NKS = rsc::stage1_steps(S, T), NQ = T + 1;
   auto D = [&](int m, int c) -> float { return m < M ? d_hat[size_t(m) * B + c] : 0.f; };
-  // 32x32 tiles, stage-1 operand: rows 0..15 give Re C_k of atoms 16g..16g+15, rows
-  // 16..31 Im C_k; the two contraction lanes of a step are (Re, Im) of one profile
-  // (k >= 1) or two consecutive profiles (k = 0, where rows 16..31 are zero).
+  // 32x32 tiles, stage-1 operand: row 8i + j (j < 4) gives Re C_k of atom 16g + 4i + j and
+  // row 8i + 4 + j its Im C_k, so that the accumulator register of an atom holds its Re C_k
+  // in the low half-wave and its Im C_k in the high one; the two contraction lanes of a
+  // step are (Re, Im) of one profile (k >= 1) or two consecutive profiles (k = 0, where
+  // the Im rows are zero).
   std::vector<float> dictA;
   if (S == 5 && T == 5) {
     dictA.assign(size_t(NG) * NKS * 64, 0.f);
     for (int g = 0; g < NG; ++g)
       for (int ks = 0; ks < NKS; ++ks)
         for (int l = 0; l < 64; ++l) {
-          const int row = l % 32, hh = l / 32, a = row % 16, m = 16 * g + a;
+          const int row = l % 32, hh = l / 32, a = 4 * (row / 8) + row % 4, m = 16 * g + a;
+          const bool im_row = (row / 4) % 2 == 1;
           float v = 0.f;
           if (ks < K0) {
             const int s = 2 * ks + hh;
-            if (row < 16 && s < S) v = D(m, s);
+            if (!im_row && s < S) v = D(m, s);
           } else {
             const int q = ks - K0, k = 1 + q / S, s = q % S, base = S + 2 * S * (k - 1);
             const float re = D(m, base + s), im = D(m, base + S + s);
-            if (row < 16) v = hh == 0 ? re : im;
+            if (!im_row) v = hh == 0 ? re : im;
             else v = hh == 0 ? -im : re;
           }
           dictA[(size_t(g) * NKS + ks) * 64 + l] = v;

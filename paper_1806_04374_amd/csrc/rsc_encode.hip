@@ -6,9 +6,10 @@
 //       diagonal per harmonic (eq. (8)), so
 //         <S_r d_m, x> = C_0 + sum_{k>=1} [cos(2 pi k r/R) Re C_k - sin(2 pi k r/R) Im C_k],
 //         C_k = sum_s conj(d_{m,s,k}) x_{s,k}.
-//       Stage 1 forms Re C_k and Im C_k on MFMA (rows: atoms x {Re, Im}); a
-//       cross-lane swap turns its accumulators into the operand of stage 2, the
-//       angle DFT on MFMA (rows: angles).  For even R the DFT is split by harmonic
+//       Stage 1 forms Re C_k and Im C_k on MFMA (rows: atoms x {Re, Im}); its
+//       accumulators are the operand of stage 2 (as they stand with the 32x32 tiles'
+//       row order, after a cross-lane swap with the 16x16 tiles), the angle DFT on MFMA
+//       (rows: angles).  For even R the DFT is split by harmonic
 //       parity (one radix-2 step): with E(r) the sum over even k and O(r) over odd k,
 //       score(r) = E(r) + O(r) and score(r + R/2) = E(r) - O(r), so only R/2 angle
 //       rows are computed, and the largest |score| of an atom over all R angles is
@@ -127,23 +128,15 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           const int k = L::harm(j);
           acc[k] = mfma32(Ag[j * 64], res[j], acc[k]);
         }
-        // rows 0..15: Re C of atoms 0..15, rows 16..31: Im C.  After the swap,
-        // register v < 8 is the stage-2 operand [Re | Im] of atom 8(v/4)+v%4 and
-        // register v+8 that of atom 8(v/4)+v%4+4.
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-          for (int v = 0; v < 8; ++v) {
-            float x = acc[q][v], y = acc[q][v + 8];
-            swap32(x, y);
-            acc[q][v] = x;
-            acc[q][v + 8] = y;
-          }
+        // Operand rows 8i..8i+3 give Re C of atoms 4i..4i+3 and rows 8i+4..8i+7 their Im C.
+        // In the accumulator layout register a of the low half-wave then holds Re C of atom
+        // a and register a of the high half-wave its Im C: acc[q][a] is the stage-2 operand
+        // [Re | Im] of atom a as it stands, with no data movement.
         // Per atom: E (even harmonics) and O (odd harmonics) chains; the E chain of
         // the next atom is issued before the reduction of the current one.  Atoms
         // past M have all-zero operands: their scores are exactly 0 and never beat
         // the first atom under the strict '>'.
-        auto vreg = [](int a) { return 4 * (a / 8) + (a % 4) + 8 * ((a / 4) % 2); };
+        auto vreg = [](int a) { return a; };
         auto chain = [&](int a, int parity) {
           f32x16 o;
 #pragma unroll
