@@ -112,6 +112,51 @@ struct Layout {
   }
 };
 
+// Stage-2 operand of atom m for this lane's patch in the two-half-wave layout (W = 2):
+// op[k] = Re C_k in the low half-wave and Im C_k in the high one, C_k = sum_s conj(d_{m,s,k})
+// x_{s,k}, from the atom's row of the packed dictionary.  Each half-wave multiplies its
+// residual coordinates (Re parts in the low half, Im parts in the high one; profiles 2j + u
+// of harmonic 0) with the matching parts of the atom, and one swap per harmonic adds the
+// two halves' partial sums into the operand layout.  Padding coordinates of the residual
+// are 0, so what the atom row holds there does not matter.
+template <class L>
+__device__ __forceinline__ void atom_operand(const float* __restrict__ hat, int m, int u,
+                                             const float (&res)[L::NKS], float (&op)[L::NQ]) {
+  static_assert(L::W == 2, "two half-waves per patch");
+  const float* d = hat + m * L::B;
+  float p0 = 0.f;
+#pragma unroll
+  for (int j = 0; j < L::J0; ++j) {
+    const int s = 2 * j + u;
+    p0 = fmaf(d[s < L::S ? s : 0], res[j], p0);
+  }
+  {
+    float x = p0, y = 0.f;
+    swap32(x, y);
+    op[0] = x + y;
+  }
+  // low half-wave (Re parts): Re += dRe r, Im -= dIm r; high half-wave (Im parts):
+  // Re += dIm r, Im += dRe r
+  const float* dA = d + (u ? L::S : 0);
+  const float* dB = d + (u ? 0 : L::S);
+  const float sg = u ? 1.f : -1.f;
+#pragma unroll
+  for (int k = 1; k <= L::T; ++k) {
+    float pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < L::J1; ++jj) {
+      const int j = L::J0 + (k - 1) * L::J1 + jj;
+      if (jj < L::S) {
+        pr = fmaf(dA[L::base(k) + jj], res[j], pr);
+        pi = fmaf(dB[L::base(k) + jj], res[j], pi);
+      }
+    }
+    float x = pr, y = sg * pi;
+    swap32(x, y);
+    op[k] = x + y;
+  }
+}
+
 // Sum over the W lanes of a patch; bit-identical in all of them.
 template <int W>
 __device__ __forceinline__ float patch_sum(float x) {
@@ -120,33 +165,43 @@ __device__ __forceinline__ float patch_sum(float x) {
 }
 
 // acc += alpha * S_r d_m on the coordinates sub-lane u holds (steering computed on
-// the fly, nothing else kept in registers).
+// the fly, nothing else kept in registers).  Steering multiplies harmonic k by
+// e^{-i k theta}: Re' = c Re + s Im, Im' = c Im - s Re.  A lane reads its own part of the
+// atom's pair (pA: Re on Re lanes, Im on Im lanes) and the other part (pB), with alpha
+// folded into the harmonic's two factors, so a coordinate costs two fused multiply-adds.
 template <class L>
 __device__ __forceinline__ void steer_axpy(float (&acc)[L::NKS], float alpha, const float* __restrict__ hat,
                                            const float* __restrict__ cs, int R, int m, int r, int u) {
   const float* d = hat + m * L::B;
-  float c[L::NQ], s[L::NQ];
+  // harmonic 0: profile W j + u
+#pragma unroll
+  for (int j = 0; j < L::J0; ++j) {
+    const int s = L::W * j + u;
+    const bool valid = s < L::S;
+    acc[j] = fmaf(valid ? alpha : 0.f, d[valid ? s : 0], acc[j]);
+  }
+  const int pt = L::part(u), so = L::soff(u);
+  const float* pA = d + (pt ? L::S : 0) + so;
+  const float* pB = d + (pt ? 0 : L::S) + so;
+  const float as = pt ? -alpha : alpha;
 #pragma unroll
   for (int k = 1; k <= L::T; ++k) {
-    c[k] = cs[k * R + r];
-    s[k] = cs[(L::NQ + k) * R + r];
-  }
+    const float ck = alpha * cs[k * R + r];
+    const float sk = as * cs[(L::NQ + k) * R + r];
 #pragma unroll
-  for (int j = 0; j < L::NKS; ++j) {
-    const int k = L::harm(j);
-    const int p = L::prof(j, u);
-    const bool valid = p < L::S;
-    const int pc = valid ? p : 0;
-    float v;
-    if (k == 0) {
-      v = d[pc];
-    } else {
-      const int pt = L::part(u);
-      const float ca = pt ? -s[k] : c[k];
-      const float cb = pt ? c[k] : s[k];
-      v = d[L::base(k) + pc] * ca + d[L::base(k) + L::S + pc] * cb;
+    for (int jj = 0; jj < L::J1; ++jj) {
+      const int j = L::J0 + (k - 1) * L::J1 + jj;
+      if (L::SW * jj >= L::S) continue;                 // padding in every lane
+      float a = ck, b = sk;
+      int off = L::base(k) + L::SW * jj;
+      if (L::SW * jj + L::SW - 1 >= L::S) {             // padding in some lanes
+        const bool valid = L::SW * jj + so < L::S;
+        a = valid ? a : 0.f;
+        b = valid ? b : 0.f;
+        off = valid ? off : L::base(k);
+      }
+      acc[j] = fmaf(pA[off], a, fmaf(pB[off], b, acc[j]));
     }
-    acc[j] = fmaf(valid ? alpha : 0.f, v, acc[j]);
   }
 }
 

@@ -14,9 +14,11 @@
 //       score(r) = E(r) + O(r) and score(r + R/2) = E(r) - O(r), so only R/2 angle
 //       rows are computed, and the largest |score| of an atom over all R angles is
 //       max_r (|E(r)| + |O(r)|), bit-identical to the maximum of the rounded scores.
-//       The argmax runs in two passes: per atom only that maximum is compared and the
-//       winning atom's stage-2 operand kept; its angles are then recomputed with the
-//       same instructions (bit-identical scores) and searched.  Exact ties go to the
+//       The argmax runs in two passes: per atom only that maximum is compared; the
+//       winning atom's angles are then recomputed and searched (16x16 tiles: from its
+//       stage-2 operand kept in pass 1, with the same instructions; 32x32 tiles: from its
+//       operand formed again from its dictionary row, which costs one product per
+//       coordinate per step instead of a register copy per atom).  Exact ties go to the
 //       smallest atom, then the smallest angle.
 //   (c) extends the Cholesky factor of the selected columns, solves the least
 //       squares and updates the residual, all in registers.
@@ -114,8 +116,6 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
       // ---------------- (b) pass 1: best atom by its maximum over all angles
       float best = -1.f;
       int bm = 0;
-      float bop[NQ];
-      zero(bop);
       for (int g = 0; g < NG; ++g) {
         const float* Ag = sA + g * NKS * 64 + lane;
         f32x16 acc[NQ];
@@ -145,11 +145,9 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           for (int q = parity; q < NQ; q += 2) o = mfma32(F[q], acc[q][vreg(a)], o);
           return o;
         };
-        // the winner inside the group is kept as a constant (ba) and a lane mask (upd), and
-        // turned into the atom index once per group
+        // each half-wave's maximum of every atom first (16 angle rows per lane)
+        float amh[16];
         f32x16 e_cur = chain(0, 0), o_cur = chain(0, 1);
-        int ba = 0;
-        bool upd = false;
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
           f32x16 e_next;
@@ -157,31 +155,52 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           float am = fabsf(e_cur[0]) + fabsf(o_cur[0]);
 #pragma unroll
           for (int i = 1; i < 16; ++i) am = fmaxf(am, fabsf(e_cur[i]) + fabsf(o_cur[i]));
-          am = max_halves_nonneg(am);
-          const bool gt = am > best;
-          best = gt ? am : best;
-          ba = gt ? a : ba;
-          upd = upd || gt;
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) bop[q] = gt ? acc[q][vreg(a)] : bop[q];
+          amh[a] = am;
           if (a + 1 < 16) {
             o_cur = chain(a + 1, 1);
             e_cur = e_next;
           }
         }
+        // then the maximum over both half-waves, two atoms per swap: [a_lo | a_hi] and
+        // [b_lo | b_hi] give [A | B] (A, B the atoms' maxima), and one more swap of [A | B]
+        // with itself broadcasts [A | A] and [B | B] (non-negative floats compared as integers)
+        float amx[16];
+#pragma unroll
+        for (int a = 0; a < 16; a += 2) {
+          float x = amh[a], y = amh[a + 1];
+          swap32(x, y);
+          float m1 = __uint_as_float(max(__float_as_uint(x), __float_as_uint(y))), m2 = m1;
+          swap32(m1, m2);
+          amx[a] = m1;
+          amx[a + 1] = m2;
+        }
+        // the winner inside the group is kept as a constant (ba) and a lane mask (upd), and
+        // turned into the atom index once per group
+        int ba = 0;
+        bool upd = false;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+          const bool gt = amx[a] > best;
+          best = gt ? amx[a] : best;
+          ba = gt ? a : ba;
+          upd = upd || gt;
+        }
         bm = upd ? g * 16 + ba : bm;
       }
-      // ---------------- (b) pass 2: angles of the best atom, same arithmetic
+      // ---------------- (b) pass 2: angles of the best atom, its stage-2 operand formed
+      // again from its dictionary row (no per-atom copy is kept in pass 1)
       int rs;
       float cval;
       {
+        float op[NQ];
+        atom_operand<L>(sHat, bm, u, res, op);
         f32x16 e, o;
 #pragma unroll
         for (int i = 0; i < 16; ++i) e[i] = o[i] = 0.f;
 #pragma unroll
-        for (int q = 0; q < NQ; q += 2) e = mfma32(F[q], bop[q], e);
+        for (int q = 0; q < NQ; q += 2) e = mfma32(F[q], op[q], e);
 #pragma unroll
-        for (int q = 1; q < NQ; q += 2) o = mfma32(F[q], bop[q], o);
+        for (int q = 1; q < NQ; q += 2) o = mfma32(F[q], op[q], o);
         float rb = -1.f, rv = 0.f;
         int rc = 0;
 #pragma unroll
