@@ -266,11 +266,18 @@ rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size
  *
  * BF16 / FP16 handles: the correlations of every (atom, angle) are formed with
  * 16-bit operands and FP32 accumulation; every atom whose 16-bit maximum over the
- * angles lies within 4u ||residual|| of the largest one (u = 2^-8 for BF16, 2^-11
- * for FP16) is re-scored over all angles in FP32, and the selection is taken from
- * the FP32 scores.  The least squares run in FP32 while an upper bound on the
- * condition number of the selected columns' Gram matrix, k ||L^{-1}||_F^2, stays
- * <= 1e6; above it the patch's least squares are re-solved in FP64 from then on.
+ * angles lies within 8.5u ||residual|| of the largest one (u = 2^-8 for BF16, 2^-11
+ * for FP16; above twice a worst-case bound, 4.02u ||residual||, on the 16-bit error of
+ * a score, so the atom with the exact maximum is always among them) is re-scored over
+ * all angles in FP32, and the selection is taken from the FP32 scores.
+ *
+ * Least squares (every handle): a Cholesky update in FP32 while an upper bound on the
+ * condition number of the selected columns' Gram matrix, k ||L^{-1}||_F^2, stays at or
+ * below 1e3 (FP32 handles) or 1e6 (BF16 / FP16 handles) and the new pivot is above 1e-6 of
+ * the column's squared norm; otherwise the patch's least squares are re-solved from scratch
+ * in FP64 for this and every later step.  A column whose FP64 pivot is at most 1e-14 of its
+ * squared norm (numerically inside the span of the selected ones) ends the patch's
+ * pursuit.  rsc_precision_stats counts the FP64 steps.
  */
 rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K,
                           int32_t* atom, int32_t* angle, float* coef, float* resid2,
@@ -534,16 +541,16 @@ rsc_status rsc_steer(const rsc_handle* h, const float* xhat, int64_t P, const fl
 rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P, float* pixels, void* stream);
 
 /*
- * Counters of the BF16 / FP16 encoder, accumulated over its launches on this handle
- * (the FP32 re-scoring of candidates and the FP64 least-squares fallback described
- * at rsc_omp_encode):
- *   out[0]  pursuit steps (patch x step) that re-scored candidates
- *   out[1]  candidates re-scored in FP32, summed over those steps
- *   out[2]  largest number of candidates in one step
- *   out[3]  steps whose least squares went to the FP64 solve
+ * Counters of the encoder, accumulated over its launches on this handle (the FP32
+ * re-scoring of candidates of the 16-bit forms and the FP64 least-squares fallback
+ * described at rsc_omp_encode):
+ *   out[0]  pursuit steps (patch x step) that re-scored candidates (16-bit handles; else 0)
+ *   out[1]  candidates re-scored in FP32, summed over those steps (16-bit handles; else 0)
+ *   out[2]  largest number of candidates in one step (16-bit handles; else 0)
+ *   out[3]  steps whose least squares went to the FP64 solve (every handle)
  *   out     host [4] int64, or NULL; reset != 0 clears the counters after reading.
  * Blocking: waits for the whole device first.  Launches that overlap the call may
- * or may not be counted.  RSC_E_UNSUPPORTED for FP32 handles.
+ * or may not be counted.
  */
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset);
 

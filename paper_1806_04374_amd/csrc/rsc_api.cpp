@@ -280,7 +280,7 @@ rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
   if (s == RSC_OK) s = upload(d.pinvI, pinvI, "image projection table");
   if (s == RSC_OK) s = upload(d.dpixI, dpixI, "image pixel table");
   d.prec = prec;
-  if (s == RSC_OK && prec != RSC_FP32) s = upload(d.lpStats, std::vector<unsigned long long>(4, 0ull), "counters");
+  if (s == RSC_OK) s = upload(d.lpStats, std::vector<unsigned long long>(4, 0ull), "counters");
   if (s == RSC_OK && prec != RSC_FP32 && b.B <= 64) {
     // compensated 16-bit projection operand: pinv split into 16-bit parts, each the
     // rounding of what the previous parts leave (3 parts for BF16, 2 for FP16)
@@ -624,14 +624,14 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
   const int HQ = 2 * T + 1;
   const bool lp = h->prec != RSC_FP32;
   std::vector<float> gramH(size_t(M) * M * HQ);
-  std::vector<double> gramH64(lp ? gramH.size() : 0);
+  std::vector<double> gramH64(gramH.size());
   for (int a = 0; a < M; ++a)
     for (int bb = 0; bb < M; ++bb) {
       float* hh = &gramH[(size_t(a) * M + bb) * HQ];
       double h0 = 0.0;
       for (int s = 0; s < S; ++s) h0 += double(D(a, s)) * double(D(bb, s));
       hh[0] = float(h0);
-      if (lp) gramH64[(size_t(a) * M + bb) * HQ] = h0;
+      gramH64[(size_t(a) * M + bb) * HQ] = h0;
       for (int k = 1; k <= T; ++k) {
         const int base = S + 2 * S * (k - 1);
         double re = 0.0, im = 0.0;
@@ -643,10 +643,8 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
         }
         hh[2 * k - 1] = float(re);
         hh[2 * k] = float(im);
-        if (lp) {
-          gramH64[(size_t(a) * M + bb) * HQ + 2 * k - 1] = re;
-          gramH64[(size_t(a) * M + bb) * HQ + 2 * k] = im;
-        }
+        gramH64[(size_t(a) * M + bb) * HQ + 2 * k - 1] = re;
+        gramH64[(size_t(a) * M + bb) * HQ + 2 * k] = im;
       }
     }
   // 16-bit encoder tables
@@ -1325,7 +1323,7 @@ rsc_status rsc_synthesize_hat(const rsc_handle* h, const float* xhat, int64_t P,
 
 rsc_status rsc_precision_stats(rsc_handle* h, int64_t* out, int reset) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
-  if (h->prec == RSC_FP32 || !h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "FP32 handles keep no counters");
+  if (!h->dev.lpStats) return fail(RSC_E_UNSUPPORTED, "this handle keeps no counters");
   if (rsc_status f = check_fault(h)) return f;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return handle_fail(h, int(e), "device synchronize");

@@ -248,25 +248,173 @@ __device__ __forceinline__ void init_state(PursuitState<KMAX>& st, bool valid) {
   st.active = valid;
 }
 
-// Least-squares step after the it-th selection (ms, rs) whose signed correlation
-// with the current residual is cval (Cholesky-based OMP):
-//   g_i = <column i, new column> (table), <new, x> = cval + sum_i g_i a_i,
+// FP64 re-solve thresholds on k ||L^{-1}||_F^2, an upper bound on cond_2 of the Gram matrix
+// of the selected columns.  FP32 handles: FP32 rounding of the Gram entries (a few u) is
+// amplified by up to the bound in the coefficients, so 1e3 keeps them within about 1e-4 of
+// exact.  16-bit handles: the FP64 trigger of their precision form, cond > 1e6.
+constexpr float kCondMaxFp32 = 1e3f;
+constexpr float kCondMax16 = 1e6f;
+
+// Tables of the least-squares step: the FP32 pair table of the Cholesky update and the
+// FP64 pair and cos/sin tables plus the input coordinates of the FP64 re-solve.
+struct LsTables {
+  const float* gramH;      // [M][M][2T+1] (pair_gram)
+  const double* gramH64;   // the same in FP64
+  const double* cs64;      // [2][T+1][R] cos, sin in FP64
+  const float* xhat;       // [P][B] input coordinates
+  int M, R;
+  float cond_max;          // FP64 re-solve once k ||L^{-1}||_F^2 exceeds this
+};
+
+// <S_{ra} d_a, S_{rb} d_b> in FP64 (same table layout as pair_gram).
+template <int T>
+__device__ __forceinline__ double pair_gram64(const double* __restrict__ H, const double* __restrict__ cs,
+                                              int M, int R, int a, int ra, int b, int rb) {
+  const double* h = H + (size_t(a) * M + b) * (2 * T + 1);
+  int dr = ra - rb;
+  dr += dr < 0 ? R : 0;
+  double g = h[0];
+#pragma unroll
+  for (int k = 1; k <= T; ++k) g += cs[k * R + dr] * h[2 * k - 1] - cs[(T + 1 + k) * R + dr] * h[2 * k];
+  return g;
+}
+
+// Coordinate j (of sub-lane u) of S_r d_m in FP64; 0 for padding.
+template <class L>
+__device__ __forceinline__ double steer64(const float* __restrict__ hat, const double* __restrict__ cs, int R,
+                                          int m, int r, int j, int u) {
+  const float* d = hat + m * L::B;
+  const int k = L::harm(j), pr = L::prof(j, u);
+  if (pr >= L::S) return 0.0;
+  if (k == 0) return double(d[pr]);
+  const double c = cs[k * R + r], s = cs[(L::NQ + k) * R + r];
+  const double ca = L::part(u) ? -s : c, cb = L::part(u) ? c : s;
+  return double(d[L::base(k) + pr]) * ca + double(d[L::base(k) + L::S + pr]) * cb;
+}
+
+// Sum of a double over the W lanes of a patch.
+template <int W>
+__device__ __forceinline__ double patch_sum64(double x) {
+  if (W == 4) x = x + __shfl_xor(x, 16);
+  return x + __shfl_xor(x, 32);
+}
+
+// FP64 least squares over the it selected columns plus (ms, rs), for the lanes with
+// go set.  Returns whether the new column was accepted (its FP64 pivot is more than
+// 1e-14 of its squared norm: a column numerically inside the span of the selected ones
+// ends the pursuit); then the coefficients, the selection and the residual
+// x_hat - sum_i a_i column_i are replaced.  The factor and the solution live in
+// dynamically indexed local arrays (private memory): the path is rare, and its loops
+// indexed at run time keep the factor out of the registers of the pursuit's main path.
+template <class L, int KMAX>
+__device__ __forceinline__ bool ls_solve64(PursuitState<KMAX>& st, int it, int ms, int rs, bool go,
+                                                     const float* hat, const LsTables& tb, int64_t p, int u,
+                                                     float (&res)[L::NKS]) {
+  const int M = tb.M, R = tb.R;
+  int cm[KMAX], cr[KMAX];
+  double Lc[KMAX][KMAX], y[KMAX], a[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    cm[i] = i < it ? (st.selm[i] < 0 ? 0 : st.selm[i]) : ms;
+    cr[i] = i < it ? (st.selr[i] < 0 ? 0 : st.selr[i]) : rs;
+  }
+  bool good = go;
+#pragma unroll 1
+  for (int i = 0; i <= it; ++i) {
+#pragma unroll 1
+    for (int j = 0; j <= i; ++j) {
+      const double g0 = pair_gram64<L::T>(tb.gramH64, tb.cs64, M, R, cm[i], cr[i], cm[j], cr[j]);
+      double g = g0;
+#pragma unroll 1
+      for (int l = 0; l < j; ++l) g -= Lc[i][l] * Lc[j][l];
+      if (j < i) {
+        Lc[i][j] = g / Lc[j][j];
+      } else {
+        if (i == it) good = good && g > 1e-14 * g0;
+        Lc[i][i] = sqrt(g > 1e-300 ? g : 1e-300);
+      }
+    }
+  }
+  // b_i = <column_i, x_hat> over this lane's coordinates, completed across the patch's lanes
+  const int64_t pp = good ? p : 0;
+#pragma unroll 1
+  for (int i = 0; i <= it; ++i) {
+    double b = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < L::NKS; ++j) {
+      const int c = L::coord(j, u);
+      const double x = (good && c >= 0) ? double(tb.xhat[pp * L::B + c]) : 0.0;
+      b += steer64<L>(hat, tb.cs64, R, cm[i], cr[i], j, u) * x;
+    }
+    b = patch_sum64<L::W>(b);
+#pragma unroll 1
+    for (int l = 0; l < i; ++l) b -= Lc[i][l] * y[l];
+    y[i] = b / Lc[i][i];
+  }
+#pragma unroll 1
+  for (int i = it; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll 1
+    for (int l = i + 1; l <= it; ++l) s -= Lc[l][i] * a[l];
+    a[i] = s / Lc[i][i];
+  }
+#pragma unroll
+  for (int j = 0; j < L::NKS; ++j) {
+    const int c = L::coord(j, u);
+    double r = (good && c >= 0) ? double(tb.xhat[pp * L::B + c]) : 0.0;
+#pragma unroll 1
+    for (int i = 0; i <= it; ++i) r -= a[i] * steer64<L>(hat, tb.cs64, R, cm[i], cr[i], j, u);
+    res[j] = good ? float(r) : res[j];
+  }
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    st.cf[i] = (good && i <= it) ? float(a[i]) : st.cf[i];
+    st.selm[i] = (good && i == it) ? ms : st.selm[i];
+    st.selr[i] = (good && i == it) ? rs : st.selr[i];
+  }
+  return good;
+}
+
+// Extra per-patch state of the least-squares step.
+template <int KMAX>
+struct LsState {
+  float Ld[KMAX];     // 1 / L[i][i]
+  float condF;        // ||L^{-1}||_F^2
+  bool fp64;          // the patch's least squares run in FP64 from now on
+};
+
+template <int KMAX>
+__device__ __forceinline__ void init_ls(LsState<KMAX>& ls) {
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) ls.Ld[i] = 0.f;
+  ls.condF = 0.f;
+  ls.fp64 = false;
+}
+
+// Least-squares step after the it-th selection (ms, rs) whose signed correlation with the
+// current residual is cval (Cholesky-based OMP):
+//   g_i = <column i, new column> (pair table), <new, x> = cval + sum_i g_i a_i,
 //   L is extended by w = L^{-1} g and sqrt(<new,new> - |w|^2),
 //   the coefficients solve L L^T a = [<column i, x>]_i,
 //   the residual moves by -sum_i (a_i - a_i^old) column_i.
-// it is a run-time value (the same in the whole wave); all state arrays are
-// indexed statically with predicates so that they stay in registers.
+// It also tracks k ||L^{-1}||_F^2, an upper bound on cond_2 of the Gram matrix of the k
+// selected unit columns (||G||_2 <= k, ||G^{-1}||_2 <= ||L^{-1}||_F^2).  Once the bound
+// exceeds tb.cond_max, or the new FP32 pivot is below 1e-6 of the column's squared norm,
+// the patch's least squares are re-solved from scratch in FP64 for this and every later
+// step (ls_solve64).  it is a run-time value (the same in the whole wave); all state arrays
+// are indexed statically with predicates so that they stay in registers.  Returns whether
+// this lane went through the FP64 solve.
 template <class L, int KMAX>
-__device__ __forceinline__ void pursuit_update(PursuitState<KMAX>& st, int it, int ms, int rs, float cval,
-                                               const float* __restrict__ hat, const float* __restrict__ cs,
-                                               const float* __restrict__ H, int M, int R, int u,
-                                               float (&res)[L::NKS]) {
+__device__ __forceinline__ bool ls_update(PursuitState<KMAX>& st, LsState<KMAX>& ls, int it, int ms, int rs,
+                                          float cval, const float* hat, const float* cs, const LsTables& tb,
+                                          int64_t p, int u, float (&res)[L::NKS]) {
+  const int M = tb.M, R = tb.R;
   bool dup = false;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) dup = dup || (i < it && st.selm[i] == ms && st.selr[i] == rs);
-  bool upd = st.active && !dup;
+  const bool upd = st.active && !dup;
 
-  const float dd = pair_gram<L::T>(H, cs, M, R, ms, rs, ms, rs);
+  const float dd = pair_gram<L::T>(tb.gramH, cs, M, R, ms, rs, ms, rs);
   float gcol[KMAX];
   float bx = cval;
 #pragma unroll
@@ -274,7 +422,7 @@ __device__ __forceinline__ void pursuit_update(PursuitState<KMAX>& st, int it, i
     gcol[i] = 0.f;
     if (i < it) {
       const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
-      gcol[i] = pair_gram<L::T>(H, cs, M, R, mi, ri, ms, rs);
+      gcol[i] = pair_gram<L::T>(tb.gramH, cs, M, R, mi, ri, ms, rs);
       bx += gcol[i] * st.cf[i];
     }
   }
@@ -285,17 +433,30 @@ __device__ __forceinline__ void pursuit_update(PursuitState<KMAX>& st, int it, i
     float s = gcol[i];
 #pragma unroll
     for (int j = 0; j < i; ++j) s -= st.L[i][j] * w[j];
-    w[i] = i < it ? s / st.L[i][i] : 0.f;
+    w[i] = i < it ? s * ls.Ld[i] : 0.f;
     l2 -= w[i] * w[i];
   }
-  // a column (numerically) inside the span of the selected ones ends the pursuit
-  upd = upd && (l2 > 1e-6f * dd);
+  // new row of L^{-1}: [-(L^{-T} w)^T, 1] / l, so ||L^{-1}||_F^2 grows by (|L^{-T} w|^2 + 1) / l^2
+  float z[KMAX];
+  float zz = 0.f;
+#pragma unroll
+  for (int i = KMAX - 1; i >= 0; --i) {
+    float s = w[i];
+#pragma unroll
+    for (int j = i + 1; j < KMAX; ++j) s -= (j < it ? st.L[j][i] : 0.f) * z[j];
+    z[i] = i < it ? s * ls.Ld[i] : 0.f;
+    zz += z[i] * z[i];
+  }
+  const float Fn = ls.condF + (zz + 1.f) / fmaxf(l2, 1e-30f);
+  const bool ok32 = !ls.fp64 && l2 > 1e-6f * dd && float(it + 1) * Fn <= tb.cond_max;
+  const bool up32 = upd && ok32;
+  const bool go64 = upd && !ok32;
 #pragma unroll
   for (int r = 0; r < KMAX; ++r) {
-    const bool row = upd && r == it;
+    const bool row = up32 && r == it;
 #pragma unroll
     for (int i = 0; i < r; ++i) st.L[r][i] = row ? w[i] : st.L[r][i];
-    st.L[r][r] = row ? sqrtf(l2) : st.L[r][r];
+    ls.Ld[r] = row ? rsqrtf(l2) : ls.Ld[r];
     st.bv[r] = row ? bx : st.bv[r];
     st.selm[r] = row ? ms : st.selm[r];
     st.selr[r] = row ? rs : st.selr[r];
@@ -306,29 +467,34 @@ __device__ __forceinline__ void pursuit_update(PursuitState<KMAX>& st, int it, i
     float s = st.bv[i];
 #pragma unroll
     for (int j = 0; j < i; ++j) s -= st.L[i][j] * y[j];
-    y[i] = i <= it ? s / st.L[i][i] : 0.f;
+    y[i] = i <= it ? s * ls.Ld[i] : 0.f;
   }
 #pragma unroll
   for (int i = KMAX - 1; i >= 0; --i) {
     float s = y[i];
 #pragma unroll
     for (int j = i + 1; j < KMAX; ++j) s -= st.L[j][i] * an[j];
-    an[i] = i <= it ? s / st.L[i][i] : 0.f;
+    an[i] = i <= it ? s * ls.Ld[i] : 0.f;
   }
-  if (__any(upd)) {
+  if (__any(up32)) {
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       if (i <= it) {
-        const float delta = upd ? an[i] - st.cf[i] : 0.f;
+        const float delta = up32 ? an[i] - st.cf[i] : 0.f;
         const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
         steer_axpy<L>(res, -delta, hat, cs, R, mi, ri, u);
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < KMAX; ++i) st.cf[i] = (upd && i <= it) ? an[i] : st.cf[i];
-  st.nsel = upd ? it + 1 : st.nsel;
-  st.active = upd;
+  for (int i = 0; i < KMAX; ++i) st.cf[i] = (up32 && i <= it) ? an[i] : st.cf[i];
+  ls.condF = up32 ? Fn : ls.condF;
+  bool ok64 = false;
+  if (__any(go64)) ok64 = ls_solve64<L, KMAX>(st, it, ms, rs, go64, hat, tb, p, u, res);
+  ls.fp64 = ls.fp64 || ok64;
+  st.nsel = (up32 || ok64) ? it + 1 : st.nsel;
+  st.active = up32 || ok64;
+  return go64;
 }
 
 template <class L>

@@ -21,7 +21,9 @@
 //       coordinate per step instead of a register copy per atom).  Exact ties go to the
 //       smallest atom, then the smallest angle.
 //   (c) extends the Cholesky factor of the selected columns, solves the least
-//       squares and updates the residual, all in registers.
+//       squares and updates the residual, all in registers; a patch whose Gram matrix
+//       grows ill-conditioned (bound k ||L^{-1}||_F^2 above 1e3) or whose new pivot is
+//       negligible has its least squares re-solved in FP64 from then on (ls_update).
 //
 // Two tile shapes:
 //   encode32: v_mfma_f32_32x32x2f32, 32 patches per wave, 16 atoms per stage-1
@@ -48,11 +50,21 @@ struct EncodeParams {
   const float* dftA;      // stage-2 operand (layout per tile shape)
   const float* cs;        // [2][T+1][R]
   const float* gramH;     // [M][M][2T+1] per-pair harmonic inner products
+  const double* gramH64;  // the same in FP64 (FP64 re-solve)
+  const double* cs64;     // [2][T+1][R] in FP64
   int32_t* atom;
   int32_t* angle;
   float* coef;
   float* resid2;
+  unsigned long long* stats;   // [4]: [3] counts pursuit steps solved in FP64
 };
+
+// Adds this wave's count of FP64 least-squares steps to stats[3] (one atomic per wave).
+__device__ __forceinline__ void count_fp64(unsigned long long* stats, unsigned n, int lane) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) n += __shfl_xor(n, off);
+  if (lane == 0 && stats && n) atomicAdd(stats + 3, (unsigned long long)n);
+}
 
 template <class L, int KMAX>
 __device__ __forceinline__ void write_codes(const EncodeParams& prm, int64_t p, const PursuitState<KMAX>& st,
@@ -91,6 +103,8 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, u = lane >> 5;
+  const LsTables tb{prm.gramH, prm.gramH64, prm.cs64, prm.xhat, M, R, kCondMaxFp32};
+  unsigned n64 = 0;
   float F[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) F[q] = prm.dftA[q * 64 + lane];
@@ -108,6 +122,8 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
     const float nx2 = norm2<L>(res);
     PursuitState<KMAX> st;
     init_state(st, valid);
+    LsState<KMAX> ls;
+    init_ls(ls);
 
     for (int it = 0; it < K; ++it) {
       st.active = st.active && (norm2<L>(res) > kTau2 * nx2);
@@ -223,11 +239,12 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
         rs = rs < R ? rs : R - 1;
       }
       // ---------------- (c)
-      pursuit_update<L, KMAX>(st, it, bm, rs, cval, sHat, sCs, prm.gramH, M, R, u, res);
+      n64 += (ls_update<L, KMAX>(st, ls, it, bm, rs, cval, sHat, sCs, tb, p, u, res) && u == 0) ? 1u : 0u;
     }
     const float rn2 = norm2<L>(res);
     if (valid && u == 0) write_codes<L, KMAX>(prm, p, st, rn2);
   }
+  count_fp64(prm.stats, n64, lane);
 }
 
 // ============================================================== 16x16 tiles
@@ -258,6 +275,8 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, u = lane >> 4;
+  const LsTables tb{prm.gramH, prm.gramH64, prm.cs64, prm.xhat, M, R, kCondMaxFp32};
+  unsigned n64 = 0;
   // stage-1 operand row of this lane: rows 0-3 Re of atoms 0-3, 4-7 Im of atoms 0-3,
   // 8-11 Re of atoms 4-7, 12-15 Im of atoms 4-7; contraction index 4j+u
   const int arow = lane & 15;
@@ -291,6 +310,8 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
     const float nx2 = norm2<L>(res);
     PursuitState<KMAX> st;
     init_state(st, valid);
+    LsState<KMAX> ls;
+    init_ls(ls);
 
     for (int it = 0; it < K; ++it) {
       st.active = st.active && (norm2<L>(res) > kTau2 * nx2);
@@ -421,11 +442,12 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
         rs = rc < R ? rc : R - 1;
         cval = rv;
       }
-      pursuit_update<L, KMAX>(st, it, bm, rs, cval, sHat, sCs, prm.gramH, M, R, u, res);
+      n64 += (ls_update<L, KMAX>(st, ls, it, bm, rs, cval, sHat, sCs, tb, p, u, res) && u == 0) ? 1u : 0u;
     }
     const float rn2 = norm2<L>(res);
     if (valid && u == 0) write_codes<L, KMAX>(prm, p, st, rn2);
   }
+  count_fp64(prm.stats, n64, lane);
 }
 
 // ============================================================== launchers
@@ -519,11 +541,12 @@ int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P,
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (tile == RSC_TILE_32) {
     if (!tile32_usable(t, K)) return int(hipErrorInvalidValue);
-    EncodeParams prm{xhat, P, K, t.M, t.R, t.dictA, t.dictHat, t.dftA32, t.cs, t.gramH, atom, angle, coef, resid2};
+    EncodeParams prm{xhat, P, K, t.M, t.R, t.dictA, t.dictHat, t.dftA32, t.cs, t.gramH, t.gramH64, t.cs64,
+                     atom, angle, coef, resid2, t.lpStats};
     return r32(t, prm, st);
   }
   EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.R % 2 == 0 ? t.dftA16s : t.dftA16, t.cs, t.gramH,
-                   atom, angle, coef, resid2};
+                   t.gramH64, t.cs64, atom, angle, coef, resid2, t.lpStats};
   if (t.S == 5 && t.T == 5) return r16<5, 5>(t, prm, st);
   if (t.S == 7 && t.T == 7) return r16<7, 7>(t, prm, st);
   return int(hipErrorInvalidValue);

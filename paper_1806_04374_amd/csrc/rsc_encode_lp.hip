@@ -13,12 +13,22 @@
 //     contraction slots 0..T of the low half-wave take (cos k theta_r, Re C_k) and
 //     those of the high half-wave (-sin k theta_r, Im C_k).  Only the largest
 //     |score| of each atom over its angles is kept.
-//   candidates: atoms whose 16-bit maximum lies within 4u ||r|| of the largest one
-//     (u: unit roundoff of the 16-bit format).  The 16-bit scores stay well inside
-//     +-u ||r|| of the exact ones on the workloads here, so the atom with the exact
-//     maximum is among them; each half-wave keeps a bit mask of its atoms and its
-//     own running maximum, and a new maximum more than the window above the old one
-//     clears the mask.
+//   candidates: atoms whose 16-bit maximum lies within 8.5u ||r|| of the largest one
+//     (u: unit roundoff of the 16-bit format).  Per harmonic k, rounding the atom and
+//     the residual moves C_k by at most (2u + u^2) sum_s |d_{k,s}| |x_{k,s}| (complex
+//     magnitudes), and rounding the stage-2 operand C_k and (cos, -sin) moves the term
+//     cos Re C_k - sin Im C_k by at most (2u + u^2) |C_k| (Cauchy-Schwarz on the
+//     2-vectors).  Summed over k with unit-norm atoms (Cauchy-Schwarz again), a 16-bit
+//     score is within (2u + u^2)(1 + (1 + u)^2) ||r|| = 4.02u ||r|| (BF16; less for FP16)
+//     of the exact one; FP32 accumulation adds below 1e-3 of that.  An atom's 16-bit
+//     maximum over the angles is then within that of its exact maximum, so the atom
+//     with the exact maximum lies within twice that (8.05u ||r||) of the largest 16-bit
+//     maximum: the window keeps it.  FP16
+//     residuals are scaled by a power of two to a norm in [0.5, 1) first, so that no
+//     coordinate that matters falls into the subnormal range, where the rounding is
+//     absolute.  Each half-wave keeps a bit mask of its atoms and its own running
+//     maximum, and a new maximum more than the window above the old one clears the
+//     mask (an atom it drops lies below the final maximum minus the window).
 //   FP32 re-score: per candidate, C_k in FP32 from the packed dictionary (each lane
 //     its half of the coordinates, a half-wave swap completes the sums) and the
 //     angle DFT on v_mfma_f32_32x32x2f32; the best candidate by exact maximum, then
@@ -59,210 +69,6 @@ struct LpParams {
   unsigned long long* stats;   // [4], see rsc_precision_stats
 };
 
-// <S_{ra} d_a, S_{rb} d_b> in FP64 (same table layout as pair_gram).
-template <int T>
-__device__ __forceinline__ double pair_gram64(const double* __restrict__ H, const double* __restrict__ cs,
-                                              int M, int R, int a, int ra, int b, int rb) {
-  const double* h = H + (size_t(a) * M + b) * (2 * T + 1);
-  int dr = ra - rb;
-  dr += dr < 0 ? R : 0;
-  double g = h[0];
-#pragma unroll
-  for (int k = 1; k <= T; ++k) g += cs[k * R + dr] * h[2 * k - 1] - cs[(T + 1 + k) * R + dr] * h[2 * k];
-  return g;
-}
-
-// Coordinate j (of sub-lane u) of S_r d_m in FP64; 0 for padding.
-template <class L>
-__device__ __forceinline__ double steer64(const float* __restrict__ hat, const double* __restrict__ cs, int R,
-                                          int m, int r, int j, int u) {
-  const float* d = hat + m * L::B;
-  const int k = L::harm(j), pr = L::prof(j, u);
-  if (pr >= L::S) return 0.0;
-  if (k == 0) return double(d[pr]);
-  const double c = cs[k * R + r], s = cs[(L::NQ + k) * R + r];
-  const double ca = L::part(u) ? -s : c, cb = L::part(u) ? c : s;
-  return double(d[L::base(k) + pr]) * ca + double(d[L::base(k) + L::S + pr]) * cb;
-}
-
-// FP64 least squares over the it selected columns plus (ms, rs), for the lanes with
-// go set.  Returns whether the new column was accepted (its FP64 pivot is not
-// negligible); then the coefficients, the selection and the residual are replaced.
-template <class L, int KMAX>
-__device__ __forceinline__ bool lp_solve64(PursuitState<KMAX>& st, int it, int ms, int rs, bool go, const float* hat,
-                           const LpParams& prm, int64_t p, int u, float (&res)[L::NKS]) {
-  const int M = prm.M, R = prm.R;
-  int cm[KMAX], cr[KMAX];
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    cm[i] = i < it ? (st.selm[i] < 0 ? 0 : st.selm[i]) : ms;
-    cr[i] = i < it ? (st.selr[i] < 0 ? 0 : st.selr[i]) : rs;
-  }
-  double Lc[KMAX][KMAX];
-  bool good = go;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      if (i <= it) {
-        const double g0 = pair_gram64<L::T>(prm.gramH64, prm.cs64, M, R, cm[i], cr[i], cm[j], cr[j]);
-        double g = g0;
-#pragma unroll
-        for (int l = 0; l < j; ++l) g -= Lc[i][l] * Lc[j][l];
-        if (j < i) {
-          Lc[i][j] = g / Lc[j][j];
-        } else {
-          if (i == it) good = good && g > 1e-14 * g0;
-          Lc[i][i] = sqrt(g > 1e-300 ? g : 1e-300);
-        }
-      } else {
-        Lc[i][j] = j == i ? 1.0 : 0.0;
-      }
-    }
-  }
-  // b_i = <column_i, x_hat> over this lane's coordinates, completed across the half-waves
-  const int64_t pp = good ? p : 0;
-  double y[KMAX];
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    double b = 0.0;
-    if (i <= it) {
-#pragma unroll 1
-      for (int j = 0; j < L::NKS; ++j) {
-        const int c = L::coord(j, u);
-        const double x = (good && c >= 0) ? double(prm.xhat[pp * L::B + c]) : 0.0;
-        b += steer64<L>(hat, prm.cs64, R, cm[i], cr[i], j, u) * x;
-      }
-    }
-    b += __shfl_xor(b, 32);
-#pragma unroll
-    for (int l = 0; l < i; ++l) b -= Lc[i][l] * y[l];
-    y[i] = i <= it ? b / Lc[i][i] : 0.0;
-  }
-  double a[KMAX];
-#pragma unroll
-  for (int i = KMAX - 1; i >= 0; --i) {
-    double s = y[i];
-#pragma unroll
-    for (int l = i + 1; l < KMAX; ++l) s -= Lc[l][i] * a[l];
-    a[i] = i <= it ? s / Lc[i][i] : 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < L::NKS; ++j) {
-    asm volatile("" ::: "memory");
-    const int c = L::coord(j, u);
-    double r = (good && c >= 0) ? double(prm.xhat[pp * L::B + c]) : 0.0;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i)
-      if (i <= it) r -= a[i] * steer64<L>(hat, prm.cs64, R, cm[i], cr[i], j, u);
-    res[j] = good ? float(r) : res[j];
-  }
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    st.cf[i] = (good && i <= it) ? float(a[i]) : st.cf[i];
-    st.selm[i] = (good && i == it) ? ms : st.selm[i];
-    st.selr[i] = (good && i == it) ? rs : st.selr[i];
-  }
-  return good;
-}
-
-// Least-squares step after the it-th selection (ms, rs) with signed correlation cval.
-// FP32 Cholesky extension as in pursuit_update, plus the cond(Gram) bound; FP64
-// re-solve where the bound is exceeded or the patch is already in FP64.  Returns
-// whether this lane went through the FP64 solve.
-template <class L, int KMAX>
-__device__ __forceinline__ bool lp_update(PursuitState<KMAX>& st, float (&Ld)[KMAX], float& condF, bool& fp64,
-                                          int it, int ms, int rs, float cval, const float* hat, const float* cs,
-                                          const LpParams& prm, int64_t p, int u, float (&res)[L::NKS]) {
-  const int M = prm.M, R = prm.R;
-  bool dup = false;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) dup = dup || (i < it && st.selm[i] == ms && st.selr[i] == rs);
-  const bool upd = st.active && !dup;
-
-  const float dd = pair_gram<L::T>(prm.gramH, cs, M, R, ms, rs, ms, rs);
-  float gcol[KMAX];
-  float bx = cval;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    gcol[i] = 0.f;
-    if (i < it) {
-      const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
-      gcol[i] = pair_gram<L::T>(prm.gramH, cs, M, R, mi, ri, ms, rs);
-      bx += gcol[i] * st.cf[i];
-    }
-  }
-  float w[KMAX];
-  float l2 = dd;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    float s = gcol[i];
-#pragma unroll
-    for (int j = 0; j < i; ++j) s -= st.L[i][j] * w[j];
-    w[i] = i < it ? s * Ld[i] : 0.f;
-    l2 -= w[i] * w[i];
-  }
-  // new row of L^{-1}: [-(L^{-T} w)^T, 1] / l, so ||L^{-1}||_F^2 grows by (|L^{-T} w|^2 + 1) / l^2
-  float z[KMAX];
-  float zz = 0.f;
-#pragma unroll
-  for (int i = KMAX - 1; i >= 0; --i) {
-    float s = w[i];
-#pragma unroll
-    for (int j = i + 1; j < KMAX; ++j) s -= (j < it ? st.L[j][i] : 0.f) * z[j];
-    z[i] = i < it ? s * Ld[i] : 0.f;
-    zz += z[i] * z[i];
-  }
-  const float Fn = condF + (zz + 1.f) / fmaxf(l2, 1e-30f);
-  const bool ok32 = !fp64 && l2 > 1e-6f * dd && float(it + 1) * Fn <= 1e6f;
-  const bool up32 = upd && ok32;
-  const bool go64 = upd && !ok32;
-#pragma unroll
-  for (int r = 0; r < KMAX; ++r) {
-    const bool row = up32 && r == it;
-#pragma unroll
-    for (int i = 0; i < r; ++i) st.L[r][i] = row ? w[i] : st.L[r][i];
-    Ld[r] = row ? rsqrtf(l2) : Ld[r];
-    st.bv[r] = row ? bx : st.bv[r];
-    st.selm[r] = row ? ms : st.selm[r];
-    st.selr[r] = row ? rs : st.selr[r];
-  }
-  float y[KMAX], an[KMAX];
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    float s = st.bv[i];
-#pragma unroll
-    for (int j = 0; j < i; ++j) s -= st.L[i][j] * y[j];
-    y[i] = i <= it ? s * Ld[i] : 0.f;
-  }
-#pragma unroll
-  for (int i = KMAX - 1; i >= 0; --i) {
-    float s = y[i];
-#pragma unroll
-    for (int j = i + 1; j < KMAX; ++j) s -= st.L[j][i] * an[j];
-    an[i] = i <= it ? s * Ld[i] : 0.f;
-  }
-  if (__any(up32)) {
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-      if (i <= it) {
-        const float delta = up32 ? an[i] - st.cf[i] : 0.f;
-        const int mi = st.selm[i] < 0 ? 0 : st.selm[i], ri = st.selr[i] < 0 ? 0 : st.selr[i];
-        steer_axpy<L>(res, -delta, hat, cs, R, mi, ri, u);
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) st.cf[i] = (up32 && i <= it) ? an[i] : st.cf[i];
-  condF = up32 ? Fn : condF;
-  bool ok64 = false;
-  if (__any(go64)) ok64 = lp_solve64<L, KMAX>(st, it, ms, rs, go64, hat, prm, p, u, res);
-  fp64 = fp64 || ok64;
-  st.nsel = (up32 || ok64) ? it + 1 : st.nsel;
-  st.active = up32 || ok64;
-  return go64;
-}
-
 // RT: 32-angle tiles of the 16-bit stage 2 (ceil(R/32)).  SPLIT: the FP32 re-score
 // uses the radix-2 angle split (even R, R/2 <= 32 rows: E from even harmonics, O
 // from odd ones, score(r) = E + O and score(r + R/2) = E - O); otherwise RT tiles
@@ -298,7 +104,8 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
     const uint4 w = prm.dft16[t * 64 + lane];
     __builtin_memcpy(&F16[t], &w, sizeof(w));
   }
-  const float wfac = 4.f * P::unit;
+  const LsTables tb{prm.gramH, prm.gramH64, prm.cs64, prm.xhat, prm.M, prm.R, kCondMax16};
+  const float wfac = 8.5f * P::unit;
   unsigned long long n_sel = 0, n_cand = 0, n_fp64 = 0, max_cand = 0;
 
   const int64_t nwt = (prm.P + 31) / 32;
@@ -314,27 +121,31 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
     const float nx2 = norm2<L>(res);
     PursuitState<KMAX> st;
     init_state(st, valid);
-    float Ld[KMAX];          // 1 / L[i][i]
-    zero(Ld);
-    float condF = 0.f;
-    bool fp64 = false;
+    LsState<KMAX> ls;
+    init_ls(ls);
 
     for (int it = 0; it < K; ++it) {
       const float n2 = norm2<L>(res);
       st.active = st.active && (n2 > kTau2 * nx2);
       if (!__any(st.active)) break;
 
-      // ---------------- 16-bit residual operand, one per harmonic
+      // ---------------- 16-bit residual operand, one per harmonic (FP16: the residual
+      // scaled by 2^-e, ||r|| = f 2^e with f in [0.5, 1); the scores and the window are
+      // compared in the scaled units)
+      const float rn = sqrtf(n2);
+      int ex = 0;
+      if (PREC == RSC_FP16) (void)frexpf(rn, &ex);
+      const float sc = PREC == RSC_FP16 ? ldexpf(1.f, -ex) : 1.f;
       V8 r16[NQ];
 #pragma unroll
       for (int k = 0; k < NQ; ++k) {
         const int j0 = k == 0 ? 0 : J0 + (k - 1) * S, cnt = k == 0 ? J0 : S;
         float v[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = i < cnt ? res[i < cnt ? j0 + i : 0] : 0.f;
+        for (int i = 0; i < 8; ++i) v[i] = i < cnt ? sc * res[i < cnt ? j0 + i : 0] : 0.f;
         r16[k] = pack8<P>(v);
       }
-      const float wnd = wfac * sqrtf(n2);
+      const float wnd = wfac * rn * sc;
 
       // ---------------- 16-bit scores: per-atom maxima and the candidate mask
       float vh = -1.f;          // running maximum over this half-wave's atoms
@@ -570,7 +381,7 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
       n_sel += counted ? 1 : 0;
       n_cand += u == 0 ? nc : 0;
       max_cand = (u == 0 && unsigned(nc) > max_cand) ? unsigned(nc) : max_cand;
-      const bool went64 = lp_update<L, KMAX>(st, Ld, condF, fp64, it, bm, rs, cval, sHat, sCs, prm, p, u, res);
+      const bool went64 = ls_update<L, KMAX>(st, ls, it, bm, rs, cval, sHat, sCs, tb, p, u, res);
       n_fp64 += (u == 0 && went64) ? 1 : 0;
     }
     const float rn2 = norm2<L>(res);

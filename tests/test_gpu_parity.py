@@ -356,3 +356,62 @@ def test_duplicate_atom_ties_go_to_smaller_index(dev, tile):
     assert np.array_equal(g, gm) and np.array_equal(c, cm)
     h.close()
     hm.close()
+
+
+@pytest.mark.parametrize("eps,fp64", [(0.2, False), (6.3e-3, True), (1e-3, True)])
+@pytest.mark.parametrize("R,tile", [(1, "16"), (2, "32")])
+def test_ill_conditioned_supports(dev, eps, fp64, R, tile):
+    """Two atoms eps apart: once both are selected the Gram matrix has cond ~ 1e2 (eps =
+    0.2, least squares in FP32), ~ 1e5 or ~ 4e6 (re-solved in FP64, since the bound
+    k ||L^{-1}||_F^2 passes 1e3).  Coefficients must match the reference's QR solve to
+    1e-4 in every case; the FP64 steps are counted by rsc_precision_stats.  With R = 2 (the
+    32x32 tiles) the direction n separating the two atoms is also orthogonal to the half
+    turn of the first, so that after one of the pair is selected the other one is the best
+    second column (as with R = 1)."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    rng = np.random.default_rng(5)
+    d1 = rng.standard_normal(g.B)
+    d1 /= np.linalg.norm(d1)
+    n = rng.standard_normal(g.B)
+    for v in [d1] + [orc.steer(d1, 2 * np.pi * r / R, g.S, g.T) for r in range(1, R)]:
+        v = v / np.linalg.norm(v)
+        n -= (n @ v) * v
+    d2 = d1 + eps * n / np.linalg.norm(n)
+    d2 /= np.linalg.norm(d2)
+    D = np.stack([d1, d2]).astype(np.float32).astype(np.float64)   # used as they are on both sides
+    cond = np.linalg.cond(D @ D.T)
+    P = 200
+    w = rng.uniform(0.5, 1.5, (P, 2)) * rng.choice([-1.0, 1.0], (P, 2))
+    xh = (w @ D).astype(np.float32)       # coordinates handed over directly
+    h = _handle(g, D, R, tile)
+    rsc.rsc_precision_stats(h, reset=True)
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, torch.from_numpy(xh).to(dev), 2)
+    torch.cuda.synchronize()
+    stats = rsc.rsc_precision_stats(h)
+    code = orc.omp(orc.augmented_dictionary(D, R, g.S, g.T), xh.astype(np.float64), 2, 2)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
+    print(f"cond {cond:.3g}", rep, stats, flush=True)
+    assert rep.match_rate >= MATCH, str(rep)
+    assert rep.coef_bad == 0, str(rep)
+    if fp64:
+        assert stats["fp64_solves"] >= P * MATCH, stats
+    else:
+        assert stats["fp64_solves"] == 0, stats
+    h.close()
+
+
+def test_workload_never_needs_fp64(dev):
+    """On the scale workload every selected support is well conditioned (bound below 1e3):
+    the FP64 fallback does not fire."""
+    from paper_1806_04374_amd import rsc
+    w = wl.SCALE
+    geom = w["geom"]
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    D, draw = wl.scale_draw(P=50000)
+    X = orc.synthesize(basis, D, draw.atom, draw.angle, draw.weight, draw.noise).astype(np.float32)
+    h = _handle(geom, D, w["R"])
+    rsc.rsc_precision_stats(h, reset=True)
+    _encode(h, X, w["K"], dev)
+    assert rsc.rsc_precision_stats(h)["fp64_solves"] == 0
+    h.close()

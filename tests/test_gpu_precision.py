@@ -99,8 +99,8 @@ def test_scale_workload_slice(dev, prec):
     D, d = wl.scale_draw(P=20011)
     X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
     _, stats = _check("scale-20011", X, D, w["R"], w["K"], g, dev, prec, basis)
-    # the window keeps few candidates per step on this workload
-    assert stats["candidates"] <= 3 * stats["steps_rescored"], stats
+    # the window keeps few candidates per step on this workload (BF16 about 2.7, FP16 about 1.1)
+    assert stats["candidates"] <= (3.5 if prec == "bf16" else 1.5) * stats["steps_rescored"], stats
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -211,4 +211,38 @@ def test_limits_and_edge_cases(dev, prec):
         _, code = orc.encode(basis, Dm, 32, X[:n].astype(np.float64), 2)
         rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL)
         assert rep.matched == n, str(rep)
+    h.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_near_tie_pairs_resolved_by_fp32_rescore(dev, prec):
+    """Each atom has a partner eta away, so that the exact maxima of a pair differ by about
+    the 16-bit error of a score (u ||r||): the 16-bit order within a pair is as good as
+    random.  The window (twice a worst-case bound on that error) keeps both of a pair as
+    candidates, and the FP32 re-score must then pick the reference's (FP64) selection."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    basis = orc.build_basis(g.N, g.S, g.T)
+    rng = np.random.default_rng(31)
+    eta = 0.03 if prec == "bf16" else 0.004
+    base = wl.draw_dictionary(16, g.B, seed=31)
+    nudge = rng.standard_normal(base.shape)
+    partner = base + eta * nudge / np.linalg.norm(nudge, axis=1, keepdims=True)
+    partner /= np.linalg.norm(partner, axis=1, keepdims=True)
+    D = np.concatenate([base, partner]).astype(np.float32).astype(np.float64)
+    M, R, K = 32, 32, 2
+    d = wl.draw_mixtures(3000, g.N, M, 2, 0.01, seed=31)
+    X = orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    h = _handle(g, D, R, prec)
+    rsc.rsc_precision_stats(h, reset=True)
+    atom, angle, coef, _ = _run(h, X, K, dev, basis)
+    stats = rsc.rsc_precision_stats(h)
+    xh_ref, code = orc.encode(basis, D, R, X.astype(np.float64), K)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, COEF_REL,
+                        xnorm=np.linalg.norm(xh_ref, axis=1))
+    print("near-ties", prec, rep, stats, flush=True)
+    assert rep.match_rate >= MATCH, str(rep)
+    assert rep.coef_bad == 0, str(rep)
+    # the pairs really are re-scored together
+    assert stats["candidates"] >= 1.5 * stats["steps_rescored"], stats
     h.close()
