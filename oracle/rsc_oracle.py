@@ -75,7 +75,9 @@ Readings where the paper is silent:
     and (Phi^* Phi)^{-1} would not exist).  The low-pass basis halves these T_s (floor).
     The centre pixel is 0 for t != 0, as above; columns are normalised and need no
     orthonormalisation (annuli are disjoint).  Packed real coordinates as above,
-    harmonic-major, with the annuli whose T_s >= k in each harmonic-k block.
+    harmonic-major, with the annuli whose T_s >= k in each harmonic-k block.  The pursuit
+    on it is the same OMP over [S_0 D, ..., S_{R-1} D], with the steering of that ragged
+    layout (harmonic k of each of its annuli multiplied by exp(-i k theta)).
   * Rotation by interpolation (Sec. III-C, rotation speed): rotating a patch by theta
     (counter-clockwise, about its centre pixel) sets output pixel (x, y) to the input
     at R_{-theta}(x, y), read with nearest-neighbour interpolation (coordinates
@@ -337,6 +339,17 @@ def augmented_dictionary(D_hat: np.ndarray, R: int, S: int, T: int) -> np.ndarra
     return rows
 
 
+def augmented_dictionary_basis(basis, D_hat: np.ndarray, R: int) -> np.ndarray:
+    """The augmented dictionary of Fig. 2 (R_r -> S_r) in the coordinate layout of either
+    basis: the full (S, T) grid or the annular basis' harmonic-major blocks of Sk[k] annuli.
+    Row j = r*M + m is S_r d_m, shape [M*R, B]."""
+    M = D_hat.shape[0]
+    rows = np.empty((R * M, D_hat.shape[1]))
+    for r in range(R):
+        rows[r * M:(r + 1) * M] = steer_basis(basis, D_hat, 2 * np.pi * r / R)
+    return rows
+
+
 # --------------------------------------------------------------------------- pursuit
 @dataclasses.dataclass
 class Code:
@@ -422,7 +435,7 @@ def encode(basis: Basis, D_hat: np.ndarray, R: int, patches: np.ndarray, K: int,
            tau: float = TAU) -> tuple[np.ndarray, Code]:
     """Sec. II-E steps 2-3 for a fixed dictionary: hat coordinates, then OMP with S_r."""
     xhat = project(basis, patches)
-    D_aug = augmented_dictionary(D_hat, R, basis.S, basis.T)
+    D_aug = augmented_dictionary_basis(basis, D_hat, R)
     return xhat, omp(D_aug, xhat, K, D_hat.shape[0], tau)
 
 
@@ -438,9 +451,21 @@ def code_to_hat(D_hat: np.ndarray, R: int, S: int, T: int, code: Code) -> np.nda
     return out
 
 
+def code_to_hat_basis(basis, D_hat: np.ndarray, R: int, code: Code) -> np.ndarray:
+    """code_to_hat in the coordinate layout of either basis."""
+    P, K = code.atom.shape
+    out = np.zeros((P, D_hat.shape[1]))
+    for p in range(P):
+        for i in range(K):
+            if code.atom[p, i] >= 0:
+                out[p] += code.coef[p, i] * steer_basis(basis, D_hat[code.atom[p, i]],
+                                                        2 * np.pi * code.angle[p, i] / R)
+    return out
+
+
 def reconstruct(basis: Basis, D_hat: np.ndarray, R: int, code: Code) -> np.ndarray:
     """Pixel-domain reconstruction Phi sum_i a_i S_{r_i} d_{m_i} (Sec. II-E step 4), [P, N, N]."""
-    return to_pixels(basis, code_to_hat(D_hat, R, basis.S, basis.T, code))
+    return to_pixels(basis, code_to_hat_basis(basis, D_hat, R, code))
 
 
 def mse(basis: Basis, patches: np.ndarray, recon: np.ndarray) -> float:
@@ -463,8 +488,7 @@ def synthesize(basis: Basis, D_hat: np.ndarray, atom, angle, weight, noise=None)
     P, J = atom.shape
     hat = np.zeros((P, D_hat.shape[1]))
     for i in range(J):
-        hat += np.asarray(weight)[:, i, None] * steer(D_hat[atom[:, i]], np.asarray(angle)[:, i],
-                                                     basis.S, basis.T)
+        hat += np.asarray(weight)[:, i, None] * steer_basis(basis, D_hat[atom[:, i]], np.asarray(angle)[:, i])
     x = to_pixels(basis, hat)
     if noise is not None:
         x = x + noise
