@@ -26,6 +26,7 @@ SOURCES = [
     ("rsc_api.cpp", "hip"),
     ("rsc_project.hip", "hip"),
     ("rsc_encode.hip", "hip"),
+    ("rsc_encode_annular.hip", "hip"),
     ("rsc_encode_lp.hip", "hip"),
     ("rsc_synth.hip", "hip"),
     ("rsc_images.hip", "hip"),

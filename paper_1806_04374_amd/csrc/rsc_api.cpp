@@ -219,6 +219,8 @@ rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
   d.S = S;
   d.T = T;
   d.B = b.B;
+  d.geo = rsc::kGeoGrid;
+  for (int k = 0; k <= T && k < 64; ++k) d.sk[k] = S;
   const int NN = N * N, KP = (NN + 1) / 2;
   const int RTB = (b.B + 31) / 32 <= 2 ? 2 : (b.B + 31) / 32 <= 4 ? 4 : 6;  // row tiles of the projection kernels
   // projection A operand: row = hat coordinate, contraction = grid pixel
@@ -420,6 +422,16 @@ rsc_status rsc_create_annular(int N, int lowpass, rsc_handle** out) {
   h->annular = true;
   rsc_status st = init_tables(h, N, b.S, b.T, RSC_FP32);
   if (st != RSC_OK) return st;
+  // per-harmonic annulus counts, and the layouts the pursuit is compiled for
+  for (int k = 0; k <= b.T; ++k) {
+    int nk = 0;
+    for (int t : h->Ts) nk += t >= k ? 1 : 0;
+    h->dev.sk[k] = nk;
+  }
+  const std::vector<int> ts11 = {1, 3, 8, 11, 15}, ts15 = {1, 3, 8, 11, 13, 18, 19};
+  h->dev.geo = (N == 11 && !lowpass && h->Ts == ts11)   ? rsc::kGeoAnnular11
+               : (N == 15 && !lowpass && h->Ts == ts15) ? rsc::kGeoAnnular15
+                                                        : rsc::kGeoAnnularOther;
   // steering table: coordinate -> (harmonic k, offset of its Re/Im partner)
   std::vector<int> tab(b.B);
   int col = 0;
@@ -520,11 +532,14 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
   if (R < 1 || R > 128) return fail(RSC_E_INVALID, "R must be in 1..128");
   rsc::DeviceTables& d = h->dev;
   const int S = d.S, T = d.T, B = d.B;
-  if (h->annular) return fail(RSC_E_UNSUPPORTED, "the annular basis serves projection, steering and synthesis only");
-  if (!rsc::encode_supported(S, T))
+  if (!rsc::encode_supported_geo(d))
     return fail(RSC_E_UNSUPPORTED,
-                "the encoders are compiled for (S, T) = (5, 5) and (7, 7); this geometry supports "
-                "projection, steering and synthesis only");
+                h->annular ? "the pursuit on the annular basis is compiled for its full form at N = 11 and N = 15; "
+                             "this handle supports projection, steering and synthesis only"
+                           : "the encoders are compiled for (S, T) = (5, 5) and (7, 7); this geometry supports "
+                             "projection, steering and synthesis only");
+  if ((d.geo == rsc::kGeoAnnular11 || d.geo == rsc::kGeoAnnular15) && (R % 2 != 0 || R > rsc::kAnnularMaxR))
+    return fail(RSC_E_UNSUPPORTED, "the pursuit on the annular basis is compiled for even R <= 64");
   for (int m = 0; m < M; ++m) {
     double n2 = 0.0;
     for (int b = 0; b < B; ++b) {
@@ -620,8 +635,11 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
       cs[size_t(NQ + k) * R + r] = sink(k, r);
     }
   // per-pair harmonic inner products in FP64: H_0 = sum_s a_s b_s (k = 0 block),
-  // H_k = sum_s conj(a_k,s) b_k,s as (Re, Im) for k >= 1
+  // H_k = sum_s conj(a_k,s) b_k,s as (Re, Im) for k >= 1, over the sk[k] profiles (or
+  // annuli) of harmonic k, whose [Re][Im] block starts at kbase[k]
   const int HQ = 2 * T + 1;
+  std::vector<int> kbase(T + 1, 0);
+  for (int k = 1; k <= T; ++k) kbase[k] = k == 1 ? d.sk[0] : kbase[k - 1] + 2 * d.sk[k - 1];
   const bool lp = h->prec != RSC_FP32;
   std::vector<float> gramH(size_t(M) * M * HQ);
   std::vector<double> gramH64(gramH.size());
@@ -629,15 +647,15 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
     for (int bb = 0; bb < M; ++bb) {
       float* hh = &gramH[(size_t(a) * M + bb) * HQ];
       double h0 = 0.0;
-      for (int s = 0; s < S; ++s) h0 += double(D(a, s)) * double(D(bb, s));
+      for (int s = 0; s < d.sk[0]; ++s) h0 += double(D(a, s)) * double(D(bb, s));
       hh[0] = float(h0);
       gramH64[(size_t(a) * M + bb) * HQ] = h0;
       for (int k = 1; k <= T; ++k) {
-        const int base = S + 2 * S * (k - 1);
+        const int base = kbase[k], nk = d.sk[k];
         double re = 0.0, im = 0.0;
-        for (int s = 0; s < S; ++s) {
-          const double ar = D(a, base + s), ai = D(a, base + S + s);
-          const double br = D(bb, base + s), bi = D(bb, base + S + s);
+        for (int s = 0; s < nk; ++s) {
+          const double ar = D(a, base + s), ai = D(a, base + nk + s);
+          const double br = D(bb, base + s), bi = D(bb, base + nk + s);
           re += ar * br + ai * bi;
           im += ar * bi - ai * br;
         }
@@ -917,6 +935,8 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
+  if (h->annular && K > rsc::kAnnularMaxK)
+    return fail(RSC_E_UNSUPPORTED, "the pursuit on the annular basis is compiled for K <= 4");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");
   if (P == 0) return ok();
   if (!xhat || !atom || !angle || !coef) return fail(RSC_E_INVALID, "null device pointer");
@@ -1016,6 +1036,7 @@ rsc_status rsc_synthesize_images(const rsc_handle* h, const int32_t* atom, const
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (n_stamps < 0 || n_stamps > (int64_t(1) << 31) - 1) return fail(RSC_E_INVALID, "n_stamps out of range");
+  if (h->annular) return fail(RSC_E_UNSUPPORTED, "image stamping is compiled for the (S, T) grid of profiles");
   if (n_stamps == 0) return ok();
   if (!atom || !theta || !amplitude || !centre || !image || !img_offset || !H || !W || !pixels)
     return fail(RSC_E_INVALID, "null device pointer");
@@ -1046,7 +1067,8 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
   if (P < 1 || P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (!xhat || !atom || !angle || !coef || !resid2 || !workspace || !d_new || !usage)
     return fail(RSC_E_INVALID, "null device pointer");
-  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
+  if (h->dev.B > 128 || h->annular)
+    return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for the (S, T) grid with B <= 128");
   const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
@@ -1068,6 +1090,8 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   if (P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
     return fail(RSC_E_INVALID, "null device pointer or empty input");
+  if (h->annular)
+    return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for the (S, T) grid with B <= 128");
   rsc_status s = rsc_set_dictionary(h, d_init, M, R, stream);
   if (s != RSC_OK) return s;
   const RkLayout L = rk_layout(h->dev, P, K);

@@ -81,34 +81,81 @@ __device__ __forceinline__ float max_quarters(float x) {
 }
 
 // ----------------------------------------------------------------------------
-// Coordinate layouts.  A patch's B = S(2T+1) packed hat coordinates are spread
-// over W lanes (W = 2: the two half-waves of a 32x32 tile; W = 4: the four
-// quarter-waves of a 16x16 tile).  Register j of sub-lane u holds one coordinate:
+// Coordinate layouts.  A patch's B packed hat coordinates are harmonic-major with Sk(k)
+// radial profiles (or annuli) in harmonic k: [k=0: Sk(0)], then for each k >= 1
+// [Re: Sk(k)][Im: Sk(k)].  They are spread over W lanes (W = 2: the two half-waves of a
+// 32x32 tile; W = 4: the four quarter-waves of a 16x16 tile).  Register j of sub-lane u
+// holds one coordinate:
 //   harmonic 0 block (j < J0): profile s = W j + u;
-//   harmonic k >= 1 block: the pair index jj = j - J0 - (k-1) J1 selects profile
-//     s = SW jj + soff(u) and part(u) (0 = Re, 1 = Im).
-// These are also the contraction orders of the stage-1 MFMAs.
-template <int S_, int T_, int W_>
-struct Layout {
-  static constexpr int S = S_, T = T_, W = W_;
-  static constexpr int B = S * (2 * T + 1);
-  static constexpr int NQ = T + 1;
-  static constexpr int J0 = (S + W - 1) / W;
-  static constexpr int J1 = (2 * S + W - 1) / W;
-  static constexpr int NKS = J0 + T * J1;
+//   harmonic k >= 1 block (joff(k) <= j < joff(k+1)): the pair index jj = j - joff(k)
+//     selects profile s = SW jj + soff(u) and part(u) (0 = Re, 1 = Im).
+// These are also the contraction orders of the stage-1 MFMAs.  The profile counts come
+// from C (C::T and C::sk(k)): the same S for every harmonic in the (S, T) grid of Gaussian
+// profiles, ragged for the paper's annular basis, whose harmonic k lives on the annuli
+// whose cut-off reaches k.
+template <class C, int W_>
+struct LayoutBase {
+  static constexpr int W = W_, T = C::T, NQ = T + 1;
   static constexpr int SW = W / 2;                       // profiles advanced per k>=1 step
-  __device__ static constexpr int harm(int j) { return j < J0 ? 0 : 1 + (j - J0) / J1; }
-  __device__ static constexpr int pair(int j) { return j < J0 ? j : (j - J0) % J1; }
-  __device__ static constexpr int base(int k) { return k == 0 ? 0 : S + 2 * S * (k - 1); }
-  __device__ static constexpr int soff(int u) { return W == 2 ? 0 : (u >> 1); }
-  __device__ static constexpr int part(int u) { return W == 2 ? u : (u & 1); }
+  __host__ __device__ static constexpr int Sk(int k) { return C::sk(k); }
+  static constexpr int S = C::sk(0);                     // profiles of harmonic 0 (the most)
+  static constexpr int J0 = (S + W - 1) / W;
+  __host__ __device__ static constexpr int J1k(int k) { return (2 * Sk(k) + W - 1) / W; }
+  __host__ __device__ static constexpr int joff(int k) {
+    int j = J0;
+    for (int q = 1; q < k; ++q) j += J1k(q);
+    return k == 0 ? 0 : j;
+  }
+  static constexpr int NKS = joff(T + 1);
+  __host__ __device__ static constexpr int base(int k) {
+    int b = Sk(0);
+    for (int q = 1; q < k; ++q) b += 2 * Sk(q);
+    return k == 0 ? 0 : b;
+  }
+  static constexpr int B = base(T + 1);
+  __host__ __device__ static constexpr int harm(int j) {
+    int k = 0;
+    while (k < T && j >= joff(k + 1)) ++k;
+    return k;
+  }
+  __host__ __device__ static constexpr int pair(int j) { return j < J0 ? j : j - joff(harm(j)); }
+  __host__ __device__ static constexpr int soff(int u) { return W == 2 ? 0 : (u >> 1); }
+  __host__ __device__ static constexpr int part(int u) { return W == 2 ? u : (u & 1); }
   // profile index of register j in sub-lane u
-  __device__ static constexpr int prof(int j, int u) {
+  __host__ __device__ static constexpr int prof(int j, int u) {
     return harm(j) == 0 ? W * j + u : SW * pair(j) + soff(u);
   }
   // packed coordinate of register j in sub-lane u, or -1 for padding
-  __device__ static constexpr int coord(int j, int u) {
-    return prof(j, u) >= S ? -1 : (harm(j) == 0 ? prof(j, u) : base(harm(j)) + part(u) * S + prof(j, u));
+  __host__ __device__ static constexpr int coord(int j, int u) {
+    return prof(j, u) >= Sk(harm(j)) ? -1
+           : (harm(j) == 0 ? prof(j, u) : base(harm(j)) + part(u) * Sk(harm(j)) + prof(j, u));
+  }
+};
+
+// The (S, T) grid: every harmonic 0..T on all S profiles.
+template <int S_, int T_>
+struct UniformCounts {
+  static constexpr int T = T_;
+  __host__ __device__ static constexpr int sk(int) { return S_; }
+};
+
+template <int S, int T, int W>
+using Layout = LayoutBase<UniformCounts<S, T>, W>;
+
+// The paper's annular basis (eq. (5)-(7)) at N = 11 and N = 15: per-annulus cut-offs
+// T_s = (1, 3, 8, 11, 15) and (1, 3, 8, 11, 13, 18, 19) (half the circumference, lowered
+// where the annulus' pixels cannot carry that many harmonics); harmonic k lives on the
+// annuli with T_s >= k.
+struct AnnularCounts11 {
+  static constexpr int T = 15;
+  __host__ __device__ static constexpr int sk(int k) {
+    return k <= 1 ? 5 : k <= 3 ? 4 : k <= 8 ? 3 : k <= 11 ? 2 : 1;
+  }
+};
+struct AnnularCounts15 {
+  static constexpr int T = 19;
+  __host__ __device__ static constexpr int sk(int k) {
+    return k <= 1 ? 7 : k <= 3 ? 6 : k <= 8 ? 5 : k <= 11 ? 4 : k <= 13 ? 3 : k <= 18 ? 2 : 1;
   }
 };
 
@@ -137,18 +184,18 @@ __device__ __forceinline__ void atom_operand(const float* __restrict__ hat, int 
   }
   // low half-wave (Re parts): Re += dRe r, Im -= dIm r; high half-wave (Im parts):
   // Re += dIm r, Im += dRe r
-  const float* dA = d + (u ? L::S : 0);
-  const float* dB = d + (u ? 0 : L::S);
   const float sg = u ? 1.f : -1.f;
 #pragma unroll
   for (int k = 1; k <= L::T; ++k) {
+    const float* dA = d + L::base(k) + (u ? L::Sk(k) : 0);
+    const float* dB = d + L::base(k) + (u ? 0 : L::Sk(k));
     float pr = 0.f, pi = 0.f;
 #pragma unroll
-    for (int jj = 0; jj < L::J1; ++jj) {
-      const int j = L::J0 + (k - 1) * L::J1 + jj;
-      if (jj < L::S) {
-        pr = fmaf(dA[L::base(k) + jj], res[j], pr);
-        pi = fmaf(dB[L::base(k) + jj], res[j], pi);
+    for (int jj = 0; jj < L::J1k(k); ++jj) {
+      const int j = L::joff(k) + jj;
+      if (jj < L::Sk(k)) {
+        pr = fmaf(dA[jj], res[j], pr);
+        pi = fmaf(dB[jj], res[j], pi);
       }
     }
     float x = pr, y = sg * pi;
@@ -177,28 +224,28 @@ __device__ __forceinline__ void steer_axpy(float (&acc)[L::NKS], float alpha, co
 #pragma unroll
   for (int j = 0; j < L::J0; ++j) {
     const int s = L::W * j + u;
-    const bool valid = s < L::S;
+    const bool valid = s < L::Sk(0);
     acc[j] = fmaf(valid ? alpha : 0.f, d[valid ? s : 0], acc[j]);
   }
   const int pt = L::part(u), so = L::soff(u);
-  const float* pA = d + (pt ? L::S : 0) + so;
-  const float* pB = d + (pt ? 0 : L::S) + so;
   const float as = pt ? -alpha : alpha;
 #pragma unroll
   for (int k = 1; k <= L::T; ++k) {
+    const float* pA = d + L::base(k) + (pt ? L::Sk(k) : 0) + so;
+    const float* pB = d + L::base(k) + (pt ? 0 : L::Sk(k)) + so;
     const float ck = alpha * cs[k * R + r];
     const float sk = as * cs[(L::NQ + k) * R + r];
 #pragma unroll
-    for (int jj = 0; jj < L::J1; ++jj) {
-      const int j = L::J0 + (k - 1) * L::J1 + jj;
-      if (L::SW * jj >= L::S) continue;                 // padding in every lane
+    for (int jj = 0; jj < L::J1k(k); ++jj) {
+      const int j = L::joff(k) + jj;
+      if (L::SW * jj >= L::Sk(k)) continue;             // padding in every lane
       float a = ck, b = sk;
-      int off = L::base(k) + L::SW * jj;
-      if (L::SW * jj + L::SW - 1 >= L::S) {             // padding in some lanes
-        const bool valid = L::SW * jj + so < L::S;
+      int off = L::SW * jj;
+      if (L::SW * jj + L::SW - 1 >= L::Sk(k)) {         // padding in some lanes
+        const bool valid = L::SW * jj + so < L::Sk(k);
         a = valid ? a : 0.f;
         b = valid ? b : 0.f;
-        off = valid ? off : L::base(k);
+        off = valid ? off : -so;
       }
       acc[j] = fmaf(pA[off], a, fmaf(pB[off], b, acc[j]));
     }
@@ -285,11 +332,11 @@ __device__ __forceinline__ double steer64(const float* __restrict__ hat, const d
                                           int m, int r, int j, int u) {
   const float* d = hat + m * L::B;
   const int k = L::harm(j), pr = L::prof(j, u);
-  if (pr >= L::S) return 0.0;
+  if (pr >= L::Sk(k)) return 0.0;
   if (k == 0) return double(d[pr]);
   const double c = cs[k * R + r], s = cs[(L::NQ + k) * R + r];
   const double ca = L::part(u) ? -s : c, cb = L::part(u) ? c : s;
-  return double(d[L::base(k) + pr]) * ca + double(d[L::base(k) + L::S + pr]) * cb;
+  return double(d[L::base(k) + pr]) * ca + double(d[L::base(k) + L::Sk(k) + pr]) * cb;
 }
 
 // Sum of a double over the W lanes of a patch.

@@ -35,52 +35,17 @@
 #include <hip/hip_runtime.h>
 
 #include "rsc_device.h"
+#include "rsc_encode16.h"
 #include "rsc_internal.h"
 #include "rsc_launch.h"
 
 namespace rsc {
 namespace {
 
-struct EncodeParams {
-  const float* xhat;
-  int64_t P;
-  int K, M, R;
-  const float* dictA;     // encode32 stage-1 operand [NG][NKS][64]
-  const float* dictHat;   // [NG8*8 or NG*16][B]
-  const float* dftA;      // stage-2 operand (layout per tile shape)
-  const float* cs;        // [2][T+1][R]
-  const float* gramH;     // [M][M][2T+1] per-pair harmonic inner products
-  const double* gramH64;  // the same in FP64 (FP64 re-solve)
-  const double* cs64;     // [2][T+1][R] in FP64
-  int32_t* atom;
-  int32_t* angle;
-  float* coef;
-  float* resid2;
-  unsigned long long* stats;   // [4]: [3] counts pursuit steps solved in FP64
-};
-
-// Adds this wave's count of FP64 least-squares steps to stats[3] (one atomic per wave).
-__device__ __forceinline__ void count_fp64(unsigned long long* stats, unsigned n, int lane) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) n += __shfl_xor(n, off);
-  if (lane == 0 && stats && n) atomicAdd(stats + 3, (unsigned long long)n);
-}
-
-template <class L, int KMAX>
-__device__ __forceinline__ void write_codes(const EncodeParams& prm, int64_t p, const PursuitState<KMAX>& st,
-                                            float rn2) {
-  const int K = prm.K;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    if (i < K) {
-      const bool s = i < st.nsel;
-      prm.atom[p * K + i] = s ? st.selm[i] : -1;
-      prm.angle[p * K + i] = s ? st.selr[i] : -1;
-      prm.coef[p * K + i] = s ? st.cf[i] : 0.f;
-    }
-  }
-  if (prm.resid2) prm.resid2[p] = rn2;
-}
+using enc::EncodeParams;
+using enc::count_fp64;
+using enc::encode16_kernel;
+using enc::write_codes;
 
 // ============================================================== 32x32 tiles
 // F[q]: stage-2 operand of harmonic q for angle rows r < R/2 (rows past R/2 zero).
@@ -247,209 +212,6 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
   count_fp64(prm.stats, n64, lane);
 }
 
-// ============================================================== 16x16 tiles
-// SPLIT (even R): each stage-2 step contracts a pair of harmonics of one parity,
-// (4j, 4j+2) for E and (4j+1, 4j+3) for O; HT tiles of 16 angle rows cover r < R/2.
-// dftA: [HT][SE + SO][64] (E steps first).
-// Direct (odd R): steps contract harmonic pairs (2q, 2q+1); HT tiles cover r < R.
-// dftA: [HT][NP][64].
-template <int S, int T, int HT, int KMAX, bool SPLIT>
-__global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
-  using L = Layout<S, T, 4>;
-  constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B;
-  constexpr int NE = T / 2 + 1, NO = (T + 1) / 2;           // even / odd harmonics
-  constexpr int SE = SPLIT ? (NE + 1) / 2 : (NQ + 1) / 2;   // steps feeding the E (or only) chain
-  constexpr int SO = SPLIT ? (NO + 1) / 2 : 0;              // steps feeding the O chain
-  constexpr int NS = SE + SO;
-  extern __shared__ float lds[];
-  const int R = prm.R, M = prm.M, K = prm.K, HALF = SPLIT ? prm.R / 2 : prm.R;
-  const int NG = (M + 7) / 8;
-  float* sHat = lds;                     // [NG*8][B]
-  float* sCs = sHat + NG * 8 * B;        // [2][NQ][R]
-  {
-    const int nH = NG * 8 * B, nC = 2 * NQ * R;
-    for (int i = threadIdx.x; i < nH; i += blockDim.x) sHat[i] = prm.dictHat[i];
-    for (int i = threadIdx.x; i < nC; i += blockDim.x) sCs[i] = prm.cs[i];
-  }
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, u = lane >> 4;
-  const LsTables tb{prm.gramH, prm.gramH64, prm.cs64, prm.xhat, M, R, kCondMaxFp32};
-  unsigned n64 = 0;
-  // stage-1 operand row of this lane: rows 0-3 Re of atoms 0-3, 4-7 Im of atoms 0-3,
-  // 8-11 Re of atoms 4-7, 12-15 Im of atoms 4-7; contraction index 4j+u
-  const int arow = lane & 15;
-  const int a_of_row = (arow & 3) + 4 * (arow >> 3);
-  const bool is_im = (arow >> 2) & 1;
-  const int part = u & 1;
-  const int sel_off = ((part ^ int(is_im)) ? S : 0) + (u >> 1);   // Re/Im column + profile offset
-  const float sgn = (is_im && part == 0) ? -1.f : 1.f;
-  const float* arow_hat = sHat + a_of_row * B;
-
-  float F[HT][NS];
-#pragma unroll
-  for (int t = 0; t < HT; ++t)
-#pragma unroll
-    for (int q = 0; q < NS; ++q) F[t][q] = prm.dftA[(t * NS + q) * 64 + lane];
-
-  // harmonics contracted by step q: (k1, k2)
-  auto k1_of = [](int q) { return SPLIT ? (q < SE ? 4 * q : 4 * (q - SE) + 1) : 2 * q; };
-  auto k2_of = [](int q) { return SPLIT ? (q < SE ? 4 * q + 2 : 4 * (q - SE) + 3) : 2 * q + 1; };
-
-  const int64_t nwt = (prm.P + 15) / 16;
-  for (int64_t wt = int64_t(blockIdx.x) * 4 + wave; wt < nwt; wt += int64_t(gridDim.x) * 4) {
-    const int64_t p = wt * 16 + col;
-    const bool valid = p < prm.P;
-    float res[NKS];
-#pragma unroll
-    for (int j = 0; j < NKS; ++j) {
-      const int c = L::coord(j, u);
-      res[j] = (valid && c >= 0) ? prm.xhat[p * B + c] : 0.f;
-    }
-    const float nx2 = norm2<L>(res);
-    PursuitState<KMAX> st;
-    init_state(st, valid);
-    LsState<KMAX> ls;
-    init_ls(ls);
-
-    for (int it = 0; it < K; ++it) {
-      st.active = st.active && (norm2<L>(res) > kTau2 * nx2);
-      if (!__any(st.active)) break;
-
-      float best = -1.f;
-      int bm = 0;
-      float bop[NS];
-      zero(bop);
-      for (int g = 0; g < NG; ++g) {
-        const float* hg = arow_hat + g * 8 * B;
-        f32x4 acc[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < NKS; ++j) {
-          const int k = L::harm(j);
-          float av;
-          if (k == 0) {
-            const int s = 4 * j + u;
-            const float h = hg[s < S ? s : 0];
-            av = (!is_im && s < S) ? h : 0.f;
-          } else {
-            const int jj = L::pair(j);
-            const int s = 2 * jj + (u >> 1);
-            const int off = L::base(k) + 2 * jj + sel_off;
-            const float h = hg[s < S ? off : 0];
-            av = s < S ? sgn * h : 0.f;
-          }
-          acc[k] = mfma16(av, res[j], acc[k]);
-        }
-        // quarters 0,1 hold (Re, Im) of atom v, quarters 2,3 of atom v+4.  Swapping
-        // harmonics (k1, k2) of a step gives the operand [Re_k1 Im_k1 Re_k2 Im_k2]
-        // of atoms v and v+4, kept in place: atom a < 4 in acc[k1][a], atom a >= 4 in
-        // acc[k2][a-4] (or pad[q][a-4] when k2 > T).
-        float pad[NS][4];
-#pragma unroll
-        for (int q = 0; q < NS; ++q)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int k1 = k1_of(q), k2 = k2_of(q);
-            float x = acc[k1][v];
-            float y = k2 <= T ? acc[k2][v] : 0.f;
-            swap32(x, y);
-            acc[k1][v] = x;
-            if (k2 <= T) acc[k2][v] = y;
-            pad[q][v] = y;
-          }
-        auto opnd = [&](int q, int a) -> float {
-          const int k1 = k1_of(q), k2 = k2_of(q);
-          return a < 4 ? acc[k1][a] : (k2 <= T ? acc[k2][a - 4] : pad[q][a - 4]);
-        };
-        // per atom: HT tiles x (E, O) chains; the chains of the next atom are issued
-        // before the reduction of the current one
-        f32x4 ob[2][2][HT];
-        auto chains = [&](int a, f32x4 (&o)[2][HT]) {
-#pragma unroll
-          for (int t = 0; t < HT; ++t) o[0][t] = o[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int q = 0; q < NS; ++q)
-#pragma unroll
-            for (int t = 0; t < HT; ++t) {
-              const int c = q < SE ? 0 : 1;
-              o[c][t] = mfma16(F[t][q], opnd(q, a), o[c][t]);
-            }
-        };
-        chains(0, ob[0]);
-        int ba = 0;
-        bool upd = false;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          if (a + 1 < 8) chains(a + 1, ob[(a + 1) & 1]);
-          const f32x4 (&o)[2][HT] = ob[a & 1];
-          float am = 0.f;
-#pragma unroll
-          for (int t = 0; t < HT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              am = fmaxf(am, SPLIT ? fabsf(o[0][t][i]) + fabsf(o[1][t][i]) : fabsf(o[0][t][i]));
-          am = max_quarters_nonneg(am);
-          const bool gt = am > best;
-          best = gt ? am : best;
-          ba = gt ? a : ba;
-          upd = upd || gt;
-#pragma unroll
-          for (int q = 0; q < NS; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
-        }
-        bm = upd ? g * 8 + ba : bm;
-      }
-      int rs;
-      float cval;
-      {
-        f32x4 o[2][HT];
-#pragma unroll
-        for (int t = 0; t < HT; ++t) o[0][t] = o[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < NS; ++q)
-#pragma unroll
-          for (int t = 0; t < HT; ++t) {
-            const int c = q < SE ? 0 : 1;
-            o[c][t] = mfma16(F[t][q], bop[q], o[c][t]);
-          }
-        float rb = -1.f, rv = 0.f;
-        int rc = 0;
-#pragma unroll
-        for (int h = 0; h < (SPLIT ? 2 : 1); ++h)   // angles r < R/2 first, then r + R/2
-#pragma unroll
-          for (int t = 0; t < HT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int row = 16 * t + 4 * u + i;
-              const float sc = SPLIT ? (h == 0 ? o[0][t][i] + o[1][t][i] : o[0][t][i] - o[1][t][i]) : o[0][t][i];
-              const float val = row < HALF ? fabsf(sc) : -1.f;
-              const bool gt = val > rb;
-              rb = gt ? val : rb;
-              rv = gt ? sc : rv;
-              rc = gt ? row + h * HALF : rc;
-            }
-#pragma unroll
-        for (int sh = 16; sh <= 32; sh *= 2) {
-          const float ob2 = __shfl_xor(rb, sh), ov = __shfl_xor(rv, sh);
-          const int oc = __shfl_xor(rc, sh);
-          const bool take = (ob2 > rb) || (ob2 == rb && oc < rc);
-          rb = take ? ob2 : rb;
-          rv = take ? ov : rv;
-          rc = take ? oc : rc;
-        }
-        rs = rc < R ? rc : R - 1;
-        cval = rv;
-      }
-      n64 += (ls_update<L, KMAX>(st, ls, it, bm, rs, cval, sHat, sCs, tb, p, u, res) && u == 0) ? 1u : 0u;
-    }
-    const float rn2 = norm2<L>(res);
-    if (valid && u == 0) write_codes<L, KMAX>(prm, p, st, rn2);
-  }
-  count_fp64(prm.stats, n64, lane);
-}
-
 // ============================================================== launchers
 template <int S, int T, int KMAX>
 int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
@@ -457,33 +219,33 @@ int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
                            t.enc_bpc, st, prm, t.NG);
 }
 
-template <int S, int T, int HT, int KMAX, bool SPLIT>
+template <class C, int HT, int KMAX, bool SPLIT>
 int launch16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  return launch_persistent(encode16_kernel<S, T, HT, KMAX, SPLIT>, encode_lds_bytes(t, RSC_TILE_16),
+  return launch_persistent(encode16_kernel<C, HT, KMAX, SPLIT>, encode_lds_bytes(t, RSC_TILE_16),
                            (prm.P + 15) / 16, t.enc_bpc, st, prm);
 }
 
-template <int S, int T, int HT, bool SPLIT>
+template <class C, int HT, bool SPLIT>
 int k16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  if (prm.K <= 2) return launch16<S, T, HT, 2, SPLIT>(t, prm, st);
-  if (prm.K <= 4) return launch16<S, T, HT, 4, SPLIT>(t, prm, st);
-  return launch16<S, T, HT, 8, SPLIT>(t, prm, st);
+  if (prm.K <= 2) return launch16<C, HT, 2, SPLIT>(t, prm, st);
+  if (prm.K <= 4) return launch16<C, HT, 4, SPLIT>(t, prm, st);
+  return launch16<C, HT, 8, SPLIT>(t, prm, st);
 }
 
 // angle tiles of 16 rows: R/2 rows with the split (even R), R rows without
-template <int S, int T>
+template <class C>
 int r16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
   if (t.R % 2 == 0) {
     const int ht = (t.R / 2 + 15) / 16;
-    if (ht <= 1) return k16<S, T, 1, true>(t, prm, st);
-    if (ht <= 2) return k16<S, T, 2, true>(t, prm, st);
-    return k16<S, T, 4, true>(t, prm, st);
+    if (ht <= 1) return k16<C, 1, true>(t, prm, st);
+    if (ht <= 2) return k16<C, 2, true>(t, prm, st);
+    return k16<C, 4, true>(t, prm, st);
   }
   const int ht = (t.R + 15) / 16;
-  if (ht <= 1) return k16<S, T, 1, false>(t, prm, st);
-  if (ht <= 2) return k16<S, T, 2, false>(t, prm, st);
-  if (ht <= 4) return k16<S, T, 4, false>(t, prm, st);
-  return k16<S, T, 8, false>(t, prm, st);
+  if (ht <= 1) return k16<C, 1, false>(t, prm, st);
+  if (ht <= 2) return k16<C, 2, false>(t, prm, st);
+  if (ht <= 4) return k16<C, 4, false>(t, prm, st);
+  return k16<C, 8, false>(t, prm, st);
 }
 
 int r32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
@@ -494,6 +256,12 @@ int r32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
 }  // namespace
 
 bool encode_supported(int S, int T) { return (S == 5 && T == 5) || (S == 7 && T == 7); }
+
+bool encode_supported_geo(const DeviceTables& t) {
+  if (t.geo == kGeoAnnular11) return t.T == AnnularCounts11::T && t.B == LayoutBase<AnnularCounts11, 4>::B;
+  if (t.geo == kGeoAnnular15) return t.T == AnnularCounts15::T && t.B == LayoutBase<AnnularCounts15, 4>::B;
+  return t.geo == kGeoGrid && encode_supported(t.S, t.T);
+}
 
 size_t encode_lds_bytes(const DeviceTables& t, int tile) {
   const size_t cs = 2 * size_t(t.T + 1) * t.R;
@@ -518,7 +286,9 @@ double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K) {
     const double per_step = double(t.NG) * (stage1_steps(S, T) + 16.0 * NQ) + NQ;
     return K * per_step * 4096.0 / 32.0;
   }
-  const int W = 4, J0 = (S + W - 1) / W, J1 = (2 * S + W - 1) / W, NKS = J0 + T * J1;
+  const int W = 4;
+  int NKS = (t.sk[0] + W - 1) / W;
+  for (int k = 1; k <= T; ++k) NKS += (2 * t.sk[k] + W - 1) / W;
   int ht, ns;
   if (t.R % 2 == 0) {
     const int NE = T / 2 + 1, NO = (T + 1) / 2;
@@ -547,8 +317,11 @@ int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P,
   }
   EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.R % 2 == 0 ? t.dftA16s : t.dftA16, t.cs, t.gramH,
                    t.gramH64, t.cs64, atom, angle, coef, resid2, t.lpStats};
-  if (t.S == 5 && t.T == 5) return r16<5, 5>(t, prm, st);
-  if (t.S == 7 && t.T == 7) return r16<7, 7>(t, prm, st);
+  if (t.geo == kGeoAnnular11 || t.geo == kGeoAnnular15)
+    return launch_encode_annular(t, xhat, P, K, atom, angle, coef, resid2, stream);
+  if (t.geo != kGeoGrid) return int(hipErrorInvalidValue);
+  if (t.S == 5 && t.T == 5) return r16<UniformCounts<5, 5>>(t, prm, st);
+  if (t.S == 7 && t.T == 7) return r16<UniformCounts<7, 7>>(t, prm, st);
   return int(hipErrorInvalidValue);
 }
 

@@ -30,9 +30,15 @@ bool build_annular_basis(int N, bool lowpass, HostBasis& out, std::vector<int>& 
 constexpr int k0_steps(int S) { return (S + 1) / 2; }
 constexpr int stage1_steps(int S, int T) { return k0_steps(S) + T * S; }
 
+// Coordinate layouts the encoders are compiled for: the (S, T) grid of Gaussian profiles,
+// and the paper's annular basis at N = 11 and N = 15 (ragged counts per harmonic).
+constexpr int kGeoGrid = 0, kGeoAnnular11 = 11, kGeoAnnular15 = 15, kGeoAnnularOther = -1;
+
 // Device tables owned by a handle (FP32 operand arrangements built on the host).
 struct DeviceTables {
   int N = 0, S = 0, T = 0, B = 0, n_pix = 0;
+  int geo = kGeoGrid;        // coordinate layout (kGeo*)
+  int sk[64] = {};           // profiles (annuli) carrying harmonic k, k = 0..T
   int prec = RSC_FP32;       // rsc_precision of the handle
   int M = 0, R = 0, NG = 0;
   int enc_bpc = 0;           // encoder blocks per CU (0: as many as fit)
@@ -81,6 +87,12 @@ int launch_synthesize(const DeviceTables& t, const int32_t* atom, const int32_t*
                       const float* theta, const float* weight, int64_t P, int J,
                       const float* noise, float* out, void* stream);
 bool encode_supported(int S, int T);
+bool encode_supported_geo(const DeviceTables& t);   // the encoder is compiled for t's layout
+// The pursuit on the paper's annular basis (rsc_encode_annular.hip): 16x16 tiles, even
+// R <= 64, K <= 4.
+constexpr int kAnnularMaxK = 4, kAnnularMaxR = 64;
+int launch_encode_annular(const DeviceTables& t, const float* xhat, int64_t P, int K, int32_t* atom,
+                          int32_t* angle, float* coef, float* resid2, void* stream);
 size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);

@@ -21,6 +21,8 @@ struct SynthParams {
   const float* dictHat;       // [.][B]
   const float* cs;            // [2][T+1][R]
   const float* phiPad;        // [NN][B]
+  const int* steerTab;        // annular basis: (k << 16) | (partner offset + 32768) per
+                              // coordinate; null for the (S, T) grid
 };
 
 constexpr int kSynthPB = 8;
@@ -45,7 +47,23 @@ __global__ __launch_bounds__(128) void synth_kernel(SynthParams p) {
         const float w = p.weight[pp * p.J + j];
         const float* d = p.dictHat + int64_t(m) * B;
         float v;
-        if (c < S) {
+        if (p.steerTab) {
+          // ragged layout: harmonic k and the offset of the Re/Im partner from the table
+          const int e2 = p.steerTab[c], k = e2 >> 16, off = (e2 & 0xffff) - 32768;
+          if (k == 0) {
+            v = d[c];
+          } else {
+            float co, sn;
+            if (p.angle_idx) {
+              co = p.cs[k * p.R + r];
+              sn = p.cs[(p.T + 1 + k) * p.R + r];
+            } else {
+              sincosf(float(k) * p.theta[pp * p.J + j], &sn, &co);
+            }
+            const float own = d[c], partner = d[c + off];
+            v = off > 0 ? (own * co + partner * sn) : (own * co - partner * sn);
+          }
+        } else if (c < S) {
           v = d[c];
         } else {
           const int q = c - S, k = 1 + q / (2 * S), rem = q % (2 * S), s = rem % S;
@@ -86,7 +104,7 @@ int launch_synthesize(const DeviceTables& t, const int32_t* atom, const int32_t*
                       float* out, void* stream) {
   if (P <= 0) return 0;
   SynthParams p{atom, angle_idx, theta, weight, noise, out, P, J, t.M, t.R, t.S, t.T, t.B,
-                t.N * t.N, t.dictHat, t.cs, t.phiPad};
+                t.N * t.N, t.dictHat, t.cs, t.phiPad, t.geo == kGeoGrid ? nullptr : t.steerTab};
   const int64_t blocks = (P + kSynthPB - 1) / kSynthPB;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(synth_kernel, dim3(unsigned(blocks)), dim3(128), sizeof(float) * kSynthPB * t.B,

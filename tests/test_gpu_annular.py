@@ -78,12 +78,91 @@ def test_annular_steering_chunk_edges_and_alignment(dev, P):
 
 
 def test_annular_refusals(dev):
+    """The pursuit is compiled for the full annular basis at N = 11 and 15, even R <= 64 and
+    K <= 4; the low-pass basis and other sizes serve projection, steering and synthesis."""
     from paper_1806_04374_amd import rsc
     with pytest.raises(rsc.RscError) as e:
         rsc.rsc_create_annular(17)           # B = 204
     assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    for N, lowpass in ((11, True), (9, False), (13, False)):
+        h = rsc.rsc_create_annular(N, lowpass)
+        with pytest.raises(rsc.RscError) as e:
+            rsc.rsc_set_dictionary(h, np.ones((2, h.B), np.float32) / np.sqrt(h.B), 8)
+        assert e.value.status == rsc.RSC_E_UNSUPPORTED
+        h.close()
     h = rsc.rsc_create_annular(11)
+    D = np.ones((2, h.B), np.float32) / np.sqrt(h.B)
+    for R in (7, 66):
+        with pytest.raises(rsc.RscError) as e:
+            rsc.rsc_set_dictionary(h, D, R)
+        assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    rsc.rsc_set_dictionary(h, D, 8)
     with pytest.raises(rsc.RscError) as e:
-        rsc.rsc_set_dictionary(h, np.ones((2, h.B), np.float32) / np.sqrt(h.B), 8)
+        rsc.rsc_omp_encode(h, torch.zeros((4, h.B), dtype=torch.float32, device=dev), 5)
     assert e.value.status == rsc.RSC_E_UNSUPPORTED
+    h.close()
+
+
+# ----------------------------------------------------------------------------- pursuit
+def _annular_check(dev, N, M, K, R, P, seed, sigma=0.02, J=3):
+    """Project + encode + reconstruct on the annular basis against the reference: selected
+    (atom, angle) sets on >= 99.9% of patches, coefficients within 1e-4, MSE within 1e-3."""
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import workloads as wl
+    from tests.parity import compare_codes
+    ab = orc.build_annular_basis(N)
+    h = rsc.rsc_create_annular(N)
+    D = wl.draw_dictionary(M, ab.B, seed=seed)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    d = wl.draw_mixtures(P, N, M, J, sigma, seed=seed)
+    X = orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev))
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, xh, K)
+    rec = rsc.rsc_reconstruct(h, atom, angle, coef)
+    torch.cuda.synchronize()
+    xh_ref, code = orc.encode(ab, D, R, X.astype(np.float64), K)
+    rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code, 1e-4,
+                        xnorm=np.linalg.norm(xh_ref, axis=1))
+    print(f"annular N={N} M={M} K={K} R={R}", rep, flush=True)
+    assert rep.match_rate >= 0.999, str(rep)
+    assert rep.coef_bad == 0, str(rep)
+    mse_dev = orc.mse(ab, X, rec.cpu().numpy().astype(np.float64))
+    mse_ref = orc.mse(ab, X, orc.reconstruct(ab, D, R, code))
+    assert abs(mse_dev - mse_ref) <= 1e-3 * mse_ref + 1e-12, (mse_dev, mse_ref)
+    r2 = r2.cpu().numpy()
+    close = np.abs(r2 - code.resid2) <= 1e-3 * code.resid2 + 1e-5 * np.einsum("ij,ij->i", xh_ref, xh_ref) + 1e-12
+    assert close.mean() >= 0.999
+    h.close()
+    return rep
+
+
+@pytest.mark.parametrize("N,M,K,R", [(11, 16, 2, 32), (11, 64, 4, 64), (15, 32, 4, 64), (15, 20, 3, 30)])
+def test_annular_pursuit_matches_reference(dev, N, M, K, R):
+    """The paper's annular basis (B = 81 at N = 11, 153 at N = 15): mixtures of rotated atoms
+    at continuous angles plus noise; 3,001 patches (a ragged last tile); atom counts on and
+    off the 8-atom groups, one and two 16-row angle tiles."""
+    _annular_check(dev, N, M, K, R, 3001, seed=N + M + K + R)
+
+
+@pytest.mark.parametrize("N", [11, 15])
+def test_annular_pursuit_exact_recovery(dev, N):
+    """Noise-free single atoms at grid angles are recovered exactly and the pursuit stops."""
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import workloads as wl
+    ab = orc.build_annular_basis(N)
+    h = rsc.rsc_create_annular(N)
+    M, R = 12, 32
+    D = wl.draw_dictionary(M, ab.B, seed=5)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    rng = np.random.default_rng(N)
+    m = rng.integers(0, M, (200, 1))
+    r = rng.integers(0, R, (200, 1))
+    w = rng.uniform(0.5, 2.0, (200, 1)) * rng.choice([-1, 1], (200, 1))
+    xh = orc.steer_ragged(D[m[:, 0]], 2 * np.pi * r[:, 0] / R, ab.Sk) * w
+    atom, angle, coef, r2 = rsc.rsc_omp_encode(h, torch.from_numpy(xh.astype(np.float32)).to(dev), 2)
+    torch.cuda.synchronize()
+    atom, angle, coef = atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy()
+    assert np.array_equal(atom[:, 0], m[:, 0]) and np.array_equal(angle[:, 0], r[:, 0])
+    assert np.abs(coef[:, 0] - w[:, 0]).max() < 1e-5 * np.abs(w).max()
+    assert np.all(atom[:, 1] == -1)
     h.close()
