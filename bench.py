@@ -743,6 +743,104 @@ def texture_learn(args, dev, xh_train, tb, R):
     return clf, learn_s
 
 
+def annular_flops_per_patch(Sk, M: int, R: int, K: int) -> float:
+    """Arithmetic of the pursuit on a ragged (annular) layout, one patch, all K steps: stage
+    1 forms C_k over the Sk[k] annuli of harmonic k (2 Sk[0] flops for k = 0, 8 Sk[k] per
+    complex product sum for k >= 1), the angle DFT split by parity (M R (2T + 1) for even
+    R), and the least squares as for the grid."""
+    T = len(Sk) - 1
+    B = Sk[0] + 2 * sum(Sk[1:])
+    stage1 = 2.0 * M * (Sk[0] + 4 * sum(Sk[1:]))
+    dft = M * R * (2 * T + 1) * (1.0 if R % 2 == 0 else 2.0)
+    ls = sum(2.0 * (2 * k * B + k * k) for k in range(1, K + 1))
+    return K * (stage1 + dft) + ls
+
+
+def run_annular(args, dev):
+    """The pursuit on the paper's annular basis (eq. (5)-(8)): the scale workload's draws
+    (10^6 11x11 patches, 1-4 atoms at continuous angles, Laplace weights, N(0, 0.05^2)
+    noise) with a 64-atom dictionary in the annular coordinates (B = 81), K = 4, R = 64."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    w = wl.SCALE
+    N, M, K, R = 11, w["M"], w["K"], w["R"]
+    P = args.patches or w["P"]
+    h = rsc.rsc_create_annular(N)
+    D = wl.draw_dictionary(M, h.B, seed=7)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    X = make_inputs(h, w, P, dev)
+    xh = torch.empty((P, h.B), dtype=torch.float32, device=dev)
+    outs = (torch.empty((P, K), dtype=torch.int32, device=dev), torch.empty((P, K), dtype=torch.int32, device=dev),
+            torch.empty((P, K), dtype=torch.float32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        rsc.rsc_project(h, X, xh, stream=stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b, c in ev:
+        a.record(stream)
+        rsc.rsc_project(h, X, xh, stream=stream)
+        b.record(stream)
+        rsc.rsc_omp_encode(h, xh, K, out=outs, stream=stream)
+        c.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    step_ms = np.array([a.elapsed_time(c) for a, _, c in ev])
+    enc = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    Ts = h.Ts
+    Sk = [sum(1 for t in Ts if t >= k) for k in range(max(Ts) + 1)]
+    own = annular_flops_per_patch(Sk, M, R, K) * P
+    tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
+    out = {
+        "metric": METRIC, "value": P / (ms * 1e-3), "unit": "patches/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"annular: {P} 11x11 patches in the paper's annular basis (T_s = {Ts}, B = {h.B}), "
+                               f"M={M}, K={K}, R={R}", "P": P, "N": N, "B": h.B, "M": M, "K": K, "R": R},
+        "kernels_ms": {"project_mean": float(np.mean([a.elapsed_time(b) for a, b, _ in ev])), "encode_mean": enc},
+        "roofline": {"kernel": "encode16_kernel (annular layout)", "bound": "mfma",
+                     "achieved": own / (enc * 1e-3) / 1e12, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": own / (enc * 1e-3) / FP32_MFMA_PEAK, "algorithmic_flops_per_launch": own,
+                     "executed_mfma_frac": mfma_pp * P / (enc * 1e-3) / FP32_MFMA_PEAK, "tile": tile_used,
+                     "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_annular(h, w, D, args.cpu_seconds, dev)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_annular(h, w, D, target_s, dev):
+    """The FP64 reference on a prefix of the annular workload, and the device's codes of that
+    prefix against it."""
+    from threadpoolctl import threadpool_info
+    from oracle import rsc_oracle as orc
+    ab = orc.build_annular_basis(11)
+
+    def sample(n):
+        _, d = wl.scale_draw(P=n)
+        return orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+
+    X0 = sample(128)
+    t0 = time.perf_counter()
+    orc.encode(ab, D, w["R"], X0.astype(np.float64), w["K"])
+    dt0 = time.perf_counter() - t0
+    n = int(min(100_000, max(128, 128 * target_s / max(dt0, 1e-3))))
+    X = sample(n)
+    t0 = time.perf_counter()
+    _, code = orc.encode(ab, D, w["R"], X.astype(np.float64), w["K"])
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    ref = {"X": X, "code": code, "mse": orc.mse(ab, X, orc.reconstruct(ab, D, w["R"], code)), "basis": ab}
+    return {"value": n / dt, "unit": "patches/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} patches of the same workload (FP64 reference, {dt:.1f} s)", "host": host_info(),
+            "check": device_check(h, ref, D, w["R"], w["K"], dev)}
+
+
 def run_rotate(args, dev):
     """Rotation speed (Sec. III-C): random N x N patches turned by 100 + sqrt(2) degrees with
     the nearest and bicubic rotation matrices (R x) and by steering precomputed hat
@@ -931,7 +1029,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture", "rotate"],
+    ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture", "rotate",
+                                           "annular"],
                     default="scale")
     ap.add_argument("--check-patches", type=int, default=50_000,
                     help="precision: scale-workload patches checked against the reference")
@@ -990,6 +1089,9 @@ def main():
         return
     if args.workload == "rotate":
         run_rotate(args, dev)
+        return
+    if args.workload == "annular":
+        run_annular(args, dev)
         return
     w = wl.SCALE if args.workload == "scale" else wl.SMALL
     g = w["geom"]

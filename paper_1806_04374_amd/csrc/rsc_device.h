@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 namespace rsc {
 
@@ -78,6 +79,19 @@ __device__ __forceinline__ float max_quarters(float x) {
   float a = x, b = x;
   swap16(a, b);
   return max_halves(fmaxf(a, b));
+}
+
+// Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1, so that the body can evaluate
+// layout lookups of index i as constant expressions.  The ragged layout's lookups loop over
+// harmonics; called from an unrolled loop, the optimiser does not always fold them, and an
+// accumulator array indexed by an unfolded value is demoted to private memory.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
 // ----------------------------------------------------------------------------
@@ -229,27 +243,28 @@ __device__ __forceinline__ void steer_axpy(float (&acc)[L::NKS], float alpha, co
   }
   const int pt = L::part(u), so = L::soff(u);
   const float as = pt ? -alpha : alpha;
-#pragma unroll
-  for (int k = 1; k <= L::T; ++k) {
-    const float* pA = d + L::base(k) + (pt ? L::Sk(k) : 0) + so;
-    const float* pB = d + L::base(k) + (pt ? 0 : L::Sk(k)) + so;
+  // harmonics as compile-time indices: the register of each coordinate is a constant
+  static_for<L::T>([&](auto K1) {
+    constexpr int k = decltype(K1)::value + 1;
+    constexpr int bk = L::base(k), nk = L::Sk(k), j0 = L::joff(k), nj = L::J1k(k);
+    const float* pA = d + bk + (pt ? nk : 0) + so;
+    const float* pB = d + bk + (pt ? 0 : nk) + so;
     const float ck = alpha * cs[k * R + r];
     const float sk = as * cs[(L::NQ + k) * R + r];
 #pragma unroll
-    for (int jj = 0; jj < L::J1k(k); ++jj) {
-      const int j = L::joff(k) + jj;
-      if (L::SW * jj >= L::Sk(k)) continue;             // padding in every lane
+    for (int jj = 0; jj < nj; ++jj) {
+      if (L::SW * jj >= nk) continue;                   // padding in every lane
       float a = ck, b = sk;
       int off = L::SW * jj;
-      if (L::SW * jj + L::SW - 1 >= L::Sk(k)) {         // padding in some lanes
-        const bool valid = L::SW * jj + so < L::Sk(k);
+      if (L::SW * jj + L::SW - 1 >= nk) {               // padding in some lanes
+        const bool valid = L::SW * jj + so < nk;
         a = valid ? a : 0.f;
         b = valid ? b : 0.f;
         off = valid ? off : -so;
       }
-      acc[j] = fmaf(pA[off], a, fmaf(pB[off], b, acc[j]));
+      acc[j0 + jj] = fmaf(pA[off], a, fmaf(pB[off], b, acc[j0 + jj]));
     }
-  }
+  });
 }
 
 // <S_{ra} d_a, S_{rb} d_b> from the per-pair harmonic table
@@ -405,14 +420,19 @@ __device__ __forceinline__ bool ls_solve64(PursuitState<KMAX>& st, int it, int m
     for (int l = i + 1; l <= it; ++l) s -= Lc[l][i] * a[l];
     a[i] = s / Lc[i][i];
   }
-#pragma unroll
+  // the new residual goes through a local array first: the loop over its coordinates runs
+  // at run time, and only the copy into res (indexed at compile time) touches the registers
+  float rn[L::NKS];
+#pragma unroll 1
   for (int j = 0; j < L::NKS; ++j) {
     const int c = L::coord(j, u);
     double r = (good && c >= 0) ? double(tb.xhat[pp * L::B + c]) : 0.0;
 #pragma unroll 1
     for (int i = 0; i <= it; ++i) r -= a[i] * steer64<L>(hat, tb.cs64, R, cm[i], cr[i], j, u);
-    res[j] = good ? float(r) : res[j];
+    rn[j] = float(r);
   }
+#pragma unroll
+  for (int j = 0; j < L::NKS; ++j) res[j] = good ? rn[j] : res[j];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
     st.cf[i] = (good && i <= it) ? float(a[i]) : st.cf[i];

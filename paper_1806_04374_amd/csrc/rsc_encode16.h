@@ -109,11 +109,11 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
     const int64_t p = wt * 16 + col;
     const bool valid = p < prm.P;
     float res[NKS];
-#pragma unroll
-    for (int j = 0; j < NKS; ++j) {
+    static_for<NKS>([&](auto J) {
+      constexpr int j = decltype(J)::value;
       const int c = L::coord(j, u);
       res[j] = (valid && c >= 0) ? prm.xhat[p * B + c] : 0.f;
-    }
+    });
     const float nx2 = norm2<L>(res);
     PursuitState<KMAX> st;
     init_state(st, valid);
@@ -133,23 +133,23 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
         f32x4 acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < NKS; ++j) {
-          const int k = L::harm(j);
+        static_for<NKS>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          constexpr int k = L::harm(j);
           float av;
-          if (k == 0) {
+          if constexpr (k == 0) {
             const int s = 4 * j + u;
             const float h = hg[s < L::S ? s : 0];
             av = (!is_im && s < L::S) ? h : 0.f;
           } else {
-            const int jj = L::pair(j);
+            constexpr int jj = L::pair(j), bk = L::base(k), sk = L::Sk(k);
             const int s = 2 * jj + (u >> 1);
-            const int off = L::base(k) + 2 * jj + (u >> 1) + (other ? L::Sk(k) : 0);
-            const float h = hg[s < L::Sk(k) ? off : 0];
-            av = s < L::Sk(k) ? sgn * h : 0.f;
+            const int off = bk + 2 * jj + (u >> 1) + (other ? sk : 0);
+            const float h = hg[s < sk ? off : 0];
+            av = s < sk ? sgn * h : 0.f;
           }
           acc[k] = mfma16(av, res[j], acc[k]);
-        }
+        });
         // quarters 0,1 hold (Re, Im) of atom v, quarters 2,3 of atom v+4.  Swapping
         // harmonics (k1, k2) of a step gives the operand [Re_k1 Im_k1 Re_k2 Im_k2]
         // of atoms v and v+4, kept in place: atom a < 4 in acc[k1][a], atom a >= 4 in
