@@ -127,8 +127,12 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * harmonic-major with the annuli whose T_s >= k in block k ([Re][Im] for k >= 1, the
  * convention of rsc_create).  B = sum_s (2 T_s + 1) (81 at N = 11, 39 low-pass).
  * The handle is FP32 and serves rsc_project, rsc_steer, rsc_synthesize_hat,
- * rsc_basis_info and rsc_get_basis; rsc_set_dictionary and image projection return
- * RSC_E_UNSUPPORTED.
+ * rsc_basis_info and rsc_get_basis.  The pursuit (rsc_set_dictionary, rsc_omp_encode,
+ * rsc_reconstruct) runs on the full basis at N = 11 (B = 81, T_s = 1, 3, 8, 11, 15) and
+ * N = 15 (B = 153, T_s = 1, 3, 8, 11, 13, 18, 19) with even R <= 64 and K <= 4, on the
+ * 16x16 encoder tile; other annular handles get RSC_E_UNSUPPORTED from
+ * rsc_set_dictionary.  Image projection, image stamping and the dictionary update return
+ * RSC_E_UNSUPPORTED for every annular handle.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
  * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
  * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 192 or some T_s > 31),
@@ -180,9 +184,9 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
  * or its staging buffer still feeds an earlier upload.
  * On any error the handle keeps its previous dictionary.
  * Errors: RSC_E_INVALID (arguments), RSC_E_UNSUPPORTED (sizes beyond the compiled
- * limits of the handle's precision, tables beyond the 160 KiB LDS of a CU, or a handle
- * of rsc_create_annular or of a geometry the pursuit is not compiled for), RSC_E_NOMEM,
- * RSC_E_DEVICE (sticky).
+ * limits of the handle's precision, tables beyond the 160 KiB LDS of a CU, an annular
+ * handle other than the full basis at N = 11 or 15 or with odd R or R > 64, or a geometry
+ * the pursuit is not compiled for), RSC_E_NOMEM, RSC_E_DEVICE (sticky).
  */
 rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, void* stream);
 

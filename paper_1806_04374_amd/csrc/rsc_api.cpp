@@ -249,7 +249,7 @@ rsc_status init_tables(rsc_handle* h, int N, int S, int T, rsc_precision prec) {
         }
   }
   // image projection operand (row tiles of 32 hat coordinates, disk-pixel contraction)
-  const int RTBI = (b.B + 31) / 32 <= 2 ? 2 : 4;
+  const int RTBI = b.B <= 64 ? 2 : b.B <= 128 ? 4 : (b.B + 31) / 32;
   std::vector<float> pinvI(size_t(RTBI) * KPD * 64, 0.f);
   std::vector<int> dpixI(size_t(2) * KPD, -1);
   for (int i = 0; i < b.n_pix; ++i) dpixI[i] = ((b.pix[i] / N) << 8) | (b.pix[i] % N);

@@ -45,7 +45,7 @@ struct DeviceTables {
   float* pinvA = nullptr;    // projection operand over the grid [RTB][ceil(N*N/2)][64]
   float* pinvD = nullptr;    // projection operand over disk pixels [2][ceil(n_pix/2)][64] (B <= 64)
   int* pixD = nullptr;       // grid index of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)] (every B)
-  float* pinvI = nullptr;    // image projection operand over disk pixels [2 or 4][ceil(n_pix/2)][64]
+  float* pinvI = nullptr;    // projection operand over disk pixels [tiles][ceil(n_pix/2)][64], tiles = 2 (B <= 64), 4 (B <= 128) or ceil(B/32)
   int* dpixI = nullptr;      // (dy << 8 | dx) of disk pixel i, -1 past n_pix [2*ceil(n_pix/2)]
   int* steerTab = nullptr;   // annular basis: per coordinate, harmonic k and partner offset
                              // ((k << 16) | (offset + 32768)); null for the full (S, T) grid

@@ -3,7 +3,7 @@
 // an FP32 MFMA GEMM with rows = hat coordinates, columns = patches and the
 // contraction over disk pixels.
 //
-//  * project_reg_kernel (11x11 with B <= 64, 15x15 with B in 97..128; 16-byte aligned
+//  * project_reg_kernel (11x11 with B <= 96, 15x15 with B in 97..160; 16-byte aligned
 //    patches): the operand in registers, one 32-row tile per wave, 32-patch chunks staged
 //    in LDS with the next one prefetched into registers, the partial last chunk in the
 //    same launch.
@@ -547,8 +547,9 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
                        reinterpret_cast<const uint4*>(t.lpPinv), t.lpPix16, t.lpPinvUnscale, vin, vout, xhat);
     return int(hipGetLastError());
   }
-  // register-operand kernel (16-byte aligned patches): 11x11 with B <= 64 (2 row tiles) and
-  // 15x15 with B in 97..128 (4 row tiles); whole 32-patch chunks and the partial last one
+  // register-operand kernel (16-byte aligned patches): 11x11 with B <= 64 or 96 (2 or 3 row
+  // tiles) and 15x15 with B in 97..128 or 129..160 (4 or 5 row tiles); whole 32-patch chunks
+  // and the partial last one
   const bool aligned = (reinterpret_cast<uintptr_t>(patches) & 15) == 0;
   const bool vout = (reinterpret_cast<uintptr_t>(xhat) & 15) == 0 && (kProjRegPatches * t.B) % 4 == 0;
   auto go_reg = [&](auto kern, int nt) {
@@ -563,8 +564,12 @@ int launch_project(const DeviceTables& t, const float* patches, int64_t P, float
   };
   if (aligned && t.N == 11 && t.n_pix == 97 && t.B <= 64 && t.pinvI && t.pixD)
     return go_reg(project_reg_kernel<121, 49, 2>, 2);
+  if (aligned && t.N == 11 && t.n_pix == 97 && t.B > 64 && t.B <= 96 && t.pinvI && t.pixD)   // annular, B = 81
+    return go_reg(project_reg_kernel<121, 49, 3>, 3);
   if (aligned && t.N == 15 && t.n_pix == 177 && t.B > 96 && t.B <= 128 && t.pinvI && t.pixD)
     return go_reg(project_reg_kernel<225, 89, 4>, 4);
+  if (aligned && t.N == 15 && t.n_pix == 177 && t.B > 128 && t.B <= 160 && t.pinvI && t.pixD)  // annular, B = 153
+    return go_reg(project_reg_kernel<225, 89, 5>, 5);
   // unaligned 11x11 input (S = T = 5): the LDS-operand tiled kernel
   if (t.N == 11 && t.S == 5 && t.T == 5 && t.pinvD) {
     constexpr int kNN = 121, kKPD = 49;

@@ -77,6 +77,26 @@ def test_annular_steering_chunk_edges_and_alignment(dev, P):
     h.close()
 
 
+@pytest.mark.parametrize("N", [11, 15])
+@pytest.mark.parametrize("P", [1, 32, 33, 32 * 700 + 5])
+def test_annular_projection_chunks_and_alignment(dev, N, P):
+    """Projection onto the annular basis (B = 81 in three 32-row tiles, B = 153 in five):
+    whole 32-patch chunks, the partial last one, and input that is not 16-byte aligned."""
+    from paper_1806_04374_amd import rsc
+    b = orc.build_annular_basis(N)
+    h = rsc.rsc_create_annular(N)
+    X = np.random.default_rng(P + N).standard_normal((P, N, N)).astype(np.float32)
+    ref = orc.project(b, X.astype(np.float64))
+    tol = 2e-5 * np.abs(ref).max()
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev)).cpu().numpy()
+    assert np.abs(xh - ref).max() < tol
+    flat = torch.zeros(P * N * N + 1, dtype=torch.float32, device=dev)
+    flat[1:] = torch.from_numpy(X.ravel()).to(dev)
+    xu = rsc.rsc_project(h, flat[1:].view(P, N, N)).cpu().numpy()
+    assert np.abs(xu - ref).max() < tol
+    h.close()
+
+
 def test_annular_refusals(dev):
     """The pursuit is compiled for the full annular basis at N = 11 and 15, even R <= 64 and
     K <= 4; the low-pass basis and other sizes serve projection, steering and synthesis."""
