@@ -191,9 +191,11 @@ def device_check(h, ref, D, R, K, dev) -> dict:
     torch.cuda.synchronize()
     rep = compare_codes(atom.cpu().numpy(), angle.cpu().numpy(), coef.cpu().numpy(), code)
     mse_dev = orc.mse(basis, X, rec.cpu().numpy().astype(np.float64))
+    # the floor under any code's MSE: the part of the patches outside span(Phi) (Sec. III-A)
+    span = orc.span_error(basis, X.astype(np.float64))
     return {"patches": int(len(X)), "selection_match": rep.match_rate, "coef_rel_err_max": rep.coef_err_max,
             "coef_bad": rep.coef_bad, "mse_device": mse_dev, "mse_oracle": ref["mse"],
-            "mse_rel_diff": abs(mse_dev - ref["mse"]) / ref["mse"]}
+            "mse_rel_diff": abs(mse_dev - ref["mse"]) / ref["mse"], "span_error": span}
 
 
 def run_ragged(args, dev):
