@@ -1214,8 +1214,8 @@ def precision_forms(D, w, X, ref, fp32_ms: float, args, dev) -> dict:
 
 def small_latency(dev, runs: int = 100) -> dict:
     """The small workload (2,000 11x11 patches, M=16, K=2, R=32): latency of one project +
-    encode over `runs` runs, HIP events on the launch stream, and its codes against the
-    FP64 reference (all 2,000 patches)."""
+    encode over `runs` runs, HIP events on the launch stream, called eagerly and replayed
+    from a HIP graph, and its codes against the FP64 reference (all 2,000 patches)."""
     import torch
     from oracle import rsc_oracle as orc
     from paper_1806_04374_amd import rsc
@@ -1246,8 +1246,29 @@ def small_latency(dev, runs: int = 100) -> dict:
             b.synchronize()
             if i >= 5:
                 lat.append(a.elapsed_time(b) * 1e3)
+        eager = outs[0].clone()
+        # the same two launches captured once in a HIP graph and replayed: what a serving loop
+        # that replays a graph sees, without the host's per-call work between the launches
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            cs = torch.cuda.current_stream()
+            rsc.rsc_project(h, x, xh, stream=cs)
+            rsc.rsc_omp_encode(h, xh, K, out=outs, stream=cs)
+        glat = []
+        for i in range(runs + 5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            graph.replay()
+            b.record(stream)
+            b.synchronize()
+            if i >= 5:
+                glat.append(a.elapsed_time(b) * 1e3)
+            if not torch.equal(outs[0], eager):
+                raise RuntimeError("graph replay changed the codes")
         res[prec] = {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+                     "graph_p50_us": float(np.percentile(glat, 50)), "graph_p99_us": float(np.percentile(glat, 99)),
                      "check": device_check(h, ref, D, w["R"], K, dev)}
+        del graph
         h.close()
     return res
 

@@ -66,7 +66,8 @@ typedef enum {
 
 /* Tile shape of the encoder (both give identical codes up to FP32 rounding order). */
 typedef enum {
-  RSC_TILE_AUTO = 0,       /* the library's choice for the geometry and K */
+  RSC_TILE_AUTO = 0,       /* the library's choice: RSC_TILE_32 where it is compiled and
+                              R > 32, else RSC_TILE_16 */
   RSC_TILE_16 = 1,         /* 16 patches x 8 atoms per MFMA tile (v_mfma_f32_16x16x4f32) */
   RSC_TILE_32 = 2          /* 32 patches x 16 atoms per MFMA tile (v_mfma_f32_32x32x2f32);
                               S = T = 5, K <= 4 and R <= 64 only */
@@ -273,7 +274,10 @@ rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size
  * angles lies within 8.5u ||residual|| of the largest one (u = 2^-8 for BF16, 2^-11
  * for FP16; above twice a worst-case bound, 4.02u ||residual||, on the 16-bit error of
  * a score, so the atom with the exact maximum is always among them) is re-scored over
- * all angles in FP32, and the selection is taken from the FP32 scores.
+ * all angles in FP32, and the selection is taken from the FP32 scores.  BF16 handles
+ * re-score the atom with the largest 16-bit maximum first and then only the candidates
+ * whose 16-bit maximum reaches its FP32 maximum minus 4.25u ||residual|| (the atom with
+ * the largest FP32 maximum always does).
  *
  * Least squares (every handle): a Cholesky update in FP32 while an upper bound on the
  * condition number of the selected columns' Gram matrix, k ||L^{-1}||_F^2, stays at or

@@ -897,6 +897,15 @@ rsc_status rsc_autotune_encode(rsc_handle* h, const float* xhat, int64_t P, int 
   return ok();
 }
 
+// Tile shape of the FP32 encoder: RSC_TILE_32 when asked for (or, under RSC_TILE_AUTO, when
+// R > 32) and compiled for the geometry and K; else RSC_TILE_16.  With R <= 32 the 32x32
+// tile's 32 angle rows are half empty (R/2 <= 16 rows after the parity split), and the 16x16
+// tile does less work per patch and runs twice as many waves.
+int encoder_tile(const rsc_handle* h, int K) {
+  const bool want32 = h->tile == RSC_TILE_32 || (h->tile == RSC_TILE_AUTO && h->dev.R > 32);
+  return want32 && rsc::tile32_usable(h->dev, K) ? RSC_TILE_32 : RSC_TILE_16;
+}
+
 rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_flops_per_patch) {
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
@@ -906,7 +915,7 @@ rsc_status rsc_encode_info(const rsc_handle* h, int K, int* tile, double* mfma_f
     if (mfma_flops_per_patch) *mfma_flops_per_patch = rsc::encode_lp_mfma_flops_per_patch(h->dev, K);
     return ok();
   }
-  const int t = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
+  const int t = encoder_tile(h, K);
   if (tile) *tile = t;
   if (mfma_flops_per_patch) *mfma_flops_per_patch = rsc::encode_mfma_flops_per_patch(h->dev, t, K);
   return ok();
@@ -945,7 +954,7 @@ rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int
     return dict_launch(h, stream, "encode launch", [&] {
       return rsc::launch_encode_lp(h->dev, h->prec, xhat, P, K, atom, angle, coef, resid2, stream);
     });
-  const int tile = (h->tile != RSC_TILE_16 && rsc::tile32_usable(h->dev, K)) ? RSC_TILE_32 : RSC_TILE_16;
+  const int tile = encoder_tile(h, K);
   return dict_launch(h, stream, "encode launch", [&] {
     return rsc::launch_encode(h->dev, tile, xhat, P, K, atom, angle, coef, resid2, stream);
   });

@@ -229,6 +229,7 @@ template <class C, int HT, bool SPLIT>
 int k16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
   if (prm.K <= 2) return launch16<C, HT, 2, SPLIT>(t, prm, st);
   if (prm.K <= 4) return launch16<C, HT, 4, SPLIT>(t, prm, st);
+  if (prm.K <= 6) return launch16<C, HT, 6, SPLIT>(t, prm, st);   // fewer registers than 8 slots
   return launch16<C, HT, 8, SPLIT>(t, prm, st);
 }
 

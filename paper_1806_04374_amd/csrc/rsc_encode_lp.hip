@@ -33,7 +33,15 @@
 //     its half of the coordinates, a half-wave swap completes the sums) and the
 //     angle DFT on v_mfma_f32_32x32x2f32; the best candidate by exact maximum, then
 //     its angles again with the same instructions for the argmax.  Candidates are
-//     visited in increasing atom order, so ties go to the smallest atom, then angle.
+//     visited in increasing atom order; equal maxima go to the smaller atom, then angle.
+//   BF16 candidate filter: the window holds several atoms per step (and a wave loops
+//     over its patches' largest candidate count), so the atom with the largest 16-bit
+//     maximum is re-scored first, and of the others only those whose 16-bit maximum
+//     reaches its FP32 maximum minus the error bound (4.02u ||r||, taken as 4.25u) are
+//     kept: the atom with the largest FP32 maximum E has a 16-bit maximum of at least
+//     E - 4.02u ||r||, and E is at least the first one's.  The 16-bit maxima are kept for
+//     this in LDS as FP16 fractions of ||r|| (each lane its own), read with a margin
+//     of 2^-10 for their rounding.
 //   least squares: the Cholesky-based update of the FP32 encoders.  It also tracks
 //     k ||L^{-1}||_F^2, an upper bound on cond_2 of the Gram matrix of the k
 //     selected unit columns; once that bound exceeds 1e6 (or the new pivot is tiny)
@@ -69,6 +77,14 @@ struct LpParams {
   unsigned long long* stats;   // [4], see rsc_precision_stats
 };
 
+// Offset, in 16-byte units from the start of the kernel's LDS, of the per-wave copies of
+// the atoms' 16-bit maxima: after the stage-1 operand (NG NQ 64 x 16 B) and the FP32
+// tables (dictionary, cos/sin, re-score operand), rounded up to 16 bytes.
+__host__ __device__ constexpr size_t lp_vmax_offset16(int NG, int NQ, int B, int R, int FT) {
+  return size_t(NG) * NQ * 64 + (sizeof(float) * (size_t(NG) * 16 * B + 2 * size_t(NQ) * R +
+                                                  size_t(FT) * NQ * 64) + 15) / 16;
+}
+
 // RT: 32-angle tiles of the 16-bit stage 2 (ceil(R/32)).  SPLIT: the FP32 re-score
 // uses the radix-2 angle split (even R, R/2 <= 32 rows: E from even harmonics, O
 // from odd ones, score(r) = E + O and score(r + R/2) = E - O); otherwise RT tiles
@@ -87,6 +103,9 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
   float* sCs = sHat + NG * 16 * B;                              // [2][NQ][R]
   float* sF = sCs + 2 * NQ * R;                                 // [SPLIT ? 1 : RT][NQ][64]
   constexpr int FT = SPLIT ? 1 : RT;
+  // [4 waves][NG][64 lanes] x 8 FP16: each lane's 16-bit atom maxima of the current step,
+  // divided by ||r|| (read back by the same lane only)
+  uint4* sV = lds4 + lp_vmax_offset16(NG, NQ, B, R, FT);
   {
     const int nA = NG * NQ * 64, nH = NG * 16 * B, nC = 2 * NQ * R, nF = FT * NQ * 64;
     for (int i = threadIdx.x; i < nA; i += blockDim.x) lds4[i] = prm.dictA[i];
@@ -106,6 +125,13 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
   }
   const LsTables tb{prm.gramH, prm.gramH64, prm.cs64, prm.xhat, prm.M, prm.R, kCondMax16};
   const float wfac = 8.5f * P::unit;
+  // a candidate is re-scored only if its 16-bit maximum reaches the best FP32 maximum found
+  // so far minus the bound on a 16-bit score's error (4.02u ||r||, taken as 4.25u), less the
+  // error of its FP16 copy (below 2^-10 in units of ||r||)
+  const float efac = 4.25f * P::unit + 0x1p-10f;
+  // BF16 only: its window holds several candidates per step; FP16's holds about one, and
+  // the bookkeeping would cost more than it saves
+  constexpr bool kFilter = PREC == RSC_BF16;
   unsigned long long n_sel = 0, n_cand = 0, n_fp64 = 0, max_cand = 0;
 
   const int64_t nwt = (prm.P + 31) / 32;
@@ -146,9 +172,11 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
         r16[k] = pack8<P>(v);
       }
       const float wnd = wfac * rn * sc;
+      const float invn = rn > 0.f ? 1.f / (rn * sc) : 0.f;
 
       // ---------------- 16-bit scores: per-atom maxima and the candidate mask
       float vh = -1.f;          // running maximum over this half-wave's atoms
+      int va = 0;               // its atom (the first one on equal maxima)
       uint64_t mask = 0;        // bit i: atom 2i + u is a candidate
       for (int g = 0; g < NG; ++g) {
         asm volatile("" ::: "memory");
@@ -221,22 +249,50 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
 #pragma unroll
         for (int i = 0; i < 8; ++i) gb |= (vs[i] >= thr && vs[i] >= 0.f) ? (1u << i) : 0u;
         mask |= uint64_t(gb) << (8 * g);
+        if constexpr (kFilter) {
+          int gi = 7;
+#pragma unroll
+          for (int i = 7; i >= 0; --i) gi = vs[i] == gm ? i : gi;
+          va = gm > vh ? ab + 2 * gi + u : va;
+        }
         vh = nvh;
+        if constexpr (kFilter) {
+          _Float16 hv[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) hv[i] = _Float16(vs[i] * invn);
+          uint4 w;
+          __builtin_memcpy(&w, hv, sizeof(w));
+          sV[(wave * NG + g) * 64 + lane] = w;
+        }
       }
-      const float vmax = fmaxf(vh, __shfl_xor(vh, 32));
+      const float vo = __shfl_xor(vh, 32);
+      const int vao = __shfl_xor(va, 32);
+      const float vmax = fmaxf(vh, vo);
       if (!(vh >= vmax - wnd) || !st.active) mask = 0;
+      // the patch's atom with the largest 16-bit maximum (the low half-wave's on equal maxima)
+      // is re-scored first; its FP32 maximum then bounds which other candidates can win
+      const int m1 = (u == 0 ? vh >= vo : vo < vh) ? va : vao;
+      const bool has1 = st.active && vmax >= 0.f;
+      if (kFilter && has1 && (m1 & 1) == u) mask &= ~(uint64_t(1) << (m1 >> 1));
 
       // ---------------- FP32 re-score of the candidates, in increasing atom order
       float best = -1.f;
       int bm = 0, nc = 0;
       float bop[NQ];
       zero(bop);
-      while (true) {
-        const int mine = mask ? 2 * int(__builtin_ctzll(mask)) + u : 0x7fffffff;
-        const int m = min(mine, __shfl_xor(mine, 32));
-        const bool has = m != 0x7fffffff;
+      for (int pass = 0;; ++pass) {
+        int m;
+        bool has;
+        if (kFilter && pass == 0) {
+          has = has1;
+          m = m1;
+        } else {
+          const int mine = mask ? 2 * int(__builtin_ctzll(mask)) + u : 0x7fffffff;
+          m = min(mine, __shfl_xor(mine, 32));
+          has = m != 0x7fffffff;
+          if (has && mine == m) mask &= mask - 1;
+        }
         if (!__any(has)) break;
-        if (has && mine == m) mask &= mask - 1;
         nc += has ? 1 : 0;
         const int mc = has ? m : 0;
         const float* d = sHat + mc * B;
@@ -316,11 +372,30 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
           }
         }
         cm = max_halves(cm);
-        const bool gt = has && cm > best;
+        // candidates after the first come in increasing atom order: equal maxima go to the
+        // smaller atom
+        const bool gt = has && (cm > best || (cm == best && mc < bm));
         best = gt ? cm : best;
         bm = gt ? mc : bm;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) bop[q] = gt ? op32[q] : bop[q];
+        if (kFilter && pass == 0) {
+          // keep the candidates whose 16-bit maximum reaches best - the error bound: the atom
+          // with the largest FP32 maximum E has a 16-bit maximum of at least E - 4.02u ||r||,
+          // and E >= best
+          const float thrn = has ? best / rn - efac : -2.f;
+          uint64_t mm = mask, keep = 0;
+          const uint4* vrow = sV + wave * NG * 64 + lane;
+          while (mm) {
+            const int i = int(__builtin_ctzll(mm));
+            mm &= mm - 1;
+            const uint4 w = vrow[(i >> 3) * 64];
+            _Float16 hv[8];
+            __builtin_memcpy(hv, &w, sizeof(w));
+            if (float(hv[i & 7]) >= thrn) keep |= uint64_t(1) << i;
+          }
+          mask = keep;
+        }
       }
       // ---------------- angles of the best atom (same instructions as its maximum)
       int rs;
@@ -446,8 +521,8 @@ bool encode_lp_supported(int S, int T, int M, int R) {
 
 size_t encode_lp_lds_bytes(const DeviceTables& t) {
   const int NG = (t.M + 15) / 16, NQ = t.T + 1, FT = (t.R <= 32 || t.lpSplit) ? 1 : 2;
-  return size_t(NG) * NQ * 64 * 16 + sizeof(float) * (size_t(NG) * 16 * t.B + 2 * size_t(NQ) * t.R +
-                                                       size_t(FT) * NQ * 64);
+  // tables, then (BF16) 4 waves x NG x 64 lanes x 16 B of FP16 atom maxima
+  return 16 * (lp_vmax_offset16(NG, NQ, t.B, t.R, FT) + (t.prec == RSC_BF16 ? size_t(4) * NG * 64 : 0));
 }
 
 double encode_lp_mfma_flops_per_patch(const DeviceTables& t, int K) {
