@@ -170,7 +170,7 @@ rsc_status rsc_get_basis(const rsc_handle* h, double* phi, double* pinv);
  * Load the dictionary D_hat (Sec. II-C; hat coordinates, Sec. II-E step 3) and the
  * angle grid size R.
  *   d_hat   HOST array [M, B] float32, packed hat coordinates, each row of unit
- *           Euclidean norm (|1 - ||d_m||| <= 1e-4, else RSC_E_INVALID); copied before
+ *           Euclidean norm (|1 - ||d_m||| <= 1e-5, else RSC_E_INVALID); copied before
  *           the call returns
  *   M       1 <= M <= 256 (BF16 / FP16 handles: M <= 128)
  *   R       1 <= R <= 128 (BF16 / FP16 handles: R <= 64)
@@ -264,6 +264,8 @@ rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size
  *   xhat         device [P, B] float32 (output of rsc_project)
  *   P            >= 0
  *   K            1 <= K <= 8 and K <= B
+ *   workspace    device scratch of ws_bytes >= rsc_encode_workspace_size(h, P, K) bytes
+ *                (that size is 0, so NULL with ws_bytes = 0 is the usual call)
  *   atom, angle  device [P, K] int32, slots in selection order; empty slots -1
  *   coef         device [P, K] float32; empty slots 0
  *   resid2       device [P] float32 squared hat-domain residual norm, or NULL
@@ -288,6 +290,7 @@ rsc_status rsc_encode_workspace_size(const rsc_handle* h, int64_t P, int K, size
  * pursuit.  rsc_precision_stats counts the FP64 steps.
  */
 rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K,
+                          void* workspace, size_t ws_bytes,
                           int32_t* atom, int32_t* angle, float* coef, float* resid2,
                           void* stream);
 

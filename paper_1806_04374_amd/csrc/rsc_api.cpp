@@ -547,7 +547,7 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
       if (!std::isfinite(v)) return fail(RSC_E_INVALID, "non-finite dictionary entry");
       n2 += v * v;
     }
-    if (std::fabs(1.0 - std::sqrt(n2)) > 1e-4)
+    if (std::fabs(1.0 - std::sqrt(n2)) > 1e-5)
       return fail(RSC_E_INVALID, "dictionary row " + std::to_string(m) + " is not unit norm");
   }
   const int NG = (M + 15) / 16;
@@ -939,8 +939,11 @@ rsc_status rsc_project(const rsc_handle* h, const float* patches, int64_t P, flo
   return e ? handle_fail(h, e, "projection launch") : ok();
 }
 
-rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K, int32_t* atom,
-                          int32_t* angle, float* coef, float* resid2, void* stream) {
+rsc_status rsc_omp_encode(const rsc_handle* h, const float* xhat, int64_t P, int K, void* workspace,
+                          size_t ws_bytes, int32_t* atom, int32_t* angle, float* coef, float* resid2,
+                          void* stream) {
+  (void)workspace;   // the pursuit keeps every per-patch value in registers: no workspace is read
+  (void)ws_bytes;    // (rsc_encode_workspace_size is 0, so every ws_bytes is enough)
   if (!h) return fail(RSC_E_INVALID, "handle is NULL");
   if (!h->has_dict) return fail(RSC_E_NOT_READY, "no dictionary loaded");
   if (K < 1 || K > 8 || K > h->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
@@ -1121,7 +1124,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
     return he == hipSuccess ? RSC_OK : handle_fail(h, int(he), "history copy");
   };
   for (int it = 0; it <= n_iter; ++it) {
-    s = rsc_omp_encode(h, xhat, P, K, atom, angle, coef, resid2, stream);
+    s = rsc_omp_encode(h, xhat, P, K, nullptr, 0, atom, angle, coef, resid2, stream);
     if (s == RSC_OK) s = coding_error(it);
     if (s != RSC_OK || it == n_iter) break;
     s = rsc_rksvd_update(h, xhat, P, K, atom, angle, coef, resid2, workspace, ws_bytes, dn, us, nullptr, stream);
@@ -1179,7 +1182,7 @@ rsc_status rsc_classify(const rsc_handle* const* classes, int C, const float* xh
   float* coef = reinterpret_cast<float*>(w + L.coef);
   float* r2 = reinterpret_cast<float*>(w + L.resid);
   for (int c = 0; c < C; ++c) {
-    rsc_status s = rsc_omp_encode(classes[c], xhat, P, K, atom, angle, coef, r2, stream);
+    rsc_status s = rsc_omp_encode(classes[c], xhat, P, K, nullptr, 0, atom, angle, coef, r2, stream);
     if (s != RSC_OK) return s;
     int e = rsc::launch_classify_min(r2, P, c, label, sse, stream);
     if (e) return handle_fail(classes[c], e, "classify launch");

@@ -57,7 +57,7 @@ def lib():
         "rsc_encode_info": [P, I, P, P],
         "rsc_autotune_encode": [P, P, I64, I, P, P, P, I, P, P, P],
         "rsc_project": [P, P, I64, P, P],
-        "rsc_omp_encode": [P, P, I64, I, P, P, P, P, P],
+        "rsc_omp_encode": [P, P, I64, I, P, ctypes.c_size_t, P, P, P, P, P],
         "rsc_reconstruct": [P, P, P, P, I64, I, P, P],
         "rsc_synthesize": [P, P, P, P, I64, I, P, P, P],
         "rsc_sync": [P, P],
@@ -275,8 +275,9 @@ def rsc_project(h: Handle, patches, xhat=None, stream=None):
     return xhat
 
 
-def rsc_omp_encode(h: Handle, xhat, K: int, out=None, stream=None):
-    """Returns (atom [P,K] int32, angle [P,K] int32, coef [P,K] f32, resid2 [P] f32)."""
+def rsc_omp_encode(h: Handle, xhat, K: int, out=None, stream=None, workspace=None):
+    """Returns (atom [P,K] int32, angle [P,K] int32, coef [P,K] f32, resid2 [P] f32).
+    workspace: optional device uint8 tensor (rsc_encode_workspace_size bytes, which is 0)."""
     import torch
     P = xhat.shape[0]
     _dev(xhat, torch.float32, "xhat", (P, h.B))
@@ -292,8 +293,9 @@ def rsc_omp_encode(h: Handle, xhat, K: int, out=None, stream=None):
     _dev(coef, torch.float32, "coef", (P, K))
     if resid2 is not None:
         _dev(resid2, torch.float32, "resid2", (P,))
-    _check(lib().rsc_omp_encode(h.ptr, _ptr(xhat), P, K, _ptr(atom), _ptr(angle), _ptr(coef),
-                                _ptr(resid2), _stream(stream)))
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().rsc_omp_encode(h.ptr, _ptr(xhat), P, K, _ptr(workspace), ws_bytes, _ptr(atom), _ptr(angle),
+                                _ptr(coef), _ptr(resid2), _stream(stream)))
     return atom, angle, coef, resid2
 
 

@@ -104,7 +104,7 @@ def test_argument_errors_without_device(L):
     assert L.rsc_precision_stats(None, None, 0) == rsc.RSC_E_INVALID
     assert L.rsc_set_dictionary(None, None, 4, 8, None) == rsc.RSC_E_INVALID
     assert L.rsc_project(None, None, 10, None, None) == rsc.RSC_E_INVALID
-    assert L.rsc_omp_encode(None, None, 10, 2, None, None, None, None, None) == rsc.RSC_E_INVALID
+    assert L.rsc_omp_encode(None, None, 10, 2, None, 0, None, None, None, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_reconstruct(None, None, None, None, 10, 2, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_synthesize(None, None, None, None, 10, 2, None, None, None) == rsc.RSC_E_INVALID
     assert L.rsc_destroy(None) == rsc.RSC_OK
