@@ -53,6 +53,54 @@ __device__ __forceinline__ void write_codes(const EncodeParams& prm, int64_t p, 
   if (prm.resid2) prm.resid2[p] = rn2;
 }
 
+// Complex harmonic products C_k = sum_s conj(d_{m,s,k}) x_{s,k} of atom m for this lane's
+// patch in the quarter-wave layout (W = 4), complete in all four lanes of the patch:
+// cre[k], cim[k].  Lane u holds profiles 4j + u of harmonic 0 and, for k >= 1, profile
+// 2jj + (u >> 1) of part u & 1 (0: Re, 1: Im); each lane multiplies its coordinates with the
+// matching parts of the atom and two exchanges complete the sums.  Padding coordinates of
+// the residual are 0, so what the atom row holds there does not matter.
+template <class L>
+__device__ __forceinline__ void atom_products4(const float* __restrict__ hat, int m, int u,
+                                               const float (&res)[L::NKS], float (&cre)[L::NQ],
+                                               float (&cim)[L::NQ]) {
+  static_assert(L::W == 4, "four quarter-waves per patch");
+  const float* d = hat + m * L::B;
+  float p0 = 0.f;
+#pragma unroll
+  for (int j = 0; j < L::J0; ++j) {
+    const int s = 4 * j + u;
+    p0 = fmaf(d[s < L::S ? s : 0], res[j], p0);
+  }
+  cre[0] = p0;
+  cim[0] = 0.f;
+  const int part = u & 1, so = u >> 1;
+  static_for<L::T>([&](auto K1) {
+    constexpr int k = decltype(K1)::value + 1;
+    constexpr int bk = L::base(k), nk = L::Sk(k), j0 = L::joff(k), nj = L::J1k(k);
+    // part 0 (x = Re): Re += dRe x, Im -= dIm x; part 1 (x = Im): Re += dIm x, Im += dRe x
+    const float* dA = d + bk + (part ? nk : 0);
+    const float* dB = d + bk + (part ? 0 : nk);
+    const float sb = part ? 1.f : -1.f;
+    float pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < nj; ++jj) {
+      const int s = 2 * jj + so;
+      const int o = s < nk ? s : 0;
+      pr = fmaf(dA[o], res[j0 + jj], pr);
+      pi = fmaf(dB[o], res[j0 + jj], pi);
+    }
+    cre[k] = pr;
+    cim[k] = sb * pi;
+  });
+#pragma unroll
+  for (int k = 0; k < L::NQ; ++k) {
+    cre[k] = cre[k] + __shfl_xor(cre[k], 16);
+    cre[k] = cre[k] + __shfl_xor(cre[k], 32);
+    cim[k] = cim[k] + __shfl_xor(cim[k], 16);
+    cim[k] = cim[k] + __shfl_xor(cim[k], 32);
+  }
+}
+
 // ============================================================== 16x16 tiles
 // SPLIT (even R): each stage-2 step contracts a pair of harmonics of one parity,
 // (4j, 4j+2) for E and (4j+1, 4j+3) for O; HT tiles of 16 angle rows cover r < R/2.
@@ -124,10 +172,13 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
       st.active = st.active && (norm2<L>(res) > kTau2 * nx2);
       if (!__any(st.active)) break;
 
-      float best = -1.f;
-      int bm = 0;
-      float bop[NS];
-      zero(bop);
+      // pass 1: every atom's maximum over its angles.  Four atoms at a time are reduced over
+      // the quarter-waves with two exchanges per pair, leaving one atom per quarter; each
+      // quarter keeps its own best atom (first on equal maxima, atoms in increasing order),
+      // and the quarters are compared once per step.
+      float bq = -1.f;
+      int aq = 0;
+      const int qperm = ((u & 1) << 1) | (u >> 1);   // atom of this quarter within a batch of 4
       for (int g = 0; g < NG; ++g) {
         const float* hg = arow_hat + g * 8 * B;
         f32x4 acc[NQ];
@@ -172,7 +223,8 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
           return a < 4 ? acc[k1][a] : (k2 <= T ? acc[k2][a - 4] : pad[q][a - 4]);
         };
         // per atom: HT tiles x (E, O) chains; the chains of the next atom are issued
-        // before the reduction of the current one
+        // before the reduction of the current one.  Atoms past M have all-zero operands:
+        // their maxima are exactly 0 and lose every tie to a smaller atom.
         f32x4 ob[2][2][HT];
         auto chains = [&](int a, f32x4 (&o)[2][HT]) {
 #pragma unroll
@@ -185,9 +237,8 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
               o[c][t] = mfma16(F[t][q], opnd(q, a), o[c][t]);
             }
         };
+        float amq[8];   // this lane's part of each atom's maximum (its four angle rows per tile)
         chains(0, ob[0]);
-        int ba = 0;
-        bool upd = false;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           if (a + 1 < 8) chains(a + 1, ob[(a + 1) & 1]);
@@ -198,19 +249,50 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
               am = fmaxf(am, SPLIT ? fabsf(o[0][t][i]) + fabsf(o[1][t][i]) : fabsf(o[0][t][i]));
-          am = max_quarters_nonneg(am);
-          const bool gt = am > best;
-          best = gt ? am : best;
-          ba = gt ? a : ba;
-          upd = upd || gt;
-#pragma unroll
-          for (int q = 0; q < NS; ++q) bop[q] = gt ? opnd(q, a) : bop[q];
+          amq[a] = am;
         }
-        bm = upd ? g * 8 + ba : bm;
+        // atoms (4b, 4b+1) and (4b+2, 4b+3): one exchange of the half-waves per pair, then
+        // one of the odd and even rows, leaves atom 4b + qperm's maximum in quarter u
+        // (non-negative floats compared as integers)
+        auto umax = [](float x, float y) { return __uint_as_float(max(__float_as_uint(x), __float_as_uint(y))); };
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          float x0 = amq[4 * b], y0 = amq[4 * b + 1], x1 = amq[4 * b + 2], y1 = amq[4 * b + 3];
+          swap32(x0, y0);
+          swap32(x1, y1);
+          float v = umax(x0, y0), w = umax(x1, y1);
+          swap16(v, w);
+          const float mx = umax(v, w);
+          const bool gt = mx > bq;
+          bq = gt ? mx : bq;
+          aq = gt ? g * 8 + 4 * b + qperm : aq;
+        }
       }
+      // the best atom over the quarters: the larger maximum, the smaller atom on equal ones
+      int bm;
+#pragma unroll
+      for (int sh = 16; sh <= 32; sh *= 2) {
+        const float ob2 = __shfl_xor(bq, sh);
+        const int oa = __shfl_xor(aq, sh);
+        const bool take = (ob2 > bq) || (ob2 == bq && oa < aq);
+        bq = take ? ob2 : bq;
+        aq = take ? oa : aq;
+      }
+      bm = aq;
+      // pass 2: the winner's stage-2 operand formed again from its dictionary row, then its
+      // angles
       int rs;
       float cval;
       {
+        float cre[NQ], cim[NQ];
+        atom_products4<L>(sHat, bm, u, res, cre, cim);
+        float bop[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          const int k1 = k1_of(q), k2 = k2_of(q);
+          const float re2 = k2 <= T ? cre[k2 <= T ? k2 : 0] : 0.f, im2 = k2 <= T ? cim[k2 <= T ? k2 : 0] : 0.f;
+          bop[q] = u == 0 ? cre[k1] : u == 1 ? cim[k1] : u == 2 ? re2 : im2;
+        }
         f32x4 o[2][HT];
 #pragma unroll
         for (int t = 0; t < HT; ++t) o[0][t] = o[1][t] = f32x4{0.f, 0.f, 0.f, 0.f};
