@@ -463,7 +463,6 @@ __global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ 
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
   const float* A = pinvA + lane;
-#pragma unroll 4
   for (int j = 0; j < KP; ++j) {
     const int px = 2 * j + u;
     const float b = px < NN ? mine[px] : 0.f;

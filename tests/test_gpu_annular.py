@@ -156,7 +156,8 @@ def _annular_check(dev, N, M, K, R, P, seed, sigma=0.02, J=3):
     return rep
 
 
-@pytest.mark.parametrize("N,M,K,R", [(11, 16, 2, 32), (11, 64, 4, 64), (15, 32, 4, 64), (15, 20, 3, 30)])
+@pytest.mark.parametrize("N,M,K,R", [(11, 16, 2, 32), (11, 64, 4, 64), (15, 32, 4, 64), (15, 20, 3, 30),
+                                     (11, 9, 2, 2), (15, 5, 1, 4), (11, 33, 3, 34)])
 def test_annular_pursuit_matches_reference(dev, N, M, K, R):
     """The paper's annular basis (B = 81 at N = 11, 153 at N = 15): mixtures of rotated atoms
     at continuous angles plus noise; 3,001 patches (a ragged last tile); atom counts on and
