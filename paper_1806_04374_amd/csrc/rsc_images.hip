@@ -16,6 +16,7 @@
 
 #include "rsc_device.h"
 #include "rsc_internal.h"
+#include "rsc_launch.h"
 
 namespace rsc {
 namespace {
@@ -266,13 +267,7 @@ int launch_project_images(const DeviceTables& t, const float* pixels, const int6
                      reinterpret_cast<int64_t*>(ws));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return int(e);
-  static int cus = -1;
-  if (cus < 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
+  const int cus = num_cus();
   // two 32-window tiles per block step, grid of one resident round
   auto go_reg = [&](auto kern, int nt) -> int {
     int per_cu = 0;

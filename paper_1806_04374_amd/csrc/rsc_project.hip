@@ -30,6 +30,7 @@
 
 #include "rsc_device.h"
 #include "rsc_internal.h"
+#include "rsc_launch.h"
 #include "rsc_lp.h"
 
 namespace rsc {
@@ -483,17 +484,7 @@ __global__ __launch_bounds__(128) void project_kernel(const float* __restrict__ 
   for (int i = threadIdx.x; i < np * B; i += blockDim.x) dst[i] = out[i];
 }
 
-int cus() {
-  static int cached = -1;
-  if (cached < 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      n = 256;
-    cached = n;
-  }
-  return cached;
-}
+int cus() { return num_cus(); }
 
 }  // namespace
 

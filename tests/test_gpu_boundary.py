@@ -130,3 +130,39 @@ def test_refused_upload_keeps_the_dictionary():
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(out[:3], ref[:3]))
     h.close()
+
+
+def test_handles_used_from_two_threads_at_once():
+    """The library is safe across handles: two threads, each with its own handle, dictionary
+    and stream, project and encode at the same time (the binding releases the interpreter lock
+    during the calls); every result equals the codes its handle gives when used alone."""
+    import threading
+    K, R = 4, 64
+    cases = [(_dict(64, 31), _xhat(20000, 32)), (_dict(48, 33), _xhat(15000, 34))]
+    want = [_alone(D, R, xh, K) for D, xh in cases]
+    errors = []
+
+    def work(i):
+        try:
+            D, xh = cases[i]
+            st = torch.cuda.Stream()
+            h = rsc.rsc_create(11, 5, 5)
+            rsc.rsc_set_dictionary(h, D, R, stream=st)
+            for _ in range(5):
+                with torch.cuda.stream(st):
+                    out = rsc.rsc_omp_encode(h, xh, K, stream=st)
+                st.synchronize()
+                if not _same(out, want[i]):
+                    errors.append(f"thread {i}: codes differ")
+            rsc.rsc_sync(h, st)
+            h.close()
+        except Exception as e:       # noqa: BLE001 -- collected and asserted below
+            errors.append(f"thread {i}: {e!r}")
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
