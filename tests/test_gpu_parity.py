@@ -415,3 +415,36 @@ def test_workload_never_needs_fp64(dev):
     _encode(h, X, w["K"], dev)
     assert rsc.rsc_precision_stats(h)["fp64_solves"] == 0
     h.close()
+
+
+def test_pursuit_that_runs_out_of_span_stops_cleanly(dev):
+    """Atom 2 is (atom 0 + 2 atom 1) normalised and x = d0 + d1 + 1e-3 e with e orthogonal to
+    the three atoms (R = 1).  The pursuit takes atom 2, then atom 0; their span holds d0 + d1,
+    so the residual is 1e-3 e and every correlation of the third step is rounding noise: the
+    best column is either already selected (the duplicate stop) or atom 1, which lies inside
+    the span (its FP64 pivot is rounding-sized: the pivot stop).  Either way the patch ends
+    with two atoms, the exact coefficients (sqrt(5)/2, 1/2) and the residual 1e-3 e, where a
+    refit with atom 1 would give meaningless coefficients."""
+    from paper_1806_04374_amd import rsc
+    g = wl.GEOM11
+    rng = np.random.default_rng(11)
+    d0 = rng.standard_normal(g.B)
+    d0 /= np.linalg.norm(d0)
+    d1 = rng.standard_normal(g.B)
+    d1 -= (d1 @ d0) * d0
+    d1 /= np.linalg.norm(d1)
+    d2 = (d0 + 2 * d1) / np.sqrt(5.0)
+    D = np.stack([d0, d1, d2]).astype(np.float32)
+    Q, _ = np.linalg.qr(D.astype(np.float64).T)
+    P = 64
+    E = rng.standard_normal((P, g.B))
+    E -= (E @ Q) @ Q.T
+    E /= np.linalg.norm(E, axis=1, keepdims=True)
+    xh = (d0 + d1)[None, :] + 1e-3 * E
+    h = _handle(g, D, 1, "16")
+    atom, angle, coef, r2 = (t.cpu().numpy() for t in rsc.rsc_omp_encode(h, torch.from_numpy(xh.astype(np.float32)).to(dev), 3))
+    h.close()
+    assert np.all(atom[:, 0] == 2) and np.all(atom[:, 1] == 0) and np.all(angle[:, :2] == 0)
+    assert np.all(atom[:, 2] == -1) and np.all(angle[:, 2] == -1) and np.all(coef[:, 2] == 0)
+    assert np.abs(coef[:, 0] - np.sqrt(5.0) / 2).max() < 1e-4 and np.abs(coef[:, 1] - 0.5).max() < 1e-4
+    assert np.abs(np.sqrt(r2) - 1e-3).max() < 2e-5
