@@ -79,13 +79,18 @@ def encoder_roofline(h, prec: str, M: int, R: int, S: int, T: int, K: int, P: in
     direct = encode_flops_per_patch(M, R, S, T, K, split=False) * P
     tile_used, mfma_pp = rsc.rsc_encode_info(h, K)
     peak = FP32_MFMA_PEAK if prec == "fp32" else HALF_MFMA_PEAK
-    return {"kernel": "encode_kernel" if prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
-            "achieved": own / enc_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": own / enc_s / peak,
-            "traffic": traffic_bytes, "algorithmic_flops_per_launch": own, "dft_split": split,
-            "launch_ms": enc_s * 1e3,
-            "frac_direct_dft_equivalent": direct / enc_s / peak,
-            "executed_mfma_tflops": mfma_pp * P / enc_s / 1e12, "executed_mfma_frac": mfma_pp * P / enc_s / peak,
-            "tile": tile_used}
+    out = {"kernel": "encode_kernel" if prec == "fp32" else "encode_lp_kernel", "bound": "mfma",
+           "achieved": own / enc_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": own / enc_s / peak,
+           "traffic": traffic_bytes, "algorithmic_flops_per_launch": own, "dft_split": split,
+           "launch_ms": enc_s * 1e3,
+           "frac_direct_dft_equivalent": direct / enc_s / peak,
+           "executed_mfma_tflops": mfma_pp * P / enc_s / 1e12, "executed_mfma_frac": mfma_pp * P / enc_s / peak,
+           "tile": tile_used}
+    if prec != "fp32":
+        # the 16-bit matrix work is a small part of the launch: the per-atom maxima over the
+        # angles (vector instructions) and the FP32 re-score of candidates bound it
+        out["limited_by"] = "vector issue (per-atom angle maxima) and the FP32 re-score, not the 16-bit matrix peak"
+    return out
 
 
 def make_inputs(h, w, P, dev):
