@@ -1035,7 +1035,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=["scale", "small", "ragged", "serving", "precision", "rksvd", "texture", "rotate",
                                            "annular"],
                     default="scale")
