@@ -538,6 +538,27 @@ def _sign_like(u: np.ndarray, ref: np.ndarray) -> np.ndarray:
     return u
 
 
+def rksvd_update_basis(basis, D_hat: np.ndarray, R: int, xhat: np.ndarray, code: Code):
+    """The atom update of rksvd_update in the coordinate layout of either basis (the full
+    (S, T) grid or the annular basis of eq. (5)-(7)): the same steps, with that basis'
+    steering S_r (Sec. II-E: the update runs in the steerable basis' coordinates)."""
+    return _rksvd_update(D_hat, R, xhat, code, lambda v, th: steer_basis(basis, v, th))
+
+
+def rksvd_basis(basis, D_init: np.ndarray, R: int, xhat: np.ndarray, K: int, n_iter: int, tau: float = TAU):
+    """rksvd in the coordinate layout of either basis (see rksvd_update_basis)."""
+    D = np.asarray(D_init, dtype=np.float64).copy()
+    M = D.shape[0]
+    history = []
+    for _ in range(n_iter):
+        code = omp(augmented_dictionary_basis(basis, D, R), xhat, K, M, tau)
+        history.append(float(code.resid2.sum()))
+        D, _, _ = rksvd_update_basis(basis, D, R, xhat, code)
+    code = omp(augmented_dictionary_basis(basis, D, R), xhat, K, M, tau)
+    history.append(float(code.resid2.sum()))
+    return D, code, history
+
+
 def rksvd_update(D_hat: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, code: Code):
     """Atom update of rotational K-SVD (Fig. 2, the loop over m; Sec. II-C).
 
@@ -551,6 +572,11 @@ def rksvd_update(D_hat: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, co
     Returns (D_new [M, B], usage [M], reset [M]) where reset[m] is the patch an
     unused atom was reset to (-1 otherwise).
     """
+    return _rksvd_update(D_hat, R, xhat, code, lambda v, th: steer(v, th, S, T))
+
+
+def _rksvd_update(D_hat: np.ndarray, R: int, xhat: np.ndarray, code: Code, steer_fn):
+    """The steps of rksvd_update with the steering S_theta given as steer_fn(v, theta)."""
     D_hat = np.asarray(D_hat, dtype=np.float64)
     xhat = np.asarray(xhat, dtype=np.float64)
     M, B = D_hat.shape
@@ -569,8 +595,8 @@ def rksvd_update(D_hat: np.ndarray, R: int, S: int, T: int, xhat: np.ndarray, co
             for i in range(K):
                 if i != i0 and code.atom[p, i] >= 0:
                     theta = 2 * np.pi * code.angle[p, i] / R
-                    others += code.coef[p, i] * steer(D_hat[code.atom[p, i]], theta, S, T)
-            cols.append(steer(xhat[p] - others, -2 * np.pi * r0 / R, S, T))
+                    others += code.coef[p, i] * steer_fn(D_hat[code.atom[p, i]], theta)
+            cols.append(steer_fn(xhat[p] - others, -2 * np.pi * r0 / R))
         usage[m] = len(cols)
         if cols:
             Y = np.stack(cols, axis=1)                       # [B, n_m]
