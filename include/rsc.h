@@ -132,7 +132,8 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * rsc_reconstruct) runs on the full basis at N = 11 (B = 81, T_s = 1, 3, 8, 11, 15) and
  * N = 15 (B = 153, T_s = 1, 3, 8, 11, 13, 18, 19) with even R <= 64 and K <= 4, on the
  * 16x16 encoder tile; other annular handles get RSC_E_UNSUPPORTED from
- * rsc_set_dictionary.  Image projection, image stamping and the dictionary update return
+ * rsc_set_dictionary.  The dictionary update (rsc_rksvd_update, rsc_rksvd_train) runs in
+ * the annular layout for B <= 128 (N = 11).  Image projection and image stamping return
  * RSC_E_UNSUPPORTED for every annular handle.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
  * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
@@ -384,7 +385,8 @@ rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, int K, size_
 
 /*
  * Dictionary update of rotational K-SVD (Fig. 2, the loop over atoms; Sec. II-C), in hat
- * coordinates (Sec. II-E), from codes computed with the handle's current dictionary D.
+ * coordinates (Sec. II-E) of the handle's basis (the (S, T) grid or the annular basis),
+ * from codes computed with the handle's current dictionary D.
  * Every atom is updated from the same codes and the same D (the augmented dictionary
  * of Fig. 2 is built once per outer iteration).  For atom m, each patch p whose code
  * uses m contributes the column S_{-r0}(xhat_p - D b_p): r0 is the angle of the first

@@ -1079,8 +1079,7 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
   if (P < 1 || P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (!xhat || !atom || !angle || !coef || !resid2 || !workspace || !d_new || !usage)
     return fail(RSC_E_INVALID, "null device pointer");
-  if (h->dev.B > 128 || h->annular)
-    return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for the (S, T) grid with B <= 128");
+  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
   const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
@@ -1102,8 +1101,7 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   if (P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
     return fail(RSC_E_INVALID, "null device pointer or empty input");
-  if (h->annular)
-    return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for the (S, T) grid with B <= 128");
+  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
   rsc_status s = rsc_set_dictionary(h, d_init, M, R, stream);
   if (s != RSC_OK) return s;
   const RkLayout L = rk_layout(h->dev, P, K);

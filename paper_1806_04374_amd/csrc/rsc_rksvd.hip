@@ -228,9 +228,18 @@ __global__ __launch_bounds__(64) void rk_scatter_kernel(SortParams prm) {
   }
 }
 
+// Harmonic blocks of the packed coordinates: harmonic 0 on [kb[0], kb[1]), harmonic k >= 1
+// on [kb[k], kb[k+1]) as [Re][Im] halves.  The (S, T) grid has kb[k] = S + 2 S (k - 1); the
+// annular basis has as many profiles per harmonic as annuli carry it.
+struct HarmBlocks {
+  int T;
+  int kb[33];
+};
+
 struct AccParams {
   const double* __restrict__ resid;   // [P][BP] residuals
-  int BP, M, R, B, S, T;
+  int BP, M, R, B, T;
+  HarmBlocks hb;
   const float* __restrict__ dict;     // [16 NG][B] old dictionary
   const double* __restrict__ cs64;    // [2][T+1][R]
   const int64_t* __restrict__ bucket; // [M + 1]
@@ -248,10 +257,12 @@ struct Coord {
   int k, part, partner;  // harmonic, 0 = Re / 1 = Im, index of the other part (b for k = 0)
 };
 
-__device__ __forceinline__ Coord coord_of(int b, int S) {
-  if (b < S) return {0, 0, b};
-  const int q = b - S, k = 1 + q / (2 * S), rem = q % (2 * S);
-  return rem < S ? Coord{k, 0, b + S} : Coord{k, 1, b - S};
+__device__ __forceinline__ Coord coord_of(int b, const HarmBlocks& hb) {
+  if (b < hb.kb[1]) return {0, 0, b};
+  int k = 1;
+  while (k < hb.T && b >= hb.kb[k + 1]) ++k;
+  const int nk = (hb.kb[k + 1] - hb.kb[k]) / 2, rem = b - hb.kb[k];
+  return rem < nk ? Coord{k, 0, b + nk} : Coord{k, 1, b - nk};
 }
 
 // Coordinate of S_theta v, theta = sgn 2 pi r / R, from the coordinate's own value, its
@@ -290,7 +301,8 @@ struct ResidParams {
   const float* __restrict__ dict;     // [16 NG][B]
   const double* __restrict__ cs64;    // [2][T+1][R]
   int64_t P;
-  int K, M, R, B, BP, S, T;
+  int K, M, R, B, BP, T;
+  HarmBlocks hb;
   double* __restrict__ resid;         // [P][BP]
 };
 
@@ -315,14 +327,14 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   for (int i = t; i < M * B; i += nt) {
     if constexpr (PAIRED) {
       const int a = i / B, bb = i - a * B;
-      sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.S).partner]};
+      sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.hb).partner]};
     } else {
       sd1[i] = prm.dict[i];
     }
   }
   __syncthreads();
   const int g = __builtin_amdgcn_readfirstlane(t / BP), b = t - g * BP, bc = b < B ? b : 0;
-  const Coord cd = coord_of(bc, prm.S);
+  const Coord cd = coord_of(bc, prm.hb);
   const double sig = cd.part == 0 ? 1.0 : -1.0;
   // Two patches per wave and pass.  Lane j of the wave loads code entry j of each (a
   // vector load, so no wait on the shared LDS/scalar counter), and the entries are
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
     const int r = i / NQ, k = i - r * NQ;
     sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
   }
-  const Coord cd = coord_of(row < B ? row : 0, prm.S);
+  const Coord cd = coord_of(row < B ? row : 0, prm.hb);
   const int rowc = row < B ? row : 0;
   const double dm = row < B ? double(prm.dict[size_t(m) * B + row]) : 0.0;
   const double sig = cd.part == 0 ? -1.0 : 1.0;   // turning back by -r0
@@ -810,7 +822,12 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
   double* partial = reinterpret_cast<double*>(w + L.partial);
   double* resid = reinterpret_cast<double*>(w + L.resid);
   const int BP = resid_stride(t.B);
-  ResidParams qp{xhat, atom, angle, coef, t.dictHat, t.cs64, P, K, t.M, t.R, t.B, BP, t.S, t.T, resid};
+  HarmBlocks hb{};
+  hb.T = t.T;
+  hb.kb[0] = 0;
+  hb.kb[1] = t.sk[0];
+  for (int k = 1; k <= t.T; ++k) hb.kb[k + 1] = hb.kb[k] + 2 * t.sk[k];
+  ResidParams qp{xhat, atom, angle, coef, t.dictHat, t.cs64, P, K, t.M, t.R, t.B, BP, t.T, hb, resid};
   {
     const int G = 256 / BP, nt = G * BP;
     const size_t table = sizeof(double) * 2 * size_t(t.R) * (t.T + 1);
@@ -826,7 +843,7 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
     e = hipGetLastError();
     if (e != hipSuccess) return int(e);
   }
-  AccParams ap{resid,     BP,        t.M,     t.R,   t.B,   t.S,   t.T,  t.dictHat, t.cs64,
+  AccParams ap{resid,     BP,       t.M,     t.R,   t.B,   t.T,  hb,   t.dictHat, t.cs64,
                sp.bucket, sp.chunk, sp.scal, sp.lp, sp.lr, sp.lc, partial};
   EigParams ep{partial, sp.bucket, sp.chunk, t.M, t.B, t.dictHat, d_new, usage};
   const int NQ = t.T + 1;

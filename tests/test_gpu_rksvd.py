@@ -253,3 +253,77 @@ def test_update_argument_errors(dev):
         rsc.rsc_rksvd_update(h, z, ia, ia, torch.zeros((10, 9), dtype=torch.float32, device=dev),
                              torch.zeros(10, dtype=torch.float32, device=dev))
     h.close()
+
+
+# ----------------------------------------------------------------- the paper's annular basis
+def test_update_matches_reference_annular_basis(dev):
+    """The update in the annular layout (N = 11, B = 81: harmonic k on the annuli that carry
+    it) against the reference's update with that basis' steering, on the reference's codes."""
+    from paper_1806_04374_amd import rsc
+    ab = orc.build_annular_basis(11)
+    M, R, K = 16, 32, 3
+    D = wl.draw_dictionary(M, ab.B, seed=41).astype(np.float32).astype(np.float64)
+    d = wl.draw_mixtures(3000, 11, M, 3, 0.05, seed=41)
+    X = orc.project(ab, orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
+    X = X.astype(np.float32).astype(np.float64)
+    Dp = D + 0.2 * np.random.default_rng(42).standard_normal(D.shape)
+    Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
+    code = _fp32_code(orc.omp(orc.augmented_dictionary_basis(ab, Dp, R), X, K, M))
+    ref, usage_ref, reset_ref = orc.rksvd_update_basis(ab, Dp, R, X, code)
+    h = rsc.rsc_create_annular(11)
+    rsc.rsc_set_dictionary(h, Dp.astype(np.float32), R)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
+    d_new, usage, reset = rsc.rsc_rksvd_update(h, t(X, np.float32), t(code.atom, np.int32), t(code.angle, np.int32),
+                                               t(code.coef, np.float32), t(code.resid2, np.float32))
+    torch.cuda.synchronize()
+    d_new, usage, reset = d_new.cpu().numpy().astype(np.float64), usage.cpu().numpy(), reset.cpu().numpy()
+    h.close()
+    assert np.array_equal(usage, usage_ref) and np.array_equal(reset, reset_ref)
+    recon = orc.code_to_hat_basis(ab, Dp, R, code)
+    worst = 0.0
+    for m in range(M):
+        C = np.zeros((ab.B, ab.B))
+        for p in range(X.shape[0]):
+            slots = np.flatnonzero(code.atom[p] == m)
+            if slots.size:
+                i0 = slots[0]
+                y = orc.steer_ragged(X[p] - recon[p], -2 * np.pi * code.angle[p, i0] / R, ab.Sk) + code.coef[p, i0] * Dp[m]
+                C += np.outer(y, y)
+        assert abs(np.linalg.norm(d_new[m]) - 1) < 1e-6
+        if usage_ref[m] == 0:
+            continue
+        ev = np.linalg.eigvalsh(C)
+        assert d_new[m] @ C @ d_new[m] >= ev[-1] * (1 - 1e-6)
+        if ev[-1] - ev[-2] > 1e-3 * ev[-1]:
+            worst = max(worst, np.abs(d_new[m] - ref[m]).max())
+    print("worst atom difference", worst)
+    assert worst < 1e-5
+
+
+def test_training_loop_recovers_toy_atoms_annular_basis(dev):
+    """The device loop on the annular basis: three atoms, two grid-rotated copies per patch,
+    noise-free, found from a random start up to a rotation, as the reference loop does."""
+    from paper_1806_04374_amd import rsc
+    ab = orc.build_annular_basis(11)
+    R, P = 32, 400
+    rng = np.random.default_rng(2)
+    D_true = rng.standard_normal((3, ab.B))
+    D_true /= np.linalg.norm(D_true, axis=1, keepdims=True)
+    a = rng.integers(0, 3, (P, 2))
+    r = rng.integers(0, R, (P, 2))
+    w = rng.uniform(0.5, 1.5, (P, 2)) * rng.choice([-1.0, 1.0], (P, 2))
+    X = np.stack([sum(w[p, j] * orc.steer_ragged(D_true[a[p, j]], 2 * np.pi * r[p, j] / R, ab.Sk) for j in range(2))
+                  for p in range(P)]).astype(np.float32)
+    D0 = np.random.default_rng(7).standard_normal((3, ab.B))
+    D0 = (D0 / np.linalg.norm(D0, axis=1, keepdims=True)).astype(np.float32)
+    h = rsc.rsc_create_annular(11)
+    D, codes, hist = rsc.rsc_rksvd_train(h, torch.from_numpy(X).to(dev), D0, R, 2, 20)
+    print("history", hist)
+    for m in range(3):
+        best = max(max(abs(orc.steer_ragged(D[m].astype(np.float64), 2 * np.pi * k / R, ab.Sk) @ D_true[j])
+                       for k in range(R)) for j in range(3))
+        assert best > 0.9999, (m, best)
+    assert hist[-1] < 1e-2 * hist[0]
+    _, _, ref_hist = orc.rksvd_basis(ab, D0.astype(np.float64), R, X.astype(np.float64), 2, 1)
+    assert abs(hist[0] - ref_hist[0]) < 1e-4 * ref_hist[0]
+    h.close()
