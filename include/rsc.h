@@ -133,8 +133,9 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * N = 15 (B = 153, T_s = 1, 3, 8, 11, 13, 18, 19) with even R <= 64 and K <= 4, on the
  * 16x16 encoder tile; other annular handles get RSC_E_UNSUPPORTED from
  * rsc_set_dictionary.  The dictionary update (rsc_rksvd_update, rsc_rksvd_train) runs in
- * the annular layout for B <= 128 (N = 11).  Image projection and image stamping return
- * RSC_E_UNSUPPORTED for every annular handle.
+ * the annular layout for B <= 128 (N = 11).  Image projection serves the full and
+ * low-pass annular bases at N = 11 and 15 (the limits of rsc_project_images); image
+ * stamping returns RSC_E_UNSUPPORTED for every annular handle.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
  * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
  * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 192 or some T_s > 31),
@@ -342,7 +343,9 @@ rsc_status rsc_images_workspace_size(int n_images, size_t* bytes);
  *   xhat        device [P_total, B] float32
  * Everything is enqueued on the stream without allocation or host synchronisation,
  * so a batch (with rsc_omp_encode after it) can be captured in a HIP graph.
- * N must be 11 or 15 (RSC_E_UNSUPPORTED otherwise).
+ * Compiled for 11x11 windows with B <= 96 (the S = T = 5 grid or the annular basis) and
+ * 15x15 windows with 64 < B <= 160 (the S = T = 7 grid or the annular basis);
+ * RSC_E_UNSUPPORTED otherwise.
  */
 rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const int64_t* img_offset,
                               const int32_t* H, const int32_t* W, int n_images, int64_t P_total,

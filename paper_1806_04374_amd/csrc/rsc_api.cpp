@@ -994,6 +994,14 @@ rsc_status rsc_synthesize(const rsc_handle* h, const int32_t* atom, const float*
   });
 }
 
+// Image projection instances: 11x11 windows (97 disk pixels) with B <= 96 (the 11x11 grid
+// of profiles and the annular basis) and 15x15 windows (177 disk pixels) with 64 < B <= 160
+// (the 15x15 grid and the annular basis).
+static bool images_supported(const rsc_handle* h) {
+  const auto& d = h->dev;
+  return (d.N == 11 && d.n_pix == 97 && d.B <= 96) || (d.N == 15 && d.n_pix == 177 && d.B > 64 && d.B <= 160);
+}
+
 rsc_status rsc_images_workspace_size(int n_images, size_t* bytes) {
   if (!bytes) return fail(RSC_E_INVALID, "bytes is NULL");
   if (n_images < 0) return fail(RSC_E_INVALID, "n_images must be >= 0");
@@ -1012,10 +1020,9 @@ rsc_status rsc_project_images(const rsc_handle* h, const float* pixels, const in
     return fail(RSC_E_INVALID, "null device pointer");
   if (ws_bytes < rsc::images_workspace_bytes(n_images)) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 7) != 0) return fail(RSC_E_INVALID, "workspace not 8-byte aligned");
-  if (h->annular || !((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
-      !rsc::encode_supported(h->dev.S, h->dev.T))
-    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
-                                   "geometries");
+  if (!images_supported(h))
+    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for 11x11 windows with B <= 96 and 15x15 "
+                                   "windows with 64 < B <= 160");
   if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_project_images(h->dev, pixels, img_offset, H, W, n_images, P_total, workspace, xhat,
                                      stream);
@@ -1032,10 +1039,9 @@ rsc_status rsc_project_images_noalloc(const rsc_handle* h, const float* pixels, 
   if (P_total < 0) return fail(RSC_E_INVALID, "P_total must be >= 0");
   if (n_images == 0 || P_total == 0) return ok();
   if (!pixels || !img_offset || !H || !W || !xhat) return fail(RSC_E_INVALID, "null device pointer");
-  if (h->annular || !((h->dev.N == 11 && h->dev.n_pix == 97) || (h->dev.N == 15 && h->dev.n_pix == 177)) ||
-      !rsc::encode_supported(h->dev.S, h->dev.T))
-    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for the 11x11 (S = T = 5) and 15x15 (S = T = 7) "
-                                   "geometries");
+  if (!images_supported(h))
+    return fail(RSC_E_UNSUPPORTED, "image projection is compiled for 11x11 windows with B <= 96 and 15x15 "
+                                   "windows with 64 < B <= 160");
   if (rsc_status f = check_fault(h)) return f;
   int e = rsc::launch_project_images_noalloc(h->dev, pixels, img_offset, H, W, n_images, P_total, xhat, stream);
   return e ? handle_fail(h, e, "image projection launch") : ok();

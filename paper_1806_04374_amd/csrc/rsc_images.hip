@@ -280,9 +280,14 @@ int launch_project_images(const DeviceTables& t, const float* pixels, const int6
                        reinterpret_cast<const int64_t*>(ws), P_total, t.B, t.pinvI, t.dpixI, xhat);
     return int(hipGetLastError());
   };
+  // one wave per 32 coordinates: the 11x11 grid (B = 55) and annular (B = 81) bases, the
+  // 15x15 grid (B = 105) and annular (B = 153) bases
   if (t.N == 11 && t.n_pix == 97 && t.B <= 64) return go_reg(project_images_reg_kernel<11, 49, 2, 2>, 2);
+  if (t.N == 11 && t.n_pix == 97 && t.B <= 96) return go_reg(project_images_reg_kernel<11, 49, 3, 2>, 3);
   if (t.N == 15 && t.n_pix == 177 && t.B > 64 && t.B <= 128)
     return go_reg(project_images_reg_kernel<15, 89, 4, 2>, 4);
+  if (t.N == 15 && t.n_pix == 177 && t.B > 128 && t.B <= 160)
+    return go_reg(project_images_reg_kernel<15, 89, 5, 2>, 5);
   return int(hipErrorInvalidValue);
 }
 

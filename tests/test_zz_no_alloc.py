@@ -19,10 +19,10 @@ def _batch(sizes, N, seed):
     return b, pix
 
 
-@pytest.mark.parametrize("geom", [(11, 5, 5), (15, 7, 7)])
+@pytest.mark.parametrize("geom", [(11, 5, 5), (15, 7, 7), (11, "annular"), (15, "annular")])
 def test_noalloc_matches_workspace_projection(geom):
-    N, S, T = geom
-    h = rsc.rsc_create(N, S, T)
+    N = geom[0]
+    h = rsc.rsc_create_annular(N) if geom[1] == "annular" else rsc.rsc_create(*geom)
     rng = np.random.default_rng(N)
     big = [(int(a), int(b)) for a, b in rng.integers(N - 2, 300, (300, 2))] + [(N, N), (5, 400), (400, 5)]
     small = [(int(a), int(b)) for a, b in rng.integers(N, 90, (7, 2))]
