@@ -182,6 +182,11 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
         for (int q = 0; q < NQ; q += 2) e = mfma32(F[q], op[q], e);
 #pragma unroll
         for (int q = 1; q < NQ; q += 2) o = mfma32(F[q], op[q], o);
+        // Rows past R/2 have all-zero operand rows, so their scores are exactly 0.  A lane
+        // reaches them after its valid rows (its rows ascend), and a 0 never beats an earlier
+        // value under the strict '>'; a lane with no valid row ends with 0 at an index of at
+        // least R/2, which loses the cross-lane tie to the other lane (row 0 is always valid).
+        // So no row mask is needed.
         float rb = -1.f, rv = 0.f;
         int rc = 0;
 #pragma unroll
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(256, 2) void encode32_kernel(EncodeParams prm, int 
           for (int i = 0; i < 16; ++i) {
             const int row = 8 * (i / 4) + 4 * u + (i % 4);
             const float sc = h == 0 ? e[i] + o[i] : e[i] - o[i];
-            const float val = row < HALF ? fabsf(sc) : -1.f;
+            const float val = fabsf(sc);
             const bool gt = val > rb;
             rb = gt ? val : rb;
             rv = gt ? sc : rv;

@@ -303,6 +303,11 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
             const int c = q < SE ? 0 : 1;
             o[c][t] = mfma16(F[t][q], bop[q], o[c][t]);
           }
+        // Rows past HALF have all-zero operand rows, so their scores are exactly 0.  A lane
+        // reaches them after its valid rows (its rows ascend), and a 0 never beats an earlier
+        // value under the strict '>'; a quarter with no valid row ends with 0 at an index of
+        // at least HALF, which loses the cross-quarter tie to a valid row (row 0 always is).
+        // So no row mask is needed.
         float rb = -1.f, rv = 0.f;
         int rc = 0;
 #pragma unroll
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
             for (int i = 0; i < 4; ++i) {
               const int row = 16 * t + 4 * u + i;
               const float sc = SPLIT ? (h == 0 ? o[0][t][i] + o[1][t][i] : o[0][t][i] - o[1][t][i]) : o[0][t][i];
-              const float val = row < HALF ? fabsf(sc) : -1.f;
+              const float val = fabsf(sc);
               const bool gt = val > rb;
               rb = gt ? val : rb;
               rv = gt ? sc : rv;

@@ -401,6 +401,11 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
       int rs;
       float cval;
       {
+        // Rows past the valid angles have all-zero operand rows, so their scores are exactly
+        // 0.  A lane reaches them after its valid rows (its rows ascend), and a 0 never beats
+        // an earlier value under the strict '>'; a lane with no valid row ends with 0 at an
+        // index past the valid ones, which loses the cross-lane tie to the other lane (row 0
+        // is always valid).  So no row mask is needed.
         float rb = -1.f, rv = 0.f;
         int rc = 0;
         if (SPLIT) {
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
             for (int i = 0; i < 16; ++i) {
               const int row = 8 * (i / 4) + 4 * u + (i % 4);
               const float sc = h == 0 ? e[i] + o[i] : e[i] - o[i];
-              const float val = row < HALF ? fabsf(sc) : -1.f;
+              const float val = fabsf(sc);
               const bool gt = val > rb;
               rb = gt ? val : rb;
               rv = gt ? sc : rv;
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
               const int r = 32 * t + 8 * (i / 4) + 4 * u + (i % 4);
-              const float val = r < R ? fabsf(sc[i]) : -1.f;
+              const float val = fabsf(sc[i]);
               const bool gt = val > rb;
               rb = gt ? val : rb;
               rv = gt ? sc[i] : rv;
