@@ -37,7 +37,7 @@ DTYPE = {"fp32": "f32", "bf16": "bf16 (FP32 accumulation, FP32 re-score)",
 # profiles/encode16_ragged-images_kernel_trace.md).  Valid for the encoder as of those
 # counter runs; a workload missing here reports null.
 TRAFFIC = {
-    "scale-fp32": {"read": 225.9e6, "write": 55.1e6},      # algorithmic 220.0e6 / 52.0e6
+    "scale-fp32": {"read": 225.8e6, "write": 55.1e6},      # algorithmic 220.0e6 / 52.0e6
     "ragged-images": {"read": 13.00e9, "write": 2.22e9},   # algorithmic 12.21e9 / 2.21e9
     "rotate-steer-11": {"read": 880.1e6, "write": 880.0e6},  # algorithmic 880e6 / 880e6 (4M x 55 x 4 B)
 }
@@ -130,10 +130,10 @@ def host_info() -> dict:
 
 def oracle_rate_one_thread(run, X, target_s: float) -> dict:
     """The reference's rate with its BLAS pools held to one thread, on a prefix of X sized
-    from a 64-patch pilot to take about target_s seconds."""
+    from a 1,024-patch pilot to take about target_s seconds."""
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
-        n0 = min(64, len(X))
+        n0 = min(1024, len(X))
         t0 = time.perf_counter()
         run(X[:n0].astype(np.float64))
         dt0 = time.perf_counter() - t0
@@ -160,7 +160,9 @@ def cpu_baseline(h, w, D, target_s: float, dev):
             _, d = wl.scale_draw(P=n)
         return orc.synthesize(basis, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
 
-    n0 = 256
+    # the sample is sized from a pilot of a few thousand patches: a smaller pilot is dominated
+    # by the reference's fixed costs and would size the sample well short of target_s
+    n0 = 2048
     X0 = sample(n0)
     t0 = time.perf_counter()
     orc.encode(basis, D, w["R"], X0.astype(np.float64), w["K"])
