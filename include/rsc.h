@@ -134,8 +134,9 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * 16x16 encoder tile; other annular handles get RSC_E_UNSUPPORTED from
  * rsc_set_dictionary.  The dictionary update (rsc_rksvd_update, rsc_rksvd_train) runs in
  * the annular layout for B <= 128 (N = 11).  Image projection serves the full and
- * low-pass annular bases at N = 11 and 15 (the limits of rsc_project_images); image
- * stamping returns RSC_E_UNSUPPORTED for every annular handle.
+ * low-pass annular bases at N = 11 and 15 (the limits of rsc_project_images), and
+ * rsc_classify takes annular class handles; image stamping returns RSC_E_UNSUPPORTED for
+ * every annular handle.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
  * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
  * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 192 or some T_s > 31),
@@ -451,7 +452,8 @@ rsc_status rsc_classify_workspace_size(int64_t P, int K, size_t* bytes);
  * rsc_omp_encode runs with classes[c]'s dictionary, and every patch keeps the class of
  * smallest squared error.
  *   classes     host array of C handles, each with a dictionary (RSC_E_NOT_READY
- *               otherwise) and the same geometry (N, S, T); their precisions and
+ *               otherwise) and the same basis: the same (N, S, T) grid, or the same
+ *               annular basis (RSC_E_INVALID otherwise); their precisions and
  *               dictionary sizes may differ
  *   C           1 <= C <= 1024
  *   xhat        device [P, B] float32 (rsc_project of any of the handles)

@@ -1170,8 +1170,10 @@ rsc_status rsc_classify(const rsc_handle* const* classes, int C, const float* xh
     if (!classes[c]->has_dict) return fail(RSC_E_NOT_READY, "a class handle has no dictionary");
     const rsc::HostBasis& b0 = classes[0]->basis;
     const rsc::HostBasis& bc = classes[c]->basis;
-    if (bc.N != b0.N || bc.S != b0.S || bc.T != b0.T)
-      return fail(RSC_E_INVALID, "class handles must share the geometry (N, S, T)");
+    if (bc.N != b0.N || bc.S != b0.S || bc.T != b0.T || classes[c]->annular != classes[0]->annular ||
+        classes[c]->dev.B != classes[0]->dev.B)
+      return fail(RSC_E_INVALID, "class handles must share the geometry: the same (N, S, T) grid or the same "
+                                 "annular basis");
   }
   if (K < 1 || K > 8 || K > classes[0]->dev.B) return fail(RSC_E_INVALID, "K must be in 1..min(8, B)");
   if (P < 0) return fail(RSC_E_INVALID, "P must be >= 0");

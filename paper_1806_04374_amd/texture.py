@@ -34,8 +34,13 @@ def window_offsets(batch, device):
 class TextureClassifier:
     """Per-class rotational dictionaries, label-histogram features, chi^2 1-NN."""
 
-    def __init__(self, N: int, S: int, T: int, R: int, K: int, prec: str = "fp32"):
+    def __init__(self, N: int, S: int, T: int, R: int, K: int, prec: str = "fp32", annular: bool = False):
+        """annular: the classes use the paper's annular basis at N (S and T are then unused;
+        FP32 only)."""
+        if annular and prec != "fp32":
+            raise ValueError("the annular basis is FP32 only")
         self.N, self.S, self.T, self.R, self.K, self.prec = N, S, T, R, K, prec
+        self.annular = annular
         self.handles: list[rsc.Handle] = []
         self.dictionaries: list[np.ndarray] = []
         self.histories: list[np.ndarray] = []
@@ -50,7 +55,7 @@ class TextureClassifier:
             pick = np.sort(rng.choice(xh.shape[0], M, replace=False))
             d0 = xh[pick].cpu().numpy().astype(np.float64)
             d0 /= np.maximum(np.linalg.norm(d0, axis=1, keepdims=True), 1e-30)
-            h = rsc.rsc_create(self.N, self.S, self.T, prec=self.prec)
+            h = rsc.rsc_create_annular(self.N) if self.annular else rsc.rsc_create(self.N, self.S, self.T, prec=self.prec)
             D, _, hist = rsc.rsc_rksvd_train(h, xh, d0.astype(np.float32), self.R, self.K, n_iter)
             rsc.rsc_set_dictionary(h, D, self.R)
             self.handles.append(h)
