@@ -133,10 +133,10 @@ rsc_status rsc_basis_host(int N, int S, int T, const double* centres, double sig
  * N = 15 (B = 153, T_s = 1, 3, 8, 11, 13, 18, 19) with even R <= 64 and K <= 4, on the
  * 16x16 encoder tile; other annular handles get RSC_E_UNSUPPORTED from
  * rsc_set_dictionary.  The dictionary update (rsc_rksvd_update, rsc_rksvd_train) runs in
- * the annular layout for B <= 128 (N = 11).  Image projection serves the full and
- * low-pass annular bases at N = 11 and 15 (the limits of rsc_project_images), and
- * rsc_classify takes annular class handles; image stamping returns RSC_E_UNSUPPORTED for
- * every annular handle.
+ * the annular layout for B <= 160 (the full basis at N = 11 and 15).  Image projection
+ * serves the full and low-pass annular bases at N = 11 and 15 (the limits of
+ * rsc_project_images), and rsc_classify takes annular class handles; image stamping
+ * returns RSC_E_UNSUPPORTED for every annular handle.
  *   N      odd, 3 <= N <= 31;  out  receives the handle
  * B <= 192 and T_s <= 31 are handled (N <= 15 for the full basis: B = 153 at N = 15).
  * Errors: RSC_E_INVALID (N, null out), RSC_E_UNSUPPORTED (B > 192 or some T_s > 31),
@@ -409,7 +409,8 @@ rsc_status rsc_rksvd_workspace_size(const rsc_handle* h, int64_t P, int K, size_
  *   reset               device [M] int32 output (reset patch or -1), or NULL
  * Enqueued on the stream; the handle's dictionary is not changed (pass d_new to
  * rsc_set_dictionary).  Errors: RSC_E_INVALID, RSC_E_NOT_READY, RSC_E_UNSUPPORTED
- * (B > 128), RSC_E_DEVICE.
+ * (B > 160, or tables of the update beyond the 160 KiB LDS of a CU: the single-value
+ * dictionary 4 M B bytes plus 16 R (T + 1) bytes of rotation table), RSC_E_DEVICE.
  */
 rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, int K, const int32_t* atom,
                             const int32_t* angle, const float* coef, const float* resid2, void* workspace,
@@ -428,6 +429,8 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
  *   history                    host [n_iter + 1] float64 or NULL: sum of resid2 after
  *                              each pursuit
  * Blocking (the dictionary returns to the host each iteration to rebuild the tables).
+ * Errors as rsc_rksvd_update and rsc_set_dictionary; a refused call leaves the handle's
+ * dictionary as it was.
  */
 rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, int n_iter, const float* d_init,
                            int M, int R, void* workspace, size_t ws_bytes, int32_t* atom, int32_t* angle,

@@ -1085,7 +1085,9 @@ rsc_status rsc_rksvd_update(const rsc_handle* h, const float* xhat, int64_t P, i
   if (P < 1 || P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (!xhat || !atom || !angle || !coef || !resid2 || !workspace || !d_new || !usage)
     return fail(RSC_E_INVALID, "null device pointer");
-  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
+  if (!rsc::rksvd_fits(h->dev))
+    return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 160 with its tables within the "
+                                   "160 KiB LDS of a CU");
   const RkLayout L = rk_layout(h->dev, P, K);
   if (ws_bytes < L.total) return fail(RSC_E_INVALID, "workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(RSC_E_INVALID, "workspace not 256-byte aligned");
@@ -1107,7 +1109,14 @@ rsc_status rsc_rksvd_train(rsc_handle* h, const float* xhat, int64_t P, int K, i
   if (P > INT32_MAX) return fail(RSC_E_INVALID, "P must be in 1..2^31-1");
   if (P < 1 || !xhat || !atom || !angle || !coef || !resid2 || !workspace)
     return fail(RSC_E_INVALID, "null device pointer or empty input");
-  if (h->dev.B > 128) return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 128");
+  {
+    rsc::DeviceTables want = h->dev;   // the update's sizes with the new dictionary (a shallow copy)
+    want.M = M;
+    want.R = R;
+    if (!rsc::rksvd_fits(want))
+      return fail(RSC_E_UNSUPPORTED, "the dictionary update is compiled for B <= 160 with its tables within the "
+                                     "160 KiB LDS of a CU");
+  }
   rsc_status s = rsc_set_dictionary(h, d_init, M, R, stream);
   if (s != RSC_OK) return s;
   const RkLayout L = rk_layout(h->dev, P, K);

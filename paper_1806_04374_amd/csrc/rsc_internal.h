@@ -97,6 +97,11 @@ size_t encode_lds_bytes(const DeviceTables& t, int tile);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
+// Largest B the dictionary update is compiled for (its covariance tiles: 10 x 10 of 16).
+constexpr int kRkMaxB = 160;
+// Whether the dictionary update's kernels fit this handle (B <= kRkMaxB and each kernel's
+// tables within the 160 KiB LDS of a CU).
+bool rksvd_fits(const DeviceTables& t);
 size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P, int K);
 int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int K, const int32_t* atom,
                         const int32_t* angle, const float* coef, const float* resid2, void* ws,

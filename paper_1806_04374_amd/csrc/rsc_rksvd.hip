@@ -43,9 +43,9 @@ struct RkWs {
   size_t cnt, off, tot, bucket, chunk, scal, lp, lr, lc, resid, partial, total;
 };
 
-// Row stride of the residuals: one or two whole waves per patch, so that a wave's
+// Row stride of the residuals: one, two or three whole waves per patch, so that a wave's
 // patch index is uniform (its code entries come through scalar loads).
-__host__ __device__ inline int resid_stride(int B) { return B <= 64 ? 64 : 128; }
+__host__ __device__ inline int resid_stride(int B) { return B <= 64 ? 64 : B <= 128 ? 128 : 192; }
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -394,21 +394,26 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   }
 }
 
-// BT (64 or 128) covers B; W waves per block, NH = 64 W / BT groups of BT threads,
+// BT (64, 128 or 192) covers B; W waves per block, NH = 64 W / BT groups of BT threads,
 // group h forming pairs h KP .. h KP + KP - 1 of each batch of KQ.  Thread (row, h)
 // forms coordinate row of y = S_{-r0} r + c d_m for its pairs into Y (LDS, [KQ][BT]);
 // sum y y^T is the symmetric product Y^T Y, taken on the FP64 matrix cores in 16 x 16
-// tiles of the upper triangle, four pairs per product, tiles shared out among the
-// waves.  Software pipeline: the pair records (patch, r0, c) of batch b + 2 and the
-// residual rows of batch b + 1 are loaded while batch b is formed and multiplied.
-template <int BT, int W, int KQ>
+// tiles of the upper triangle of the ceil(B/16) row blocks that B needs (at most NRMAX),
+// four pairs per product, tiles shared out among the waves.  Software pipeline: the pair
+// records (patch, r0, c) of batch b + 2 and the residual rows of batch b + 1 are loaded
+// while batch b is formed and multiplied.  FULL: B needs all NRMAX row blocks and every
+// wave has the same number of tiles, so the tile loop needs no test.
+template <int BT, int W, int KQ, int NRMAX, bool FULL>
 __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
   constexpr int NT = 64 * W, NH = NT / BT, KP = KQ / NH;
-  constexpr int NR = BT / 16, NTILE = NR * (NR + 1) / 2, TW = (NTILE + W - 1) / W;
-  static_assert(NT % BT == 0 && KQ % NH == 0 && KQ % 4 == 0, "block shape");
+  constexpr int TW = (NRMAX * (NRMAX + 1) / 2 + W - 1) / W;
+  static_assert(NT % BT == 0 && KQ % NH == 0 && KQ % 4 == 0 && BT % 64 == 0 && 16 * NRMAX <= BT, "block shape");
+  static_assert(!FULL || (NRMAX * (NRMAX + 1) / 2) % W == 0, "FULL needs whole tile rounds");
   typedef double d4 __attribute__((ext_vector_type(4)));
   extern __shared__ double ldsd[];
   const int B = prm.B, BP = prm.BP, R = prm.R, M = prm.M, NQ = prm.T + 1;
+  // NR <= NRMAX (checked by the host); NR == NRMAX when FULL
+  const int NR = FULL ? NRMAX : (B + 15) / 16, NTILE = NR * (NR + 1) / 2;
   double* yb = ldsd;                                         // [KQ][BT]
   double2* sc = reinterpret_cast<double2*>(yb + KQ * BT);    // [R][NQ] (cos, sin) of k 2 pi r / R
   const int t = threadIdx.x, row = t % BT, lane = t % 64;
@@ -504,7 +509,7 @@ __global__ __launch_bounds__(64 * W) void rk_accum_kernel(AccParams prm) {
       const double* yg = yb + (4 * g + lane / 16) * BT + lane % 16;
 #pragma unroll
       for (int i = 0; i < TW; ++i)
-        if (NTILE % W == 0 || ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(yg[ta[i]], yg[tb[i]], acc[i], 0, 0, 0);
+        if (FULL || ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(yg[ta[i]], yg[tb[i]], acc[i], 0, 0, 0);
     }
     __syncthreads();
     rC = rN;
@@ -558,27 +563,45 @@ struct EigParams {
 
 constexpr int kMaxSquarings = 40;
 
+// Symmetric NP x NP matrices in LDS as their upper-triangle 16 x 16 tiles: tile (r, s),
+// r <= s, is number r NR - r (r - 1) / 2 + (s - r) (the order of tile_r / tile_s), stored
+// row-major with a row stride of kEigTS doubles (17: a tile's columns, read transposed for
+// the lower triangle, then fall in distinct banks).  The diagonal tiles hold both halves.
+constexpr int kEigTS = 17;
+__device__ __forceinline__ int tile_index(int r, int s, int NR) { return r * NR - r * (r - 1) / 2 + (s - r); }
+__device__ __forceinline__ double sym_at(const double* A, int i, int j, int NR) {
+  const int bi = i >> 4, bj = j >> 4;
+  return bi <= bj ? A[(tile_index(bi, bj, NR) * 16 + (i & 15)) * kEigTS + (j & 15)]
+                  : A[(tile_index(bj, bi, NR) * 16 + (j & 15)) * kEigTS + (i & 15)];
+}
+
+__host__ __device__ inline size_t eig_lds_bytes(int B, int W) {
+  const int NR = (B + 15) / 16;
+  return sizeof(double) * (size_t(NR) * (NR + 1) / 2 * 16 * kEigTS + W + 16 * size_t(NR));
+}
+
 // Top eigenvector of one atom's C_m = Y_m Y_m^T (symmetric positive semidefinite), one
 // block per atom, W waves.  C is scaled to unit trace and squared repeatedly,
-// C <- C^2 / trace(C^2), on the FP64 matrix cores (16 x 16 tiles of the upper triangle,
-// the zero-padded NP x NP matrix in LDS; as C is symmetric, lane l's A operand of tile row
-// r is C[4g + l/16][16r + l%16], the same pattern as its B operand).  With the eigenvalues
-// of the scaled C written mu_i (sum 1), trace(C^2) = sum mu_i^2; it reaches 1 - 2 eps when the
+// C <- C^2 / trace(C^2), on the FP64 matrix cores (16 x 16 tiles of the upper triangle of
+// the zero-padded NP x NP matrix, NP = 16 ceil(B / 16) <= 16 NRMAX, kept in LDS as those
+// tiles only; as C is symmetric, lane l's A operand of tile row r is
+// C[4g + l/16][16r + l%16], the same pattern as its B operand).  With the eigenvalues of
+// the scaled C written mu_i (sum 1), trace(C^2) = sum mu_i^2; it reaches 1 - 2 eps when the
 // second share is eps, so the loop stops once 1 - trace(C^2) < 1e-14 (every other direction
 // then carries a weight below 1e-14), or after kMaxSquarings.  The result is C d_old
 // (or, if d_old has no component in that eigenspace, the column of largest diagonal),
 // normalised and signed to agree with d_old.  A repeated top eigenvalue gives the
 // projection of d_old onto its eigenspace.
-template <int W>
+template <int W, int NRMAX>
 __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
   typedef double d4 __attribute__((ext_vector_type(4)));
-  constexpr int NT = 64 * W, TW = (36 + W - 1) / W;   // at most 8 x 8 tiles, 36 in the upper triangle
+  constexpr int NT = 64 * W, TW = (NRMAX * (NRMAX + 1) / 2 + W - 1) / W;
   extern __shared__ double ldsd[];
   const int n = prm.B, m = blockIdx.x, t = threadIdx.x, lane = t % 64;
   const int wv = __builtin_amdgcn_readfirstlane(t / 64);
-  const int NP = (n + 15) / 16 * 16, NR = NP / 16, NTILE = NR * (NR + 1) / 2;
-  double* A = ldsd;                  // [NP][NP]
-  double* red = A + NP * NP;         // [W] reduction slots, then [NP] vector
+  const int NR = (n + 15) / 16, NP = 16 * NR, NTILE = NR * (NR + 1) / 2;   // NR <= NRMAX (host)
+  double* A = ldsd;                          // [NTILE][16][kEigTS]
+  double* red = A + NTILE * 16 * kEigTS;     // [W] reduction slots, then [NP] vector
   double* vec = red + W;
   const int used = int(prm.bucket[m + 1] - prm.bucket[m]);
   if (t == 0) prm.usage[m] = used;
@@ -588,9 +611,10 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
   }
   // load C_m (the sum of its chunk partials sits in its first chunk's slot), zero padding
   const double* Cm = prm.partial + size_t(prm.chunk[m]) * n * n;
-  for (int i = t; i < NP * NP; i += NT) {
-    const int r = i / NP, c = i - r * NP;
-    A[i] = r < n && c < n ? Cm[size_t(r) * n + c] : 0.0;
+  for (int i = t; i < NTILE * 256; i += NT) {
+    const int u = i >> 8, ii = (i >> 4) & 15, jj = i & 15;
+    const int row = 16 * tile_r(u, NR) + ii, col = 16 * tile_s(u, NR) + jj;
+    A[(u * 16 + ii) * kEigTS + jj] = row < n && col < n ? Cm[size_t(row) * n + col] : 0.0;
   }
   __syncthreads();   // the trace below reads diagonal entries other threads wrote
   // block sum in a fixed order: per wave a butterfly (identical bits in every lane),
@@ -608,7 +632,7 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
   double tr = 0.0;
   {
     double p = 0.0;
-    for (int i = t; i < n; i += NT) p += A[i * NP + i];
+    for (int i = t; i < n; i += NT) p += sym_at(A, i, i, NR);
     tr = block_sum(p);
   }
   if (!(tr > 0.0)) {   // C_m = 0: nothing to fit
@@ -617,25 +641,31 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
   }
   {
     const double sc = 1.0 / tr;
-    for (int i = t; i < NP * NP; i += NT) A[i] *= sc;
+    for (int i = t; i < NTILE * 256; i += NT) A[(i >> 4) * kEigTS + (i & 15)] *= sc;
   }
   __syncthreads();
-  int ta[TW], tb[TW];
+  int ta[TW], tb[TW];   // block row and column of this wave's tiles (-1: no tile)
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int u = wv + W * i;
-    ta[i] = u < NTILE ? 16 * tile_r(u, NR) : -1;
-    tb[i] = u < NTILE ? 16 * tile_s(u, NR) : -1;
+    ta[i] = u < NTILE ? tile_r(u, NR) : -1;
+    tb[i] = u < NTILE ? tile_s(u, NR) : -1;
   }
+  const int l16 = lane / 16, lc = lane % 16;
   for (int it = 0; it < kMaxSquarings; ++it) {
     d4 acc[TW];
 #pragma unroll
     for (int i = 0; i < TW; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
     for (int g = 0; g < NP / 4; ++g) {
-      const double* Ag = A + (4 * g + lane / 16) * NP + lane % 16;
+      // rows 4g .. 4g + 3 of C lie in row block kb (the same for the whole wave)
+      const int kb = g >> 2, i0 = 4 * (g & 3) + l16;
+      auto opnd = [&](int rb) {
+        return kb <= rb ? A[(tile_index(kb, rb, NR) * 16 + i0) * kEigTS + lc]
+                        : A[(tile_index(rb, kb, NR) * 16 + lc) * kEigTS + i0];
+      };
 #pragma unroll
       for (int i = 0; i < TW; ++i)
-        if (ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ag[ta[i]], Ag[tb[i]], acc[i], 0, 0, 0);
+        if (ta[i] >= 0) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(opnd(ta[i]), opnd(tb[i]), acc[i], 0, 0, 0);
     }
     // trace of the square from the diagonal tiles: lane l register e holds row
     // 16r + l/16 + 4e, column 16r + l%16
@@ -645,20 +675,15 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
       if (ta[i] >= 0 && ta[i] == tb[i])
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (lane / 16 + 4 * e == lane % 16) p += acc[i][e];
+          if (l16 + 4 * e == lc) p += acc[i][e];
     const double tr2 = block_sum(p);   // its barriers also end every read of A
     const double sc = 1.0 / tr2;
 #pragma unroll
     for (int i = 0; i < TW; ++i) {
       if (ta[i] < 0) continue;
-      const int col = tb[i] + lane % 16;
+      double* tile = A + tile_index(ta[i], tb[i], NR) * 16 * kEigTS;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = ta[i] + lane / 16 + 4 * e;
-        const double x = acc[i][e] * sc;
-        A[row * NP + col] = x;
-        if (ta[i] != tb[i]) A[col * NP + row] = x;
-      }
+      for (int e = 0; e < 4; ++e) tile[(l16 + 4 * e) * kEigTS + lc] = acc[i][e] * sc;
     }
     __syncthreads();
     if (1.0 - tr2 < 1e-14) break;
@@ -668,13 +693,13 @@ __global__ __launch_bounds__(64 * W) void rk_eig_kernel(EigParams prm) {
   __syncthreads();
   double zt = 0.0;
   if (t < n)
-    for (int j = 0; j < n; ++j) zt += A[t * NP + j] * vec[j];
+    for (int j = 0; j < n; ++j) zt += sym_at(A, t, j, NR) * vec[j];
   double nz = block_sum(t < n ? zt * zt : 0.0);
   if (!(nz > 1e-20)) {
     int jm = 0;
     for (int j = 1; j < n; ++j)
-      if (A[j * NP + j] > A[jm * NP + jm]) jm = j;
-    zt = t < n ? A[t * NP + jm] : 0.0;
+      if (sym_at(A, j, j, NR) > sym_at(A, jm, jm, NR)) jm = j;
+    zt = t < n ? sym_at(A, t, jm, NR) : 0.0;
     nz = block_sum(t < n ? zt * zt : 0.0);
   }
   const double dot = block_sum(t < n ? zt * vec[t] : 0.0);
@@ -792,6 +817,16 @@ __global__ __launch_bounds__(256) void rk_sum_final_kernel(double* out) {
 
 }  // namespace
 
+bool rksvd_fits(const DeviceTables& t) {
+  if (t.B < 1 || t.B > kRkMaxB) return false;
+  const size_t lim = 160 * 1024;
+  const size_t table = sizeof(double) * 2 * size_t(t.R) * (t.T + 1);
+  const size_t resid = table + sizeof(float) * size_t(t.M) * t.B;   // the single-value form
+  const int bt = t.B <= 64 ? 64 : t.B <= 128 ? 128 : 192;
+  const size_t acc = sizeof(double) * (16 * size_t(bt) + 2 * size_t(t.T + 1) * t.R);
+  return resid <= lim && acc <= lim && eig_lds_bytes(t.B, 8) <= lim;
+}
+
 size_t rksvd_workspace_bytes(const DeviceTables& t, int64_t P, int K) {
   return rk_ws(t.M, t.B, P, K).total + al256(sizeof(double) * kSumSlots);
 }
@@ -848,10 +883,9 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
   EigParams ep{partial, sp.bucket, sp.chunk, t.M, t.B, t.dictHat, d_new, usage};
   const int NQ = t.T + 1;
   const int64_t nblk = max_chunks(t.M, P, K);
-  auto run = [&](auto acc_kern, auto eig_kern, int bt, int nt, int kq) -> int {
+  auto run = [&](auto acc_kern, auto eig_kern, int bt, int nt, int kq, int eig_threads) -> int {
     const size_t lds1 = sizeof(double) * (size_t(kq) * bt + 2 * size_t(NQ) * t.R);
-    const size_t np2 = size_t((t.B + 15) / 16 * 16);
-    const size_t lds2 = sizeof(double) * (np2 * np2 + 8 + np2);
+    const size_t lds2 = eig_lds_bytes(t.B, 8);
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(acc_kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1));
     if (err == hipSuccess)
@@ -867,11 +901,18 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
                        sp.chunk, BB);
     err = hipGetLastError();
     if (err != hipSuccess) return int(err);
-    hipLaunchKernelGGL(eig_kern, dim3(unsigned(t.M)), dim3(bt <= 64 ? 256 : 512), lds2, st, ep);
+    hipLaunchKernelGGL(eig_kern, dim3(unsigned(t.M)), dim3(eig_threads), lds2, st, ep);
     return int(hipGetLastError());
   };
-  const int r = t.B <= 64 ? run(rk_accum_kernel<64, 2, 16>, rk_eig_kernel<4>, 64, 128, 16)
-                          : run(rk_accum_kernel<128, 4, 16>, rk_eig_kernel<8>, 128, 256, 16);
+  if (t.B > kRkMaxB) return int(hipErrorInvalidValue);
+  // 49..64 (the 11x11 grid, B = 55) fills the fourth row block: the tile loop needs no test;
+  // any other B up to 128 (the 15x15 grid, the annular basis at N = 11) takes the general
+  // 128-row form, B up to 160 (the annular basis at N = 15) the 192-row one
+  const int r = t.B > 48 && t.B <= 64
+                    ? run(rk_accum_kernel<64, 2, 16, 4, true>, rk_eig_kernel<4, 4>, 64, 128, 16, 256)
+                : t.B <= 128 ? (t.B <= 64 ? run(rk_accum_kernel<128, 4, 16, 8, false>, rk_eig_kernel<4, 4>, 128, 256, 16, 256)
+                                          : run(rk_accum_kernel<128, 4, 16, 8, false>, rk_eig_kernel<8, 8>, 128, 256, 16, 512))
+                             : run(rk_accum_kernel<192, 6, 16, 10, false>, rk_eig_kernel<8, 10>, 192, 384, 16, 512);
   if (r) return r;
   ResetParams rp{xhat, resid2, P, t.M, t.B, usage, d_new, reset};
   hipLaunchKernelGGL(rk_reset_kernel, dim3(1), dim3(256), 0, st, rp);

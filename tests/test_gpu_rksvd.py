@@ -256,21 +256,23 @@ def test_update_argument_errors(dev):
 
 
 # ----------------------------------------------------------------- the paper's annular basis
-def test_update_matches_reference_annular_basis(dev):
-    """The update in the annular layout (N = 11, B = 81: harmonic k on the annuli that carry
-    it) against the reference's update with that basis' steering, on the reference's codes."""
+@pytest.mark.parametrize("N", [11, 15])
+def test_update_matches_reference_annular_basis(dev, N):
+    """The update in the annular layout (harmonic k on the annuli that carry it; B = 81 at
+    N = 11, 153 at N = 15, whose covariance takes 10 x 10 tiles) against the reference's
+    update with that basis' steering, on the reference's codes."""
     from paper_1806_04374_amd import rsc
-    ab = orc.build_annular_basis(11)
+    ab = orc.build_annular_basis(N)
     M, R, K = 16, 32, 3
     D = wl.draw_dictionary(M, ab.B, seed=41).astype(np.float32).astype(np.float64)
-    d = wl.draw_mixtures(3000, 11, M, 3, 0.05, seed=41)
+    d = wl.draw_mixtures(3000, N, M, 3, 0.05, seed=41)
     X = orc.project(ab, orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32))
     X = X.astype(np.float32).astype(np.float64)
     Dp = D + 0.2 * np.random.default_rng(42).standard_normal(D.shape)
     Dp = (Dp / np.linalg.norm(Dp, axis=1, keepdims=True)).astype(np.float32).astype(np.float64)
     code = _fp32_code(orc.omp(orc.augmented_dictionary_basis(ab, Dp, R), X, K, M))
     ref, usage_ref, reset_ref = orc.rksvd_update_basis(ab, Dp, R, X, code)
-    h = rsc.rsc_create_annular(11)
+    h = rsc.rsc_create_annular(N)
     rsc.rsc_set_dictionary(h, Dp.astype(np.float32), R)
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).astype(dt)).to(dev)
     d_new, usage, reset = rsc.rsc_rksvd_update(h, t(X, np.float32), t(code.atom, np.int32), t(code.angle, np.int32),
@@ -300,11 +302,12 @@ def test_update_matches_reference_annular_basis(dev):
     assert worst < 1e-5
 
 
-def test_training_loop_recovers_toy_atoms_annular_basis(dev):
+@pytest.mark.parametrize("N", [11, 15])
+def test_training_loop_recovers_toy_atoms_annular_basis(dev, N):
     """The device loop on the annular basis: three atoms, two grid-rotated copies per patch,
     noise-free, found from a random start up to a rotation, as the reference loop does."""
     from paper_1806_04374_amd import rsc
-    ab = orc.build_annular_basis(11)
+    ab = orc.build_annular_basis(N)
     R, P = 32, 400
     rng = np.random.default_rng(2)
     D_true = rng.standard_normal((3, ab.B))
@@ -316,7 +319,7 @@ def test_training_loop_recovers_toy_atoms_annular_basis(dev):
                   for p in range(P)]).astype(np.float32)
     D0 = np.random.default_rng(7).standard_normal((3, ab.B))
     D0 = (D0 / np.linalg.norm(D0, axis=1, keepdims=True)).astype(np.float32)
-    h = rsc.rsc_create_annular(11)
+    h = rsc.rsc_create_annular(N)
     D, codes, hist = rsc.rsc_rksvd_train(h, torch.from_numpy(X).to(dev), D0, R, 2, 20)
     print("history", hist)
     for m in range(3):
