@@ -633,8 +633,11 @@ def run_texture(args, dev):
     n_train = w["n_train"]
     n_test = args.images or w["n_test"]
     rots = w["test_rot_deg"]
+    annular = args.basis == "annular"
+    if annular and args.prec != "fp32":
+        sys.exit("the annular basis is FP32 only")
     t_setup = time.perf_counter()
-    proj = rsc.rsc_create(g.N, g.S, g.T)
+    proj = rsc.rsc_create_annular(g.N) if annular else rsc.rsc_create(g.N, g.S, g.T)
     tr_images = [wl.draw_texture_image(c, i, side, w["sigma"]) for c in range(C) for i in range(n_train)]
     tb, tpix = tx.upload_batch(tr_images, g.N, dev)
     del tr_images
@@ -652,7 +655,7 @@ def run_texture(args, dev):
         b, pix = tx.upload_batch(te, g.N, dev)
         batches.append((b, pix, tx.window_offsets(b, dev)))
     P = batches[0][0].P_total
-    xh = torch.empty((P, g.B), dtype=torch.float32, device=dev)
+    xh = torch.empty((P, proj.B), dtype=torch.float32, device=dev)
     ws = torch.empty(rsc.rsc_classify_workspace_size(P, K), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     test_class = np.repeat(np.arange(C), n_test)
@@ -694,7 +697,11 @@ def run_texture(args, dev):
         parts["histogram_nn"].append(e[2].elapsed_time(e[3]))
     # dominant kernel: the encoder, C launches per step (events around rsc_classify)
     cls_ms = float(np.median(parts["classify"]))
-    flops = encode_flops_per_patch(w["M"], R, g.S, g.T, K, split=args.prec == "fp32" and R % 2 == 0) * P * C
+    if annular:
+        Sk = [sum(1 for t in proj.Ts if t >= k) for k in range(max(proj.Ts) + 1)]
+        flops = annular_flops_per_patch(Sk, w["M"], R, K) * P * C
+    else:
+        flops = encode_flops_per_patch(w["M"], R, g.S, g.T, K, split=args.prec == "fp32" and R % 2 == 0) * P * C
     peak = FP32_MFMA_PEAK if args.prec == "fp32" else HALF_MFMA_PEAK
     images = batches[0][0].n
     out = {
@@ -705,7 +712,9 @@ def run_texture(args, dev):
         "config": {"workload": f"texture: {C} band-pass classes, {images} test images of {side}x{side} per step "
                                f"({P} 15x15 windows), one step per rotation {list(rots)} deg; R-K-SVD "
                                f"dictionaries M={w['M']}, K={K}, R={R} learned from {n_train} upright images "
-                               "per class", "precision": args.prec},
+                               "per class", "precision": args.prec,
+                   "basis": (f"the paper's annular basis, B={proj.B}" if annular
+                             else f"Gaussian profiles S={g.S}, T={g.T}, B={g.B}")},
         "images_per_s": images * n_steps / wall,
         "accuracy": {"per_rotation_deg": {str(k): v for k, v in acc.items()}, "mean": float(np.mean(list(acc.values())))},
         "parts_ms": {k: float(np.median(v)) for k, v in parts.items()},
@@ -740,7 +749,7 @@ def texture_learn(args, dev, xh_train, tb, R):
                                                                            replace=False))
                               for j in range(n_train)])
         cls_windows.append(xh_train.index_select(0, torch.from_numpy(idx).to(dev)).contiguous())
-    clf = tx.TextureClassifier(g.N, g.S, g.T, R, K, prec=args.prec)
+    clf = tx.TextureClassifier(g.N, g.S, g.T, R, K, prec=args.prec, annular=args.basis == "annular")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     clf.learn(cls_windows, w["M"], w["n_iter"])
@@ -984,15 +993,25 @@ def cpu_baseline_texture(clf, proj, xh, batch0, target_s, dev):
     b, pix, _ = batch0
     rsc.rsc_project_images(proj, pix, b, xhat=xh)
     D = [d.astype(np.float64) for d in clf.dictionaries]
+    if clf.annular:
+        ab = orc.build_annular_basis(g.N)
+
+        def classify(X):   # the reference classifier's rule with the annular basis' steering
+            sse = np.stack([orc.omp(orc.augmented_dictionary_basis(ab, Dc, w["R"]), X, w["K"], Dc.shape[0]).resid2
+                            for Dc in D], axis=1)
+            return np.argmin(sse, axis=1), sse
+    else:
+        def classify(X):
+            return orc.classify(D, w["R"], g.S, g.T, X, w["K"])
     n0 = 96
     X0 = xh[:n0].cpu().numpy().astype(np.float64)
     t0 = time.perf_counter()
-    orc.classify(D, w["R"], g.S, g.T, X0, w["K"])
+    classify(X0)
     dt0 = time.perf_counter() - t0
     n = int(min(20_000, max(n0, n0 * target_s / max(dt0, 1e-3))))
     X = xh[:n].cpu().numpy().astype(np.float64)
     t0 = time.perf_counter()
-    ref_label, ref_sse = orc.classify(D, w["R"], g.S, g.T, X, w["K"])
+    ref_label, ref_sse = classify(X)
     dt = time.perf_counter() - t0
     label, _ = rsc.rsc_classify(clf.handles, xh[:n].contiguous(), w["K"])
     torch.cuda.synchronize()
@@ -1057,6 +1076,8 @@ def main():
                     help="scale: skip the BF16 / FP16 forms and the small-workload latency")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", choices=["auto", "16", "32"], default="auto")
+    ap.add_argument("--basis", choices=["grid", "annular"], default="grid",
+                    help="texture: the classes' basis (the paper's annular basis is FP32)")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32",
                     help="encoder correlation precision (16-bit forms re-score candidates in FP32)")
     ap.add_argument("--mode", choices=["encode", "copy"], default="encode",

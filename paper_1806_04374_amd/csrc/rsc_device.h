@@ -144,6 +144,15 @@ struct LayoutBase {
     return prof(j, u) >= Sk(harm(j)) ? -1
            : (harm(j) == 0 ? prof(j, u) : base(harm(j)) + part(u) * Sk(harm(j)) + prof(j, u));
   }
+  // coord(J, u) for a run-time sub-lane u: the W candidates are constants, so the harmonic
+  // search inside coord never runs on the device (left to the optimiser it can stay a
+  // run-time loop nest for layouts with many harmonics)
+  template <int J>
+  __device__ static int coord_u(int u) {
+    constexpr int c0 = coord(J, 0), c1 = coord(J, 1);
+    constexpr int c2 = W == 4 ? coord(J, 2) : -1, c3 = W == 4 ? coord(J, 3) : -1;
+    return u == 0 ? c0 : u == 1 ? c1 : u == 2 ? c2 : c3;
+  }
 };
 
 // The (S, T) grid: every harmonic 0..T on all S profiles.

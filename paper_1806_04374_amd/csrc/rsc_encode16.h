@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
     float res[NKS];
     static_for<NKS>([&](auto J) {
       constexpr int j = decltype(J)::value;
-      const int c = L::coord(j, u);
+      const int c = L::template coord_u<j>(u);
       res[j] = (valid && c >= 0) ? prm.xhat[p * B + c] : 0.f;
     });
     const float nx2 = norm2<L>(res);

@@ -139,11 +139,11 @@ __global__ __launch_bounds__(256, (S <= 5 && KMAX <= 4) ? 2 : 1) void encode_lp_
     const int64_t p = wt * 32 + col;
     const bool valid = p < prm.P;
     float res[NKS];
-#pragma unroll
-    for (int j = 0; j < NKS; ++j) {
-      const int c = L::coord(j, u);
+    static_for<NKS>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const int c = L::template coord_u<j>(u);
       res[j] = (valid && c >= 0) ? prm.xhat[p * B + c] : 0.f;
-    }
+    });
     const float nx2 = norm2<L>(res);
     PursuitState<KMAX> st;
     init_state(st, valid);
