@@ -320,14 +320,17 @@ __global__ __launch_bounds__(256) void rk_resid_kernel(ResidParams prm) {
   float2* sd = reinterpret_cast<float2*>(sc + R * NQ);        // [M][B] (d_b, d_partner(b)) if PAIRED
   float* sd1 = reinterpret_cast<float*>(sc + R * NQ);         // [M][B] otherwise
   const int t = threadIdx.x, nt = blockDim.x, G = nt / BP;
+  __shared__ int spart[kRkMaxB];   // partner of each coordinate, found once per block
+  for (int i = t; i < B; i += nt) spart[i] = coord_of(i, prm.hb).partner;
   for (int i = t; i < R * NQ; i += nt) {
     const int r = i / NQ, k = i - r * NQ;
     sc[i] = double2{prm.cs64[k * R + r], prm.cs64[(NQ + k) * R + r]};
   }
+  if constexpr (PAIRED) __syncthreads();   // spart
   for (int i = t; i < M * B; i += nt) {
     if constexpr (PAIRED) {
       const int a = i / B, bb = i - a * B;
-      sd[i] = float2{prm.dict[i], prm.dict[a * B + coord_of(bb, prm.hb).partner]};
+      sd[i] = float2{prm.dict[i], prm.dict[a * B + spart[bb]]};
     } else {
       sd1[i] = prm.dict[i];
     }
@@ -821,7 +824,8 @@ bool rksvd_fits(const DeviceTables& t) {
   if (t.B < 1 || t.B > kRkMaxB) return false;
   const size_t lim = 160 * 1024;
   const size_t table = sizeof(double) * 2 * size_t(t.R) * (t.T + 1);
-  const size_t resid = table + sizeof(float) * size_t(t.M) * t.B;   // the single-value form
+  // the single-value form, plus the partner table in static LDS
+  const size_t resid = table + sizeof(float) * size_t(t.M) * t.B + sizeof(int) * kRkMaxB;
   const int bt = t.B <= 64 ? 64 : t.B <= 128 ? 128 : 192;
   const size_t acc = sizeof(double) * (16 * size_t(bt) + 2 * size_t(t.T + 1) * t.R);
   return resid <= lim && acc <= lim && eig_lds_bytes(t.B, 8) <= lim;
