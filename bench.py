@@ -774,19 +774,38 @@ def annular_flops_per_patch(Sk, M: int, R: int, K: int) -> float:
     return K * (stage1 + dft) + ls
 
 
+def annular_inputs(h, w, N, P, dev):
+    """The scale workload's draws (1-4 atoms at continuous angles, Laplace weights,
+    N(0, 0.05^2) noise) as N x N patches, synthesized on the device in the handle's basis."""
+    import torch
+    from paper_1806_04374_amd import rsc
+    X = torch.empty((P, N, N), dtype=torch.float32, device=dev)
+    step = 1 << 18
+    for lo in range(0, P, step):
+        n = min(step, P - lo)
+        d = wl.draw_mixtures(n, N, w["M"], w["J"], w["sigma"], 0, lo)
+        rsc.rsc_synthesize(h, torch.from_numpy(d.atom.astype(np.int32)).to(dev),
+                           torch.from_numpy(d.angle.astype(np.float32)).to(dev),
+                           torch.from_numpy(d.weight.astype(np.float32)).to(dev),
+                           torch.from_numpy(d.noise.astype(np.float32)).to(dev), out=X[lo:lo + n])
+    torch.cuda.synchronize()
+    return X
+
+
 def run_annular(args, dev):
     """The pursuit on the paper's annular basis (eq. (5)-(8)): the scale workload's draws
-    (10^6 11x11 patches, 1-4 atoms at continuous angles, Laplace weights, N(0, 0.05^2)
-    noise) with a 64-atom dictionary in the annular coordinates (B = 81), K = 4, R = 64."""
+    (10^6 patches, 1-4 atoms at continuous angles, Laplace weights, N(0, 0.05^2) noise) at
+    N = 11 (B = 81) or 15 (B = 153, --annular-n 15) with a 64-atom dictionary in the annular
+    coordinates, K = 4, R = 64."""
     import torch
     from paper_1806_04374_amd import rsc
     w = wl.SCALE
-    N, M, K, R = 11, w["M"], w["K"], w["R"]
+    N, M, K, R = args.annular_n, w["M"], w["K"], w["R"]
     P = args.patches or w["P"]
     h = rsc.rsc_create_annular(N)
     D = wl.draw_dictionary(M, h.B, seed=7)
     rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
-    X = make_inputs(h, w, P, dev)
+    X = make_inputs(h, w, P, dev) if N == 11 else annular_inputs(h, w, N, P, dev)
     xh = torch.empty((P, h.B), dtype=torch.float32, device=dev)
     outs = (torch.empty((P, K), dtype=torch.int32, device=dev), torch.empty((P, K), dtype=torch.int32, device=dev),
             torch.empty((P, K), dtype=torch.float32, device=dev), torch.empty((P,), dtype=torch.float32, device=dev))
@@ -817,7 +836,7 @@ def run_annular(args, dev):
         "warmup": args.warmup, "ms_per_step": ms, "p50_ms": float(np.percentile(step_ms, 50)),
         "p99_ms": float(np.percentile(step_ms, 99)), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"annular: {P} 11x11 patches in the paper's annular basis (T_s = {Ts}, B = {h.B}), "
+        "config": {"workload": f"annular: {P} {N}x{N} patches in the paper's annular basis (T_s = {Ts}, B = {h.B}), "
                                f"M={M}, K={K}, R={R}", "P": P, "N": N, "B": h.B, "M": M, "K": K, "R": R},
         "kernels_ms": {"project_mean": float(np.mean([a.elapsed_time(b) for a, b, _ in ev])), "encode_mean": enc},
         "roofline": {"kernel": "encode16_kernel (annular layout)", "bound": "mfma",
@@ -837,10 +856,13 @@ def cpu_baseline_annular(h, w, D, target_s, dev):
     prefix against it."""
     from threadpoolctl import threadpool_info
     from oracle import rsc_oracle as orc
-    ab = orc.build_annular_basis(11)
+    ab = orc.build_annular_basis(h.N)
 
     def sample(n):
-        _, d = wl.scale_draw(P=n)
+        if h.N == 11:
+            _, d = wl.scale_draw(P=n)
+        else:
+            d = wl.draw_mixtures(n, h.N, w["M"], w["J"], w["sigma"], 0, 0)
         return orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
 
     X0 = sample(128)
@@ -1076,6 +1098,8 @@ def main():
                     help="scale: skip the BF16 / FP16 forms and the small-workload latency")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", choices=["auto", "16", "32"], default="auto")
+    ap.add_argument("--annular-n", type=int, choices=[11, 15], default=11,
+                    help="annular: patch side (B = 81 or 153)")
     ap.add_argument("--basis", choices=["grid", "annular"], default="grid",
                     help="texture: the classes' basis (the paper's annular basis is FP32)")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32",
