@@ -514,7 +514,10 @@ int dispatch_lp(const DeviceTables& t, const LpParams& prm, hipStream_t st) {
     if (prm.K <= 4) return angles_lp<5, 5, 4, PREC>(t, prm, st);
     return angles_lp<5, 5, 8, PREC>(t, prm, st);
   }
-  if (t.S == 7 && t.T == 7) return angles_lp<7, 7, 8, PREC>(t, prm, st);
+  if (t.S == 7 && t.T == 7) {
+    if (prm.K <= 6) return angles_lp<7, 7, 6, PREC>(t, prm, st);   // the six-slot state: fewer registers
+    return angles_lp<7, 7, 8, PREC>(t, prm, st);
+  }
   return int(hipErrorInvalidValue);
 }
 
