@@ -29,6 +29,7 @@
 #include <cfloat>
 
 #include "rsc_internal.h"
+#include "rsc_launch.h"
 
 namespace rsc {
 namespace {
@@ -872,12 +873,16 @@ int launch_rksvd_update(const DeviceTables& t, const float* xhat, int64_t P, int
     const size_t table = sizeof(double) * 2 * size_t(t.R) * (t.T + 1);
     const bool paired = table + sizeof(float) * 2 * size_t(t.M) * t.B <= kResidLdsPaired;
     const size_t lds = table + sizeof(float) * (paired ? 2 : 1) * size_t(t.M) * t.B;
-    const int64_t want = (P + G - 1) / G;
-    const unsigned grid = unsigned(want < 2048 ? want : 2048);
     auto kern = paired ? (K <= 4 ? rk_resid_kernel<4, true> : rk_resid_kernel<8, true>)
                        : (K <= 4 ? rk_resid_kernel<4, false> : rk_resid_kernel<8, false>);
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return int(e);
+    // one resident round of blocks: every block fills its LDS with the dictionary once, so
+    // more blocks than fit at a time would only repeat that fill
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t want = (P + G - 1) / G, cap = int64_t(num_cus()) * per_cu;
+    const unsigned grid = unsigned(want < cap ? want : cap);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), lds, st, qp);
     e = hipGetLastError();
     if (e != hipSuccess) return int(e);
