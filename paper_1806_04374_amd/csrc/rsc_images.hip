@@ -135,12 +135,22 @@ __global__ __launch_bounds__(64 * NT) void project_images_reg_kernel(
   float nxt[TPB][RPT];
   ImgTile cur[TPB];
   bool has[TPB];
-  const int64_t stride = int64_t(gridDim.x) * TPB;
-  // decode tiles wt0 .. wt0 + TPB - 1 (those below ntiles) and load their regions
+  // Blocks go to the XCDs round-robin (block b to XCD b % 8), each XCD with its own L2.  The
+  // tiles are cut into one contiguous range per such group of blocks, which its blocks stride
+  // over, so the window rows that share 14 of their 15 pixel rows are taken on one XCD in
+  // consecutive rounds and their pixels come from its L2.  (Only where the tiles run; every
+  // tile is taken once whatever the placement.)
+  constexpr int kXcd = 8;
+  const int grp = int(blockIdx.x) % kXcd, slot = int(blockIdx.x) / kXcd;
+  const int ngrp = gridDim.x < kXcd ? int(gridDim.x) : kXcd;
+  const int nblk = (int(gridDim.x) - grp + kXcd - 1) / kXcd;   // blocks in this group
+  const int64_t hi = ntiles * (grp + 1) / ngrp;
+  const int64_t stride = int64_t(nblk) * TPB;
+  // decode tiles wt0 .. wt0 + TPB - 1 (those below hi) and load their regions
   auto fetch = [&](int64_t wt0, bool first) {
 #pragma unroll
     for (int k = 0; k < TPB; ++k) {
-      has[k] = wt0 + k < ntiles;
+      has[k] = wt0 + k < hi;
       if (has[k]) {
         cur[k] = img_tile<N>(tile_start, W, n, wt0 + k, first ? -1 : cur[k].img);
         const float* img = pixels + img_offset[cur[k].img] + int64_t(cur[k].y) * cur[k].w + cur[k].x0;
@@ -150,9 +160,9 @@ __global__ __launch_bounds__(64 * NT) void project_images_reg_kernel(
       }
     }
   };
-  int64_t wt0 = int64_t(blockIdx.x) * TPB;
-  if (wt0 < ntiles) fetch(wt0, true);
-  for (; wt0 < ntiles; wt0 += stride) {
+  int64_t wt0 = ntiles * grp / ngrp + int64_t(slot) * TPB;
+  if (wt0 < hi) fetch(wt0, true);
+  for (; wt0 < hi; wt0 += stride) {
     __syncthreads();   // the previous tiles' region and staging reads are done
 #pragma unroll
     for (int k = 0; k < TPB; ++k)
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(64 * NT) void project_images_reg_kernel(
       now[k] = cur[k];
       nhas[k] = has[k];
     }
-    if (wt0 + stride < ntiles) fetch(wt0 + stride, false);
+    if (wt0 + stride < hi) fetch(wt0 + stride, false);
     f32x16 acc[TPB];
 #pragma unroll
     for (int k = 0; k < TPB; ++k)
