@@ -163,3 +163,25 @@ def test_full_ragged_batch_sampled(dev):
     print("ragged-full-sampled", rep, flush=True)
     assert rep.match_rate >= 0.999 and rep.coef_bad == 0, str(rep)
     h.close()
+
+
+@pytest.mark.parametrize("geom", [wl.GEOM15, wl.GEOM11])
+@pytest.mark.parametrize("sizes", [[(15, 15)], [(16, 20)], [(15, 15), (17, 17)], [(40, 15)], [(15, 300)],
+                                   [(20, 33)] * 9])
+def test_small_batches_with_few_blocks(dev, geom, sizes):
+    """Batches of a handful of tiles (launches of fewer than 8 blocks, where the tile ranges
+    per XCD group shrink to one per block, and empty ranges): every window against the
+    reference's projection."""
+    from paper_1806_04374_amd import rsc
+    basis = orc.build_basis(geom.N, geom.S, geom.T)
+    h = rsc.rsc_create(geom.N, geom.S, geom.T)
+    rng = np.random.default_rng(len(sizes) + sizes[0][1])
+    imgs = [rng.standard_normal(s).astype(np.float32) for s in sizes]
+    batch = rsc.ImageBatch(sizes, geom.N, dev)
+    xh = rsc.rsc_project_images(h, _pack(imgs, dev), batch)
+    torch.cuda.synchronize()
+    patches = np.concatenate([orc.image_patches(im.astype(np.float64), geom.N) for im in imgs])
+    assert patches.shape[0] == batch.P_total
+    ref = orc.project(basis, patches)
+    assert np.abs(xh.cpu().numpy() - ref).max() < 2e-5 * np.abs(ref).max()
+    h.close()
