@@ -256,3 +256,33 @@ def test_annular_lowpass_image_projection(dev, N):
     ref = orc.project(ab, np.concatenate([orc.image_patches(im.astype(np.float64), N) for im in imgs]))
     assert np.abs(xh.cpu().numpy() - ref).max() < 2e-5 * np.abs(ref).max()
     h.close()
+
+
+@pytest.mark.parametrize("N", [11, 15])
+def test_annular_workload_full_size_sampled(dev, N):
+    """The annular workload as the bench runs it (10^6 patches of the scale draws at N = 11 or
+    15, a 64-atom dictionary in the annular coordinates, K = 4, R = 64): one projection and
+    one encode launch over all patches; 20,000 sampled patches and the last one against the
+    reference."""
+    from paper_1806_04374_amd import rsc
+    from paper_1806_04374_amd import workloads as wl
+    from tests.parity import compare_codes
+    w = wl.SCALE
+    P, M, K, R = w["P"], w["M"], w["K"], w["R"]
+    ab = orc.build_annular_basis(N)
+    D = wl.draw_dictionary(M, ab.B, seed=7)
+    d = wl.draw_mixtures(P, N, M, w["J"], w["sigma"], 0, 0)
+    X = orc.synthesize(ab, D, d.atom, d.angle, d.weight, d.noise).astype(np.float32)
+    del d
+    h = rsc.rsc_create_annular(N)
+    rsc.rsc_set_dictionary(h, D.astype(np.float32), R)
+    xh = rsc.rsc_project(h, torch.from_numpy(X).to(dev))
+    atom, angle, coef, _ = rsc.rsc_omp_encode(h, xh, K)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(N).choice(P - 1, 20000, replace=False))
+    idx = np.concatenate([idx, [P - 1]])
+    _, code = orc.encode(ab, D, R, X[idx].astype(np.float64), K)
+    rep = compare_codes(atom.cpu().numpy()[idx], angle.cpu().numpy()[idx], coef.cpu().numpy()[idx], code)
+    print(f"annular{N}-full-sampled", rep, flush=True)
+    assert rep.match_rate >= 0.999 and rep.coef_bad == 0, str(rep)
+    h.close()
