@@ -1,5 +1,6 @@
 """Pins of the reference R-K-SVD update in the paper's annular basis (Fig. 2, Sec. II-C, run in
-the steerable basis' coordinates as Sec. II-E does), CPU only.
+the steerable basis' coordinates as Sec. II-E does), at N = 11 (B = 81) and 15 (B = 153), CPU
+only.
 
 The update is the grid's (rksvd_update) with the annular layout's steering: harmonic k of each
 annulus that carries it turned by exp(-i k theta).  Pinned here, as for the grid, by things
@@ -14,9 +15,9 @@ import pytest
 from oracle import rsc_oracle as orc
 
 
-@pytest.fixture(scope="module")
-def ab():
-    return orc.build_annular_basis(11)
+@pytest.fixture(scope="module", params=[11, 15])
+def ab(request):
+    return orc.build_annular_basis(request.param)
 
 
 def _unit(v):
@@ -109,13 +110,13 @@ def test_invariant_to_rotating_every_patch(ab):
 def test_R1_matches_the_layout_free_form(ab):
     """With R = 1 nothing is turned, so the update does not depend on the layout: it equals
     the grid routine run on the same coordinates (any S, T with S (2T + 1) = B would do;
-    B = 81 = 27 x 3 is read as S = 27, T = 1)."""
+    B = 81 = 27 x 3 is read as S = 27, T = 1, and B = 153 = 51 x 3 as S = 51, T = 1)."""
     R, M, K = 1, 5, 2
     D_true, X = _toy(ab, 200, M, K, R, seed=9)
     D = _unit(D_true + 0.2 * np.random.default_rng(10).standard_normal(D_true.shape))
     code = orc.omp(orc.augmented_dictionary_basis(ab, D, R), X, K, M)
     a, ua, ra = orc.rksvd_update_basis(ab, D, R, X, code)
-    b, ub, rb = orc.rksvd_update(D, R, 27, 1, X, code)
+    b, ub, rb = orc.rksvd_update(D, R, ab.B // 3, 1, X, code)
     assert np.abs(a - b).max() < 1e-12 and np.array_equal(ua, ub) and np.array_equal(ra, rb)
 
 
