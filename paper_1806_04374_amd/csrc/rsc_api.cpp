@@ -641,6 +641,20 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
   std::vector<int> kbase(T + 1, 0);
   for (int k = 1; k <= T; ++k) kbase[k] = k == 1 ? d.sk[0] : kbase[k - 1] + 2 * d.sk[k - 1];
   const bool lp = h->prec != RSC_FP32;
+  // i * d in the row layout of hat (FP32 16x16 tile): the stage-1 Im rows read it at the
+  // offsets the Re rows read d, so neither needs a sign; zero at harmonic 0, whose Im row is 0
+  std::vector<float> hatI;
+  if (!lp) {
+    hatI.assign(hat.size(), 0.f);
+    for (int m = 0; m < M; ++m)
+      for (int k = 1; k <= T; ++k) {
+        const int base = kbase[k], nk = d.sk[k];
+        for (int s = 0; s < nk; ++s) {
+          hatI[size_t(m) * B + base + s] = -D(m, base + nk + s);
+          hatI[size_t(m) * B + base + nk + s] = D(m, base + s);
+        }
+      }
+  }
   std::vector<float> gramH(size_t(M) * M * HQ);
   std::vector<double> gramH64(gramH.size());
   for (int a = 0; a < M; ++a)
@@ -743,6 +757,7 @@ rsc_status rsc_set_dictionary(rsc_handle* h, const float* d_hat, int M, int R, v
   Arena arena;
   arena.add(d.dictA, dictA);
   arena.add(d.dictHat, hat);
+  arena.add(d.dictHatI, hatI);
   arena.add(d.dftA32, dftA32);
   arena.add(d.dftA16, dftA16);
   arena.add(d.dftA16s, dftA16s);

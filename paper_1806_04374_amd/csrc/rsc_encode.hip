@@ -226,7 +226,10 @@ int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
 
 template <class C, int HT, int KMAX, bool SPLIT>
 int launch16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  return launch_persistent(encode16_kernel<C, HT, KMAX, SPLIT>, encode_lds_bytes(t, RSC_TILE_16),
+  if (encode16_irows(t, (prm.P + 15) / 16))
+    return launch_persistent_n(encode16_kernel<C, HT, KMAX, SPLIT, true>, 512, encode16_lds_bytes(t, true),
+                               (prm.P + 15) / 16, t.enc_bpc, st, prm);
+  return launch_persistent(encode16_kernel<C, HT, KMAX, SPLIT, false>, encode16_lds_bytes(t, false),
                            (prm.P + 15) / 16, t.enc_bpc, st, prm);
 }
 
@@ -269,14 +272,24 @@ bool encode_supported_geo(const DeviceTables& t) {
   return t.geo == kGeoGrid && encode_supported(t.S, t.T);
 }
 
-size_t encode_lds_bytes(const DeviceTables& t, int tile) {
+size_t encode16_lds_bytes(const DeviceTables& t, bool irows) {
   const size_t cs = 2 * size_t(t.T + 1) * t.R;
+  const int ng = (t.M + 7) / 8;
+  return sizeof(float) * (size_t(ng) * 8 * t.B * (irows ? 2 : 1) + cs);
+}
+
+bool encode16_irows(const DeviceTables& t, int64_t wave_tiles) {
+  return t.dictHatI != nullptr && encode16_lds_bytes(t, true) <= 160 * 1024 &&
+         wave_tiles >= 8 * int64_t(num_cus());
+}
+
+size_t encode_lds_bytes(const DeviceTables& t, int tile) {
   if (tile == RSC_TILE_32) {
+    const size_t cs = 2 * size_t(t.T + 1) * t.R;
     const int ng = (t.M + 15) / 16;
     return sizeof(float) * (size_t(ng) * stage1_steps(t.S, t.T) * 64 + size_t(ng) * 16 * t.B + cs);
   }
-  const int ng = (t.M + 7) / 8;
-  return sizeof(float) * (size_t(ng) * 8 * t.B + cs);
+  return encode16_lds_bytes(t, false);   // the smaller form, used when the copy does not fit
 }
 
 bool tile32_usable(const DeviceTables& t, int K) {
@@ -318,11 +331,11 @@ int launch_encode(const DeviceTables& t, int tile, const float* xhat, int64_t P,
   if (tile == RSC_TILE_32) {
     if (!tile32_usable(t, K)) return int(hipErrorInvalidValue);
     EncodeParams prm{xhat, P, K, t.M, t.R, t.dictA, t.dictHat, t.dftA32, t.cs, t.gramH, t.gramH64, t.cs64,
-                     atom, angle, coef, resid2, t.lpStats};
+                     atom, angle, coef, resid2, t.lpStats, nullptr};
     return r32(t, prm, st);
   }
   EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.R % 2 == 0 ? t.dftA16s : t.dftA16, t.cs, t.gramH,
-                   t.gramH64, t.cs64, atom, angle, coef, resid2, t.lpStats};
+                   t.gramH64, t.cs64, atom, angle, coef, resid2, t.lpStats, t.dictHatI};
   if (t.geo == kGeoAnnular11 || t.geo == kGeoAnnular15)
     return launch_encode_annular(t, xhat, P, K, atom, angle, coef, resid2, stream);
   if (t.geo != kGeoGrid) return int(hipErrorInvalidValue);

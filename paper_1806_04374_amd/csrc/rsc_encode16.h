@@ -28,6 +28,7 @@ struct EncodeParams {
   float* coef;
   float* resid2;
   unsigned long long* stats;   // [4]: [3] counts pursuit steps solved in FP64
+  const float* dictHatI;       // i * dictionary rows, as dictHat (16x16 tile with IROWS; else unused)
 };
 
 // Adds this wave's count of FP64 least-squares steps to stats[3] (one atomic per wave).
@@ -108,9 +109,14 @@ __device__ __forceinline__ void atom_products4(const float* __restrict__ hat, in
 // Direct (odd R): steps contract harmonic pairs (2q, 2q+1); HT tiles cover r < R.
 // dftA: [HT][NP][64].
 // C: the profile counts per harmonic (LayoutBase): the (S, T) grid or the annular basis.
-template <class C, int HT, int KMAX, bool SPLIT>
-__global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
+// IROWS: the stage-1 Im rows read i * d (dictHatI, a second LDS table) at the offsets where
+// the Re rows read d, so no lane applies a sign; the block then has 8 waves (one block per
+// CU shares the two tables); without it the Im rows negate what they read and a block has
+// 4 waves.
+template <class C, int HT, int KMAX, bool SPLIT, bool IROWS>
+__global__ __launch_bounds__(IROWS ? 512 : 256, 2) void encode16_kernel(EncodeParams prm) {
   using L = LayoutBase<C, 4>;
+  constexpr int NW = IROWS ? 8 : 4;                          // waves per block
   constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B, T = L::T;
   constexpr int NE = T / 2 + 1, NO = (T + 1) / 2;           // even / odd harmonics
   constexpr int SE = SPLIT ? (NE + 1) / 2 : (NQ + 1) / 2;   // steps feeding the E (or only) chain
@@ -119,11 +125,14 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
   extern __shared__ float lds[];
   const int R = prm.R, M = prm.M, K = prm.K, HALF = SPLIT ? prm.R / 2 : prm.R;
   const int NG = (M + 7) / 8;
-  float* sHat = lds;                     // [NG*8][B]
-  float* sCs = sHat + NG * 8 * B;        // [2][NQ][R]
+  float* sHat = lds;                              // [NG*8][B]
+  float* sHatI = sHat + (IROWS ? NG * 8 * B : 0);  // [NG*8][B] with IROWS
+  float* sCs = sHatI + NG * 8 * B;                // [2][NQ][R]
   {
     const int nH = NG * 8 * B, nC = 2 * NQ * R;
     for (int i = threadIdx.x; i < nH; i += blockDim.x) sHat[i] = prm.dictHat[i];
+    if (IROWS)
+      for (int i = threadIdx.x; i < nH; i += blockDim.x) sHatI[i] = prm.dictHatI[i];
     for (int i = threadIdx.x; i < nC; i += blockDim.x) sCs[i] = prm.cs[i];
   }
   __syncthreads();
@@ -138,9 +147,10 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
   const int a_of_row = (arow & 3) + 4 * (arow >> 3);
   const bool is_im = (arow >> 2) & 1;
   const int part = u & 1;
-  const bool other = part ^ int(is_im);          // this row reads the partner part (Re <-> Im)
-  const float sgn = (is_im && part == 0) ? -1.f : 1.f;
-  const float* arow_hat = sHat + a_of_row * B;
+  // without IROWS: the Im rows read the partner part of d (Re <-> Im), negated for x's Re part
+  const bool other = IROWS ? bool(part) : bool(part ^ int(is_im));
+  const float sgn = (!IROWS && is_im && part == 0) ? -1.f : 1.f;
+  const float* arow_hat = (IROWS && is_im ? sHatI : sHat) + a_of_row * B;
 
   float F[HT][NS];
 #pragma unroll
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
   auto k2_of = [](int q) { return SPLIT ? (q < SE ? 4 * q + 2 : 4 * (q - SE) + 3) : 2 * q + 1; };
 
   const int64_t nwt = (prm.P + 15) / 16;
-  for (int64_t wt = int64_t(blockIdx.x) * 4 + wave; wt < nwt; wt += int64_t(gridDim.x) * 4) {
+  for (int64_t wt = int64_t(blockIdx.x) * NW + wave; wt < nwt; wt += int64_t(gridDim.x) * NW) {
     const int64_t p = wt * 16 + col;
     const bool valid = p < prm.P;
     float res[NKS];
@@ -187,17 +197,29 @@ __global__ __launch_bounds__(256, 2) void encode16_kernel(EncodeParams prm) {
         static_for<NKS>([&](auto J) {
           constexpr int j = decltype(J)::value;
           constexpr int k = L::harm(j);
+          // With IROWS a lane past its harmonic's count (a padding coordinate, at most three
+          // past harmonic 0's and one past any other's) reads the next values of the row, or
+          // of the next row (after the last row of either table come the other table or the
+          // angle table): finite values that meet a residual coordinate held at exactly 0.
           float av;
           if constexpr (k == 0) {
             const int s = 4 * j + u;
-            const float h = hg[s < L::S ? s : 0];
-            av = (!is_im && s < L::S) ? h : 0.f;
+            if constexpr (IROWS) {
+              av = hg[s];                                     // i * d is 0 at harmonic 0
+            } else {
+              const float h = hg[s < L::S ? s : 0];
+              av = (!is_im && s < L::S) ? h : 0.f;
+            }
           } else {
             constexpr int jj = L::pair(j), bk = L::base(k), sk = L::Sk(k);
             const int s = 2 * jj + (u >> 1);
             const int off = bk + 2 * jj + (u >> 1) + (other ? sk : 0);
-            const float h = hg[s < sk ? off : 0];
-            av = s < sk ? sgn * h : 0.f;
+            if constexpr (IROWS) {
+              av = hg[off];
+            } else {
+              const float h = hg[s < sk ? off : 0];
+              av = s < sk ? sgn * h : 0.f;
+            }
           }
           acc[k] = mfma16(av, res[j], acc[k]);
         });

@@ -20,7 +20,10 @@ namespace {
 
 template <class C, int HT, int KMAX>
 int launchA(const DeviceTables& t, const enc::EncodeParams& prm, hipStream_t st) {
-  return launch_persistent(enc::encode16_kernel<C, HT, KMAX, true>, encode_lds_bytes(t, RSC_TILE_16),
+  if (encode16_irows(t, (prm.P + 15) / 16))
+    return launch_persistent_n(enc::encode16_kernel<C, HT, KMAX, true, true>, 512, encode16_lds_bytes(t, true),
+                               (prm.P + 15) / 16, t.enc_bpc, st, prm);
+  return launch_persistent(enc::encode16_kernel<C, HT, KMAX, true, false>, encode16_lds_bytes(t, false),
                            (prm.P + 15) / 16, t.enc_bpc, st, prm);
 }
 
@@ -38,7 +41,7 @@ int launch_encode_annular(const DeviceTables& t, const float* xhat, int64_t P, i
   if (P <= 0) return 0;
   if (K < 1 || K > kAnnularMaxK || t.R % 2 != 0 || t.R > kAnnularMaxR) return int(hipErrorInvalidValue);
   const enc::EncodeParams prm{xhat, P, K, t.M, t.R, nullptr, t.dictHat, t.dftA16s, t.cs, t.gramH, t.gramH64,
-                              t.cs64, atom, angle, coef, resid2, t.lpStats};
+                              t.cs64, atom, angle, coef, resid2, t.lpStats, t.dictHatI};
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (t.geo == kGeoAnnular11) return dispatchA<AnnularCounts11>(t, prm, st);
   if (t.geo == kGeoAnnular15) return dispatchA<AnnularCounts15>(t, prm, st);

@@ -57,6 +57,8 @@ struct DeviceTables {
   size_t dictArenaBytes = 0;
   float* dictA = nullptr;    // 32x32-tile stage-1 operand [NG][stage1_steps][64] (S = T = 5 only)
   float* dictHat = nullptr;  // dictionary rows [16*ceil(M/16)][B] (zero rows past M)
+  float* dictHatI = nullptr; // i times the dictionary rows, same shape: per harmonic k >= 1 the
+                             // (Re, Im) slots hold (-Im d, Re d); zero at k = 0 (16x16 FP32 tile)
   float* dftA32 = nullptr;   // 32x32-tile stage-2 operand, angles r < R/2 [T+1][64] (even R <= 64)
   float* dftA16 = nullptr;   // 16x16-tile stage-2 operand, all angles [ceil(R/16)->1,2,4,8][(T+2)/2][64]
   float* dftA16s = nullptr;  // 16x16-tile stage-2 operand, parity split [ceil(R/32)->1,2,4][E+O steps][64]
@@ -94,6 +96,12 @@ constexpr int kAnnularMaxK = 4, kAnnularMaxR = 64;
 int launch_encode_annular(const DeviceTables& t, const float* xhat, int64_t P, int K, int32_t* atom,
                           int32_t* angle, float* coef, float* resid2, void* stream);
 size_t encode_lds_bytes(const DeviceTables& t, int tile);
+// 16x16 FP32 tile: LDS of one block with (irows) or without the i * dictionary copy, and
+// whether a launch over wave_tiles tiles of 16 patches takes the copy: when it fits a CU
+// (the kernel then runs 512-thread blocks, one per CU) and the tiles fill every CU with 8
+// waves (fewer tiles run faster as 4-wave blocks, one wave per SIMD).
+size_t encode16_lds_bytes(const DeviceTables& t, bool irows);
+bool encode16_irows(const DeviceTables& t, int64_t wave_tiles);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);
