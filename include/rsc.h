@@ -203,7 +203,10 @@ rsc_status rsc_set_tile(rsc_handle* h, rsc_tile tile);
 
 /*
  * Encoder launch shape: tile shape and persistent blocks per compute unit
- * (0 = as many as fit; larger requests are capped at what fits).  Codes do not
+ * (0 = as many as fit; larger requests are capped at what fits), counted in blocks
+ * of 4 waves: where the FP32 16x16 encoder runs 8-wave blocks (both of its
+ * dictionary tables fit a CU and the launch has at least 8 tiles of 16 patches per
+ * CU) each counts as two, and a cap below two still admits one.  Codes do not
  * depend on blocks_per_cu; the tile shape changes only FP32 rounding order.
  * Errors: RSC_E_INVALID for an unknown tile or blocks_per_cu outside 0..16.
  */
