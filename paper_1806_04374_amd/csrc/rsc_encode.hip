@@ -15,11 +15,10 @@
 //       rows are computed, and the largest |score| of an atom over all R angles is
 //       max_r (|E(r)| + |O(r)|), bit-identical to the maximum of the rounded scores.
 //       The argmax runs in two passes: per atom only that maximum is compared; the
-//       winning atom's angles are then recomputed and searched (16x16 tiles: from its
-//       stage-2 operand kept in pass 1, with the same instructions; 32x32 tiles: from its
-//       operand formed again from its dictionary row, which costs one product per
-//       coordinate per step instead of a register copy per atom).  Exact ties go to the
-//       smallest atom, then the smallest angle.
+//       winning atom's angles are then recomputed and searched from its stage-2 operand
+//       formed again from its dictionary row (one product per coordinate per step instead
+//       of a register copy per atom).  Exact ties go to the smallest atom, then the
+//       smallest angle.
 //   (c) extends the Cholesky factor of the selected columns, solves the least
 //       squares and updates the residual, all in registers; a patch whose Gram matrix
 //       grows ill-conditioned (bound k ||L^{-1}||_F^2 above 1e3) or whose new pivot is
@@ -30,7 +29,8 @@
 //             tile; dictionary operand pre-arranged in LDS.  (S, T) = (5, 5), K <= 4,
 //             even R <= 64.
 //   encode16: v_mfma_f32_16x16x4f32, 16 patches per wave, 8 atoms per stage-1
-//             tile; dictionary operand read from the packed dictionary in LDS.
+//             tile; dictionary operand read from the packed dictionary in LDS (the Im
+//             rows from a second table holding i * d where both fit).
 //             Any compiled (S, T), K <= 8, any R (odd R without the split).
 #include <hip/hip_runtime.h>
 
