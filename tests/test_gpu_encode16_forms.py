@@ -9,7 +9,8 @@ coded on its own, so one launch over all patches (first form) and launches over 
 feed the matrix cores the same operand values (-Im d exactly, and zero-residual padding
 products of +-0).  The one-launch codes are also held to the parity bar against the FP64
 reference on their first patches (selected (atom, angle) sets equal on >= 99.9%, every
-matched coefficient within 1e-4 relative).
+matched coefficient within 1e-4 relative).  The cases cover both grids and both annular bases,
+one to eight 16-row angle tiles (even R split by parity, odd R direct) and K from 2 to 8.
 
 A dictionary too large for both tables (M = 200 at 15x15, 2 x 84 KB) runs the second form
 in the large launch too; the chunked comparison then checks position invariance only.
@@ -34,6 +35,9 @@ CASES = [
     ("grid15-ragged-config", "grid", 15, 7, 7, 128, 64, 6),
     ("grid11-K8-oddR", "grid", 11, 5, 5, 40, 33, 8),
     ("grid11-R32", "grid", 11, 5, 5, 64, 32, 2),
+    ("grid11-R128", "grid", 11, 5, 5, 24, 128, 3),       # four 16-row angle tiles after the split
+    ("grid11-R97", "grid", 11, 5, 5, 16, 97, 2),         # odd R: eight tiles of the direct DFT
+    ("grid15-R100-K8", "grid", 15, 7, 7, 32, 100, 8),
     ("annular11", "annular", 11, 0, 0, 64, 64, 4),
     ("annular15", "annular", 15, 0, 0, 48, 30, 2),
     ("grid15-large-dictionary", "grid", 15, 7, 7, 200, 16, 2),
