@@ -226,11 +226,12 @@ int launch32(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
 
 template <class C, int HT, int KMAX, bool SPLIT>
 int launch16(const DeviceTables& t, const EncodeParams& prm, hipStream_t st) {
-  if (encode16_irows(t, (prm.P + 15) / 16))
-    return launch_persistent_n(encode16_kernel<C, HT, KMAX, SPLIT, true>, 512, encode16_lds_bytes(t, true),
-                               (prm.P + 15) / 16, t.enc_bpc, st, prm);
-  return launch_persistent(encode16_kernel<C, HT, KMAX, SPLIT, false>, encode16_lds_bytes(t, false),
-                           (prm.P + 15) / 16, t.enc_bpc, st, prm);
+  const int64_t tiles = (prm.P + 15) / 16;
+  if (encode16_irows(t))
+    return launch_persistent_n(encode16_kernel<C, HT, KMAX, SPLIT, true>, encode16_threads(tiles),
+                               encode16_lds_bytes(t, true), tiles, t.enc_bpc, st, prm);
+  return launch_persistent(encode16_kernel<C, HT, KMAX, SPLIT, false>, encode16_lds_bytes(t, false), tiles,
+                           t.enc_bpc, st, prm);
 }
 
 template <class C, int HT, bool SPLIT>
@@ -278,10 +279,11 @@ size_t encode16_lds_bytes(const DeviceTables& t, bool irows) {
   return sizeof(float) * (size_t(ng) * 8 * t.B * (irows ? 2 : 1) + cs);
 }
 
-bool encode16_irows(const DeviceTables& t, int64_t wave_tiles) {
-  return t.dictHatI != nullptr && encode16_lds_bytes(t, true) <= 160 * 1024 &&
-         wave_tiles >= 8 * int64_t(num_cus());
+bool encode16_irows(const DeviceTables& t) {
+  return t.dictHatI != nullptr && encode16_lds_bytes(t, true) <= 160 * 1024;
 }
+
+int encode16_threads(int64_t wave_tiles) { return wave_tiles >= 8 * int64_t(num_cus()) ? 512 : 256; }
 
 size_t encode_lds_bytes(const DeviceTables& t, int tile) {
   if (tile == RSC_TILE_32) {

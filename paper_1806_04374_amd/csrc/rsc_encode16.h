@@ -110,13 +110,13 @@ __device__ __forceinline__ void atom_products4(const float* __restrict__ hat, in
 // dftA: [HT][NP][64].
 // C: the profile counts per harmonic (LayoutBase): the (S, T) grid or the annular basis.
 // IROWS: the stage-1 Im rows read i * d (dictHatI, a second LDS table) at the offsets where
-// the Re rows read d, so no lane applies a sign; the block then has 8 waves (one block per
-// CU shares the two tables); without it the Im rows negate what they read and a block has
-// 4 waves.
+// the Re rows read d, so no lane applies a sign; without it the Im rows negate what they read
+// and mask the padding coordinates.  Blocks of 4 or 8 waves (256 or 512 threads; with 8, one
+// block per CU shares the tables).
 template <class C, int HT, int KMAX, bool SPLIT, bool IROWS>
 __global__ __launch_bounds__(IROWS ? 512 : 256, 2) void encode16_kernel(EncodeParams prm) {
   using L = LayoutBase<C, 4>;
-  constexpr int NW = IROWS ? 8 : 4;                          // waves per block
+  const int NW = int(blockDim.x) >> 6;                       // waves per block (4 or 8)
   constexpr int NKS = L::NKS, NQ = L::NQ, B = L::B, T = L::T;
   constexpr int NE = T / 2 + 1, NO = (T + 1) / 2;           // even / odd harmonics
   constexpr int SE = SPLIT ? (NE + 1) / 2 : (NQ + 1) / 2;   // steps feeding the E (or only) chain

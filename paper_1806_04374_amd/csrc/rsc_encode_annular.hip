@@ -20,11 +20,12 @@ namespace {
 
 template <class C, int HT, int KMAX>
 int launchA(const DeviceTables& t, const enc::EncodeParams& prm, hipStream_t st) {
-  if (encode16_irows(t, (prm.P + 15) / 16))
-    return launch_persistent_n(enc::encode16_kernel<C, HT, KMAX, true, true>, 512, encode16_lds_bytes(t, true),
-                               (prm.P + 15) / 16, t.enc_bpc, st, prm);
-  return launch_persistent(enc::encode16_kernel<C, HT, KMAX, true, false>, encode16_lds_bytes(t, false),
-                           (prm.P + 15) / 16, t.enc_bpc, st, prm);
+  const int64_t tiles = (prm.P + 15) / 16;
+  if (encode16_irows(t))
+    return launch_persistent_n(enc::encode16_kernel<C, HT, KMAX, true, true>, encode16_threads(tiles),
+                               encode16_lds_bytes(t, true), tiles, t.enc_bpc, st, prm);
+  return launch_persistent(enc::encode16_kernel<C, HT, KMAX, true, false>, encode16_lds_bytes(t, false), tiles,
+                           t.enc_bpc, st, prm);
 }
 
 template <class C>

@@ -96,12 +96,13 @@ constexpr int kAnnularMaxK = 4, kAnnularMaxR = 64;
 int launch_encode_annular(const DeviceTables& t, const float* xhat, int64_t P, int K, int32_t* atom,
                           int32_t* angle, float* coef, float* resid2, void* stream);
 size_t encode_lds_bytes(const DeviceTables& t, int tile);
-// 16x16 FP32 tile: LDS of one block with (irows) or without the i * dictionary copy, and
-// whether a launch over wave_tiles tiles of 16 patches takes the copy: when it fits a CU
-// (the kernel then runs 512-thread blocks, one per CU) and the tiles fill every CU with 8
-// waves (fewer tiles run faster as 4-wave blocks, one wave per SIMD).
+// 16x16 FP32 tile: LDS of one block with (irows) or without the i * dictionary copy, whether
+// the copy is used (both tables fit a CU), and the block size of a launch over wave_tiles
+// tiles of 16 patches with the copy: 512 threads (one block per CU, 8 waves) once the tiles
+// fill every CU with 8 waves, else 256 (fewer tiles run faster one wave per SIMD).
 size_t encode16_lds_bytes(const DeviceTables& t, bool irows);
-bool encode16_irows(const DeviceTables& t, int64_t wave_tiles);
+bool encode16_irows(const DeviceTables& t);
+int encode16_threads(int64_t wave_tiles);
 bool tile32_usable(const DeviceTables& t, int K);
 double encode_mfma_flops_per_patch(const DeviceTables& t, int tile, int K);
 size_t project_tiled_lds_bytes(int N, int n_pix);

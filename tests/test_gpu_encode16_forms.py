@@ -1,19 +1,15 @@
-"""The two forms of the 16x16-tile FP32 encoder against each other and the FP64 reference.
+"""The 16x16-tile FP32 encoder's launch forms against each other and the FP64 reference.
 
-The encoder's stage-1 Im rows either read a second LDS table holding i * d (one 8-wave block
-per CU), or negate what they read from d and mask the padding coordinates (4-wave blocks).
-The first form runs when both tables fit a CU's LDS and the launch has at least 8 tiles of
-16 patches per CU; the second for larger dictionaries and smaller launches.  Every patch is
-coded on its own, so one launch over all patches (first form) and launches over chunks of
-1,600 patches (100 tiles: second form) must give the same codes bit for bit: the two forms
-feed the matrix cores the same operand values (-Im d exactly, and zero-residual padding
-products of +-0).  The one-launch codes are also held to the parity bar against the FP64
-reference on their first patches (selected (atom, angle) sets equal on >= 99.9%, every
-matched coefficient within 1e-4 relative).  The cases cover both grids and both annular bases,
-one to eight 16-row angle tiles (even R split by parity, odd R direct) and K from 2 to 8.
-
-A dictionary too large for both tables (M = 200 at 15x15, 2 x 84 KB) runs the second form
-in the large launch too; the chunked comparison then checks position invariance only.
+The encoder's stage-1 Im rows read a second LDS table holding i * d when both tables fit a
+CU's LDS; a launch with at least 8 tiles of 16 patches per CU then runs 8-wave blocks (one
+per CU), a smaller one 4-wave blocks.  A dictionary too large for both tables (M = 200 at
+15x15, 2 x 84 KB) takes the other form, whose Im rows negate what they read from d and mask
+the padding coordinates.  Every patch is coded on its own, so one launch over all patches
+and launches over chunks of 1,600 patches (100 tiles) must give the same codes bit for bit.
+The one-launch codes are also held to the parity bar against the FP64 reference on their
+first patches (selected (atom, angle) sets equal on >= 99.9%, every matched coefficient
+within 1e-4 relative).  The cases cover both grids and both annular bases, one to eight
+16-row angle tiles (even R split by parity, odd R direct) and K from 2 to 8.
 """
 import numpy as np
 import pytest
