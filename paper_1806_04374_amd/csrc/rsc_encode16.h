@@ -110,9 +110,9 @@ __device__ __forceinline__ void atom_products4(const float* __restrict__ hat, in
 // dftA: [HT][NP][64].
 // C: the profile counts per harmonic (LayoutBase): the (S, T) grid or the annular basis.
 // IROWS: the stage-1 Im rows read i * d (dictHatI, a second LDS table) at the offsets where
-// the Re rows read d, so no lane applies a sign; without it the Im rows negate what they read
-// and mask the padding coordinates.  Blocks of 4 or 8 waves (256 or 512 threads; with 8, one
-// block per CU shares the tables).
+// the Re rows read d, so no lane applies a sign; without it (dictionaries too large for two
+// tables) the Im rows negate what they read.  Blocks of 4 or 8 waves (256 or 512 threads;
+// with 8, one block per CU shares the tables).
 template <class C, int HT, int KMAX, bool SPLIT, bool IROWS>
 __global__ __launch_bounds__(IROWS ? 512 : 256, 2) void encode16_kernel(EncodeParams prm) {
   using L = LayoutBase<C, 4>;
@@ -197,28 +197,25 @@ __global__ __launch_bounds__(IROWS ? 512 : 256, 2) void encode16_kernel(EncodePa
         static_for<NKS>([&](auto J) {
           constexpr int j = decltype(J)::value;
           constexpr int k = L::harm(j);
-          // With IROWS a lane past its harmonic's count (a padding coordinate, at most three
-          // past harmonic 0's and one past any other's) reads the next values of the row, or
-          // of the next row (after the last row of either table come the other table or the
-          // angle table): finite values that meet a residual coordinate held at exactly 0.
+          // A lane past its harmonic's count (a padding coordinate, at most three past
+          // harmonic 0's and one past any other's) reads the next values of the row, or of
+          // the next row (after the last row of a table comes the other table or the angle
+          // table): finite values that meet a residual coordinate held at exactly 0.
           float av;
           if constexpr (k == 0) {
-            const int s = 4 * j + u;
             if constexpr (IROWS) {
-              av = hg[s];                                     // i * d is 0 at harmonic 0
+              av = hg[4 * j + u];                             // i * d is 0 at harmonic 0
             } else {
-              const float h = hg[s < L::S ? s : 0];
-              av = (!is_im && s < L::S) ? h : 0.f;
+              const float h = hg[4 * j + u];
+              av = is_im ? 0.f : h;                           // the Im rows of harmonic 0 are 0
             }
           } else {
             constexpr int jj = L::pair(j), bk = L::base(k), sk = L::Sk(k);
-            const int s = 2 * jj + (u >> 1);
             const int off = bk + 2 * jj + (u >> 1) + (other ? sk : 0);
             if constexpr (IROWS) {
               av = hg[off];
             } else {
-              const float h = hg[s < sk ? off : 0];
-              av = s < sk ? sgn * h : 0.f;
+              av = sgn * hg[off];
             }
           }
           acc[k] = mfma16(av, res[j], acc[k]);

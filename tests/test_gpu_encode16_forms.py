@@ -3,9 +3,9 @@
 The encoder's stage-1 Im rows read a second LDS table holding i * d when both tables fit a
 CU's LDS; a launch with at least 8 tiles of 16 patches per CU then runs 8-wave blocks (one
 per CU), a smaller one 4-wave blocks.  A dictionary too large for both tables (M = 200 at
-15x15, 2 x 84 KB) takes the other form, whose Im rows negate what they read from d and mask
-the padding coordinates.  Every patch is coded on its own, so one launch over all patches
-and launches over chunks of 1,600 patches (100 tiles) must give the same codes bit for bit.
+15x15, 2 x 84 KB) takes the other form, whose Im rows negate what they read from d.  Every
+patch is coded on its own, so one launch over all patches and launches over chunks of 1,600
+patches (100 tiles) must give the same codes bit for bit.
 The one-launch codes are also held to the parity bar against the FP64 reference on their
 first patches (selected (atom, angle) sets equal on >= 99.9%, every matched coefficient
 within 1e-4 relative).  The cases cover both grids and both annular bases, one to eight
